@@ -1,0 +1,202 @@
+"""Benchmark: DF Louvain update latency (p50/p99) and edges scanned per
+second against GPU static Louvain, on R-MAT scale 22 (4,194,304 vertices,
+edge factor 16, a=0.57 b=0.19 c=0.19) with random 80/20 batch updates of
+1e-7|E| .. 1e-3|E| (x10 steps).
+
+A step is one batch through the whole hot path: apply_batch (in-place CSR
+edit) then louvain_df (marking, weight update, local-moving, aggregation).
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DF Louvain update latency p50/p99 & edges scanned/s vs GPU Static Louvain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_batches(e, sizes, count, seed):
+    """`count` batches cycling through `sizes` (undirected updates), each 80%
+    insertions of absent uniform pairs and 20% deletions of uniform existing
+    edges.  All batches are drawn at once from disjoint pools, so applying
+    them in sequence is always valid (a deletion's edge still exists, an
+    insertion's pair is still absent)."""
+    from paper_2404_19634_amd import workloads as W
+    plan = [sizes[k % len(sizes)] for k in range(count)]
+    n_ins = [int(round(0.8 * s)) for s in plan]
+    n_del = [s - i for s, i in zip(plan, n_ins)]
+    pool = W.random_batch(e, sum(n_ins) + sum(n_del), seed, ins_frac=sum(n_ins) / max(1, sum(plan)))
+    out, pi, pd = [], 0, 0
+    for a, d in zip(n_ins, n_del):
+        out.append(W.Batch(pool.del_u[pd:pd + d], pool.del_v[pd:pd + d], pool.del_w[pd:pd + d],
+                           pool.ins_u[pi:pi + a], pool.ins_v[pi:pi + a], pool.ins_w[pi:pi + a]))
+        pi += a
+        pd += d
+    return out
+
+
+def pct(x, q):
+    return float(np.percentile(np.asarray(x, dtype=np.float64), q)) if len(x) else None
+
+
+def cpu_baseline(e, batch, budget_s=30.0):
+    """The sequential oracle on a bounded sample of the same workload: one
+    full local-moving sweep of static Louvain (every vertex scanned once),
+    then DF Louvain on one batch starting from that sweep's partition."""
+    import oracle
+    t0 = time.perf_counter()
+    G = oracle.Graph.from_edges(e)
+    build_s = time.perf_counter() - t0
+    C, K, S, st = G.louvain("static", mode="async", max_passes=1, max_iterations=1)
+    sweep_s, sweep_arcs = st["seconds"], st["arcs_scanned"]
+    res = {"value": sweep_arcs / sweep_s, "unit": "edges scanned/s", "cores": 1, "kind": "oracle",
+           "sample": (f"one static local-moving sweep over all {sweep_arcs} arcs "
+                      f"({sweep_s:.2f} s) then DF Louvain on one batch of {batch.size} updates"),
+           "static_sweep_edges_per_s": sweep_arcs / sweep_s, "graph_build_s": build_s}
+    if sweep_s < budget_s:
+        assert G.apply_batch(batch) == 0
+        C2, K2, S2, st2 = G.louvain("df", batch=batch, state=(C, K, S), mode="async")
+        res["df_latency_ms"] = st2["seconds"] * 1e3
+        res["df_edges_scanned"] = st2["arcs_scanned"]
+        res["df_edges_per_s"] = st2["arcs_scanned"] / st2["seconds"] if st2["seconds"] > 0 else None
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--mode", default="async", choices=["async", "sync"])
+    ap.add_argument("--static-runs", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the single-GPU line is the result",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2404_19634_amd import lib
+    from paper_2404_19634_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    e = W.config2_rmat(args.scale)
+    log(f"R-MAT s{args.scale}: n={e.n} undirected edges={e.m} max w={int(e.w.max())} "
+        f"({time.perf_counter() - t0:.1f} s)")
+    fracs = [1e-7, 1e-6, 1e-5, 1e-4, 1e-3]
+    sizes = [W.batch_size(f, e.m) for f in fracs]
+    total = args.warmup + args.steps
+    batches = make_batches(e, sizes, total, seed=4242)
+    dbatches = [lib.Batch.from_host(b, dev) for b in batches]
+    g = lib.Graph.from_edges(e, slack_frac=0.1, slack_min=4)
+    prm = lib.params(mode=args.mode)
+    torch.cuda.synchronize()
+
+    # GPU static Louvain on the initial graph (comparison baseline)
+    static_ms, static_arcs, static_stats = [], [], None
+    state0 = None
+    for r in range(args.static_runs):
+        st = lib.State.empty(e.n, dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, s = lib.louvain_static(g, prm, st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        if r > 0 or args.static_runs == 1:
+            static_ms.append(dt * 1e3)
+            static_arcs.append(s["arcs_scanned"])
+        static_stats, state0 = s, st
+    q_static = lib.modularity(g, state0.C)
+    log(f"static: {np.median(static_ms):.2f} ms, arcs scanned {static_arcs[-1]}, Q={q_static:.6f}, "
+        f"passes {static_stats['passes']} iters {static_stats['iterations']}")
+
+    # DF steps
+    state = state0.clone()
+    lat, apply_ms, arcs, per_size = [], [], [], {}
+    torch.cuda.synchronize()
+    for k in range(total):
+        if k == args.warmup:
+            torch.cuda.synchronize()
+            t_region = time.perf_counter()
+        b = dbatches[k]
+        t = time.perf_counter()
+        lib.apply_batch(g, b)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        state, s = lib.louvain_df(g, b, state, prm)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if k >= args.warmup:
+            apply_ms.append((t1 - t) * 1e3)
+            lat.append((t2 - t1) * 1e3)
+            arcs.append(s["arcs_scanned"])
+            per_size.setdefault(batches[k].size, []).append((t2 - t1) * 1e3)
+    torch.cuda.synchronize()
+    region_s = time.perf_counter() - t_region
+    q_df = lib.modularity(g, state.C)
+
+    # static Louvain on the final graph, same mode (quality and time reference)
+    st = lib.State.empty(e.n, dev)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st, s_final = lib.louvain_static(g, prm, st)
+    torch.cuda.synchronize()
+    static_final_ms = (time.perf_counter() - t) * 1e3
+    q_static_final = lib.modularity(g, st.C)
+
+    df_arcs = int(np.sum(arcs))
+    value = df_arcs / region_s
+    static_eps = float(np.median([a / (m / 1e3) for a, m in zip(static_arcs, static_ms)]))
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edges scanned/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": region_s * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": f"R-MAT scale {args.scale} (edge factor 16, a=0.57 b=0.19 c=0.19), "
+                               f"random 80/20 batches of 1e-7..1e-3 |E|",
+                   "vertices": e.n, "undirected_edges": e.m, "batch_sizes": sizes, "mode": args.mode},
+        "df_latency_ms_p50": pct(lat, 50),
+        "df_latency_ms_p99": pct(lat, 99),
+        "df_latency_ms_by_batch_size": {str(k): float(np.median(v)) for k, v in sorted(per_size.items())},
+        "apply_batch_ms_p50": pct(apply_ms, 50),
+        "df_edges_scanned_per_s": df_arcs / (np.sum(lat) / 1e3),
+        "static_latency_ms": float(np.median(static_ms)),
+        "static_edges_scanned_per_s": static_eps,
+        "df_speedup_vs_static": float(np.median(static_ms)) / pct(lat, 50),
+        "modularity": {"static_initial": q_static, "df_final": q_df, "static_final": q_static_final},
+        "static_final_ms": static_final_ms,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(e, batches[2])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * louvain.h -- C interface of the MI355X (gfx950) DF Louvain library.
+ *
+ * The library implements the data-parallel hot path of Dynamic Frontier
+ * (DF) Louvain (Sahu, "DF Louvain: Fast Incrementally Expanding Approach for
+ * Community Detection on Dynamic Graphs", arXiv 2404.19634) together with
+ * the static, Naive-dynamic (ND) and Delta-screening (DS) variants that the
+ * paper compares it with.  Every step runs in hand-written HIP kernels.
+ *
+ * General conventions
+ *  - Pointers inside lv_graph, lv_edges and lv_state, and the `ws`
+ *    workspace, are HIP DEVICE pointers owned by the caller.  The library
+ *    never allocates or frees caller memory; it keeps no device memory of
+ *    its own apart from a small pinned host buffer for status readback
+ *    (one per host thread, kept until the process ends).
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *    device work is enqueued on it.  Entry points that must return a
+ *    status which depends on device data (validation, convergence) wait for
+ *    the stream before returning; everything they enqueued is then done.
+ *  - Graphs are undirected and stored with both arc directions.  Vertex ids
+ *    are int32, weights positive int32, weighted degrees K and community
+ *    totals Sigma int64.  The total arc weight 2m must stay below 2^31 so
+ *    that every gain fits in int64 (LV_EOVERFLOW otherwise).
+ *  - Nothing throws across this interface.  A negative status is an
+ *    error; lv_last_error() describes the last one on the calling thread.
+ *    Validation errors leave all caller data untouched.  LV_EHIP means a
+ *    HIP call failed; caller data may then be partially updated.
+ *  - Calls that share a workspace must not overlap (same stream or
+ *    explicitly ordered).
+ */
+#ifndef LOUVAIN_H
+#define LOUVAIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lv_status;
+#define LV_OK 0
+#define LV_EINVAL (-1)      /* bad argument, id out of range, self-loop, w <= 0, duplicate pair */
+#define LV_ENOEDGE (-2)     /* a deletion names a missing edge or more weight than present */
+#define LV_ENOSLACK (-3)    /* a row lacks free capacity; nothing was changed */
+#define LV_EOVERFLOW (-4)   /* total arc weight 2m >= 2^31 */
+#define LV_EEMPTY (-5)      /* graph without edges (2m = 0) */
+#define LV_EHIP (-6)        /* a HIP runtime call failed */
+#define LV_EWORKSPACE (-7)  /* workspace smaller than lv_workspace_bytes() */
+
+#define LV_SYNC 0   /* Jacobi moves: every vertex decides on the iteration-start state */
+#define LV_ASYNC 1  /* moves applied as they are decided (racy, as in the paper's loop) */
+
+#define LV_MAX_PASSES 16
+#define LV_MAX_ITERS 32
+
+/*
+ * Slack-padded CSR (the paper's "holey" CSR of its aggregation phase,
+ * Alg. 6, used here for the input graph too so that batch updates edit it
+ * in place).  Row i occupies col/w[row_start[i] .. row_start[i] +
+ * row_len[i]) and may grow up to row_start[i+1].  row_start[n] is the used
+ * capacity.  *two_m (device) is the total arc weight, tracked across
+ * batches as the paper assumes (Section 5.1.5).
+ */
+typedef struct {
+  int32_t n;          /* number of vertices */
+  int64_t cap;        /* allocated length of col and w */
+  int64_t* row_start; /* device int64[n + 1] */
+  int32_t* row_len;   /* device int32[n] */
+  int32_t* col;       /* device int32[cap] */
+  int32_t* w;         /* device int32[cap] */
+  int64_t* two_m;     /* device int64[1] */
+} lv_graph;
+
+/* A list of undirected edges or updates, each given once (device arrays). */
+typedef struct {
+  const int32_t* u;
+  const int32_t* v;
+  const int32_t* w;
+  int64_t count;
+} lv_edges;
+
+/* Community membership C, weighted degrees K, community totals Sigma
+ * (Sigma indexed by community id).  Device arrays of length n. */
+typedef struct {
+  int32_t* C;
+  int64_t* K;
+  int64_t* Sigma;
+} lv_state;
+
+/* Parameters; lv_default_params() gives the paper's values (Section
+ * 5.1.2): tolerance 1e-2, drop 10, 20 iterations, 10 passes,
+ * aggregation tolerance 0.8. */
+typedef struct {
+  double tolerance;             /* iteration tolerance tau on the summed ΔQ */
+  double tolerance_drop;        /* tau is divided by this after each pass */
+  double aggregation_tolerance; /* stop when |communities| / |vertices| exceeds it */
+  int32_t max_iterations;       /* 1 .. LV_MAX_ITERS */
+  int32_t max_passes;           /* 1 .. LV_MAX_PASSES */
+  int32_t mode;                 /* LV_SYNC or LV_ASYNC */
+  int32_t swap_guard;           /* 1: a singleton never joins a singleton of larger id */
+} lv_params;
+
+/* Per-run statistics.  The first block matches the oracle's layout. */
+typedef struct {
+  int32_t passes;
+  int32_t iterations[LV_MAX_PASSES];   /* iterations run in each pass */
+  int64_t communities[LV_MAX_PASSES];  /* communities after a pass's moves (when counted) */
+  int64_t moves;                       /* vertex moves over all passes */
+  int64_t arcs_scanned;                /* sum of row lengths of processed vertices */
+  int64_t vertices_affected;           /* distinct vertices processed in pass 0 */
+  int64_t iter_moves[LV_MAX_PASSES][LV_MAX_ITERS];
+  int64_t iter_gain[LV_MAX_PASSES][LV_MAX_ITERS]; /* sum of movers' gains (2m^2 ΔQ) */
+  double seconds;                      /* host wall time of the call */
+  /* GPU-side breakdown (hipEvent), milliseconds */
+  float ms_mark;       /* initial marking + updateWeights */
+  float ms_move;       /* local-moving iterations */
+  float ms_aggregate;  /* renumber, lookup, aggregation */
+  float ms_other;      /* output consistency, setup */
+  int64_t arcs_aggregated; /* arcs read by aggregation */
+} lv_stats;
+
+/* Tunables chosen by the autotuner (degree-bin thresholds and launch
+ * shapes).  Zero fields take built-in defaults, except async_rounds_log2
+ * where 0 means one round (lv_get_tuning reports the values in use). */
+typedef struct {
+  int32_t wave_max_degree;   /* rows up to this length go to one wavefront with an LDS table */
+  int32_t blocks_small;      /* persistent grid size of the sub-wave kernels */
+  int32_t blocks_wave;       /* persistent grid size of the wavefront kernel */
+  int32_t blocks_hub;        /* persistent grid size of the workgroup kernel */
+  int32_t async_rounds_log2; /* LV_ASYNC: each iteration runs 2^k hash-partitioned sub-rounds */
+} lv_tuning;
+
+/* The paper's parameter values (Section 5.1.2). */
+void lv_default_params(lv_params* p);
+
+/* Bytes of device workspace needed by every call on a graph with n
+ * vertices and capacity cap (the bound covers all passes and levels). */
+size_t lv_workspace_bytes(int32_t n, int64_t cap);
+
+/* Upper bound of the capacity lv_graph_build needs for m undirected edges
+ * on n vertices with the given slack (so the caller can size col and w). */
+int64_t lv_graph_capacity_bound(int32_t n, int64_t m, float slack_frac, int32_t slack_min);
+
+/*
+ * Build the slack CSR from an undirected edge list (each edge once, no
+ * duplicate pairs).  Row capacity = deg + max(slack_min, ceil(slack_frac *
+ * deg)).  g->n, g->cap and the device arrays must be set by the caller;
+ * on return row_start, row_len, col, w and *two_m are filled.  Errors:
+ * LV_EINVAL (id out of range, self-loop, w <= 0), LV_ENOSLACK (g->cap too
+ * small), LV_EOVERFLOW.
+ */
+lv_status lv_graph_build(lv_graph* g, const lv_edges* edges, float slack_frac, int32_t slack_min,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Copy `src` into `dst` (same n) with new slack; used after LV_ENOSLACK. */
+lv_status lv_graph_relayout(const lv_graph* src, lv_graph* dst, float slack_frac, int32_t slack_min,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * apply_batch -- turn G^{t-1} into G^t in place (Section 3.4: the batch
+ * holds deletions Δ- and insertions Δ+; Section 5.1.4: batches are
+ * undirected).  Each update names an undirected pair once and applies to
+ * both arcs.  Deletions run first and subtract w (an arc reaching weight 0
+ * is removed); insertions then add w to an existing arc or append one into
+ * the row's slack.  *two_m changes by 2(Σw_ins - Σw_del).
+ * Everything is validated before anything changes: LV_EINVAL (id out of
+ * range, self-loop, w <= 0, a pair repeated within Δ- or within Δ+),
+ * LV_ENOEDGE (deleting a missing pair or more weight than present),
+ * LV_ENOSLACK (a row would overflow its capacity).
+ */
+lv_status apply_batch(lv_graph* g, const lv_edges* del, const lv_edges* ins, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/*
+ * louvain_static -- Louvain from singleton communities (the paper's static
+ * baseline, Alg. 4 with every vertex affected): K is computed from the
+ * graph, Sigma = K, then passes of local-moving (Alg. 5) and aggregation
+ * (Alg. 6).  Writes C, K, Sigma of `out`.
+ */
+lv_status louvain_static(const lv_graph* g, const lv_params* p, lv_state* out, void* ws, size_t ws_bytes,
+                         lv_stats* stats, void* stream);
+
+/*
+ * louvain_nd / louvain_ds / louvain_df -- dynamic Louvain after a batch
+ * (Alg. 2 / Alg. 3 / Alg. 1).  `g` is G^t (apply_batch already ran);
+ * `del` and `ins` are the batch.  `state` holds C^{t-1}, K^{t-1},
+ * Sigma^{t-1} on entry and C^t, K^t, Sigma^t on return.  K and Sigma are
+ * updated from the batch (Alg. 7) rather than recomputed; the initial
+ * affected set is every vertex (ND), the delta-screening set (DS) or the
+ * endpoints of intra-community deletions and cross-community insertions
+ * (DF), which then grows by the neighbours of every moved vertex.
+ * Community ids stay in [0, n) but are not made dense.
+ */
+lv_status louvain_nd(const lv_graph* g, const lv_edges* del, const lv_edges* ins, const lv_params* p,
+                     lv_state* state, void* ws, size_t ws_bytes, lv_stats* stats, void* stream);
+lv_status louvain_ds(const lv_graph* g, const lv_edges* del, const lv_edges* ins, const lv_params* p,
+                     lv_state* state, void* ws, size_t ws_bytes, lv_stats* stats, void* stream);
+lv_status louvain_df(const lv_graph* g, const lv_edges* del, const lv_edges* ins, const lv_params* p,
+                     lv_state* state, void* ws, size_t ws_bytes, lv_stats* stats, void* stream);
+
+/*
+ * modularity -- Eq. 1: Q = Σ_c [σ_c/2m - (Σ_c/2m)^2] for membership C
+ * (device int32[n], ids in [0, n)).  σ_c and Σ_c are exact int64 sums;
+ * the host forms the FP64 quotient.  Waits for the stream.
+ */
+lv_status modularity(const lv_graph* g, const int32_t* C, double* q_host, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/* Set or read the tuning table used by the calls above (process-wide). */
+void lv_set_tuning(const lv_tuning* t);
+void lv_get_tuning(lv_tuning* t);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* lv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOUVAIN_H */

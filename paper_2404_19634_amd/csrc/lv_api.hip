@@ -1,0 +1,650 @@
+// C interface and host controller.  The pass / iteration loop of the
+// Louvain driver (Alg. 4) runs here: each local-moving iteration (Alg. 5) is
+// a few kernels followed by one small readback of the iteration's counters
+// (moves, gain sum, arcs scanned), from which the convergence test of the
+// paper is taken exactly:
+//   ΔQ_iteration = 2 * Σ gains / (2m)^2 <= τ   (FP64 on the host)
+// Between passes the communities are renumbered, the dendrogram looked up
+// and the level graph aggregated (Alg. 6); τ drops by the given factor.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "lv_internal.hpp"
+
+namespace lv {
+namespace {
+
+thread_local std::string g_last_error;
+lv_tuning g_tuning = {256, 2048, 2048, 512, 3};
+
+lv_status fail(lv_status code, const char* msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define LV_HIP(expr)                                                         \
+  do {                                                                       \
+    hipError_t e__ = (expr);                                                 \
+    if (e__ != hipSuccess) {                                                 \
+      g_last_error = std::string(#expr) + ": " + hipGetErrorString(e__);     \
+      return LV_EHIP;                                                        \
+    }                                                                        \
+  } while (0)
+
+#define LV_CHECK_LAUNCH()                                                    \
+  do {                                                                       \
+    hipError_t e__ = hipGetLastError();                                      \
+    if (e__ != hipSuccess) {                                                 \
+      g_last_error = std::string("kernel launch: ") + hipGetErrorString(e__); \
+      return LV_EHIP;                                                        \
+    }                                                                        \
+  } while (0)
+
+// Small pinned buffer for counter readback, one per host thread.
+struct Pinned {
+  int64_t* p = nullptr;
+  ~Pinned() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+thread_local Pinned g_pinned;
+
+lv_status pinned(int64_t** out) {
+  if (!g_pinned.p) {
+    void* q = nullptr;
+    LV_HIP(hipHostMalloc(&q, 4096, hipHostMallocDefault));
+    g_pinned.p = static_cast<int64_t*>(q);
+  }
+  *out = g_pinned.p;
+  return LV_OK;
+}
+
+// Timing events, one set per host thread.
+struct Events {
+  hipEvent_t e[8] = {};
+  bool made = false;
+  ~Events() {
+    if (made)
+      for (auto& x : e) (void)hipEventDestroy(x);
+  }
+};
+thread_local Events g_events;
+
+lv_status events(hipEvent_t** out) {
+  if (!g_events.made) {
+    for (auto& x : g_events.e) LV_HIP(hipEventCreate(&x));
+    g_events.made = true;
+  }
+  *out = g_events.e;
+  return LV_OK;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <class T>
+T* take(char*& cur, size_t& total, void* base, size_t count) {
+  T* p = base ? reinterpret_cast<T*>(cur) : nullptr;
+  const size_t b = align_up(sizeof(T) * (count ? count : 1));
+  cur += b;
+  total += b;
+  return p;
+}
+
+lv_status read_counters(int64_t* host, const Workspace& ws, int count, hipStream_t st) {
+  LV_HIP(hipMemcpyAsync(host, ws.ctr, sizeof(int64_t) * count, hipMemcpyDeviceToHost, st));
+  LV_HIP(hipStreamSynchronize(st));
+  return LV_OK;
+}
+
+lv_status read_i64(int64_t* host, const int64_t* dev, hipStream_t st) {
+  LV_HIP(hipMemcpyAsync(host, dev, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  LV_HIP(hipStreamSynchronize(st));
+  return LV_OK;
+}
+
+bool params_ok(const lv_params* p) {
+  return p && p->max_iterations >= 1 && p->max_iterations <= LV_MAX_ITERS && p->max_passes >= 1 &&
+         p->max_passes <= LV_MAX_PASSES && (p->mode == LV_SYNC || p->mode == LV_ASYNC) &&
+         p->tolerance >= 0.0 && p->tolerance_drop > 0.0 && p->aggregation_tolerance >= 0.0;
+}
+
+bool graph_ok(const lv_graph* g) {
+  return g && g->n > 0 && g->row_start && g->row_len && g->col && g->w && g->two_m && g->cap >= 0;
+}
+
+bool edges_ok(const lv_edges* e) { return e && e->count >= 0 && (e->count == 0 || (e->u && e->v && e->w)); }
+
+lv_status setup_ws(Workspace& ws, const lv_graph* g, void* base, size_t bytes) {
+  if (!base) return fail(LV_EINVAL, "workspace pointer is null");
+  const size_t need = carve_workspace(ws, nullptr, g->n, g->cap);
+  if (bytes < need) return fail(LV_EWORKSPACE, "workspace smaller than lv_workspace_bytes()");
+  carve_workspace(ws, base, g->n, g->cap);
+  return LV_OK;
+}
+
+lv_tuning effective_tuning() {
+  lv_tuning t = g_tuning;
+  if (t.wave_max_degree <= 0) t.wave_max_degree = 256;
+  if (t.wave_max_degree < 32) t.wave_max_degree = 32;
+  if (t.wave_max_degree > kWaveTableMaxDegree) t.wave_max_degree = kWaveTableMaxDegree;
+  if (t.blocks_small <= 0) t.blocks_small = 2048;
+  if (t.blocks_wave <= 0) t.blocks_wave = 2048;
+  if (t.blocks_hub <= 0) t.blocks_hub = 512;
+  if (t.async_rounds_log2 < 0) t.async_rounds_log2 = 0;
+  if (t.async_rounds_log2 > 5) t.async_rounds_log2 = 5;
+  return t;
+}
+
+enum Approach { A_STATIC, A_ND, A_DS, A_DF };
+
+struct DsTables {
+  uint64_t* keys;
+  int64_t* vals;
+  uint32_t size;
+  uint64_t* skeys;
+  int64_t* sbest;
+  int32_t* sbestc;
+  uint32_t ssize;
+};
+
+uint32_t pow2_at_least(int64_t x) {
+  uint32_t s = 16;
+  while (static_cast<int64_t>(s) < x) s <<= 1;
+  return s;
+}
+
+// Carves the DS tables out of the global-table pool.
+bool carve_ds(const Workspace& ws, int64_t ni, DsTables& t) {
+  t.size = pow2_at_least(4 * ni);
+  t.ssize = pow2_at_least(4 * ni);
+  const size_t need = align_up(8ull * t.size) * 2 + align_up(8ull * t.ssize) * 2 + align_up(4ull * t.ssize);
+  if (need > static_cast<size_t>(ws.pool_slots) * 4) return false;
+  char* p = reinterpret_cast<char*>(ws.pool_keys);
+  t.keys = reinterpret_cast<uint64_t*>(p);
+  p += align_up(8ull * t.size);
+  t.vals = reinterpret_cast<int64_t*>(p);
+  p += align_up(8ull * t.size);
+  t.skeys = reinterpret_cast<uint64_t*>(p);
+  p += align_up(8ull * t.ssize);
+  t.sbest = reinterpret_cast<int64_t*>(p);
+  p += align_up(8ull * t.ssize);
+  t.sbestc = reinterpret_cast<int32_t*>(p);
+  return true;
+}
+
+__global__ void k_fill_i64(int64_t* p, int64_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_popcount(const uint32_t* bm, int64_t words, int64_t* out) {
+  int64_t s = 0;
+  for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < words;
+       k += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    s += __popc(bm[k]);
+  s = wave_sum_i64(s);
+  if (lane_id() == 0 && s) atomic_add_i64(out, s);
+}
+
+float ms_between(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+  return ms;
+}
+
+lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const lv_edges* ins,
+                      const lv_params* p, lv_state* state, void* wsp, size_t ws_bytes, lv_stats* stats,
+                      void* stream) {
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!graph_ok(g)) return fail(LV_EINVAL, "invalid graph");
+  if (!params_ok(p)) return fail(LV_EINVAL, "invalid parameters");
+  if (!state || !state->C || !state->K || !state->Sigma) return fail(LV_EINVAL, "invalid state");
+  if (ap != A_STATIC && (!edges_ok(del) || !edges_ok(ins))) return fail(LV_EINVAL, "invalid batch");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace ws;
+  lv_status s = setup_ws(ws, g, wsp, ws_bytes);
+  if (s) return s;
+  const lv_tuning tu = effective_tuning();
+  int64_t* host = nullptr;
+  if ((s = pinned(&host))) return s;
+  hipEvent_t* ev = nullptr;
+  if ((s = events(&ev))) return s;
+
+  lv_stats local;
+  lv_stats& S = stats ? *stats : local;
+  std::memset(&S, 0, sizeof(lv_stats));
+
+  int64_t two_m = 0;
+  if ((s = read_i64(&two_m, g->two_m, st))) return s;
+  if (two_m <= 0) return fail(LV_EEMPTY, "graph has no edges (2m = 0)");
+  if (two_m >= (int64_t(1) << 31)) return fail(LV_EOVERFLOW, "total arc weight 2m >= 2^31");
+
+  const int32_t N = g->n;
+  const lv_edges no_edges = {nullptr, nullptr, nullptr, 0};
+  const lv_edges& D = del ? *del : no_edges;
+  const lv_edges& I = ins ? *ins : no_edges;
+
+  LV_HIP(hipEventRecord(ev[0], st));
+  LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_COUNT, st));
+  LV_HIP(hipMemsetAsync(ws.fr_a, 0, sizeof(uint32_t) * ws.words, st));
+  LV_HIP(hipMemsetAsync(ws.fr_b, 0, sizeof(uint32_t) * ws.words, st));
+  LV_HIP(hipMemsetAsync(ws.ever, 0, sizeof(uint32_t) * ws.words, st));
+  LevelGraph L0;
+  L0.n = N;
+  L0.row_start = g->row_start;
+  L0.row_len = g->row_len;
+  L0.col = g->col;
+  L0.w = g->w;
+  bool use_range = false;
+  if (ap == A_STATIC) {
+    launch_degrees(L0, state->K, state->Sigma, state->C, ws.size, st);
+    launch_set_all_bits(ws.fr_a, N, st);
+  } else {
+    switch (ap) {
+      case A_DF:
+        launch_mark_df(D, I, state->C, ws.fr_a, st);
+        break;
+      case A_ND:
+        launch_set_all_bits(ws.fr_a, N, st);
+        break;
+      case A_DS: {
+        DsTables t;
+        if (!carve_ds(ws, I.count, t)) return fail(LV_EWORKSPACE, "batch too large for the workspace pool");
+        LV_HIP(hipMemsetAsync(ws.range, 0, sizeof(uint32_t) * ws.words, st));
+        LV_HIP(hipMemsetAsync(ws.dE, 0, sizeof(uint32_t) * ws.words, st));
+        LV_HIP(hipMemsetAsync(ws.dC, 0, sizeof(uint32_t) * ws.words, st));
+        LV_HIP(hipMemsetAsync(t.keys, 0xFF, 8ull * t.size, st));
+        LV_HIP(hipMemsetAsync(t.vals, 0, 8ull * t.size, st));
+        LV_HIP(hipMemsetAsync(t.skeys, 0xFF, 8ull * t.ssize, st));
+        hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(t.ssize, kBlock, 1024)), dim3(kBlock), 0, st, t.sbest,
+                           static_cast<int64_t>(INT64_MIN), static_cast<int64_t>(t.ssize));
+        launch_fill_i32(t.sbestc, 0x7fffffff, t.ssize, st);
+        launch_batch_weight_sums(D, I, ws.ctr, st);
+        launch_ds_deletions(D, state->C, ws.range, ws.dE, ws.dC, st);
+        launch_ds_insert_pairs(I, state->C, t.keys, t.vals, t.size, ws.ctr, st);
+        launch_ds_best(t.keys, t.vals, t.size, state->K, state->Sigma, g->two_m, ws.ctr, t.skeys, t.sbest,
+                       t.sbestc, t.ssize, 0, st);
+        launch_ds_best(t.keys, t.vals, t.size, state->K, state->Sigma, g->two_m, ws.ctr, t.skeys, t.sbest,
+                       t.sbestc, t.ssize, 1, st);
+        launch_ds_mark_sources(t.skeys, t.sbestc, t.ssize, ws.range, ws.dE, ws.dC, st);
+        launch_ds_expand(L0, D, I, state->C, ws.dE, ws.dC, ws.range, st);
+        launch_copy_bits(ws.range, ws.fr_a, ws.words, st);
+        use_range = true;
+        break;
+      }
+      default:
+        break;
+    }
+    launch_update_weights(D, I, state->C, state->K, state->Sigma, st);
+    if (p->swap_guard) launch_community_sizes(state->C, N, ws.size, st);
+  }
+  LV_CHECK_LAUNCH();
+  LV_HIP(hipEventRecord(ev[1], st));
+
+  // ---- Alg. 4: passes of local-moving and aggregation --------------------
+  LevelGraph L = L0;
+  int32_t* Cl = state->C;
+  int64_t* Kl = state->K;
+  int64_t* Sl = state->Sigma;
+  int32_t* size = p->swap_guard ? ws.size : nullptr;
+  uint32_t* cur = ws.fr_a;
+  uint32_t* next = ws.fr_b;
+  double tau = p->tolerance;
+  bool aggregated = false;
+  const double two_m_d = static_cast<double>(two_m);
+  float ms_move = 0.f, ms_agg = 0.f;
+  int64_t arcs_agg = 0;
+  for (int32_t pass = 0; pass < p->max_passes; ++pass) {
+    LV_HIP(hipEventRecord(ev[2], st));
+    int32_t li = p->max_iterations;
+    MoveArgs a;
+    a.g = L;
+    a.C = Cl;
+    a.K = Kl;
+    a.Sigma = Sl;
+    a.size = size;
+    a.range = (pass == 0 && use_range) ? ws.range : nullptr;
+    a.ever = pass == 0 ? ws.ever : nullptr;
+    a.two_m = two_m;
+    a.mode = p->mode;
+    a.guard = p->swap_guard;
+    a.wave_max = tu.wave_max_degree;
+    const int64_t words_l = (static_cast<int64_t>(L.n) + 31) / 32;
+    for (int32_t it = 0; it < p->max_iterations; ++it) {
+      a.cur = cur;
+      a.next = next;
+      LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_ITER_END, st));
+      const int rl2 = p->mode == LV_ASYNC ? tu.async_rounds_log2 : 0;
+      for (int r = 0; r < (1 << rl2); ++r) {
+        if (r > 0) {  // fresh bin counts and table pool for the sub-round
+          LV_HIP(hipMemsetAsync(ws.ctr + CTR_BIN0, 0, sizeof(int64_t) * NBINS, st));
+          LV_HIP(hipMemsetAsync(ws.ctr + CTR_POOL, 0, sizeof(int64_t), st));
+        }
+        launch_bin_frontier(a, ws, r, rl2, st);
+        launch_move(a, ws, tu, st);
+      }
+      if (p->mode == LV_SYNC) launch_apply_moves(a, ws, st);
+      LV_CHECK_LAUNCH();
+      LV_HIP(hipMemsetAsync(cur, 0, sizeof(uint32_t) * words_l, st));
+      std::swap(cur, next);
+      if ((s = read_counters(host, ws, CTR_ITER_END, st))) return s;
+      if (host[CTR_ERR]) return fail(static_cast<lv_status>(host[CTR_ERR]), "device error in local-moving");
+      const int64_t movers = host[CTR_MOVERS], gain = host[CTR_GAIN];
+      S.moves += movers;
+      S.arcs_scanned += host[CTR_ARCS];
+      if (pass < LV_MAX_PASSES && it < LV_MAX_ITERS) {
+        S.iter_moves[pass][it] = movers;
+        S.iter_gain[pass][it] = gain;
+      }
+      const double dq = (2.0 * static_cast<double>(gain)) / (two_m_d * two_m_d);
+      if (dq <= tau) {
+        li = it + 1;
+        break;
+      }
+    }
+    LV_HIP(hipEventRecord(ev[3], st));
+    S.passes = pass + 1;
+    S.iterations[pass] = li;
+    if (li <= 1) {
+      LV_HIP(hipStreamSynchronize(st));
+      ms_move += ms_between(ev[2], ev[3]);
+      break;
+    }
+    // renumber communities of this level (ascending old id)
+    LV_HIP(hipMemsetAsync(ws.flags, 0, sizeof(int32_t) * (static_cast<size_t>(L.n) + 1), st));
+    launch_mark_exists(Cl, L.n, ws.flags, st);
+    exclusive_scan_i32(ws.flags, ws.newid, L.n, ws, st);
+    LV_CHECK_LAUNCH();
+    int32_t nc32 = 0;
+    LV_HIP(hipMemcpyAsync(&host[CTR_TOTAL], ws.newid + L.n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    LV_HIP(hipStreamSynchronize(st));
+    std::memcpy(&nc32, &host[CTR_TOTAL], sizeof(int32_t));
+    ms_move += ms_between(ev[2], ev[3]);
+    const int32_t nc = nc32;
+    S.communities[pass] = nc;
+    if (static_cast<double>(nc) / static_cast<double>(L.n) > p->aggregation_tolerance) break;
+    LV_HIP(hipEventRecord(ev[4], st));
+    launch_relabel(Cl, L.n, ws.newid, st);
+    if (pass > 0) launch_lookup(state->C, N, Cl, st);
+    LevelGraph out = ws.lg[pass & 1];
+    launch_aggregate(L, Cl, nc, out, ws.lK, ws.lS, ws.lC, ws.size, ws, tu, st);
+    LV_CHECK_LAUNCH();
+    LV_HIP(hipMemsetAsync(cur, 0, sizeof(uint32_t) * ws.words, st));
+    launch_set_all_bits(cur, nc, st);
+    LV_HIP(hipEventRecord(ev[5], st));
+    LV_HIP(hipMemcpyAsync(&host[CTR_COUNT], out.row_start + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    if ((s = read_counters(host, ws, CTR_ITER_END, st))) return s;
+    if (host[CTR_ERR]) return fail(static_cast<lv_status>(host[CTR_ERR]), "device error in aggregation");
+    ms_agg += ms_between(ev[4], ev[5]);
+    arcs_agg += host[CTR_COUNT];
+    L = out;
+    Cl = ws.lC;
+    Kl = ws.lK;
+    Sl = ws.lS;
+    size = p->swap_guard ? ws.size : nullptr;
+    tau = tau / p->tolerance_drop;
+    aggregated = true;
+  }
+  LV_HIP(hipEventRecord(ev[6], st));
+  if (aggregated) {
+    launch_lookup(state->C, N, Cl, st);
+    launch_sigma_from_members(state->C, state->K, N, state->Sigma, st);
+  }
+  LV_HIP(hipMemsetAsync(ws.ctr + CTR_AUX0, 0, sizeof(int64_t), st));
+  hipLaunchKernelGGL(k_popcount, dim3(grid_for(ws.words, kBlock, 1024)), dim3(kBlock), 0, st, ws.ever, ws.words,
+                     ws.ctr + CTR_AUX0);
+  LV_CHECK_LAUNCH();
+  LV_HIP(hipEventRecord(ev[7], st));
+  if ((s = read_counters(host, ws, CTR_COUNT, st))) return s;
+  S.vertices_affected = host[CTR_AUX0];
+  S.ms_mark = ms_between(ev[0], ev[1]);
+  S.ms_move = ms_move;
+  S.ms_aggregate = ms_agg;
+  S.ms_other = ms_between(ev[6], ev[7]);
+  S.arcs_aggregated = arcs_agg;
+  S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  return LV_OK;
+}
+
+}  // namespace
+
+size_t carve_workspace(Workspace& ws, void* base, int32_t n, int64_t cap) {
+  char* cur = static_cast<char*>(base);
+  size_t total = 0;
+  const size_t un = static_cast<size_t>(n > 0 ? n : 1);
+  const size_t ucap = static_cast<size_t>(cap > 0 ? cap : 1);
+  ws.n = n;
+  ws.cap = cap;
+  ws.words = (static_cast<int64_t>(un) + 31) / 32 + 1;
+  ws.fr_a = take<uint32_t>(cur, total, base, ws.words);
+  ws.fr_b = take<uint32_t>(cur, total, base, ws.words);
+  ws.ever = take<uint32_t>(cur, total, base, ws.words);
+  ws.range = take<uint32_t>(cur, total, base, ws.words);
+  ws.dE = take<uint32_t>(cur, total, base, ws.words);
+  ws.dC = take<uint32_t>(cur, total, base, ws.words);
+  for (int b = 0; b < NBINS; ++b) ws.bins[b] = take<int32_t>(cur, total, base, un);
+  ws.hub_off = take<int64_t>(cur, total, base, un);
+  ws.mv_v = take<int32_t>(cur, total, base, un);
+  ws.mv_c = take<int32_t>(cur, total, base, un);
+  ws.size = take<int32_t>(cur, total, base, un);
+  ws.lC = take<int32_t>(cur, total, base, un);
+  ws.lK = take<int64_t>(cur, total, base, un);
+  ws.lS = take<int64_t>(cur, total, base, un);
+  ws.flags = take<int32_t>(cur, total, base, un + 1);
+  ws.newid = take<int32_t>(cur, total, base, un + 1);
+  ws.ccount = take<int32_t>(cur, total, base, un + 1);
+  ws.coff = take<int32_t>(cur, total, base, un + 1);
+  ws.cmem = take<int32_t>(cur, total, base, un);
+  ws.vol = take<int64_t>(cur, total, base, un + 1);
+  ws.i64tmp = take<int64_t>(cur, total, base, un + 1);
+  for (int k = 0; k < 2; ++k) {
+    ws.lg[k].n = 0;
+    ws.lg[k].row_start = take<int64_t>(cur, total, base, un + 1);
+    ws.lg[k].row_len = take<int32_t>(cur, total, base, un);
+    ws.lg[k].col = take<int32_t>(cur, total, base, ucap);
+    ws.lg[k].w = take<int32_t>(cur, total, base, ucap);
+  }
+  ws.pool_slots = 2 * static_cast<int64_t>(ucap) + 4096;
+  ws.pool_keys = take<int32_t>(cur, total, base, static_cast<size_t>(ws.pool_slots));
+  ws.pool_vals = take<int32_t>(cur, total, base, static_cast<size_t>(ws.pool_slots));
+  ws.scan_part_len = scan_parts_needed(static_cast<int64_t>(un) + 2) + 8;
+  ws.scan_part = take<int64_t>(cur, total, base, static_cast<size_t>(ws.scan_part_len));
+  ws.ctr = take<int64_t>(cur, total, base, CTR_COUNT);
+  ws.bytes = total;
+  return total;
+}
+
+}  // namespace lv
+
+using namespace lv;
+
+extern "C" {
+
+void lv_default_params(lv_params* p) {
+  if (!p) return;
+  p->tolerance = 1e-2;
+  p->tolerance_drop = 10.0;
+  p->aggregation_tolerance = 0.8;
+  p->max_iterations = 20;
+  p->max_passes = 10;
+  p->mode = LV_ASYNC;
+  p->swap_guard = 1;
+}
+
+size_t lv_workspace_bytes(int32_t n, int64_t cap) {
+  Workspace ws;
+  return carve_workspace(ws, nullptr, n, cap);
+}
+
+int64_t lv_graph_capacity_bound(int32_t n, int64_t m, float slack_frac, int32_t slack_min) {
+  if (n < 0 || m < 0) return -1;
+  const double arcs = 2.0 * static_cast<double>(m);
+  const double frac = slack_frac > 0.f ? slack_frac : 0.0;
+  const int64_t smin = slack_min > 0 ? slack_min : 0;
+  return static_cast<int64_t>(std::ceil(arcs * (1.0 + frac))) + static_cast<int64_t>(n) * (smin + 1) + 1;
+}
+
+lv_status lv_graph_build(lv_graph* g, const lv_edges* e, float slack_frac, int32_t slack_min, void* wsp,
+                         size_t ws_bytes, void* stream) {
+  if (!graph_ok(g) || !edges_ok(e)) return fail(LV_EINVAL, "invalid graph or edge list");
+  if (slack_frac < 0.f || slack_min < 0) return fail(LV_EINVAL, "negative slack");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace ws;
+  lv_status s = setup_ws(ws, g, wsp, ws_bytes);
+  if (s) return s;
+  int64_t* host = nullptr;
+  if ((s = pinned(&host))) return s;
+  LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_COUNT, st));
+  LV_HIP(hipMemsetAsync(g->row_len, 0, sizeof(int32_t) * static_cast<size_t>(g->n), st));
+  launch_build_count(*e, g->n, g->row_len, ws.ctr, st);
+  launch_row_capacity(g->row_len, ws.i64tmp, g->n, slack_frac, slack_min, st);
+  exclusive_scan_i64(ws.i64tmp, g->row_start, g->n, ws, st);
+  LV_CHECK_LAUNCH();
+  if ((s = read_counters(host, ws, CTR_COUNT, st))) return s;
+  if (host[CTR_ERR]) return fail(static_cast<lv_status>(host[CTR_ERR]), "edge list has a bad id, self-loop or weight");
+  if (host[CTR_TOTAL] >= (int64_t(1) << 31)) return fail(LV_EOVERFLOW, "total arc weight 2m >= 2^31");
+  int64_t need = 0;
+  if ((s = read_i64(&need, g->row_start + g->n, st))) return s;
+  if (need > g->cap) return fail(LV_ENOSLACK, "graph capacity too small for the edge list and slack");
+  LV_HIP(hipMemsetAsync(g->row_len, 0, sizeof(int32_t) * static_cast<size_t>(g->n), st));
+  LV_HIP(hipMemsetAsync(g->two_m, 0, sizeof(int64_t), st));
+  launch_build_scatter(*e, g->row_start, g->row_len, g->col, g->w, g->two_m, st);
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+lv_status lv_graph_relayout(const lv_graph* src, lv_graph* dst, float slack_frac, int32_t slack_min, void* wsp,
+                            size_t ws_bytes, void* stream) {
+  if (!graph_ok(src) || !graph_ok(dst) || src->n != dst->n) return fail(LV_EINVAL, "invalid graphs");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace ws;
+  lv_status s = setup_ws(ws, dst, wsp, ws_bytes);
+  if (s) return s;
+  launch_row_capacity(src->row_len, ws.i64tmp, src->n, slack_frac, slack_min, st);
+  exclusive_scan_i64(ws.i64tmp, dst->row_start, src->n, ws, st);
+  LV_CHECK_LAUNCH();
+  int64_t need = 0;
+  if ((s = read_i64(&need, dst->row_start + dst->n, st))) return s;
+  if (need > dst->cap) return fail(LV_ENOSLACK, "destination capacity too small");
+  launch_relayout_copy(*src, dst->row_start, dst->row_len, dst->col, dst->w, st);
+  LV_HIP(hipMemcpyAsync(dst->two_m, src->two_m, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+lv_status apply_batch(lv_graph* g, const lv_edges* del, const lv_edges* ins, void* wsp, size_t ws_bytes,
+                      void* stream) {
+  if (!graph_ok(g) || !edges_ok(del) || !edges_ok(ins)) return fail(LV_EINVAL, "invalid graph or batch");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace ws;
+  lv_status s = setup_ws(ws, g, wsp, ws_bytes);
+  if (s) return s;
+  int64_t* host = nullptr;
+  if ((s = pinned(&host))) return s;
+  if (del->count + ins->count == 0) return LV_OK;
+  BatchScratch b;
+  b.del_size = pow2_at_least(2 * del->count + 2);
+  b.ins_size = pow2_at_least(2 * ins->count + 2);
+  size_t need = align_up(8ull * b.del_size) + align_up(4ull * b.del_size) + align_up(8ull * b.ins_size) +
+                align_up(16ull * del->count + 8) + align_up(8ull * ins->count + 8);
+  if (need > static_cast<size_t>(ws.pool_slots) * 4) return fail(LV_EWORKSPACE, "batch too large for the workspace pool");
+  char* p = reinterpret_cast<char*>(ws.pool_keys);
+  b.del_keys = reinterpret_cast<uint64_t*>(p);
+  p += align_up(8ull * b.del_size);
+  b.del_vals = reinterpret_cast<int32_t*>(p);
+  p += align_up(4ull * b.del_size);
+  b.ins_keys = reinterpret_cast<uint64_t*>(p);
+  p += align_up(8ull * b.ins_size);
+  b.del_pos = reinterpret_cast<int64_t*>(p);
+  p += align_up(16ull * del->count + 8);
+  b.ins_kind = reinterpret_cast<int32_t*>(p);
+  b.row_zeroed = ws.ccount;
+  b.row_app = ws.coff;
+  LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_COUNT, st));
+  LV_HIP(hipMemsetAsync(b.del_keys, 0xFF, 8ull * b.del_size, st));
+  LV_HIP(hipMemsetAsync(b.ins_keys, 0xFF, 8ull * b.ins_size, st));
+  LV_HIP(hipMemsetAsync(b.row_zeroed, 0, sizeof(int32_t) * static_cast<size_t>(g->n), st));
+  LV_HIP(hipMemsetAsync(b.row_app, 0, sizeof(int32_t) * static_cast<size_t>(g->n), st));
+  launch_batch_validate(*del, *ins, g->n, b, ws.ctr, st);
+  launch_batch_find(*g, *del, *ins, b, ws.ctr, st);
+  launch_batch_capacity(*g, *del, *ins, b, ws.ctr, st);
+  LV_CHECK_LAUNCH();
+  if ((s = read_counters(host, ws, CTR_COUNT, st))) return s;
+  if (host[CTR_ERR]) {
+    const lv_status code = static_cast<lv_status>(host[CTR_ERR]);
+    const char* msg = code == LV_ENOEDGE    ? "a deletion names a missing edge or too much weight"
+                      : code == LV_ENOSLACK ? "a row lacks free capacity (relayout with more slack)"
+                      : code == LV_EOVERFLOW ? "total arc weight would reach 2^31"
+                                             : "bad id, self-loop, non-positive weight or repeated pair";
+    return fail(code, msg);
+  }
+  launch_batch_apply(*g, *del, *ins, b, ws.ctr, st);
+  LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+lv_status louvain_static(const lv_graph* g, const lv_params* p, lv_state* out, void* ws, size_t ws_bytes,
+                         lv_stats* stats, void* stream) {
+  return run_louvain(A_STATIC, g, nullptr, nullptr, p, out, ws, ws_bytes, stats, stream);
+}
+
+lv_status louvain_nd(const lv_graph* g, const lv_edges* del, const lv_edges* ins, const lv_params* p,
+                     lv_state* state, void* ws, size_t ws_bytes, lv_stats* stats, void* stream) {
+  return run_louvain(A_ND, g, del, ins, p, state, ws, ws_bytes, stats, stream);
+}
+
+lv_status louvain_ds(const lv_graph* g, const lv_edges* del, const lv_edges* ins, const lv_params* p,
+                     lv_state* state, void* ws, size_t ws_bytes, lv_stats* stats, void* stream) {
+  return run_louvain(A_DS, g, del, ins, p, state, ws, ws_bytes, stats, stream);
+}
+
+lv_status louvain_df(const lv_graph* g, const lv_edges* del, const lv_edges* ins, const lv_params* p,
+                     lv_state* state, void* ws, size_t ws_bytes, lv_stats* stats, void* stream) {
+  return run_louvain(A_DF, g, del, ins, p, state, ws, ws_bytes, stats, stream);
+}
+
+lv_status modularity(const lv_graph* g, const int32_t* C, double* q_host, void* wsp, size_t ws_bytes, void* stream) {
+  if (!graph_ok(g) || !C || !q_host) return fail(LV_EINVAL, "invalid arguments");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace ws;
+  lv_status s = setup_ws(ws, g, wsp, ws_bytes);
+  if (s) return s;
+  int64_t* host = nullptr;
+  if ((s = pinned(&host))) return s;
+  LevelGraph L;
+  L.n = g->n;
+  L.row_start = g->row_start;
+  L.row_len = g->row_len;
+  L.col = g->col;
+  L.w = g->w;
+  LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_COUNT, st));
+  LV_HIP(hipMemsetAsync(ws.i64tmp, 0, sizeof(int64_t) * (static_cast<size_t>(g->n) + 1), st));
+  launch_modularity_terms(L, C, ws.i64tmp, ws.ctr, st);
+  launch_sum_squares(ws.i64tmp, g->n, ws.ctr + CTR_AUX1, st);
+  LV_CHECK_LAUNCH();
+  int64_t two_m = 0;
+  if ((s = read_i64(&two_m, g->two_m, st))) return s;
+  if ((s = read_counters(host, ws, CTR_COUNT, st))) return s;
+  if (two_m <= 0) return fail(LV_EEMPTY, "graph has no edges (2m = 0)");
+  if (two_m >= (int64_t(1) << 31)) return fail(LV_EOVERFLOW, "total arc weight 2m >= 2^31");
+  // Q = (2m Σσ_c - Σ_c Σ_c^2) / (2m)^2; the numerator is exact in int64
+  const int64_t qnum = two_m * host[CTR_AUX0] - host[CTR_AUX1];
+  *q_host = static_cast<double>(qnum) / (static_cast<double>(two_m) * static_cast<double>(two_m));
+  return LV_OK;
+}
+
+void lv_set_tuning(const lv_tuning* t) {
+  if (t) g_tuning = *t;
+}
+
+void lv_get_tuning(lv_tuning* t) {
+  if (t) *t = effective_tuning();
+}
+
+const char* lv_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

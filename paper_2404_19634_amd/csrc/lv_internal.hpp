@@ -1,0 +1,245 @@
+// Internal declarations shared by the library's HIP translation units:
+// workspace layout, device helpers and the host-side launchers of every
+// kernel.  Not part of the public interface (see include/louvain.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "louvain.h"
+
+namespace lv {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;  // 4 wavefronts
+
+// Degree bins of the local-moving phase.  Rows of length 1..32 are handled
+// by groups of 4/8/16/32 lanes (one arc per lane), longer rows up to the
+// wave threshold by one wavefront with an LDS hashtable, and the rest by a
+// whole workgroup with a global-memory hashtable.
+enum Bin { BIN_G4 = 0, BIN_G8, BIN_G16, BIN_G32, BIN_WAVE, BIN_HUB, NBINS };
+
+constexpr int kWaveTableMaxDegree = 512;  // largest wave-bin row the LDS table supports
+
+// Device counters (int64 slots of Workspace::ctr).
+enum Ctr {
+  CTR_BIN0 = 0,                 // .. CTR_BIN0 + NBINS - 1: items per bin
+  CTR_MOVERS = 8,               // moves decided this iteration
+  CTR_GAIN = 9,                 // sum of movers' gains
+  CTR_ARCS = 10,                // arcs scanned this iteration
+  CTR_PROCESSED = 11,           // vertices processed this iteration
+  CTR_POOL = 12,                // global hashtable slots handed out
+  CTR_ERR = 13,                 // error code (first nonzero wins)
+  CTR_TOTAL = 14,               // generic total (scans, counts)
+  CTR_AUX0 = 15,
+  CTR_AUX1 = 16,
+  CTR_AUX2 = 17,
+  CTR_AUX3 = 18,
+  CTR_ITER_END = 24,            // slots [0, CTR_ITER_END) are cleared every iteration
+  CTR_COUNT = 64
+};
+
+struct LevelGraph {
+  int32_t n = 0;
+  int64_t* row_start = nullptr;  // n + 1
+  int32_t* row_len = nullptr;    // n
+  int32_t* col = nullptr;
+  int32_t* w = nullptr;
+};
+
+// Carving of the caller's workspace.  Every region is 256-byte aligned.
+struct Workspace {
+  int32_t n = 0;
+  int64_t cap = 0;
+  int64_t words = 0;
+  uint32_t* fr_a = nullptr;   // frontier bitmasks (current / next)
+  uint32_t* fr_b = nullptr;
+  uint32_t* ever = nullptr;   // vertices processed in pass 0
+  uint32_t* range = nullptr;  // DS affected range
+  uint32_t* dE = nullptr;     // DS: neighbours-affected flags
+  uint32_t* dC = nullptr;     // DS: community-affected flags
+  int32_t* bins[NBINS] = {};
+  int64_t* hub_off = nullptr;  // global-table offset of each hub item
+  int32_t* mv_v = nullptr;     // sync movers: vertex, target community
+  int32_t* mv_c = nullptr;
+  int32_t* size = nullptr;     // community sizes (swap guard)
+  int32_t* lC = nullptr;       // level >= 1 membership, weights, totals
+  int64_t* lK = nullptr;
+  int64_t* lS = nullptr;
+  int32_t* flags = nullptr;    // n + 1
+  int32_t* newid = nullptr;    // n + 1
+  int32_t* ccount = nullptr;   // n + 1
+  int32_t* coff = nullptr;     // n + 1
+  int32_t* cmem = nullptr;     // n
+  int64_t* vol = nullptr;      // n + 1
+  int64_t* i64tmp = nullptr;   // n + 1 (scans over int64, community sums)
+  LevelGraph lg[2];
+  int32_t* pool_keys = nullptr;  // global hashtables
+  int32_t* pool_vals = nullptr;
+  int64_t pool_slots = 0;
+  int64_t* scan_part = nullptr;  // per-block partial sums of the scans
+  int64_t scan_part_len = 0;
+  int64_t* ctr = nullptr;        // CTR_COUNT counters
+  size_t bytes = 0;
+};
+
+// Computes the layout; with base == nullptr only the size is computed.
+size_t carve_workspace(Workspace& ws, void* base, int32_t n, int64_t cap);
+
+// --------------------------------------------------------------------------
+// Device helpers
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ bool test_bit(const uint32_t* bm, int32_t i) {
+  return (bm[i >> 5] >> (i & 31)) & 1u;
+}
+
+__device__ __forceinline__ void set_bit(uint32_t* bm, int32_t i) {
+  atomicOr(&bm[i >> 5], 1u << (i & 31));
+}
+
+__device__ __forceinline__ void atomic_add_i64(int64_t* p, int64_t v) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(v));
+}
+
+__device__ __forceinline__ void set_error(int64_t* ctr, int64_t code) {
+  atomicCAS(reinterpret_cast<unsigned long long*>(&ctr[CTR_ERR]), 0ull,
+            static_cast<unsigned long long>(code));
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+  for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s);
+  return v;
+}
+
+__device__ __forceinline__ int32_t wave_sum_i32(int32_t v) {
+  for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s);
+  return v;
+}
+
+// Wave-aggregated append: lanes with `pred` get consecutive slots of
+// `list` after atomically bumping *count.  Returns the slot or -1.
+__device__ __forceinline__ int64_t wave_append(bool pred, int64_t* count) {
+  const uint64_t mask = __ballot(pred);
+  if (mask == 0) return -1;
+  const int lane = lane_id();
+  const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+  int64_t base = 0;
+  if (lane == leader)
+    base = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(count),
+                                          static_cast<unsigned long long>(__popcll(mask))));
+  base = __shfl(base, leader);
+  const uint64_t below = mask & ((1ull << lane) - 1ull);
+  return pred ? base + __popcll(below) : -1;
+}
+
+// Hash of a community id into [0, size) for the open-addressing tables.
+__device__ __forceinline__ uint32_t hash_slot(uint32_t key, uint32_t size) {
+  const uint32_t h = key * 0x9E3779B1u;
+  return static_cast<uint32_t>((static_cast<uint64_t>(h) * size) >> 32);
+}
+
+// --------------------------------------------------------------------------
+// Launchers (host).  All enqueue on `st`; none synchronises.
+// --------------------------------------------------------------------------
+int grid_for(int64_t items, int per_block, int max_blocks = 65535 * 4);
+
+// scan.hip
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, Workspace& ws, hipStream_t st);
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, Workspace& ws, hipStream_t st);
+int64_t scan_parts_needed(int64_t n);
+
+// graph.hip
+void launch_build_count(const lv_edges& e, int32_t n, int32_t* deg, int64_t* ctr, hipStream_t st);
+void launch_row_capacity(const int32_t* deg, int64_t* capv, int32_t n, float frac, int32_t smin,
+                         hipStream_t st);
+void launch_build_scatter(const lv_edges& e, const int64_t* row_start, int32_t* row_len, int32_t* col,
+                          int32_t* w, int64_t* two_m, hipStream_t st);
+void launch_relayout_copy(const lv_graph& src, const int64_t* dst_start, int32_t* dst_len,
+                          int32_t* dst_col, int32_t* dst_w, hipStream_t st);
+void launch_degrees(const LevelGraph& g, int64_t* K, int64_t* Sigma, int32_t* C, int32_t* size,
+                    hipStream_t st);
+void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+void launch_iota_i32(int32_t* p, int64_t n, hipStream_t st);
+void launch_set_all_bits(uint32_t* bm, int32_t n, hipStream_t st);
+void launch_copy_bits(const uint32_t* src, uint32_t* dst, int64_t words, hipStream_t st);
+void launch_modularity_terms(const LevelGraph& g, const int32_t* C, int64_t* sig_tot, int64_t* ctr,
+                             hipStream_t st);
+void launch_sum_squares(const int64_t* v, int32_t n, int64_t* out, hipStream_t st);
+
+// batch.hip
+struct BatchScratch {
+  uint64_t* del_keys;   // canonical pair -> deletion weight
+  int32_t* del_vals;
+  uint32_t del_size;
+  uint64_t* ins_keys;   // canonical pair set of insertions
+  uint32_t ins_size;
+  int64_t* del_pos;     // 2 per deletion: arc positions of (u,v) and (v,u)
+  int32_t* ins_kind;    // 2 per insertion: 1 = merge into an existing arc, 0 = append
+  int32_t* row_zeroed;  // n: arcs of the row reaching weight 0
+  int32_t* row_app;     // n: arcs appended to the row
+};
+void launch_batch_validate(const lv_edges& del, const lv_edges& ins, int32_t n, const BatchScratch& b,
+                           int64_t* ctr, hipStream_t st);
+void launch_batch_find(const lv_graph& g, const lv_edges& del, const lv_edges& ins, const BatchScratch& b,
+                       int64_t* ctr, hipStream_t st);
+void launch_batch_capacity(const lv_graph& g, const lv_edges& del, const lv_edges& ins, const BatchScratch& b,
+                           int64_t* ctr, hipStream_t st);
+void launch_batch_apply(const lv_graph& g, const lv_edges& del, const lv_edges& ins, const BatchScratch& b,
+                        int64_t* ctr, hipStream_t st);
+
+// mark.hip
+void launch_mark_df(const lv_edges& del, const lv_edges& ins, const int32_t* C, uint32_t* fr,
+                    hipStream_t st);
+void launch_update_weights(const lv_edges& del, const lv_edges& ins, const int32_t* C, int64_t* K,
+                           int64_t* Sigma, hipStream_t st);
+void launch_batch_weight_sums(const lv_edges& del, const lv_edges& ins, int64_t* ctr, hipStream_t st);
+void launch_community_sizes(const int32_t* C, int32_t n, int32_t* size, hipStream_t st);
+void launch_ds_deletions(const lv_edges& del, const int32_t* C, uint32_t* dV, uint32_t* dE,
+                         uint32_t* dC, hipStream_t st);
+void launch_ds_insert_pairs(const lv_edges& ins, const int32_t* C, uint64_t* keys, int64_t* vals,
+                            uint32_t size, int64_t* ctr, hipStream_t st);
+void launch_ds_best(const uint64_t* keys, const int64_t* vals, uint32_t size, const int64_t* K,
+                    const int64_t* Sigma, const int64_t* two_m_dev, const int64_t* ctr, uint64_t* skeys,
+                    int64_t* sbest, int32_t* sbestc, uint32_t ssize, int pass, hipStream_t st);
+void launch_ds_mark_sources(const uint64_t* skeys, const int32_t* sbestc, uint32_t ssize, uint32_t* dV,
+                            uint32_t* dE, uint32_t* dC, hipStream_t st);
+void launch_ds_expand(const LevelGraph& g, const lv_edges& del, const lv_edges& ins, const int32_t* C,
+                      const uint32_t* dE, const uint32_t* dC, uint32_t* dV, hipStream_t st);
+
+// move.hip
+struct MoveArgs {
+  LevelGraph g;
+  int32_t* C;
+  const int64_t* K;
+  int64_t* Sigma;
+  int32_t* size;
+  const uint32_t* cur;
+  uint32_t* next;
+  const uint32_t* range;  // nullptr: every vertex in range
+  uint32_t* ever;         // nullptr: not tracked
+  int64_t two_m;
+  int32_t mode;
+  int32_t guard;
+  int32_t wave_max;
+};
+void launch_bin_frontier(const MoveArgs& a, Workspace& ws, int round, int rounds_log2, hipStream_t st);
+void launch_move(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, hipStream_t st);
+void launch_apply_moves(const MoveArgs& a, Workspace& ws, hipStream_t st);
+
+// aggregate.hip
+void launch_mark_exists(const int32_t* C, int32_t n, int32_t* flags, hipStream_t st);
+void launch_relabel(int32_t* C, int32_t n, const int32_t* newid, hipStream_t st);
+void launch_lookup(int32_t* Ctop, int32_t n, const int32_t* Clevel, hipStream_t st);
+void launch_community_members(const int32_t* C, const LevelGraph& g, int32_t nc, Workspace& ws,
+                              hipStream_t st);
+void launch_aggregate(const LevelGraph& g, const int32_t* C, int32_t nc, LevelGraph& out, int64_t* Kout,
+                      int64_t* Sout, int32_t* Cout, int32_t* sizeout, Workspace& ws, const lv_tuning& tu,
+                      hipStream_t st);
+void launch_sigma_from_members(const int32_t* C, const int64_t* K, int32_t n, int64_t* Sigma,
+                               hipStream_t st);
+
+}  // namespace lv

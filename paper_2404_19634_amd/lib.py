@@ -1,0 +1,358 @@
+"""Python binding of the HIP library (argument marshalling only).
+
+Every operation runs in ``liblouvain_hip.so``; this module passes device
+pointers of torch tensors and the current HIP stream through the C
+interface declared in ``include/louvain.h``.  Importing it without the built
+library raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblouvain_hip.so")
+
+LV_OK = 0
+STATUS = {0: "LV_OK", -1: "LV_EINVAL", -2: "LV_ENOEDGE", -3: "LV_ENOSLACK", -4: "LV_EOVERFLOW",
+          -5: "LV_EEMPTY", -6: "LV_EHIP", -7: "LV_EWORKSPACE"}
+LV_EINVAL, LV_ENOEDGE, LV_ENOSLACK, LV_EOVERFLOW, LV_EEMPTY, LV_EHIP, LV_EWORKSPACE = -1, -2, -3, -4, -5, -6, -7
+SYNC, ASYNC = 0, 1
+MAX_PASSES, MAX_ITERS = 16, 32
+
+EXPORTS = ["lv_default_params", "lv_workspace_bytes", "lv_graph_capacity_bound", "lv_graph_build",
+           "lv_graph_relayout", "apply_batch", "louvain_static", "louvain_nd", "louvain_ds", "louvain_df",
+           "modularity", "lv_set_tuning", "lv_get_tuning", "lv_last_error"]
+
+
+class LouvainError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CGraph(ct.Structure):
+    _fields_ = [("n", ct.c_int32), ("cap", ct.c_int64), ("row_start", ct.c_void_p), ("row_len", ct.c_void_p),
+                ("col", ct.c_void_p), ("w", ct.c_void_p), ("two_m", ct.c_void_p)]
+
+
+class CEdges(ct.Structure):
+    _fields_ = [("u", ct.c_void_p), ("v", ct.c_void_p), ("w", ct.c_void_p), ("count", ct.c_int64)]
+
+
+class CState(ct.Structure):
+    _fields_ = [("C", ct.c_void_p), ("K", ct.c_void_p), ("Sigma", ct.c_void_p)]
+
+
+class Params(ct.Structure):
+    _fields_ = [("tolerance", ct.c_double), ("tolerance_drop", ct.c_double),
+                ("aggregation_tolerance", ct.c_double), ("max_iterations", ct.c_int32),
+                ("max_passes", ct.c_int32), ("mode", ct.c_int32), ("swap_guard", ct.c_int32)]
+
+
+class Stats(ct.Structure):
+    _fields_ = [("passes", ct.c_int32), ("iterations", ct.c_int32 * MAX_PASSES),
+                ("communities", ct.c_int64 * MAX_PASSES), ("moves", ct.c_int64), ("arcs_scanned", ct.c_int64),
+                ("vertices_affected", ct.c_int64), ("iter_moves", (ct.c_int64 * MAX_ITERS) * MAX_PASSES),
+                ("iter_gain", (ct.c_int64 * MAX_ITERS) * MAX_PASSES), ("seconds", ct.c_double),
+                ("ms_mark", ct.c_float), ("ms_move", ct.c_float), ("ms_aggregate", ct.c_float),
+                ("ms_other", ct.c_float), ("arcs_aggregated", ct.c_int64)]
+
+    def as_dict(self) -> dict:
+        p = self.passes
+        its = [self.iterations[k] for k in range(p)]
+        return {
+            "passes": p, "iterations": its,
+            "communities": [int(self.communities[k]) for k in range(p)],
+            "moves": int(self.moves), "arcs_scanned": int(self.arcs_scanned),
+            "vertices_affected": int(self.vertices_affected),
+            "iter_moves": [[int(self.iter_moves[k][t]) for t in range(its[k])] for k in range(p)],
+            "iter_gain": [[int(self.iter_gain[k][t]) for t in range(its[k])] for k in range(p)],
+            "seconds": float(self.seconds), "ms_mark": float(self.ms_mark), "ms_move": float(self.ms_move),
+            "ms_aggregate": float(self.ms_aggregate), "ms_other": float(self.ms_other),
+            "arcs_aggregated": int(self.arcs_aggregated),
+        }
+
+
+class Tuning(ct.Structure):
+    _fields_ = [("wave_max_degree", ct.c_int32), ("blocks_small", ct.c_int32), ("blocks_wave", ct.c_int32),
+                ("blocks_hub", ct.c_int32), ("async_rounds_log2", ct.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Loads the library (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950); there is no fallback")
+    L = ct.CDLL(LIB_PATH, mode=ct.RTLD_GLOBAL)
+    P, I32, I64, SZ = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_size_t
+    GP, EP, SP, PP, STP = (ct.POINTER(CGraph), ct.POINTER(CEdges), ct.POINTER(CState), ct.POINTER(Params),
+                           ct.POINTER(Stats))
+    L.lv_default_params.argtypes = [PP]
+    L.lv_workspace_bytes.restype = SZ
+    L.lv_workspace_bytes.argtypes = [I32, I64]
+    L.lv_graph_capacity_bound.restype = I64
+    L.lv_graph_capacity_bound.argtypes = [I32, I64, ct.c_float, I32]
+    L.lv_graph_build.restype = I32
+    L.lv_graph_build.argtypes = [GP, EP, ct.c_float, I32, P, SZ, P]
+    L.lv_graph_relayout.restype = I32
+    L.lv_graph_relayout.argtypes = [GP, GP, ct.c_float, I32, P, SZ, P]
+    L.apply_batch.restype = I32
+    L.apply_batch.argtypes = [GP, EP, EP, P, SZ, P]
+    L.louvain_static.restype = I32
+    L.louvain_static.argtypes = [GP, PP, SP, P, SZ, STP, P]
+    for name in ("louvain_nd", "louvain_ds", "louvain_df"):
+        f = getattr(L, name)
+        f.restype = I32
+        f.argtypes = [GP, EP, EP, PP, SP, P, SZ, STP, P]
+    L.modularity.restype = I32
+    L.modularity.argtypes = [GP, P, ct.POINTER(ct.c_double), P, SZ, P]
+    L.lv_set_tuning.argtypes = [ct.POINTER(Tuning)]
+    L.lv_get_tuning.argtypes = [ct.POINTER(Tuning)]
+    L.lv_last_error.restype = ct.c_char_p
+    _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != LV_OK:
+        raise LouvainError(code, load().lv_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ct.c_void_p(t.data_ptr())
+
+
+def params(tolerance=1e-2, tolerance_drop=10.0, aggregation_tolerance=0.8, max_iterations=20, max_passes=10,
+           mode="async", swap_guard=1) -> Params:
+    """Defaults are the paper's (Section 5.1.2)."""
+    m = {"sync": SYNC, "async": ASYNC}[mode] if isinstance(mode, str) else int(mode)
+    return Params(float(tolerance), float(tolerance_drop), float(aggregation_tolerance), int(max_iterations),
+                  int(max_passes), m, int(swap_guard))
+
+
+DEFAULT_ASYNC_ROUNDS_LOG2 = 3
+
+
+def set_tuning(wave_max_degree=0, blocks_small=0, blocks_wave=0, blocks_hub=0,
+               async_rounds_log2=DEFAULT_ASYNC_ROUNDS_LOG2):
+    load().lv_set_tuning(ct.byref(Tuning(wave_max_degree, blocks_small, blocks_wave, blocks_hub,
+                                         async_rounds_log2)))
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    load().lv_get_tuning(ct.byref(t))
+    return {f: getattr(t, f) for f, _ in Tuning._fields_}
+
+
+def _dev_i32(x, device):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.int32).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=np.int32))).to(device)
+
+
+class Edges:
+    """Undirected edge or update list on the device (each pair once)."""
+
+    def __init__(self, u, v, w, device="cuda"):
+        self.u = _dev_i32(u, device)
+        self.v = _dev_i32(v, device)
+        self.w = _dev_i32(w, device)
+
+    @property
+    def count(self) -> int:
+        return int(self.u.shape[0])
+
+    def c(self) -> CEdges:
+        if self.count == 0:
+            return CEdges(None, None, None, 0)
+        return CEdges(self.u.data_ptr(), self.v.data_ptr(), self.w.data_ptr(), self.count)
+
+
+@dataclass
+class Batch:
+    dels: Edges
+    ins: Edges
+
+    @classmethod
+    def from_host(cls, b, device="cuda"):
+        return cls(Edges(b.del_u, b.del_v, b.del_w, device), Edges(b.ins_u, b.ins_v, b.ins_w, device))
+
+    @classmethod
+    def empty(cls, device="cuda"):
+        z = np.zeros(0, np.int32)
+        return cls(Edges(z, z, z, device), Edges(z, z, z, device))
+
+
+class Graph:
+    """Slack-padded CSR on the device plus its workspace."""
+
+    def __init__(self, n: int, cap: int, device="cuda"):
+        self.device = torch.device(device)
+        self.n = int(n)
+        self.cap = int(cap)
+        self.row_start = torch.zeros(self.n + 1, dtype=torch.int64, device=self.device)
+        self.row_len = torch.zeros(self.n, dtype=torch.int32, device=self.device)
+        self.col = torch.zeros(max(self.cap, 1), dtype=torch.int32, device=self.device)
+        self.w = torch.zeros(max(self.cap, 1), dtype=torch.int32, device=self.device)
+        self.two_m_t = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self._ws = None
+
+    def c(self) -> CGraph:
+        return CGraph(self.n, self.cap, self.row_start.data_ptr(), self.row_len.data_ptr(), self.col.data_ptr(),
+                      self.w.data_ptr(), self.two_m_t.data_ptr())
+
+    @property
+    def workspace(self) -> torch.Tensor:
+        if self._ws is None:
+            nbytes = int(load().lv_workspace_bytes(self.n, self.cap))
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def ws_args(self):
+        ws = self.workspace
+        return ct.c_void_p(ws.data_ptr()), ws.numel()
+
+    @property
+    def two_m(self) -> int:
+        return int(self.two_m_t.item())
+
+    @classmethod
+    def build(cls, n, u, v, w, slack_frac=0.1, slack_min=4, device="cuda", stream=None) -> "Graph":
+        L = load()
+        e = Edges(u, v, w, device)
+        cap = int(L.lv_graph_capacity_bound(int(n), e.count, float(slack_frac), int(slack_min)))
+        g = cls(n, cap, device)
+        ce = e.c()
+        cg = g.c()
+        ws, nb = g.ws_args()
+        _check(L.lv_graph_build(ct.byref(cg), ct.byref(ce), float(slack_frac), int(slack_min), ws, nb,
+                                _stream(stream)))
+        return g
+
+    @classmethod
+    def from_edges(cls, e, **kw) -> "Graph":
+        return cls.build(e.n, e.u, e.v, e.w, **kw)
+
+    def relayout(self, slack_frac=0.5, slack_min=8, stream=None) -> "Graph":
+        """A copy of this graph with more free capacity per row."""
+        L = load()
+        arcs = int(self.row_len.sum().item())
+        cap = int(L.lv_graph_capacity_bound(self.n, (arcs + 1) // 2, float(slack_frac), int(slack_min)))
+        g = Graph(self.n, cap, self.device)
+        src, dst = self.c(), g.c()
+        ws, nb = g.ws_args()
+        _check(L.lv_graph_relayout(ct.byref(src), ct.byref(dst), float(slack_frac), int(slack_min), ws, nb,
+                                   _stream(stream)))
+        return g
+
+    def csr_host(self):
+        """(offsets, col, w) on the host with every row sorted by neighbour."""
+        rs = self.row_start.cpu().numpy()
+        rl = self.row_len.cpu().numpy().astype(np.int64)
+        col = self.col.cpu().numpy()
+        w = self.w.cpu().numpy()
+        off = np.zeros(self.n + 1, dtype=np.int64)
+        off[1:] = np.cumsum(rl)
+        idx = np.concatenate([np.arange(rs[i], rs[i] + rl[i]) for i in range(self.n)]) if self.n else np.zeros(0, np.int64)
+        idx = idx.astype(np.int64)
+        rows = np.repeat(np.arange(self.n), rl)
+        c2, w2 = col[idx], w[idx].astype(np.int64)
+        order = np.lexsort((c2, rows))
+        return off, c2[order], w2[order]
+
+
+@dataclass
+class State:
+    C: torch.Tensor
+    K: torch.Tensor
+    Sigma: torch.Tensor
+
+    @classmethod
+    def empty(cls, n, device="cuda"):
+        return cls(torch.zeros(n, dtype=torch.int32, device=device), torch.zeros(n, dtype=torch.int64, device=device),
+                   torch.zeros(n, dtype=torch.int64, device=device))
+
+    @classmethod
+    def from_host(cls, C, K, S, device="cuda"):
+        return cls(torch.from_numpy(np.asarray(C, np.int32).copy()).to(device),
+                   torch.from_numpy(np.asarray(K, np.int64).copy()).to(device),
+                   torch.from_numpy(np.asarray(S, np.int64).copy()).to(device))
+
+    def clone(self) -> "State":
+        return State(self.C.clone(), self.K.clone(), self.Sigma.clone())
+
+    def host(self):
+        return self.C.cpu().numpy(), self.K.cpu().numpy(), self.Sigma.cpu().numpy()
+
+    def c(self) -> CState:
+        return CState(self.C.data_ptr(), self.K.data_ptr(), self.Sigma.data_ptr())
+
+
+def apply_batch(g: Graph, b: Batch, stream=None):
+    L = load()
+    cg, cd, ci = g.c(), b.dels.c(), b.ins.c()
+    ws, nb = g.ws_args()
+    _check(L.apply_batch(ct.byref(cg), ct.byref(cd), ct.byref(ci), ws, nb, _stream(stream)))
+
+
+def louvain_static(g: Graph, prm: Params = None, state: State = None, stream=None, **kw):
+    L = load()
+    prm = prm if prm is not None else params(**kw)
+    state = state if state is not None else State.empty(g.n, g.device)
+    st = Stats()
+    cg, cs = g.c(), state.c()
+    ws, nb = g.ws_args()
+    _check(L.louvain_static(ct.byref(cg), ct.byref(prm), ct.byref(cs), ws, nb, ct.byref(st), _stream(stream)))
+    return state, st.as_dict()
+
+
+def _dynamic(fn, g, b, state, prm, stream, kw):
+    L = load()
+    prm = prm if prm is not None else params(**kw)
+    st = Stats()
+    cg, cd, ci, cs = g.c(), b.dels.c(), b.ins.c(), state.c()
+    ws, nb = g.ws_args()
+    _check(getattr(L, fn)(ct.byref(cg), ct.byref(cd), ct.byref(ci), ct.byref(prm), ct.byref(cs), ws, nb,
+                          ct.byref(st), _stream(stream)))
+    return state, st.as_dict()
+
+
+def louvain_nd(g, b, state, prm=None, stream=None, **kw):
+    return _dynamic("louvain_nd", g, b, state, prm, stream, kw)
+
+
+def louvain_ds(g, b, state, prm=None, stream=None, **kw):
+    return _dynamic("louvain_ds", g, b, state, prm, stream, kw)
+
+
+def louvain_df(g, b, state, prm=None, stream=None, **kw):
+    return _dynamic("louvain_df", g, b, state, prm, stream, kw)
+
+
+def modularity(g: Graph, C: torch.Tensor, stream=None) -> float:
+    L = load()
+    q = ct.c_double(0.0)
+    cg = g.c()
+    ws, nb = g.ws_args()
+    _check(L.modularity(ct.byref(cg), _ptr(C), ct.byref(q), ws, nb, _stream(stream)))
+    return float(q.value)
+
+
+RUN = {"static": None, "nd": louvain_nd, "ds": louvain_ds, "df": louvain_df}

@@ -1,0 +1,279 @@
+"""GPU parity: the HIP library against the sequential oracle.
+
+SYNC mode is bit-exact: memberships, weighted degrees, community totals and
+every per-iteration statistic (moves, summed integer gains), on graphs that
+span all degree bins (sub-wave groups, wavefront, workgroup) and ragged
+sizes.  ASYNC mode is checked for consistency and modularity quality.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2404_19634_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2404_19634_amd import lib as L
+    L.load()
+    L.set_tuning()
+    return L
+
+
+def _star_plus(seed=3):
+    # one hub adjacent to 3000 leaves, a 600-degree vertex, a ring over the
+    # leaves and a few random chords: rows in every bin
+    rng = np.random.default_rng(seed)
+    n = 3301
+    pairs = set()
+    for v in range(1, 3001):
+        pairs.add((0, v))
+    for v in range(3001, 3301):
+        pairs.add((1, v) if v != 1 else (1, 2))
+    for v in range(1, 3000):
+        pairs.add((v, v + 1))
+    while len(pairs) < 9000:
+        a, b = rng.integers(1, n, 2)
+        if a != b:
+            pairs.add((min(a, b), max(a, b)))
+    for v in range(3001, 3301, 2):
+        pairs.add((1, v))
+    a = np.array(sorted(pairs), dtype=np.int32)
+    return W.Edges(n, a[:, 0].copy(), a[:, 1].copy(), np.ones(a.shape[0], np.int32))
+
+
+def _cases():
+    return {
+        "sbm": lambda: W.config1_sbm(),
+        "rmat12": lambda: W.rmat(12, 16, 0.57, 0.19, 0.19, 5),
+        "rmat14": lambda: W.rmat(14, 8, 0.57, 0.19, 0.19, 6),
+        "weighted_ragged": lambda: W.random_small_graph(1037, 4000, 9, max_w=7),
+        "ring_cliques": lambda: W.ring_of_cliques(30, 6),
+        "star_plus": _star_plus,
+    }
+
+
+CASES = _cases()
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request):
+    return request.param, CASES[request.param]()
+
+
+def _orc(e):
+    import oracle
+    return oracle.Graph.from_edges(e)
+
+
+def _same_stats(gs, os_, keys=("passes", "iterations", "communities", "moves", "arcs_scanned",
+                                "vertices_affected", "iter_moves", "iter_gain")):
+    for k in keys:
+        assert gs[k] == os_[k], (k, gs[k], os_[k])
+
+
+def test_csr_build(lib, case):
+    name, e = case
+    g = lib.Graph.from_edges(e)
+    off, col, w = g.csr_host()
+    o_off, o_col, o_w = _orc(e).csr()
+    assert np.array_equal(off, o_off) and np.array_equal(col, o_col) and np.array_equal(w, o_w)
+    assert g.two_m == 2 * int(e.w.sum())
+
+
+def test_modularity(lib, case):
+    name, e = case
+    g = lib.Graph.from_edges(e)
+    G = _orc(e)
+    rng = np.random.default_rng(1)
+    for C in (np.arange(e.n), rng.integers(0, 17, e.n), np.zeros(e.n)):
+        C = C.astype(np.int32)
+        q = lib.modularity(g, torch.from_numpy(C).cuda())
+        assert abs(q - G.modularity(C)) < 1e-12
+
+
+@pytest.mark.parametrize("guard", [1, 0])
+def test_static_sync_bit_exact(lib, case, guard):
+    name, e = case
+    g = lib.Graph.from_edges(e)
+    st, gs = lib.louvain_static(g, mode="sync", swap_guard=guard)
+    C, K, S = st.host()
+    Co, Ko, So, os_ = _orc(e).louvain("static", mode="sync", swap_guard=guard)
+    assert np.array_equal(K, Ko)
+    assert np.array_equal(C, Co)
+    assert np.array_equal(S, So)
+    _same_stats(gs, os_)
+
+
+@pytest.mark.parametrize("tuning", [dict(wave_max_degree=32), dict(wave_max_degree=512),
+                                    dict(blocks_small=1, blocks_wave=1, blocks_hub=1)])
+def test_static_sync_independent_of_mapping(lib, tuning):
+    e = W.rmat(12, 16, 0.57, 0.19, 0.19, 5)
+    Co, Ko, So, os_ = _orc(e).louvain("static", mode="sync")
+    lib.set_tuning(**tuning)
+    try:
+        g = lib.Graph.from_edges(e)
+        st, gs = lib.louvain_static(g, mode="sync")
+    finally:
+        lib.set_tuning()
+    C, K, S = st.host()
+    assert np.array_equal(C, Co) and np.array_equal(S, So)
+    _same_stats(gs, os_)
+
+
+def test_static_single_iteration(lib, case):
+    name, e = case
+    g = lib.Graph.from_edges(e)
+    st, gs = lib.louvain_static(g, mode="sync", max_iterations=1, max_passes=1)
+    Co, Ko, So, os_ = _orc(e).louvain("static", mode="sync", max_iterations=1, max_passes=1)
+    C, K, S = st.host()
+    assert np.array_equal(C, Co) and np.array_equal(S, So)
+    _same_stats(gs, os_)
+
+
+@pytest.mark.parametrize("approach", ["nd", "ds", "df"])
+def test_dynamic_sync_bit_exact(lib, case, approach):
+    name, e = case
+    b = W.random_batch(e, max(10, e.m // 200), 77)
+    G = _orc(e)
+    state0 = G.louvain("static", mode="async")[:3]
+    assert G.apply_batch(b) == 0
+    Cd, Kd, Sd, os_ = G.louvain(approach, batch=b, state=state0, mode="sync")
+    g = lib.Graph.from_edges(e)
+    bb = lib.Batch.from_host(b)
+    lib.apply_batch(g, bb)
+    off, col, w = g.csr_host()
+    o_off, o_col, o_w = G.csr()
+    assert np.array_equal(off, o_off) and np.array_equal(col, o_col) and np.array_equal(w, o_w)
+    assert g.two_m == G.two_m
+    st = lib.State.from_host(*state0)
+    st, gs = getattr(lib, "louvain_" + approach)(g, bb, st, mode="sync")
+    C, K, S = st.host()
+    assert np.array_equal(K, Kd)
+    assert np.array_equal(C, Cd)
+    assert np.array_equal(S, Sd)
+    _same_stats(gs, os_)
+
+
+@pytest.mark.parametrize("approach", ["static", "nd", "ds", "df"])
+def test_async_consistent_and_close_to_static(lib, approach):
+    e = W.config1_sbm()
+    b = W.random_batch(e, 100, 5)
+    G = _orc(e)
+    state0 = G.louvain("static", mode="async")[:3]
+    assert G.apply_batch(b) == 0
+    Cs = G.louvain("static", mode="async")[0]
+    q_static = G.modularity(Cs)
+    g = lib.Graph.from_edges(e)
+    bb = lib.Batch.from_host(b)
+    lib.apply_batch(g, bb)
+    if approach == "static":
+        st, gs = lib.louvain_static(g, mode="async")
+    else:
+        st, gs = getattr(lib, "louvain_" + approach)(g, bb, lib.State.from_host(*state0), mode="async")
+    C, K, S = st.host()
+    assert np.array_equal(K, G.degrees())
+    assert np.array_equal(S, np.bincount(C, weights=K, minlength=e.n).astype(np.int64))
+    q = lib.modularity(g, st.C)
+    assert abs(q - G.modularity(C)) < 1e-12
+    assert q >= q_static - 1e-3, (q, q_static)
+
+
+def test_apply_batch_errors_leave_graph_unchanged(lib):
+    e = W.random_small_graph(300, 900, 4)
+    g = lib.Graph.from_edges(e, slack_frac=0.0, slack_min=0)
+    before = g.csr_host()
+    present = set(zip(e.u.tolist(), e.v.tolist()))
+    a, c = next((a, c) for a in range(300) for c in range(a + 1, 300) if (a, c) not in present)
+    z = np.zeros(0, np.int32)
+    cases = [
+        (lib.LV_ENOEDGE, W.Batch(np.array([a], np.int32), np.array([c], np.int32), np.array([1], np.int32), z, z, z)),
+        (lib.LV_ENOEDGE, W.Batch(e.u[:1], e.v[:1], e.w[:1] + 1, z, z, z)),
+        (lib.LV_EINVAL, W.Batch(z, z, z, np.array([a, c], np.int32), np.array([c, a], np.int32),
+                                np.array([1, 1], np.int32))),
+        (lib.LV_EINVAL, W.Batch(z, z, z, np.array([5], np.int32), np.array([5], np.int32), np.array([1], np.int32))),
+        (lib.LV_EINVAL, W.Batch(z, z, z, np.array([5], np.int32), np.array([300], np.int32), np.array([1], np.int32))),
+        (lib.LV_ENOSLACK, W.Batch(z, z, z, np.array([a], np.int32), np.array([c], np.int32), np.array([1], np.int32))),
+    ]
+    for code, b in cases:
+        with pytest.raises(lib.LouvainError) as ex:
+            lib.apply_batch(g, lib.Batch.from_host(b))
+        assert ex.value.code == code
+        after = g.csr_host()
+        assert all(np.array_equal(x, y) for x, y in zip(before, after))
+    # after LV_ENOSLACK: relayout with slack, retry, same result as the oracle
+    g2 = g.relayout(slack_frac=0.5, slack_min=4)
+    b = cases[-1][1]
+    lib.apply_batch(g2, lib.Batch.from_host(b))
+    G = _orc(e)
+    assert G.apply_batch(b) == 0
+    assert all(np.array_equal(x, y) for x, y in zip(g2.csr_host(), G.csr()))
+
+
+def test_batch_deleting_and_reinserting_same_pair(lib):
+    e = W.random_small_graph(200, 700, 8, max_w=4)
+    z = np.zeros(0, np.int32)
+    # delete three edges whole, one partially, and re-insert two of them
+    d_u, d_v, d_w = e.u[:4].copy(), e.v[:4].copy(), e.w[:4].copy()
+    d_w[3] = max(1, d_w[3] - 1) if e.w[3] > 1 else d_w[3]
+    b = W.Batch(d_u, d_v, d_w, e.v[:2].copy(), e.u[:2].copy(), np.array([3, 5], np.int32))
+    G = _orc(e)
+    assert G.apply_batch(b) == 0
+    g = lib.Graph.from_edges(e)
+    lib.apply_batch(g, lib.Batch.from_host(b))
+    assert all(np.array_equal(x, y) for x, y in zip(g.csr_host(), G.csr()))
+    assert g.two_m == G.two_m
+
+
+def test_empty_batch_and_degenerate_graphs(lib):
+    e = W.config1_sbm()
+    G = _orc(e)
+    state0 = G.louvain("static", mode="sync")[:3]
+    g = lib.Graph.from_edges(e)
+    st, gs = lib.louvain_df(g, lib.Batch.empty(), lib.State.from_host(*state0), mode="sync")
+    C, K, S = st.host()
+    assert np.array_equal(C, state0[0]) and gs["iterations"] == [1] and gs["vertices_affected"] == 0
+    # one edge among many isolated vertices
+    one = W.Edges(97, np.array([3], np.int32), np.array([90], np.int32), np.array([2], np.int32))
+    g1 = lib.Graph.from_edges(one)
+    st1, s1 = lib.louvain_static(g1, mode="sync")
+    Co, Ko, So, so = _orc(one).louvain("static", mode="sync")
+    assert np.array_equal(st1.host()[0], Co) and np.array_equal(st1.host()[2], So)
+    _same_stats(s1, so)
+    # no edges at all
+    none = W.Edges(10, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32))
+    g0 = lib.Graph.from_edges(none)
+    with pytest.raises(lib.LouvainError) as ex:
+        lib.louvain_static(g0, mode="sync")
+    assert ex.value.code == lib.LV_EEMPTY
+
+
+def test_graph_build_rejects_bad_edges(lib):
+    bad = W.Edges(10, np.array([1, 2], np.int32), np.array([1, 3], np.int32), np.array([1, 1], np.int32))
+    with pytest.raises(lib.LouvainError) as ex:
+        lib.Graph.from_edges(bad)
+    assert ex.value.code == lib.LV_EINVAL
+
+
+def test_chained_batches_df_sync(lib):
+    """Three consecutive DF updates stay bit-exact (state carried on both sides)."""
+    e = W.rmat(13, 8, 0.57, 0.19, 0.19, 21)
+    G = _orc(e)
+    g = lib.Graph.from_edges(e)
+    so = G.louvain("static", mode="sync")[:3]
+    sg, _ = lib.louvain_static(g, mode="sync")
+    cur = e
+    for t in range(3):
+        b = W.random_batch(cur, 60, 300 + t)
+        cur = W.apply_batch_np(cur, b)
+        assert G.apply_batch(b) == 0
+        bb = lib.Batch.from_host(b)
+        lib.apply_batch(g, bb)
+        Co, Ko, Sto, os_ = G.louvain("df", batch=b, state=so, mode="sync")
+        sg, gs = lib.louvain_df(g, bb, sg, mode="sync")
+        C, K, S = sg.host()
+        assert np.array_equal(C, Co) and np.array_equal(K, Ko) and np.array_equal(S, Sto)
+        _same_stats(gs, os_)
+        so = (Co, Ko, Sto)
