@@ -121,14 +121,15 @@ typedef struct {
 } lv_stats;
 
 /* Tunables chosen by the autotuner (degree-bin thresholds and launch
- * shapes).  Zero fields take built-in defaults, except async_rounds_log2
- * where 0 means one round (lv_get_tuning reports the values in use). */
+ * shapes).  Zero fields take built-in defaults, except the two async_rounds
+ * fields, where 0 is a value (lv_get_tuning reports the values in use). */
 typedef struct {
   int32_t wave_max_degree;   /* rows up to this length go to one wavefront with an LDS table */
   int32_t blocks_small;      /* persistent grid size of the sub-wave kernels */
   int32_t blocks_wave;       /* persistent grid size of the wavefront kernel */
   int32_t blocks_hub;        /* persistent grid size of the workgroup kernel */
   int32_t async_rounds_log2; /* LV_ASYNC: each iteration runs 2^k hash-partitioned sub-rounds */
+  int32_t async_rounds_min_frontier; /* ... when the frontier may exceed this many vertices */
 } lv_tuning;
 
 /* The paper's parameter values (Section 5.1.2). */

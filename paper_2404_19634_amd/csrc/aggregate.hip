@@ -4,17 +4,34 @@
 // "holey" offsets), and per community a hashtable over its members' arcs,
 // self-loops included, whose entries become the super-vertex's row.
 //
-// Communities of volume <= the wave threshold are merged by one wavefront
-// with an LDS table; larger ones by a workgroup with a global table from
-// the workspace pool.  The super-vertex weight K''_c (= Σ''_c) is the row
-// sum written at the same time.
+// Three tiers by community volume (arcs of all members):
+//   <= 256   one wavefront, LDS table of 512 slots;
+//   <= 2048  one workgroup, LDS table of 4096 slots;
+//   larger   many workgroups: the community's arc range is cut into units of
+//            8192 arcs; each unit pre-aggregates in an LDS table and flushes
+//            into the community's global table (2 x min(volume, communities)
+//            slots), then emit units compact the table into the row.
+// Arcs into the community itself (its self-loop weight, usually the most
+// frequent key) are summed in registers in every tier.  K''_c = Σ''_c is
+// the row sum.
 #include "lv_internal.hpp"
 
 namespace lv {
 namespace {
 
-constexpr int kAggWaveVol = 256;  // volume limit of the wavefront merge
-constexpr int kAggTS = 512;       // LDS slots per wavefront (>= 2 * kAggWaveVol)
+constexpr int kAggWaveVol = 256;
+constexpr int kAggWaveTS = 512;
+constexpr int kAggBlockVol = 2048;
+constexpr int kAggBlockTS = 4096;
+constexpr int kUnitArcs = 8192;       // arcs per insert unit of a big community
+constexpr int kArcsPerThread = kUnitArcs / kBlock;
+constexpr int kEmitSlots = 4096;      // table slots per emit unit
+constexpr int kUnitTS = 4096;         // LDS slots for a unit's pre-aggregation
+constexpr int kUnitProbes = 8;
+
+// Global table slots of a big community: distinct neighbour communities are
+// at most min(volume, communities), load factor <= 1/2.
+__device__ __forceinline__ int64_t big_slots(int64_t vol, int32_t nc) { return 2 * min(vol, static_cast<int64_t>(nc)); }
 
 __global__ void k_mark_exists(const int32_t* __restrict__ C, int32_t n, int32_t* __restrict__ flags) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
@@ -34,56 +51,266 @@ __global__ void k_lookup(int32_t* __restrict__ Ctop, int32_t n, const int32_t* _
     Ctop[i] = Cl[Ctop[i]];
 }
 
-// count members and volume (arcs incl. self-loops) of each community
-__global__ void k_count_members(const int32_t* __restrict__ C, const int32_t* __restrict__ row_len, int32_t n,
-                                int32_t* __restrict__ ccount, int64_t* __restrict__ vol) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int32_t c = C[i];
-    atomicAdd(&ccount[c], 1);
-    const int32_t l = row_len[i];
-    if (l) atomic_add_i64(&vol[c], l);
-  }
+// arcs of the k-th member in community-vertex order (for the arc prefix)
+__global__ void k_member_degrees(const int32_t* __restrict__ cmem, const int32_t* __restrict__ row_len, int32_t n,
+                                 int64_t* __restrict__ out) {
+  for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < n;
+       k += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    out[k] = row_len[cmem[k]];
 }
 
-// fill the community-vertex CSR; ccount is consumed as a per-community cursor
-__global__ void k_fill_members(const int32_t* __restrict__ C, int32_t n, const int32_t* __restrict__ coff,
-                               int32_t* __restrict__ ccount, int32_t* __restrict__ cmem) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int32_t c = C[i];
-    const int32_t slot = atomicSub(&ccount[c], 1) - 1;
-    cmem[coff[c] + slot] = static_cast<int32_t>(i);
-  }
-}
-
-// split communities into the wavefront list and the workgroup list; big
-// communities get a global table of 2*volume slots
-__global__ void k_bin_communities(const int64_t* __restrict__ row_start_out, int32_t nc,
-                                  int32_t* __restrict__ small, int32_t* __restrict__ big,
-                                  int64_t* __restrict__ big_off, int32_t* __restrict__ row_len_out,
+// Split communities by volume; big ones get a global table (their insert /
+// emit units are written by k_big_units).
+__global__ void k_bin_communities(const int64_t* __restrict__ out_start, int32_t nc, int32_t* __restrict__ small,
+                                  int32_t* __restrict__ medium, int32_t* __restrict__ big,
+                                  int64_t* __restrict__ big_off, int32_t* __restrict__ out_len,
                                   int64_t* __restrict__ Kout, int64_t* __restrict__ Sout, int64_t* __restrict__ ctr) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t c0 = blockIdx.x * static_cast<int64_t>(blockDim.x); c0 < nc; c0 += stride) {
     const int64_t c = c0 + threadIdx.x;
-    int64_t vol = 0;
     const bool valid = c < nc;
+    int64_t vol = 0;
     if (valid) {
-      vol = row_start_out[c + 1] - row_start_out[c];
-      if (vol == 0) {
-        row_len_out[c] = 0;
+      vol = out_start[c + 1] - out_start[c];
+      if (vol == 0 || vol > kAggBlockVol) {  // empty rows and big rows start from zero
+        out_len[c] = 0;
         Kout[c] = 0;
         Sout[c] = 0;
       }
     }
-    const int64_t ps = wave_append(valid && vol > 0 && vol <= kAggWaveVol, &ctr[CTR_AUX1]);
+    const int64_t ps = wave_append(valid && vol > 0 && vol <= kAggWaveVol, &ctr[CTR_AGG_SMALL]);
     if (ps >= 0) small[ps] = static_cast<int32_t>(c);
-    const int64_t pb = wave_append(valid && vol > kAggWaveVol, &ctr[CTR_AUX2]);
+    const int64_t pm = wave_append(valid && vol > kAggWaveVol && vol <= kAggBlockVol, &ctr[CTR_AGG_MEDIUM]);
+    if (pm >= 0) medium[pm] = static_cast<int32_t>(c);
+    const int64_t pb = wave_append(valid && vol > kAggBlockVol, &ctr[CTR_AGG_BIG]);
     if (pb >= 0) {
       big[pb] = static_cast<int32_t>(c);
-      big_off[pb] = static_cast<int64_t>(
-          atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_POOL]), 2ull * static_cast<unsigned long long>(vol)));
+      big_off[pb] = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_POOL]),
+                                                   static_cast<unsigned long long>(big_slots(vol, nc))));
     }
+  }
+}
+
+// One thread per big community writes its unit descriptors.
+__global__ void k_big_units(const int32_t* __restrict__ big, const int64_t* __restrict__ out_start, int32_t nc,
+                            int32_t* __restrict__ ins_b, int64_t* __restrict__ ins_a, int32_t* __restrict__ emit_b,
+                            int64_t* __restrict__ emit_s, int64_t* __restrict__ ctr) {
+  const int64_t count = ctr[CTR_AGG_BIG];
+  for (int64_t b = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; b < count;
+       b += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int32_t c = big[b];
+    const int64_t vol = out_start[c + 1] - out_start[c];
+    const int64_t nu = (vol + kUnitArcs - 1) / kUnitArcs;
+    const int64_t ne = (big_slots(vol, nc) + kEmitSlots - 1) / kEmitSlots;
+    const int64_t bu = static_cast<int64_t>(
+        atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_UNITS_INS]), static_cast<unsigned long long>(nu)));
+    const int64_t be = static_cast<int64_t>(
+        atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_UNITS_EMIT]), static_cast<unsigned long long>(ne)));
+    for (int64_t u = 0; u < nu; ++u) {
+      ins_b[bu + u] = static_cast<int32_t>(b);
+      ins_a[bu + u] = u * kUnitArcs;
+    }
+    for (int64_t u = 0; u < ne; ++u) {
+      emit_b[be + u] = static_cast<int32_t>(b);
+      emit_s[be + u] = u * kEmitSlots;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_big_clear(const int32_t* __restrict__ emit_b,
+                                                     const int64_t* __restrict__ emit_s,
+                                                     const int32_t* __restrict__ big, const int64_t* __restrict__ big_off,
+                                                     const int64_t* __restrict__ out_start,
+                                                     const int64_t* __restrict__ ctr, int32_t nc, int32_t* __restrict__ keys,
+                                                     int32_t* __restrict__ vals, int64_t pool_slots) {
+  const int64_t count = ctr[CTR_UNITS_EMIT];
+  for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
+    const int32_t b = emit_b[u];
+    const int32_t c = big[b];
+    const int64_t tsz = big_slots(out_start[c + 1] - out_start[c], nc);
+    const int64_t off = big_off[b];
+    if (off + tsz > pool_slots) continue;  // reported by the insert kernel
+    const int64_t s1 = min(tsz, emit_s[u] + kEmitSlots);
+    for (int64_t s = emit_s[u] + threadIdx.x; s < s1; s += kBlock) {
+      keys[off + s] = -1;
+      vals[off + s] = 0;
+    }
+  }
+}
+
+__device__ __forceinline__ void global_table_add(int32_t* keys, int32_t* vals, uint32_t tsz, int32_t d, int32_t x) {
+  uint32_t h = hash_slot(static_cast<uint32_t>(d), tsz);
+  while (true) {
+    const int32_t old = atomicCAS(&keys[h], -1, d);
+    if (old == -1 || old == d) {
+      atomicAdd(&vals[h], x);
+      return;
+    }
+    h = (h + 1 == tsz) ? 0 : h + 1;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_big_insert(
+    const int64_t* __restrict__ row_start, const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
+    const int32_t* __restrict__ C, const int32_t* __restrict__ coff, const int32_t* __restrict__ cmem,
+    const int64_t* __restrict__ mpre, const int32_t* __restrict__ ins_b, const int64_t* __restrict__ ins_a,
+    const int32_t* __restrict__ big, const int64_t* __restrict__ big_off, const int64_t* __restrict__ out_start,
+    int64_t* __restrict__ ctr, int32_t nc, int32_t* __restrict__ keys, int32_t* __restrict__ vals,
+    int64_t pool_slots) {
+  __shared__ int32_t tk[kUnitTS];
+  __shared__ int32_t tv[kUnitTS];
+  __shared__ int64_t r_self[kBlock / kWave];
+  const int64_t count = ctr[CTR_UNITS_INS];
+  const int lane = lane_id();
+  const int wid = threadIdx.x / kWave;
+  for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
+    const int32_t b = ins_b[u];
+    const int32_t c = big[b];
+    const int64_t vol = out_start[c + 1] - out_start[c];
+    const uint32_t tsz = static_cast<uint32_t>(big_slots(vol, nc));
+    const int64_t off = big_off[b];
+    if (off + static_cast<int64_t>(tsz) > pool_slots) {
+      if (threadIdx.x == 0) set_error(ctr, LV_EWORKSPACE);
+      continue;
+    }
+    int32_t* gk = keys + off;
+    int32_t* gv = vals + off;
+    for (int s = threadIdx.x; s < kUnitTS; s += kBlock) {
+      tk[s] = -1;
+      tv[s] = 0;
+    }
+    __syncthreads();
+    // this thread's arcs, as offsets into the community's arc range
+    const int32_t m0 = coff[c], m1 = coff[c + 1];
+    const int64_t base = mpre[m0];
+    const int64_t a_begin = ins_a[u] + static_cast<int64_t>(threadIdx.x) * kArcsPerThread;
+    const int64_t a_end = min(vol, min(ins_a[u] + kUnitArcs, a_begin + kArcsPerThread));
+    int64_t self = 0;
+    if (a_begin < a_end) {
+      // last member whose first arc is <= a_begin
+      int32_t lo = m0, hi = m1 - 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (mpre[mid] - base <= a_begin) lo = mid;
+        else hi = mid - 1;
+      }
+      int32_t k = lo;
+      int64_t k_first = mpre[k] - base, k_next = mpre[k + 1] - base;
+      int64_t rs = row_start[cmem[k]];
+      for (int64_t a = a_begin; a < a_end; ++a) {
+        while (a >= k_next) {
+          ++k;
+          k_first = k_next;
+          k_next = mpre[k + 1] - base;
+          rs = row_start[cmem[k]];
+        }
+        const int64_t p = rs + (a - k_first);
+        const int32_t d = C[col[p]];
+        const int32_t x = wt[p];
+        if (d == c) {
+          self += x;
+          continue;
+        }
+        uint32_t h = hash_slot(static_cast<uint32_t>(d), kUnitTS);
+        bool done = false;
+        for (int q = 0; q < kUnitProbes; ++q) {
+          const int32_t old = atomicCAS(&tk[h], -1, d);
+          if (old == -1 || old == d) {
+            atomicAdd(&tv[h], x);
+            done = true;
+            break;
+          }
+          h = (h + 1) & (kUnitTS - 1);
+        }
+        if (!done) global_table_add(gk, gv, tsz, d, x);
+      }
+    }
+    self = wave_sum_i64(self);
+    if (lane == 0) r_self[wid] = self;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t s = 0;
+      for (int q = 0; q < kBlock / kWave; ++q) s += r_self[q];
+      if (s) global_table_add(gk, gv, tsz, c, static_cast<int32_t>(s));
+    }
+    for (int s = threadIdx.x; s < kUnitTS; s += kBlock)
+      if (tk[s] >= 0) global_table_add(gk, gv, tsz, tk[s], tv[s]);
+    __syncthreads();
+  }
+}
+
+// Compacts one unit of a big community's table into its row: one global
+// atomic per unit reserves the row positions.
+__global__ void __launch_bounds__(kBlock) k_big_emit(const int32_t* __restrict__ emit_b,
+                                                    const int64_t* __restrict__ emit_s,
+                                                    const int32_t* __restrict__ big, const int64_t* __restrict__ big_off,
+                                                    const int64_t* __restrict__ out_start, const int64_t* __restrict__ ctr,
+                                                    int32_t nc, const int32_t* __restrict__ keys,
+                                                    const int32_t* __restrict__ vals, int64_t pool_slots,
+                                                    int32_t* __restrict__ out_len, int32_t* __restrict__ out_col,
+                                                    int32_t* __restrict__ out_w, int64_t* __restrict__ Kout,
+                                                    int64_t* __restrict__ Sout) {
+  constexpr int kPer = kEmitSlots / kBlock;
+  __shared__ int32_t s_cnt[kBlock / kWave];
+  __shared__ int32_t s_base;
+  __shared__ int64_t s_sum[kBlock / kWave];
+  const int64_t count = ctr[CTR_UNITS_EMIT];
+  const int lane = lane_id();
+  const int wid = threadIdx.x / kWave;
+  for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
+    const int32_t b = emit_b[u];
+    const int32_t c = big[b];
+    const int64_t tsz = big_slots(out_start[c + 1] - out_start[c], nc);
+    const int64_t off = big_off[b];
+    if (off + tsz > pool_slots) continue;
+    // this thread's slots: emit_s[u] + threadIdx.x * kPer + [0, kPer)
+    const int64_t s0 = emit_s[u] + static_cast<int64_t>(threadIdx.x) * kPer;
+    int32_t d[kPer], x[kPer];
+    int32_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int64_t s = s0 + j;
+      d[j] = s < tsz ? keys[off + s] : -1;
+      x[j] = d[j] >= 0 ? vals[off + s] : 0;
+      mine += d[j] >= 0 ? 1 : 0;
+    }
+    // exclusive scan of `mine` over the workgroup
+    int32_t incl = mine;
+    for (int q = 1; q < kWave; q <<= 1) {
+      const int32_t o = __shfl_up(incl, q);
+      if (lane >= q) incl += o;
+    }
+    if (lane == kWave - 1) s_cnt[wid] = incl;
+    __syncthreads();
+    int32_t before = 0, total = 0;
+    for (int q = 0; q < kBlock / kWave; ++q) {
+      if (q < wid) before += s_cnt[q];
+      total += s_cnt[q];
+    }
+    if (threadIdx.x == 0) s_base = total ? atomicAdd(&out_len[c], total) : 0;
+    __syncthreads();
+    int64_t p = out_start[c] + s_base + before + incl - mine;
+    int64_t ksum = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j)
+      if (d[j] >= 0) {
+        out_col[p] = d[j];
+        out_w[p] = x[j];
+        ksum += x[j];
+        ++p;
+      }
+    ksum = wave_sum_i64(ksum);
+    if (lane == 0) s_sum[wid] = ksum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t t = 0;
+      for (int q = 0; q < kBlock / kWave; ++q) t += s_sum[q];
+      if (t) {
+        atomic_add_i64(&Kout[c], t);
+        atomic_add_i64(&Sout[c], t);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -93,9 +320,9 @@ __global__ void __launch_bounds__(kBlock) k_merge_wave(
     const int32_t* __restrict__ cmem, const int32_t* __restrict__ list, const int64_t* __restrict__ ctr,
     const int64_t* __restrict__ out_start, int32_t* __restrict__ out_len, int32_t* __restrict__ out_col,
     int32_t* __restrict__ out_w, int64_t* __restrict__ Kout, int64_t* __restrict__ Sout) {
-  __shared__ int32_t s_keys[kBlock / kWave][kAggTS];
-  __shared__ int32_t s_vals[kBlock / kWave][kAggTS];
-  const int64_t count = ctr[CTR_AUX1];
+  __shared__ int32_t s_keys[kBlock / kWave][kAggWaveTS];
+  __shared__ int32_t s_vals[kBlock / kWave][kAggWaveTS];
+  const int64_t count = ctr[CTR_AGG_SMALL];
   const int lane = lane_id();
   const int wid = threadIdx.x / kWave;
   int32_t* keys = s_keys[wid];
@@ -104,7 +331,9 @@ __global__ void __launch_bounds__(kBlock) k_merge_wave(
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
   for (int64_t idx = wave; idx < count; idx += nwaves) {
     const int32_t c = list[idx];
-    for (int t = lane; t < kAggTS; t += kWave) {
+    const int32_t vol = static_cast<int32_t>(out_start[c + 1] - out_start[c]);
+    const uint32_t ts = max(64u, 1u << (32 - __clz(static_cast<uint32_t>(2 * vol - 1))));
+    for (uint32_t t = lane; t < ts; t += kWave) {
       keys[t] = -1;
       vals[t] = 0;
     }
@@ -112,6 +341,7 @@ __global__ void __launch_bounds__(kBlock) k_merge_wave(
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int32_t m0 = coff[c], m1 = coff[c + 1];
+    int32_t self = 0;
     for (int32_t m = m0; m < m1; ++m) {
       const int32_t i = cmem[m];
       const int64_t s = row_start[i];
@@ -119,24 +349,37 @@ __global__ void __launch_bounds__(kBlock) k_merge_wave(
       for (int32_t k = lane; k < l; k += kWave) {
         const int32_t d = C[col[s + k]];
         const int32_t x = wt[s + k];
-        uint32_t h = hash_slot(static_cast<uint32_t>(d), kAggTS);
+        if (d == c) {
+          self += x;
+          continue;
+        }
+        uint32_t h = hash_slot(static_cast<uint32_t>(d), ts);
         while (true) {
           const int32_t old = atomicCAS(&keys[h], -1, d);
           if (old == -1 || old == d) {
             atomicAdd(&vals[h], x);
             break;
           }
-          h = (h + 1) & (kAggTS - 1);
+          h = (h + 1) & (ts - 1);
         }
       }
     }
+    self = wave_sum_i32(self);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int64_t base = out_start[c];
     int32_t written = 0;
     int64_t ksum = 0;
-    for (int t0 = 0; t0 < kAggTS; t0 += kWave) {
+    if (self > 0) {  // the self-loop arc (c, c) first
+      if (lane == 0) {
+        out_col[base] = c;
+        out_w[base] = self;
+      }
+      written = 1;
+      ksum = lane == 0 ? self : 0;
+    }
+    for (uint32_t t0 = 0; t0 < ts; t0 += kWave) {
       const int32_t d = keys[t0 + lane];
       const bool occ = d >= 0;
       const uint64_t mask = __ballot(occ);
@@ -158,40 +401,30 @@ __global__ void __launch_bounds__(kBlock) k_merge_wave(
   }
 }
 
-__device__ __forceinline__ int32_t ld_relaxed(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __global__ void __launch_bounds__(kBlock) k_merge_block(
     const int64_t* __restrict__ row_start, const int32_t* __restrict__ row_len, const int32_t* __restrict__ col,
     const int32_t* __restrict__ wt, const int32_t* __restrict__ C, const int32_t* __restrict__ coff,
-    const int32_t* __restrict__ cmem, const int32_t* __restrict__ list, const int64_t* __restrict__ big_off,
-    int64_t* __restrict__ ctr, int32_t* __restrict__ pool_keys, int32_t* __restrict__ pool_vals, int64_t pool_slots,
+    const int32_t* __restrict__ cmem, const int32_t* __restrict__ list, const int64_t* __restrict__ ctr,
     const int64_t* __restrict__ out_start, int32_t* __restrict__ out_len, int32_t* __restrict__ out_col,
     int32_t* __restrict__ out_w, int64_t* __restrict__ Kout, int64_t* __restrict__ Sout) {
+  __shared__ int32_t keys[kAggBlockTS];
+  __shared__ int32_t vals[kAggBlockTS];
   __shared__ int32_t s_cnt[kBlock / kWave];
   __shared__ int64_t s_sum[kBlock / kWave];
-  const int64_t count = ctr[CTR_AUX2];
+  const int64_t count = ctr[CTR_AGG_MEDIUM];
   const int lane = lane_id();
   const int wid = threadIdx.x / kWave;
   for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
     const int32_t c = list[idx];
-    const int64_t vol = out_start[c + 1] - out_start[c];
-    const int64_t tsz64 = 2 * vol;
-    if (big_off[idx] + tsz64 > pool_slots || tsz64 > 0x7fffffff) {
-      if (threadIdx.x == 0) set_error(ctr, LV_EWORKSPACE);
-      continue;
-    }
-    const uint32_t tsz = static_cast<uint32_t>(tsz64);
-    int32_t* keys = pool_keys + big_off[idx];
-    int32_t* vals = pool_vals + big_off[idx];
-    for (uint32_t t = threadIdx.x; t < tsz; t += kBlock) {
+    const int32_t vol = static_cast<int32_t>(out_start[c + 1] - out_start[c]);
+    const uint32_t ts = max(static_cast<uint32_t>(kBlock), 1u << (32 - __clz(static_cast<uint32_t>(2 * vol - 1))));
+    for (uint32_t t = threadIdx.x; t < ts; t += kBlock) {
       keys[t] = -1;
       vals[t] = 0;
     }
-    __threadfence_block();
     __syncthreads();
     const int32_t m0 = coff[c], m1 = coff[c + 1];
+    int32_t self = 0;
     for (int32_t m = m0; m < m1; ++m) {
       const int32_t i = cmem[m];
       const int64_t s = row_start[i];
@@ -199,29 +432,37 @@ __global__ void __launch_bounds__(kBlock) k_merge_block(
       for (int32_t k = threadIdx.x; k < l; k += kBlock) {
         const int32_t d = C[col[s + k]];
         const int32_t x = wt[s + k];
-        uint32_t h = hash_slot(static_cast<uint32_t>(d), tsz);
+        if (d == c) {
+          self += x;
+          continue;
+        }
+        uint32_t h = hash_slot(static_cast<uint32_t>(d), ts);
         while (true) {
           const int32_t old = atomicCAS(&keys[h], -1, d);
           if (old == -1 || old == d) {
             atomicAdd(&vals[h], x);
             break;
           }
-          h = (h + 1 == tsz) ? 0 : h + 1;
+          h = (h + 1) & (ts - 1);
         }
       }
     }
-    __threadfence_block();
+    self = wave_sum_i32(self);
+    if (lane == 0) s_cnt[wid] = self;
+    __syncthreads();
+    int32_t selfsum = 0;
+    for (int q = 0; q < kBlock / kWave; ++q) selfsum += s_cnt[q];
     __syncthreads();
     const int64_t base = out_start[c];
-    int32_t written = 0;
-    int64_t ksum = 0;
-    for (uint32_t t0 = 0; t0 < tsz; t0 += kBlock) {
+    int32_t written = selfsum > 0 ? 1 : 0;
+    int64_t ksum = (threadIdx.x == 0) ? selfsum : 0;
+    if (selfsum > 0 && threadIdx.x == 0) {
+      out_col[base] = c;
+      out_w[base] = selfsum;
+    }
+    for (uint32_t t0 = 0; t0 < ts; t0 += kBlock) {
       const uint32_t t = t0 + threadIdx.x;
-      int32_t d = -1, x = 0;
-      if (t < tsz) {
-        d = ld_relaxed(&keys[t]);
-        if (d >= 0) x = ld_relaxed(&vals[t]);
-      }
+      const int32_t d = keys[t];
       const bool occ = d >= 0;
       const uint64_t mask = __ballot(occ);
       if (lane == 0) s_cnt[wid] = __popcll(mask);
@@ -233,6 +474,7 @@ __global__ void __launch_bounds__(kBlock) k_merge_block(
       }
       if (occ) {
         const int32_t pos = written + before + __popcll(mask & ((1ull << lane) - 1ull));
+        const int32_t x = vals[t];
         out_col[base + pos] = d;
         out_w[base + pos] = x;
         ksum += x;
@@ -251,15 +493,6 @@ __global__ void __launch_bounds__(kBlock) k_merge_block(
       Sout[c] = tot;
     }
     __syncthreads();
-  }
-}
-
-__global__ void k_sigma_from_members(const int32_t* __restrict__ C, const int64_t* __restrict__ K, int32_t n,
-                                     int64_t* __restrict__ Sigma) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t k = K[i];
-    if (k) atomic_add_i64(&Sigma[C[i]], k);
   }
 }
 
@@ -284,11 +517,10 @@ void launch_lookup(int32_t* Ctop, int32_t n, const int32_t* Cl, hipStream_t st) 
 void launch_community_members(const int32_t* C, const LevelGraph& g, int32_t nc, Workspace& ws, hipStream_t st) {
   (void)hipMemsetAsync(ws.ccount, 0, sizeof(int32_t) * (static_cast<size_t>(nc) + 1), st);
   (void)hipMemsetAsync(ws.vol, 0, sizeof(int64_t) * (static_cast<size_t>(nc) + 1), st);
-  hipLaunchKernelGGL(k_count_members, dim3(grid_for(g.n, kBlock, 8192)), dim3(kBlock), 0, st, C, g.row_len, g.n,
-                     ws.ccount, ws.vol);
+  launch_accumulate(C, g.n, g.row_len, nullptr, ws.ccount, ws.vol, st);
   exclusive_scan_i32(ws.ccount, ws.coff, nc, ws, st);
-  hipLaunchKernelGGL(k_fill_members, dim3(grid_for(g.n, kBlock, 8192)), dim3(kBlock), 0, st, C, g.n, ws.coff,
-                     ws.ccount, ws.cmem);
+  (void)hipMemsetAsync(ws.flags, 0, sizeof(int32_t) * (static_cast<size_t>(nc) + 1), st);
+  launch_fill_members(C, g.n, ws.coff, ws.flags, ws.cmem, st);
 }
 
 void launch_aggregate(const LevelGraph& g, const int32_t* C, int32_t nc, LevelGraph& out, int64_t* Kout,
@@ -297,17 +529,32 @@ void launch_aggregate(const LevelGraph& g, const int32_t* C, int32_t nc, LevelGr
   launch_community_members(C, g, nc, ws, st);
   // super-vertex row offsets = exclusive scan of community volumes
   exclusive_scan_i64(ws.vol, out.row_start, nc, ws, st);
+  // arc prefix over the members in community order (for big communities)
+  hipLaunchKernelGGL(k_member_degrees, dim3(grid_for(g.n, kBlock, 8192)), dim3(kBlock), 0, st, ws.cmem, g.row_len,
+                     g.n, ws.i64tmp);
+  exclusive_scan_i64(ws.i64tmp, ws.vol, g.n, ws, st);
   out.n = nc;
-  (void)hipMemsetAsync(ws.ctr + CTR_AUX1, 0, 2 * sizeof(int64_t), st);
+  (void)hipMemsetAsync(ws.ctr + CTR_AGG_SMALL, 0, sizeof(int64_t) * 5, st);
   (void)hipMemsetAsync(ws.ctr + CTR_POOL, 0, sizeof(int64_t), st);
   hipLaunchKernelGGL(k_bin_communities, dim3(grid_for(nc, kBlock, 4096)), dim3(kBlock), 0, st, out.row_start, nc,
-                     ws.bins[0], ws.bins[1], ws.hub_off, out.row_len, Kout, Sout, ws.ctr);
+                     ws.bins[0], ws.bins[1], ws.bins[2], ws.hub_off, out.row_len, Kout, Sout, ws.ctr);
   hipLaunchKernelGGL(k_merge_wave, dim3(tu.blocks_wave), dim3(kBlock), 0, st, g.row_start, g.row_len, g.col,
                      g.w, C, ws.coff, ws.cmem, ws.bins[0], ws.ctr, out.row_start, out.row_len, out.col, out.w,
                      Kout, Sout);
   hipLaunchKernelGGL(k_merge_block, dim3(tu.blocks_hub), dim3(kBlock), 0, st, g.row_start, g.row_len, g.col,
-                     g.w, C, ws.coff, ws.cmem, ws.bins[1], ws.hub_off, ws.ctr, ws.pool_keys, ws.pool_vals,
-                     ws.pool_slots, out.row_start, out.row_len, out.col, out.w, Kout, Sout);
+                     g.w, C, ws.coff, ws.cmem, ws.bins[1], ws.ctr, out.row_start, out.row_len, out.col, out.w,
+                     Kout, Sout);
+  hipLaunchKernelGGL(k_big_units, dim3(64), dim3(kBlock), 0, st, ws.bins[2], out.row_start, nc, ws.u_ins_b,
+                     ws.u_ins_a, ws.u_emit_b, ws.u_emit_s, ws.ctr);
+  const int gb = 4 * tu.blocks_hub;
+  hipLaunchKernelGGL(k_big_clear, dim3(gb), dim3(kBlock), 0, st, ws.u_emit_b, ws.u_emit_s, ws.bins[2], ws.hub_off,
+                     out.row_start, ws.ctr, nc, ws.pool_keys, ws.pool_vals, ws.pool_slots);
+  hipLaunchKernelGGL(k_big_insert, dim3(gb), dim3(kBlock), 0, st, g.row_start, g.col, g.w, C, ws.coff, ws.cmem,
+                     ws.vol, ws.u_ins_b, ws.u_ins_a, ws.bins[2], ws.hub_off, out.row_start, ws.ctr, nc,
+                     ws.pool_keys, ws.pool_vals, ws.pool_slots);
+  hipLaunchKernelGGL(k_big_emit, dim3(gb), dim3(kBlock), 0, st, ws.u_emit_b, ws.u_emit_s, ws.bins[2], ws.hub_off,
+                     out.row_start, ws.ctr, nc, ws.pool_keys, ws.pool_vals, ws.pool_slots, out.row_len, out.col,
+                     out.w, Kout, Sout);
   // the next level starts from singletons; written only after the merges,
   // which still read the current membership (the same array from pass 1 on)
   launch_iota_i32(Cout, nc, st);
@@ -316,8 +563,7 @@ void launch_aggregate(const LevelGraph& g, const int32_t* C, int32_t nc, LevelGr
 
 void launch_sigma_from_members(const int32_t* C, const int64_t* K, int32_t n, int64_t* Sigma, hipStream_t st) {
   (void)hipMemsetAsync(Sigma, 0, sizeof(int64_t) * static_cast<size_t>(n), st);
-  if (n == 0) return;
-  hipLaunchKernelGGL(k_sigma_from_members, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, st, C, K, n, Sigma);
+  launch_accumulate(C, n, nullptr, K, nullptr, Sigma, st);
 }
 
 }  // namespace lv

@@ -85,80 +85,94 @@ __global__ void k_relayout_copy(const int64_t* __restrict__ s_start, const int32
   }
 }
 
-// Row reduction pattern: each lane owns one row of the wave's 64; rows of
-// at most kWave arcs are summed by their own lane, longer rows by the whole
-// wavefront one after another.
-template <class PerArc, class PerRow>
-__device__ __forceinline__ void wave_rows(int64_t row0, int32_t n, const int64_t* __restrict__ row_start,
-                                          const int32_t* __restrict__ row_len, PerArc arc, PerRow fin) {
+// Row sums: a group of 16 lanes per row for rows of up to 1024 arcs; longer
+// rows are listed and summed by a whole workgroup each.  With C given, also
+// the total weight of arcs whose endpoints share a community (modularity).
+constexpr int kRowGroup = 16;
+constexpr int kRowGroupMax = 1024;
+
+__global__ void __launch_bounds__(kBlock) k_rows_group(const int64_t* __restrict__ row_start,
+                                                      const int32_t* __restrict__ row_len,
+                                                      const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
+                                                      int32_t n, const int32_t* __restrict__ C, int64_t* __restrict__ K,
+                                                      int64_t* __restrict__ Sigma, int32_t* __restrict__ Cinit,
+                                                      int32_t* __restrict__ size, int32_t* __restrict__ longlist,
+                                                      int64_t* __restrict__ ctr) {
   const int lane = lane_id();
-  const int64_t i = row0 + lane;
-  const bool valid = i < n;
-  const int32_t len = valid ? row_len[i] : 0;
-  const int64_t start = valid ? row_start[i] : 0;
-  const bool shortrow = valid && len <= kWave;
-  int64_t a0 = 0, a1 = 0;
-  if (shortrow) {
-    for (int32_t k = 0; k < len; ++k) arc(static_cast<int32_t>(i), start + k, a0, a1);
-    fin(static_cast<int32_t>(i), a0, a1);
-  }
-  uint64_t longmask = __ballot(valid && !shortrow);
-  while (longmask) {
-    const int src = __ffsll(static_cast<unsigned long long>(longmask)) - 1;
-    longmask &= longmask - 1;
-    const int32_t r = static_cast<int32_t>(row0 + src);
-    const int64_t rs = __shfl(start, src);
-    const int32_t rl = __shfl(len, src);
-    int64_t b0 = 0, b1 = 0;
-    for (int32_t k = lane; k < rl; k += kWave) arc(r, rs + k, b0, b1);
-    b0 = wave_sum_i64(b0);
-    b1 = wave_sum_i64(b1);
-    if (lane == 0) fin(r, b0, b1);
-  }
-}
-
-__global__ void k_degrees(const int64_t* __restrict__ row_start, const int32_t* __restrict__ row_len,
-                          const int32_t* __restrict__ wt, int32_t n, int64_t* __restrict__ K,
-                          int64_t* __restrict__ Sigma, int32_t* __restrict__ C, int32_t* __restrict__ size) {
-  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
-  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
-  for (int64_t r0 = wave * kWave; r0 < n; r0 += nwaves * kWave) {
-    wave_rows(
-        r0, n, row_start, row_len,
-        [&](int32_t, int64_t p, int64_t& s, int64_t&) { s += wt[p]; },
-        [&](int32_t i, int64_t s, int64_t) {
-          K[i] = s;
-          if (Sigma) Sigma[i] = s;
-          if (C) C[i] = i;
-          if (size) size[i] = 1;
-        });
-  }
-}
-
-// Per vertex i: Σ_c[C_i] += K_i; total intra-community arc weight += Σ of
-// w over arcs (i, j) with C_j = C_i.
-__global__ void k_modularity_terms(const int64_t* __restrict__ row_start, const int32_t* __restrict__ row_len,
-                                   const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
-                                   int32_t n, const int32_t* __restrict__ C, int64_t* __restrict__ sig_tot,
-                                   int64_t* __restrict__ ctr) {
-  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
-  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+  const int sub = lane % kRowGroup;
+  const int64_t first = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kRowGroup;
+  const int64_t ngroups = static_cast<int64_t>(gridDim.x) * blockDim.x / kRowGroup;
   int64_t intra = 0;
-  for (int64_t r0 = wave * kWave; r0 < n; r0 += nwaves * kWave) {
-    wave_rows(
-        r0, n, row_start, row_len,
-        [&](int32_t i, int64_t p, int64_t& s, int64_t& in) {
-          const int32_t x = wt[p];
-          s += x;
-          if (C[col[p]] == C[i]) in += x;
-        },
-        [&](int32_t i, int64_t s, int64_t in) {
-          if (s) atomic_add_i64(&sig_tot[C[i]], s);
-          intra += in;
-        });
+  for (int64_t i = first; i < n; i += ngroups) {
+    const int32_t len = row_len[i];
+    if (len > kRowGroupMax) {
+      if (sub == 0) {
+        const int64_t pos = static_cast<int64_t>(
+            atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_AUX1]), 1ull));
+        longlist[pos] = static_cast<int32_t>(i);
+      }
+      continue;
+    }
+    const int64_t s = row_start[i];
+    const int32_t ci = C ? C[i] : 0;
+    int64_t acc = 0, in = 0;
+    for (int32_t k = sub; k < len; k += kRowGroup) {
+      const int32_t x = wt[s + k];
+      acc += x;
+      if (C && C[col[s + k]] == ci) in += x;
+    }
+#pragma unroll
+    for (int q = 1; q < kRowGroup; q <<= 1) acc += __shfl_xor(acc, q);
+    intra += in;
+    if (sub == 0) {
+      K[i] = acc;
+      if (Sigma) Sigma[i] = acc;
+      if (Cinit) Cinit[i] = static_cast<int32_t>(i);
+      if (size) size[i] = 1;
+    }
   }
   intra = wave_sum_i64(intra);
-  if (lane_id() == 0 && intra) atomic_add_i64(&ctr[CTR_AUX0], intra);
+  if (lane == 0 && C && intra) atomic_add_i64(&ctr[CTR_AUX0], intra);
+}
+
+__global__ void __launch_bounds__(kBlock) k_rows_long(const int64_t* __restrict__ row_start,
+                                                     const int32_t* __restrict__ row_len,
+                                                     const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
+                                                     const int32_t* __restrict__ C, int64_t* __restrict__ K,
+                                                     int64_t* __restrict__ Sigma, int32_t* __restrict__ Cinit,
+                                                     int32_t* __restrict__ size, const int32_t* __restrict__ longlist,
+                                                     int64_t* __restrict__ ctr) {
+  __shared__ int64_t r[kBlock / kWave];
+  const int64_t count = ctr[CTR_AUX1];
+  const int lane = lane_id();
+  const int wid = threadIdx.x / kWave;
+  int64_t intra = 0;
+  for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+    const int32_t i = longlist[idx];
+    const int64_t s = row_start[i];
+    const int32_t len = row_len[i];
+    const int32_t ci = C ? C[i] : 0;
+    int64_t acc = 0;
+    for (int32_t k = threadIdx.x; k < len; k += kBlock) {
+      const int32_t x = wt[s + k];
+      acc += x;
+      if (C && C[col[s + k]] == ci) intra += x;
+    }
+    acc = wave_sum_i64(acc);
+    if (lane == 0) r[wid] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t t = 0;
+      for (int q = 0; q < kBlock / kWave; ++q) t += r[q];
+      K[i] = t;
+      if (Sigma) Sigma[i] = t;
+      if (Cinit) Cinit[i] = i;
+      if (size) size[i] = 1;
+    }
+    __syncthreads();
+  }
+  intra = wave_sum_i64(intra);
+  if (lane == 0 && C && intra) atomic_add_i64(&ctr[CTR_AUX0], intra);
 }
 
 __global__ void k_sum_squares(const int64_t* __restrict__ v, int32_t n, int64_t* __restrict__ out) {
@@ -229,18 +243,18 @@ void launch_relayout_copy(const lv_graph& src, const int64_t* dst_start, int32_t
                      dst_len, dst_col, dst_w);
 }
 
-void launch_degrees(const LevelGraph& g, int64_t* K, int64_t* Sigma, int32_t* C, int32_t* size,
-                    hipStream_t st) {
+// K[i] = row sum (and Sigma = K, C = identity, size = 1 when given); with
+// C_mod given, ctr[CTR_AUX0] += weight of intra-community arcs.  Uses
+// ctr[CTR_AUX1] and `longlist` (n entries) as scratch.
+void launch_row_sums(const LevelGraph& g, const int32_t* C_mod, int64_t* K, int64_t* Sigma, int32_t* Cinit,
+                     int32_t* size, int32_t* longlist, int64_t* ctr, hipStream_t st) {
   if (g.n == 0) return;
-  hipLaunchKernelGGL(k_degrees, dim3(grid_for(g.n, kBlock, 4096)), dim3(kBlock), 0, st, g.row_start,
-                     g.row_len, g.w, g.n, K, Sigma, C, size);
-}
-
-void launch_modularity_terms(const LevelGraph& g, const int32_t* C, int64_t* sig_tot, int64_t* ctr,
-                             hipStream_t st) {
-  if (g.n == 0) return;
-  hipLaunchKernelGGL(k_modularity_terms, dim3(grid_for(g.n, kBlock, 4096)), dim3(kBlock), 0, st,
-                     g.row_start, g.row_len, g.col, g.w, g.n, C, sig_tot, ctr);
+  (void)hipMemsetAsync(ctr + CTR_AUX1, 0, sizeof(int64_t), st);
+  hipLaunchKernelGGL(k_rows_group, dim3(grid_for(static_cast<int64_t>(g.n) * kRowGroup, kBlock, 8192)),
+                     dim3(kBlock), 0, st, g.row_start, g.row_len, g.col, g.w, g.n, C_mod, K, Sigma, Cinit, size,
+                     longlist, ctr);
+  hipLaunchKernelGGL(k_rows_long, dim3(1024), dim3(kBlock), 0, st, g.row_start, g.row_len, g.col, g.w, C_mod, K,
+                     Sigma, Cinit, size, longlist, ctr);
 }
 
 void launch_sum_squares(const int64_t* v, int32_t n, int64_t* out, hipStream_t st) {

@@ -18,7 +18,7 @@ namespace lv {
 namespace {
 
 thread_local std::string g_last_error;
-lv_tuning g_tuning = {256, 2048, 2048, 512, 3};
+lv_tuning g_tuning = {256, 2048, 2048, 512, 3, 4096};
 
 lv_status fail(lv_status code, const char* msg) {
   g_last_error = msg;
@@ -135,6 +135,7 @@ lv_tuning effective_tuning() {
   if (t.blocks_hub <= 0) t.blocks_hub = 512;
   if (t.async_rounds_log2 < 0) t.async_rounds_log2 = 0;
   if (t.async_rounds_log2 > 5) t.async_rounds_log2 = 5;
+  if (t.async_rounds_min_frontier < 0) t.async_rounds_min_frontier = 0;
   return t;
 }
 
@@ -241,7 +242,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
   L0.w = g->w;
   bool use_range = false;
   if (ap == A_STATIC) {
-    launch_degrees(L0, state->K, state->Sigma, state->C, ws.size, st);
+    launch_row_sums(L0, nullptr, state->K, state->Sigma, state->C, ws.size, ws.bins[5], ws.ctr, st);
     launch_set_all_bits(ws.fr_a, N, st);
   } else {
     switch (ap) {
@@ -314,16 +315,20 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     a.guard = p->swap_guard;
     a.wave_max = tu.wave_max_degree;
     const int64_t words_l = (static_cast<int64_t>(L.n) + 31) / 32;
+    // upper bound of the frontier size, for the choice of sub-rounds
+    int64_t est_frontier = L.n;
+    if (pass == 0 && ap == A_DF) est_frontier = 2 * (D.count + I.count);
     for (int32_t it = 0; it < p->max_iterations; ++it) {
       a.cur = cur;
       a.next = next;
       LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_ITER_END, st));
-      const int rl2 = p->mode == LV_ASYNC ? tu.async_rounds_log2 : 0;
+      // sub-rounds pay off when many vertices decide at once, and always on
+      // super-vertex levels, whose graphs are dense
+      const bool rounds = pass > 0 || est_frontier > tu.async_rounds_min_frontier;
+      const int rl2 = (p->mode == LV_ASYNC && rounds) ? tu.async_rounds_log2 : 0;
       for (int r = 0; r < (1 << rl2); ++r) {
-        if (r > 0) {  // fresh bin counts and table pool for the sub-round
-          LV_HIP(hipMemsetAsync(ws.ctr + CTR_BIN0, 0, sizeof(int64_t) * NBINS, st));
-          LV_HIP(hipMemsetAsync(ws.ctr + CTR_POOL, 0, sizeof(int64_t), st));
-        }
+        if (r > 0)  // fresh bin counts, unit counts and table pool for the sub-round
+          LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_ROUND_END, st));
         launch_bin_frontier(a, ws, r, rl2, st);
         launch_move(a, ws, tu, st);
       }
@@ -334,6 +339,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
       if ((s = read_counters(host, ws, CTR_ITER_END, st))) return s;
       if (host[CTR_ERR]) return fail(static_cast<lv_status>(host[CTR_ERR]), "device error in local-moving");
       const int64_t movers = host[CTR_MOVERS], gain = host[CTR_GAIN];
+      est_frontier = host[CTR_EXPAND];
       S.moves += movers;
       S.arcs_scanned += host[CTR_ARCS];
       if (pass < LV_MAX_PASSES && it < LV_MAX_ITERS) {
@@ -428,6 +434,10 @@ size_t carve_workspace(Workspace& ws, void* base, int32_t n, int64_t cap) {
   ws.dC = take<uint32_t>(cur, total, base, ws.words);
   for (int b = 0; b < NBINS; ++b) ws.bins[b] = take<int32_t>(cur, total, base, un);
   ws.hub_off = take<int64_t>(cur, total, base, un);
+  ws.hub_kid = take<int64_t>(cur, total, base, un);
+  ws.hub_moved = take<int32_t>(cur, total, base, un);
+  ws.hub_cbase = take<int64_t>(cur, total, base, un);
+  ws.hub_cnum = take<int32_t>(cur, total, base, un);
   ws.mv_v = take<int32_t>(cur, total, base, un);
   ws.mv_c = take<int32_t>(cur, total, base, un);
   ws.size = take<int32_t>(cur, total, base, un);
@@ -448,6 +458,13 @@ size_t carve_workspace(Workspace& ws, void* base, int32_t n, int64_t cap) {
     ws.lg[k].col = take<int32_t>(cur, total, base, ucap);
     ws.lg[k].w = take<int32_t>(cur, total, base, ucap);
   }
+  ws.units_max = static_cast<int64_t>(un) + static_cast<int64_t>(ucap) / 2048 + 64;
+  ws.u_ins_b = take<int32_t>(cur, total, base, static_cast<size_t>(ws.units_max));
+  ws.u_ins_a = take<int64_t>(cur, total, base, static_cast<size_t>(ws.units_max));
+  ws.u_emit_b = take<int32_t>(cur, total, base, static_cast<size_t>(ws.units_max));
+  ws.u_emit_s = take<int64_t>(cur, total, base, static_cast<size_t>(ws.units_max));
+  ws.unit_g = take<int64_t>(cur, total, base, static_cast<size_t>(ws.units_max));
+  ws.unit_c = take<int32_t>(cur, total, base, static_cast<size_t>(ws.units_max));
   ws.pool_slots = 2 * static_cast<int64_t>(ucap) + 4096;
   ws.pool_keys = take<int32_t>(cur, total, base, static_cast<size_t>(ws.pool_slots));
   ws.pool_vals = take<int32_t>(cur, total, base, static_cast<size_t>(ws.pool_slots));
@@ -623,7 +640,10 @@ lv_status modularity(const lv_graph* g, const int32_t* C, double* q_host, void* 
   L.w = g->w;
   LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_COUNT, st));
   LV_HIP(hipMemsetAsync(ws.i64tmp, 0, sizeof(int64_t) * (static_cast<size_t>(g->n) + 1), st));
-  launch_modularity_terms(L, C, ws.i64tmp, ws.ctr, st);
+  // K_i and the intra-community arc weight (ctr[AUX0]), then Σ_c and Σ_c^2
+  launch_row_sums(L, C, ws.lK, nullptr, nullptr, nullptr, ws.bins[5], ws.ctr, st);
+  launch_accumulate(C, g->n, nullptr, ws.lK, nullptr, ws.i64tmp, st);
+  LV_HIP(hipMemsetAsync(ws.ctr + CTR_AUX1, 0, sizeof(int64_t), st));
   launch_sum_squares(ws.i64tmp, g->n, ws.ctr + CTR_AUX1, st);
   LV_CHECK_LAUNCH();
   int64_t two_m = 0;

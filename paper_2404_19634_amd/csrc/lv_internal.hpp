@@ -17,27 +17,40 @@ constexpr int kBlock = 256;  // 4 wavefronts
 
 // Degree bins of the local-moving phase.  Rows of length 1..32 are handled
 // by groups of 4/8/16/32 lanes (one arc per lane), longer rows up to the
-// wave threshold by one wavefront with an LDS hashtable, and the rest by a
-// whole workgroup with a global-memory hashtable.
-enum Bin { BIN_G4 = 0, BIN_G8, BIN_G16, BIN_G32, BIN_WAVE, BIN_HUB, NBINS };
+// wave threshold by one wavefront with an LDS hashtable, rows up to
+// kBlockMaxDegree by one workgroup with an LDS hashtable, and the rest (hub
+// rows) by many workgroups sharing a global-memory hashtable.
+enum Bin { BIN_G4 = 0, BIN_G8, BIN_G16, BIN_G32, BIN_WAVE, BIN_BLOCK, BIN_HUB, NBINS };
 
 constexpr int kWaveTableMaxDegree = 512;  // largest wave-bin row the LDS table supports
+constexpr int kBlockMaxDegree = 2048;     // largest workgroup-bin row (LDS table of 4096 slots)
+constexpr int kHubUnitArcs = 8192;        // arcs per work unit of a hub row
+constexpr int kHubClearSlots = 4096;      // table slots per clear unit of a hub row
 
 // Device counters (int64 slots of Workspace::ctr).
 enum Ctr {
-  CTR_BIN0 = 0,                 // .. CTR_BIN0 + NBINS - 1: items per bin
-  CTR_MOVERS = 8,               // moves decided this iteration
-  CTR_GAIN = 9,                 // sum of movers' gains
-  CTR_ARCS = 10,                // arcs scanned this iteration
-  CTR_PROCESSED = 11,           // vertices processed this iteration
-  CTR_POOL = 12,                // global hashtable slots handed out
-  CTR_ERR = 13,                 // error code (first nonzero wins)
-  CTR_TOTAL = 14,               // generic total (scans, counts)
-  CTR_AUX0 = 15,
-  CTR_AUX1 = 16,
-  CTR_AUX2 = 17,
-  CTR_AUX3 = 18,
-  CTR_ITER_END = 24,            // slots [0, CTR_ITER_END) are cleared every iteration
+  CTR_BIN0 = 0,        // .. CTR_BIN0 + NBINS - 1: items per bin
+  CTR_POOL = 7,        // global hashtable slots handed out
+  CTR_HUB_UNITS = 8,   // hub work units (insert / expand)
+  CTR_HUB_CUNITS = 9,  // hub table-clear units
+  CTR_ROUND_END = 10,  // slots [0, CTR_ROUND_END) are cleared every sub-round
+  CTR_MOVERS = 10,     // moves decided this iteration
+  CTR_GAIN = 11,       // sum of movers' gains
+  CTR_ARCS = 12,       // arcs scanned this iteration
+  CTR_PROCESSED = 13,  // vertices processed this iteration
+  CTR_EXPAND = 14,     // arcs of movers (bound on the next frontier)
+  CTR_ERR = 15,        // error code (first nonzero wins)
+  CTR_TOTAL = 16,      // generic total (scans, counts)
+  CTR_AUX0 = 17,
+  CTR_AUX1 = 18,
+  CTR_AUX2 = 19,
+  CTR_AUX3 = 20,
+  CTR_ITER_END = 24,   // slots [0, CTR_ITER_END) are cleared every iteration
+  CTR_AGG_SMALL = 32,  // aggregation: communities per tier and unit counts
+  CTR_AGG_MEDIUM = 33,
+  CTR_AGG_BIG = 34,
+  CTR_UNITS_INS = 35,
+  CTR_UNITS_EMIT = 36,
   CTR_COUNT = 64
 };
 
@@ -62,6 +75,12 @@ struct Workspace {
   uint32_t* dC = nullptr;     // DS: community-affected flags
   int32_t* bins[NBINS] = {};
   int64_t* hub_off = nullptr;  // global-table offset of each hub item
+  int64_t* hub_kid = nullptr;  // hub items: weight into the vertex's own community
+  int32_t* hub_moved = nullptr;
+  int64_t* hub_cbase = nullptr;  // hub items: first table-slot unit and unit count
+  int32_t* hub_cnum = nullptr;
+  int64_t* unit_g = nullptr;     // per table-slot unit: best gain and community
+  int32_t* unit_c = nullptr;
   int32_t* mv_v = nullptr;     // sync movers: vertex, target community
   int32_t* mv_c = nullptr;
   int32_t* size = nullptr;     // community sizes (swap guard)
@@ -76,6 +95,11 @@ struct Workspace {
   int64_t* vol = nullptr;      // n + 1
   int64_t* i64tmp = nullptr;   // n + 1 (scans over int64, community sums)
   LevelGraph lg[2];
+  int32_t* u_ins_b = nullptr;    // work units of big items (item, first arc)
+  int64_t* u_ins_a = nullptr;
+  int32_t* u_emit_b = nullptr;   // table-slot units of big items (item, first slot)
+  int64_t* u_emit_s = nullptr;
+  int64_t units_max = 0;
   int32_t* pool_keys = nullptr;  // global hashtables
   int32_t* pool_vals = nullptr;
   int64_t pool_slots = 0;
@@ -152,6 +176,12 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, Workspace& w
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, Workspace& ws, hipStream_t st);
 int64_t scan_parts_needed(int64_t n);
 
+// hist.hip
+void launch_accumulate(const int32_t* C, int32_t n, const int32_t* v32, const int64_t* v64, int32_t* out_count,
+                       int64_t* out_val, hipStream_t st);
+void launch_fill_members(const int32_t* C, int32_t n, const int32_t* coff, int32_t* cursor, int32_t* cmem,
+                         hipStream_t st);
+
 // graph.hip
 void launch_build_count(const lv_edges& e, int32_t n, int32_t* deg, int64_t* ctr, hipStream_t st);
 void launch_row_capacity(const int32_t* deg, int64_t* capv, int32_t n, float frac, int32_t smin,
@@ -160,14 +190,12 @@ void launch_build_scatter(const lv_edges& e, const int64_t* row_start, int32_t* 
                           int32_t* w, int64_t* two_m, hipStream_t st);
 void launch_relayout_copy(const lv_graph& src, const int64_t* dst_start, int32_t* dst_len,
                           int32_t* dst_col, int32_t* dst_w, hipStream_t st);
-void launch_degrees(const LevelGraph& g, int64_t* K, int64_t* Sigma, int32_t* C, int32_t* size,
-                    hipStream_t st);
+void launch_row_sums(const LevelGraph& g, const int32_t* C_mod, int64_t* K, int64_t* Sigma, int32_t* Cinit,
+                     int32_t* size, int32_t* longlist, int64_t* ctr, hipStream_t st);
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 void launch_iota_i32(int32_t* p, int64_t n, hipStream_t st);
 void launch_set_all_bits(uint32_t* bm, int32_t n, hipStream_t st);
 void launch_copy_bits(const uint32_t* src, uint32_t* dst, int64_t words, hipStream_t st);
-void launch_modularity_terms(const LevelGraph& g, const int32_t* C, int64_t* sig_tot, int64_t* ctr,
-                             hipStream_t st);
 void launch_sum_squares(const int64_t* v, int32_t n, int64_t* out, hipStream_t st);
 
 // batch.hip

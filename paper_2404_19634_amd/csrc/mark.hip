@@ -73,12 +73,6 @@ __global__ void k_batch_weight_sums(const int32_t* __restrict__ dw, int64_t nd, 
   }
 }
 
-__global__ void k_community_sizes(const int32_t* __restrict__ C, int32_t n, int32_t* __restrict__ size) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    atomicAdd(&size[C[i]], 1);
-}
-
 __global__ void k_ds_deletions(const int32_t* __restrict__ du, const int32_t* __restrict__ dv, int64_t nd,
                                const int32_t* __restrict__ C, uint32_t* __restrict__ dV, uint32_t* __restrict__ dE,
                                uint32_t* __restrict__ dC) {
@@ -242,8 +236,7 @@ void launch_batch_weight_sums(const lv_edges& del, const lv_edges& ins, int64_t*
 
 void launch_community_sizes(const int32_t* C, int32_t n, int32_t* size, hipStream_t st) {
   (void)hipMemsetAsync(size, 0, sizeof(int32_t) * static_cast<size_t>(n), st);
-  if (n == 0) return;
-  hipLaunchKernelGGL(k_community_sizes, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, st, C, n, size);
+  launch_accumulate(C, n, nullptr, nullptr, size, nullptr, st);
 }
 
 void launch_ds_deletions(const lv_edges& del, const int32_t* C, uint32_t* dV, uint32_t* dE, uint32_t* dC,

@@ -13,11 +13,17 @@
 //   rows of 1..4/5..8/9..16/17..32 arcs: groups of 4/8/16/32 lanes, one arc
 //     per lane; community weights are summed by all-pairs lane exchange
 //     within the group (no memory traffic, no atomics, conflict free);
-//   rows up to the wave threshold: one wavefront with an open-addressing
-//     table in LDS; arcs into the vertex's own community are summed in
-//     registers, which keeps the most common key out of the LDS atomics;
-//   longer rows: one workgroup with an open-addressing table in global
-//     memory (a slice of the workspace pool sized 2*deg).
+//   rows up to the wave threshold: one wavefront, open-addressing table in
+//     LDS;
+//   rows up to 2048 arcs: one workgroup, open-addressing table in LDS;
+//   hub rows: units of 8192 arcs spread over workgroups; each unit
+//     pre-aggregates in LDS and flushes into the row's global table
+//     (2 x deg slots from the workspace pool); units of 4096 table slots
+//     take partial argmaxes, one wavefront per hub picks the best, and
+//     units expand the frontier of moved hubs.
+// LDS tables are sized to the smallest power of two >= 2 x deg.
+// Arcs into the vertex's own community d are summed in registers in every
+// tier, which keeps the most frequent key out of the hashtable atomics.
 // SYNC mode reads the iteration-start state and records movers; a separate
 // kernel applies them.  ASYNC mode applies each move at once.  Both expand
 // the next frontier from the kernel that holds the mover's arcs.
@@ -83,14 +89,33 @@ __device__ __forceinline__ bool decide_move(const Dev& D, int32_t d, int32_t c, 
   return true;
 }
 
-// Applies a move immediately (ASYNC) -- one lane per mover.
-__device__ __forceinline__ void apply_now(const Dev& D, int32_t i, int32_t d, int32_t c, int64_t Ki) {
+// Records (SYNC) or applies (ASYNC) one move -- one lane per mover.
+__device__ __forceinline__ void commit_move(const Dev& D, int32_t i, int32_t d, int32_t c, int64_t Ki) {
+  if (D.mode == LV_SYNC) {
+    const int64_t pos =
+        static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&D.ctr[CTR_MOVERS]), 1ull));
+    D.mv_v[pos] = i;
+    D.mv_c[pos] = c;
+    return;
+  }
   D.C[i] = c;
   atomic_add_i64(&D.Sigma[d], -Ki);
   atomic_add_i64(&D.Sigma[c], Ki);
   if (D.size) {
     atomicSub(&D.size[d], 1);
     atomicAdd(&D.size[c], 1);
+  }
+}
+
+// Wavefront totals of gains, moves and mover arcs into the counters.
+__device__ __forceinline__ void flush_totals(const Dev& D, int64_t gain, int64_t moved, int64_t arcs) {
+  gain = wave_sum_i64(gain);
+  moved = wave_sum_i64(moved);
+  arcs = wave_sum_i64(arcs);
+  if (lane_id() == 0 && moved) {
+    atomic_add_i64(&D.ctr[CTR_GAIN], gain);
+    atomic_add_i64(&D.ctr[CTR_EXPAND], arcs);
+    if (D.mode != LV_SYNC) atomic_add_i64(&D.ctr[CTR_MOVERS], moved);
   }
 }
 
@@ -108,23 +133,72 @@ __device__ __forceinline__ uint32_t round_mask(uint32_t k, uint32_t round, uint3
   return m;
 }
 
+struct Bins {
+  int32_t* list[NBINS];
+};
+
+__device__ __forceinline__ int bin_of(int32_t deg, int32_t wave_max) {
+  if (deg <= 0) return -1;
+  if (deg <= 4) return BIN_G4;
+  if (deg <= 8) return BIN_G8;
+  if (deg <= 16) return BIN_G16;
+  if (deg <= 32) return BIN_G32;
+  if (deg <= wave_max) return BIN_WAVE;
+  if (deg <= kBlockMaxDegree) return BIN_BLOCK;
+  return BIN_HUB;
+}
+
+struct HubOut {
+  int64_t* off;    // global table offset
+  int64_t* cbase;  // first clear / decide unit
+  int32_t* cnum;   // number of clear / decide units
+  int32_t* u_b;    // insert / expand units: (hub item, first arc)
+  int64_t* u_a;
+  int32_t* c_b;    // clear / decide units: (hub item, first slot)
+  int64_t* c_s;
+};
+
+// Reserves the hub row's global table (2*deg slots) and writes its units.
+__device__ __forceinline__ void hub_setup(const HubOut& H, int64_t pos, int32_t deg, int64_t* ctr) {
+  H.off[pos] = static_cast<int64_t>(
+      atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_POOL]), 2ull * static_cast<unsigned long long>(deg)));
+  const int64_t nu = (deg + kHubUnitArcs - 1) / kHubUnitArcs;
+  const int64_t nc = (2 * static_cast<int64_t>(deg) + kHubClearSlots - 1) / kHubClearSlots;
+  const int64_t bu = static_cast<int64_t>(
+      atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_HUB_UNITS]), static_cast<unsigned long long>(nu)));
+  const int64_t bc = static_cast<int64_t>(
+      atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_HUB_CUNITS]), static_cast<unsigned long long>(nc)));
+  H.cbase[pos] = bc;
+  H.cnum[pos] = static_cast<int32_t>(nc);
+  for (int64_t u = 0; u < nu; ++u) {
+    H.u_b[bu + u] = static_cast<int32_t>(pos);
+    H.u_a[bu + u] = u * kHubUnitArcs;
+  }
+  for (int64_t u = 0; u < nc; ++u) {
+    H.c_b[bc + u] = static_cast<int32_t>(pos);
+    H.c_s[bc + u] = u * kHubClearSlots;
+  }
+}
+
 // --------------------------------------------------------------------------
-// Frontier -> degree bins.  One lane per 32-vertex bitmask word; set bits
-// are peeled one per step so the wavefront stays converged for the
-// aggregated appends.
+// Frontier -> degree bins.  One thread per 32-vertex bitmask word.  Each
+// workgroup counts its vertices per bin in LDS, reserves one range per bin
+// with a single global atomic, then places them.
 // --------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_bin_frontier(const uint32_t* __restrict__ cur,
                                                         const uint32_t* __restrict__ range,
                                                         uint32_t* __restrict__ ever,
                                                         const int32_t* __restrict__ row_len, int32_t n,
                                                         int32_t wave_max, uint32_t round, uint32_t round_shift,
-                                                        int32_t* b0, int32_t* b1,
-                                                        int32_t* b2, int32_t* b3, int32_t* b4, int32_t* b5,
-                                                        int64_t* __restrict__ hub_off, int64_t* __restrict__ ctr) {
+                                                        Bins bins, HubOut H, int64_t* __restrict__ ctr) {
+  __shared__ int32_t s_cnt[NBINS];
+  __shared__ int64_t s_base[NBINS];
   const int64_t words = (static_cast<int64_t>(n) + 31) / 32;
   int64_t arcs = 0, processed = 0;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t w0 = blockIdx.x * static_cast<int64_t>(blockDim.x); w0 < words; w0 += stride) {
+    if (threadIdx.x < NBINS) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t k = w0 + threadIdx.x;
     uint32_t bits = 0;
     if (k < words) {
@@ -133,37 +207,41 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(const uint32_t* __restr
       if (round_shift < 32 && bits) bits &= round_mask(static_cast<uint32_t>(k), round, round_shift);
       if (ever && bits) ever[k] |= bits;
     }
-    while (__ballot(bits != 0)) {
-      const bool has = bits != 0;
-      int32_t i = 0, deg = 0;
-      if (has) {
-        i = static_cast<int32_t>(k * 32 + (__ffs(bits) - 1));
-        bits &= bits - 1;
-        deg = row_len[i];
-        processed += 1;
-        arcs += deg;
-      }
-      int bin = -1;
-      if (has && deg > 0) {
-        if (deg <= 4) bin = BIN_G4;
-        else if (deg <= 8) bin = BIN_G8;
-        else if (deg <= 16) bin = BIN_G16;
-        else if (deg <= 32) bin = BIN_G32;
-        else if (deg <= wave_max) bin = BIN_WAVE;
-        else bin = BIN_HUB;
-      }
-      int32_t* lists[NBINS] = {b0, b1, b2, b3, b4, b5};
+    int32_t cnt[NBINS];
 #pragma unroll
-      for (int b = 0; b < NBINS; ++b) {
-        const int64_t pos = wave_append(bin == b, &ctr[CTR_BIN0 + b]);
-        if (pos >= 0) {
-          lists[b][pos] = i;
-          if (b == BIN_HUB)
-            hub_off[pos] = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_POOL]),
-                                                          2ull * static_cast<unsigned long long>(deg)));
-        }
-      }
+    for (int q = 0; q < NBINS; ++q) cnt[q] = 0;
+    for (uint32_t r = bits; r; r &= r - 1) {
+      const int32_t i = static_cast<int32_t>(k * 32 + (__ffs(r) - 1));
+      const int32_t deg = row_len[i];
+      processed += 1;
+      arcs += deg;
+      const int bin = bin_of(deg, wave_max);
+#pragma unroll
+      for (int q = 0; q < NBINS; ++q) cnt[q] += (bin == q) ? 1 : 0;
     }
+#pragma unroll
+    for (int q = 0; q < NBINS; ++q)
+      if (cnt[q]) atomicAdd(&s_cnt[q], cnt[q]);
+    __syncthreads();
+    if (threadIdx.x < NBINS) {
+      const int32_t c = s_cnt[threadIdx.x];
+      s_base[threadIdx.x] = c ? static_cast<int64_t>(atomicAdd(
+                                    reinterpret_cast<unsigned long long*>(&ctr[CTR_BIN0 + threadIdx.x]),
+                                    static_cast<unsigned long long>(c)))
+                              : 0;
+      s_cnt[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    for (uint32_t r = bits; r; r &= r - 1) {
+      const int32_t i = static_cast<int32_t>(k * 32 + (__ffs(r) - 1));
+      const int32_t deg = row_len[i];
+      const int bin = bin_of(deg, wave_max);
+      if (bin < 0) continue;
+      const int64_t pos = s_base[bin] + atomicAdd(&s_cnt[bin], 1);
+      bins.list[bin][pos] = i;
+      if (bin == BIN_HUB) hub_setup(H, pos, deg, ctr);
+    }
+    __syncthreads();
   }
   processed = wave_sum_i64(processed);
   arcs = wave_sum_i64(arcs);
@@ -185,7 +263,7 @@ __global__ void __launch_bounds__(kBlock) k_move_small(Dev D, const int32_t* __r
   const int k = lane % G;
   const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
-  int64_t gain_acc = 0, moved = 0;
+  int64_t gain_acc = 0, moved = 0, marcs = 0;
   for (int64_t base = wave * VPW; base < count; base += nwaves * VPW) {
     const int64_t idx = base + sub;
     const bool valid = idx < count;
@@ -246,20 +324,16 @@ __global__ void __launch_bounds__(kBlock) k_move_small(Dev D, const int32_t* __r
         D.mv_c[pos] = bc;
       }
     } else if (lead && mv) {
-      apply_now(D, i, d, bc, Ki);
+      commit_move(D, i, d, bc, Ki);
     }
     if (lead && mv) {
       gain_acc += bg;
       moved += 1;
+      marcs += deg;
     }
     if (mv && has) set_bit(D.next, j);
   }
-  gain_acc = wave_sum_i64(gain_acc);
-  moved = wave_sum_i64(moved);
-  if (lane == 0 && moved) {
-    atomic_add_i64(&D.ctr[CTR_GAIN], gain_acc);
-    if (D.mode != LV_SYNC) atomic_add_i64(&D.ctr[CTR_MOVERS], moved);
-  }
+  flush_totals(D, gain_acc, moved, marcs);
 }
 
 // --------------------------------------------------------------------------
@@ -276,13 +350,15 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __re
   int32_t* vals = s_vals[wid];
   const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
-  int64_t gain_acc = 0, moved = 0;
+  int64_t gain_acc = 0, moved = 0, marcs = 0;
   for (int64_t idx = wave; idx < count; idx += nwaves) {
     const int32_t i = list[idx];
     const int64_t start = D.row_start[i];
     const int32_t deg = D.row_len[i];
     const int32_t d = D.C[i];
-    for (int t = lane; t < TS; t += kWave) {
+    // table of the smallest power of two >= 2*deg slots (at least 64)
+    const uint32_t ts = max(64u, 1u << (32 - __clz(static_cast<uint32_t>(2 * deg - 1))));
+    for (uint32_t t = lane; t < ts; t += kWave) {
       keys[t] = -1;
       vals[t] = 0;
     }
@@ -300,14 +376,14 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __re
           if (c == d) {
             kid += x;
           } else {
-            uint32_t h = hash_slot(static_cast<uint32_t>(c), TS);
+            uint32_t h = hash_slot(static_cast<uint32_t>(c), ts);
             while (true) {
               const int32_t old = atomicCAS(&keys[h], -1, c);
               if (old == -1 || old == c) {
                 atomicAdd(&vals[h], x);
                 break;
               }
-              h = (h + 1) & (TS - 1);
+              h = (h + 1) & (ts - 1);
             }
           }
         }
@@ -321,7 +397,7 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __re
     const int64_t Sd = D.Sigma[d];
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
-    for (int t = lane; t < TS; t += kWave) {
+    for (uint32_t t = lane; t < ts; t += kWave) {
       const int32_t c = keys[t];
       if (c >= 0) {
         const int64_t g = gain_of(D.two_m, vals[t], kid, Ki, D.Sigma[c], Sd);
@@ -339,19 +415,12 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __re
         bc = oc;
       }
     }
-    const bool mv = decide_move(D, d, bc, bg);
-    if (mv) {
+    if (decide_move(D, d, bc, bg)) {
       if (lane == 0) {
-        if (D.mode == LV_SYNC) {
-          const int64_t pos = static_cast<int64_t>(
-              atomicAdd(reinterpret_cast<unsigned long long*>(&D.ctr[CTR_MOVERS]), 1ull));
-          D.mv_v[pos] = i;
-          D.mv_c[pos] = bc;
-        } else {
-          apply_now(D, i, d, bc, Ki);
-        }
+        commit_move(D, i, d, bc, Ki);
         gain_acc += bg;
         moved += 1;
+        marcs += deg;
       }
       for (int32_t b = lane; b < deg; b += kWave) {
         const int32_t j = D.col[start + b];
@@ -359,51 +428,65 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __re
       }
     }
   }
-  gain_acc = wave_sum_i64(gain_acc);
-  moved = wave_sum_i64(moved);
-  if (lane == 0 && moved) {
-    atomic_add_i64(&D.ctr[CTR_GAIN], gain_acc);
-    if (D.mode != LV_SYNC) atomic_add_i64(&D.ctr[CTR_MOVERS], moved);
+  flush_totals(D, gain_acc, moved, marcs);
+}
+
+// --------------------------------------------------------------------------
+// Rows up to kBlockMaxDegree: one workgroup, LDS table of 4096 slots.
+// --------------------------------------------------------------------------
+constexpr int kBlockTS = 2 * kBlockMaxDegree;
+
+__device__ __forceinline__ void block_argmax(int64_t& bg, int32_t& bc, int64_t* r_g, int32_t* r_c) {
+  for (int s = 1; s < kWave; s <<= 1) {
+    const int64_t og = __shfl_xor(bg, s);
+    const int32_t oc = __shfl_xor(bc, s);
+    if (better(og, oc, bg, bc)) {
+      bg = og;
+      bc = oc;
+    }
   }
+  const int wid = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    r_g[wid] = bg;
+    r_c[wid] = bc;
+  }
+  __syncthreads();
+  for (int t = 0; t < kBlock / kWave; ++t)
+    if (better(r_g[t], r_c[t], bg, bc)) {
+      bg = r_g[t];
+      bc = r_c[t];
+    }
 }
 
-// --------------------------------------------------------------------------
-// Long rows: one workgroup, global-memory table of 2*deg slots.
-// --------------------------------------------------------------------------
-__device__ __forceinline__ int32_t ld_relaxed(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* r) {
+  v = wave_sum_i64(v);
+  if (lane_id() == 0) r[threadIdx.x / kWave] = v;
+  __syncthreads();
+  int64_t s = 0;
+  for (int t = 0; t < kBlock / kWave; ++t) s += r[t];
+  return s;
 }
 
-__global__ void __launch_bounds__(kBlock) k_move_hub(Dev D, const int32_t* __restrict__ list,
-                                                    const int64_t* __restrict__ hub_off,
-                                                    int32_t* __restrict__ pool_keys,
-                                                    int32_t* __restrict__ pool_vals, int64_t pool_slots) {
+__global__ void __launch_bounds__(kBlock) k_move_block(Dev D, const int32_t* __restrict__ list) {
+  __shared__ int32_t keys[kBlockTS];
+  __shared__ int32_t vals[kBlockTS];
   __shared__ int64_t r_g[kBlock / kWave];
   __shared__ int32_t r_c[kBlock / kWave];
-  __shared__ int32_t r_k[kBlock / kWave];
-  const int64_t count = D.ctr[CTR_BIN0 + BIN_HUB];
-  const int lane = lane_id();
-  const int wid = threadIdx.x / kWave;
-  int64_t gain_acc = 0, moved = 0;
+  __shared__ int64_t r_s[kBlock / kWave];
+  const int64_t count = D.ctr[CTR_BIN0 + BIN_BLOCK];
+  int64_t gain_acc = 0, moved = 0, marcs = 0;
   for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
     const int32_t i = list[idx];
     const int64_t start = D.row_start[i];
     const int32_t deg = D.row_len[i];
     const int32_t d = D.C[i];
-    const uint32_t tsz = 2u * static_cast<uint32_t>(deg);
-    if (hub_off[idx] + tsz > pool_slots) {  // cannot happen with the workspace bound; never write past it
-      if (threadIdx.x == 0) set_error(D.ctr, LV_EWORKSPACE);
-      continue;
-    }
-    int32_t* keys = pool_keys + hub_off[idx];
-    int32_t* vals = pool_vals + hub_off[idx];
-    for (uint32_t t = threadIdx.x; t < tsz; t += kBlock) {
+    const uint32_t ts = max(256u, 1u << (32 - __clz(static_cast<uint32_t>(2 * deg - 1))));
+    for (uint32_t t = threadIdx.x; t < ts; t += kBlock) {
       keys[t] = -1;
       vals[t] = 0;
     }
-    __threadfence_block();
     __syncthreads();
-    int32_t kid = 0;
+    int64_t kid = 0;
     for (int32_t k = threadIdx.x; k < deg; k += kBlock) {
       const int32_t j = D.col[start + k];
       const int32_t x = D.wt[start + k];
@@ -413,36 +496,217 @@ __global__ void __launch_bounds__(kBlock) k_move_hub(Dev D, const int32_t* __res
         kid += x;
         continue;
       }
-      uint32_t h = hash_slot(static_cast<uint32_t>(c), tsz);
+      uint32_t h = hash_slot(static_cast<uint32_t>(c), ts);
       while (true) {
         const int32_t old = atomicCAS(&keys[h], -1, c);
         if (old == -1 || old == c) {
           atomicAdd(&vals[h], x);
           break;
         }
-        h = (h + 1 == tsz) ? 0 : h + 1;
+        h = (h + 1) & (ts - 1);
       }
     }
-    kid = wave_sum_i32(kid);
-    if (lane == 0) r_k[wid] = kid;
-    __threadfence_block();
-    __syncthreads();
-    kid = 0;
-    for (int t = 0; t < kBlock / kWave; ++t) kid += r_k[t];
+    kid = block_sum(kid, r_s);
     const int64_t Ki = D.K[i];
     const int64_t Sd = D.Sigma[d];
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
-    for (uint32_t t = threadIdx.x; t < tsz; t += kBlock) {
-      const int32_t c = ld_relaxed(&keys[t]);
+    for (uint32_t t = threadIdx.x; t < ts; t += kBlock) {
+      const int32_t c = keys[t];
       if (c >= 0) {
-        const int64_t g = gain_of(D.two_m, ld_relaxed(&vals[t]), kid, Ki, D.Sigma[c], Sd);
+        const int64_t g = gain_of(D.two_m, vals[t], kid, Ki, D.Sigma[c], Sd);
         if (better(g, c, bg, bc)) {
           bg = g;
           bc = c;
         }
       }
     }
+    block_argmax(bg, bc, r_g, r_c);
+    if (decide_move(D, d, bc, bg)) {
+      if (threadIdx.x == 0) {
+        commit_move(D, i, d, bc, Ki);
+        gain_acc += bg;
+        moved += 1;
+        marcs += deg;
+      }
+      for (int32_t k = threadIdx.x; k < deg; k += kBlock) {
+        const int32_t j = D.col[start + k];
+        if (j != i) set_bit(D.next, j);
+      }
+    }
+    __syncthreads();
+  }
+  flush_totals(D, gain_acc, moved, marcs);
+}
+
+// --------------------------------------------------------------------------
+// Hub rows: clear, insert (units), argmax (one workgroup per hub), expand.
+// --------------------------------------------------------------------------
+constexpr int kHubTS = 4096;     // LDS pre-aggregation slots per unit
+constexpr int kHubProbes = 8;
+
+__device__ __forceinline__ void gtable_add(int32_t* keys, int32_t* vals, uint32_t tsz, int32_t c, int32_t x) {
+  uint32_t h = hash_slot(static_cast<uint32_t>(c), tsz);
+  while (true) {
+    const int32_t old = atomicCAS(&keys[h], -1, c);
+    if (old == -1 || old == c) {
+      atomicAdd(&vals[h], x);
+      return;
+    }
+    h = (h + 1 == tsz) ? 0 : h + 1;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_hub_clear(Dev D, const int32_t* __restrict__ list,
+                                                     const int64_t* __restrict__ hub_off,
+                                                     const int32_t* __restrict__ c_b, const int64_t* __restrict__ c_s,
+                                                     int32_t* __restrict__ keys, int32_t* __restrict__ vals,
+                                                     int64_t* __restrict__ hub_kid, int32_t* __restrict__ hub_moved,
+                                                     int64_t pool_slots) {
+  const int64_t count = D.ctr[CTR_HUB_CUNITS];
+  for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
+    const int32_t h = c_b[u];
+    const int64_t tsz = 2 * static_cast<int64_t>(D.row_len[list[h]]);
+    const int64_t off = hub_off[h];
+    if (off + tsz > pool_slots) continue;  // reported by the insert kernel
+    if (c_s[u] == 0 && threadIdx.x == 0) {
+      hub_kid[h] = 0;
+      hub_moved[h] = 0;
+    }
+    const int64_t s1 = min(tsz, c_s[u] + kHubClearSlots);
+    for (int64_t s = c_s[u] + threadIdx.x; s < s1; s += kBlock) {
+      keys[off + s] = -1;
+      vals[off + s] = 0;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_hub_insert(Dev D, const int32_t* __restrict__ list,
+                                                      const int64_t* __restrict__ hub_off,
+                                                      const int32_t* __restrict__ u_b, const int64_t* __restrict__ u_a,
+                                                      int32_t* __restrict__ keys, int32_t* __restrict__ vals,
+                                                      int64_t* __restrict__ hub_kid, int64_t pool_slots) {
+  __shared__ int32_t tk[kHubTS];
+  __shared__ int32_t tv[kHubTS];
+  __shared__ int64_t r_s[kBlock / kWave];
+  const int64_t count = D.ctr[CTR_HUB_UNITS];
+  for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
+    const int32_t h = u_b[u];
+    const int32_t i = list[h];
+    const int64_t start = D.row_start[i];
+    const int32_t deg = D.row_len[i];
+    const int32_t d = D.C[i];
+    const uint32_t tsz = 2u * static_cast<uint32_t>(deg);
+    const int64_t off = hub_off[h];
+    if (off + static_cast<int64_t>(tsz) > pool_slots) {
+      if (threadIdx.x == 0) set_error(D.ctr, LV_EWORKSPACE);
+      continue;
+    }
+    for (int s = threadIdx.x; s < kHubTS; s += kBlock) {
+      tk[s] = -1;
+      tv[s] = 0;
+    }
+    __syncthreads();
+    const int64_t a1 = min(static_cast<int64_t>(deg), u_a[u] + kHubUnitArcs);
+    int64_t kid = 0;
+    for (int64_t a = u_a[u] + threadIdx.x; a < a1; a += kBlock) {
+      const int32_t j = D.col[start + a];
+      const int32_t x = D.wt[start + a];
+      if (j == i) continue;
+      const int32_t c = D.C[j];
+      if (c == d) {
+        kid += x;
+        continue;
+      }
+      uint32_t q = hash_slot(static_cast<uint32_t>(c), kHubTS);
+      bool done = false;
+      for (int p = 0; p < kHubProbes; ++p) {
+        const int32_t old = atomicCAS(&tk[q], -1, c);
+        if (old == -1 || old == c) {
+          atomicAdd(&tv[q], x);
+          done = true;
+          break;
+        }
+        q = (q + 1) & (kHubTS - 1);
+      }
+      if (!done) gtable_add(keys + off, vals + off, tsz, c, x);
+    }
+    kid = block_sum(kid, r_s);
+    if (threadIdx.x == 0 && kid) atomic_add_i64(&hub_kid[h], kid);
+    for (int s = threadIdx.x; s < kHubTS; s += kBlock)
+      if (tk[s] >= 0) gtable_add(keys + off, vals + off, tsz, tk[s], tv[s]);
+    __syncthreads();
+  }
+}
+
+// best (gain, community) of each table-slot unit of a hub table
+__global__ void __launch_bounds__(kBlock) k_hub_decide_units(Dev D, const int32_t* __restrict__ list,
+                                                            const int64_t* __restrict__ hub_off,
+                                                            const int32_t* __restrict__ c_b,
+                                                            const int64_t* __restrict__ c_s,
+                                                            const int32_t* __restrict__ keys,
+                                                            const int32_t* __restrict__ vals,
+                                                            const int64_t* __restrict__ hub_kid,
+                                                            int64_t* __restrict__ unit_g, int32_t* __restrict__ unit_c,
+                                                            int64_t pool_slots) {
+  __shared__ int64_t r_g[kBlock / kWave];
+  __shared__ int32_t r_c[kBlock / kWave];
+  const int64_t count = D.ctr[CTR_HUB_CUNITS];
+  for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
+    const int32_t h = c_b[u];
+    const int32_t i = list[h];
+    const int32_t d = D.C[i];
+    const int64_t tsz = 2 * static_cast<int64_t>(D.row_len[i]);
+    const int64_t off = hub_off[h];
+    int64_t bg = LLONG_MIN;
+    int32_t bc = INT_MAX;
+    if (off + tsz <= pool_slots) {
+      const int64_t kid = hub_kid[h];
+      const int64_t Ki = D.K[i];
+      const int64_t Sd = D.Sigma[d];
+      const int64_t s1 = min(tsz, c_s[u] + kHubClearSlots);
+      for (int64_t t = c_s[u] + threadIdx.x; t < s1; t += kBlock) {
+        const int32_t c = keys[off + t];
+        if (c >= 0) {
+          const int64_t g = gain_of(D.two_m, vals[off + t], kid, Ki, D.Sigma[c], Sd);
+          if (better(g, c, bg, bc)) {
+            bg = g;
+            bc = c;
+          }
+        }
+      }
+    }
+    block_argmax(bg, bc, r_g, r_c);
+    if (threadIdx.x == 0) {
+      unit_g[u] = bg;
+      unit_c[u] = bc;
+    }
+    __syncthreads();
+  }
+}
+
+// one wavefront per hub: best over its units, then the move decision
+__global__ void __launch_bounds__(kBlock) k_hub_final(Dev D, const int32_t* __restrict__ list,
+                                                     const int64_t* __restrict__ hub_cbase,
+                                                     const int32_t* __restrict__ hub_cnum,
+                                                     const int64_t* __restrict__ unit_g,
+                                                     const int32_t* __restrict__ unit_c,
+                                                     int32_t* __restrict__ hub_moved) {
+  const int64_t count = D.ctr[CTR_BIN0 + BIN_HUB];
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+  int64_t gain_acc = 0, moved = 0, marcs = 0;
+  for (int64_t h = wave; h < count; h += nwaves) {
+    const int64_t b0 = hub_cbase[h];
+    const int32_t nu = hub_cnum[h];
+    int64_t bg = LLONG_MIN;
+    int32_t bc = INT_MAX;
+    for (int32_t t = lane; t < nu; t += kWave)
+      if (better(unit_g[b0 + t], unit_c[b0 + t], bg, bc)) {
+        bg = unit_g[b0 + t];
+        bc = unit_c[b0 + t];
+      }
     for (int s = 1; s < kWave; s <<= 1) {
       const int64_t og = __shfl_xor(bg, s);
       const int32_t oc = __shfl_xor(bc, s);
@@ -452,39 +716,35 @@ __global__ void __launch_bounds__(kBlock) k_move_hub(Dev D, const int32_t* __res
       }
     }
     if (lane == 0) {
-      r_g[wid] = bg;
-      r_c[wid] = bc;
-    }
-    __syncthreads();
-    for (int t = 0; t < kBlock / kWave; ++t)
-      if (better(r_g[t], r_c[t], bg, bc)) {
-        bg = r_g[t];
-        bc = r_c[t];
-      }
-    const bool mv = decide_move(D, d, bc, bg);
-    if (mv) {
-      if (threadIdx.x == 0) {
-        if (D.mode == LV_SYNC) {
-          const int64_t pos = static_cast<int64_t>(
-              atomicAdd(reinterpret_cast<unsigned long long*>(&D.ctr[CTR_MOVERS]), 1ull));
-          D.mv_v[pos] = i;
-          D.mv_c[pos] = bc;
-        } else {
-          apply_now(D, i, d, bc, Ki);
-        }
+      const int32_t i = list[h];
+      const int32_t d = D.C[i];
+      const bool mv = decide_move(D, d, bc, bg);
+      hub_moved[h] = mv ? 1 : 0;
+      if (mv) {
+        commit_move(D, i, d, bc, D.K[i]);
         gain_acc += bg;
         moved += 1;
-      }
-      for (int32_t k = threadIdx.x; k < deg; k += kBlock) {
-        const int32_t j = D.col[start + k];
-        if (j != i) set_bit(D.next, j);
+        marcs += D.row_len[i];
       }
     }
-    __syncthreads();
   }
-  if (threadIdx.x == 0 && moved) {
-    atomic_add_i64(&D.ctr[CTR_GAIN], gain_acc);
-    if (D.mode != LV_SYNC) atomic_add_i64(&D.ctr[CTR_MOVERS], moved);
+  flush_totals(D, gain_acc, moved, marcs);
+}
+
+__global__ void __launch_bounds__(kBlock) k_hub_expand(Dev D, const int32_t* __restrict__ list,
+                                                      const int32_t* __restrict__ u_b, const int64_t* __restrict__ u_a,
+                                                      const int32_t* __restrict__ hub_moved) {
+  const int64_t count = D.ctr[CTR_HUB_UNITS];
+  for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
+    const int32_t h = u_b[u];
+    if (!hub_moved[h]) continue;
+    const int32_t i = list[h];
+    const int64_t start = D.row_start[i];
+    const int64_t a1 = min(static_cast<int64_t>(D.row_len[i]), u_a[u] + kHubUnitArcs);
+    for (int64_t a = u_a[u] + threadIdx.x; a < a1; a += kBlock) {
+      const int32_t j = D.col[start + a];
+      if (j != i) set_bit(D.next, j);
+    }
   }
 }
 
@@ -524,9 +784,11 @@ int table_slots_for(int wave_max) {
 void launch_bin_frontier(const MoveArgs& a, Workspace& ws, int round, int rounds_log2, hipStream_t st) {
   const int64_t words = (static_cast<int64_t>(a.g.n) + 31) / 32;
   const uint32_t shift = rounds_log2 > 0 ? 32u - static_cast<uint32_t>(rounds_log2) : 32u;
-  hipLaunchKernelGGL(k_bin_frontier, dim3(grid_for(words, kBlock, 4096)), dim3(kBlock), 0, st, a.cur,
-                     a.range, a.ever, a.g.row_len, a.g.n, a.wave_max, static_cast<uint32_t>(round), shift,
-                     ws.bins[0], ws.bins[1], ws.bins[2], ws.bins[3], ws.bins[4], ws.bins[5], ws.hub_off, ws.ctr);
+  Bins b;
+  for (int k = 0; k < NBINS; ++k) b.list[k] = ws.bins[k];
+  HubOut H{ws.hub_off, ws.hub_cbase, ws.hub_cnum, ws.u_ins_b, ws.u_ins_a, ws.u_emit_b, ws.u_emit_s};
+  hipLaunchKernelGGL(k_bin_frontier, dim3(grid_for(words, kBlock, 4096)), dim3(kBlock), 0, st, a.cur, a.range,
+                     a.ever, a.g.row_len, a.g.n, a.wave_max, static_cast<uint32_t>(round), shift, b, H, ws.ctr);
 }
 
 void launch_move(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, hipStream_t st) {
@@ -545,13 +807,24 @@ void launch_move(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, hipStrea
     hipLaunchKernelGGL(k_move_wave<512>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
   else
     hipLaunchKernelGGL(k_move_wave<1024>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
-  hipLaunchKernelGGL(k_move_hub, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off,
-                     ws.pool_keys, ws.pool_vals, ws.pool_slots);
+  hipLaunchKernelGGL(k_move_block, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_BLOCK]);
+  // hub rows
+  hipLaunchKernelGGL(k_hub_clear, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off, ws.u_emit_b,
+                     ws.u_emit_s, ws.pool_keys, ws.pool_vals, ws.hub_kid, ws.hub_moved, ws.pool_slots);
+  hipLaunchKernelGGL(k_hub_insert, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off, ws.u_ins_b,
+                     ws.u_ins_a, ws.pool_keys, ws.pool_vals, ws.hub_kid, ws.pool_slots);
+  hipLaunchKernelGGL(k_hub_decide_units, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off,
+                     ws.u_emit_b, ws.u_emit_s, ws.pool_keys, ws.pool_vals, ws.hub_kid, ws.unit_g, ws.unit_c,
+                     ws.pool_slots);
+  hipLaunchKernelGGL(k_hub_final, dim3(64), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_cbase, ws.hub_cnum,
+                     ws.unit_g, ws.unit_c, ws.hub_moved);
+  hipLaunchKernelGGL(k_hub_expand, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.u_ins_b, ws.u_ins_a,
+                     ws.hub_moved);
 }
 
 void launch_apply_moves(const MoveArgs& a, Workspace& ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_apply_moves, dim3(grid_for(a.g.n, kBlock, 2048)), dim3(kBlock), 0, st, a.C, a.K,
-                     a.Sigma, a.size, ws.mv_v, ws.mv_c, ws.ctr);
+  hipLaunchKernelGGL(k_apply_moves, dim3(grid_for(a.g.n, kBlock, 2048)), dim3(kBlock), 0, st, a.C, a.K, a.Sigma,
+                     a.size, ws.mv_v, ws.mv_c, ws.ctr);
 }
 
 }  // namespace lv

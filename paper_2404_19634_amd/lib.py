@@ -80,7 +80,8 @@ class Stats(ct.Structure):
 
 class Tuning(ct.Structure):
     _fields_ = [("wave_max_degree", ct.c_int32), ("blocks_small", ct.c_int32), ("blocks_wave", ct.c_int32),
-                ("blocks_hub", ct.c_int32), ("async_rounds_log2", ct.c_int32)]
+                ("blocks_hub", ct.c_int32), ("async_rounds_log2", ct.c_int32),
+                ("async_rounds_min_frontier", ct.c_int32)]
 
 
 _lib = None
@@ -149,10 +150,14 @@ def params(tolerance=1e-2, tolerance_drop=10.0, aggregation_tolerance=0.8, max_i
 DEFAULT_ASYNC_ROUNDS_LOG2 = 3
 
 
+DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER = 4096
+
+
 def set_tuning(wave_max_degree=0, blocks_small=0, blocks_wave=0, blocks_hub=0,
-               async_rounds_log2=DEFAULT_ASYNC_ROUNDS_LOG2):
+               async_rounds_log2=DEFAULT_ASYNC_ROUNDS_LOG2,
+               async_rounds_min_frontier=DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER):
     load().lv_set_tuning(ct.byref(Tuning(wave_max_degree, blocks_small, blocks_wave, blocks_hub,
-                                         async_rounds_log2)))
+                                         async_rounds_log2, async_rounds_min_frontier)))
 
 
 def get_tuning() -> dict:
