@@ -76,6 +76,30 @@ def cpu_baseline(e, batch, budget_s=30.0):
     return res
 
 
+def sweep(g, e, runs):
+    """One SYNC local-moving iteration over every vertex from singletons,
+    `runs` times (the kernels a full sweep launches, for rocprofv3), then a
+    plain 1 GiB device-to-device copy whose counters calibrate FETCH_SIZE
+    and WRITE_SIZE."""
+    import torch
+    from paper_2404_19634_amd import lib
+    prm = lib.params(mode="sync", max_iterations=1, max_passes=1)
+    st = lib.State.empty(e.n, g.device)
+    for r in range(runs):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, s = lib.louvain_static(g, prm, st)
+        torch.cuda.synchronize()
+        log(f"sweep {r}: {1e3 * (time.perf_counter() - t):.3f} ms, arcs {s['arcs_scanned']}, "
+            f"moves {s['moves']}, ms_move {s['ms_move']:.3f}")
+    x = torch.empty(1 << 28, dtype=torch.int32, device=g.device).fill_(1)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    log("copy: 1 GiB read + 1 GiB written")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +109,9 @@ def main():
     ap.add_argument("--mode", default="async", choices=["async", "sync"])
     ap.add_argument("--static-runs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", type=int, default=0,
+                    help="profiling mode: run this many single full local-moving sweeps (SYNC, all vertices "
+                         "from singletons) and one 1 GiB device copy for counter calibration, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the single-GPU line is the result",
@@ -106,9 +133,12 @@ def main():
     total = args.warmup + args.steps
     batches = make_batches(e, sizes, total, seed=4242)
     dbatches = [lib.Batch.from_host(b, dev) for b in batches]
-    g = lib.Graph.from_edges(e, slack_frac=0.1, slack_min=4)
+    g = lib.Graph.from_edges(e, slack_frac=0.1, slack_min=8)
     prm = lib.params(mode=args.mode)
     torch.cuda.synchronize()
+    if args.sweep:
+        sweep(g, e, args.sweep)
+        return
 
     # GPU static Louvain on the initial graph (comparison baseline)
     static_ms, static_arcs, static_stats = [], [], None
@@ -131,6 +161,7 @@ def main():
     # DF steps
     state = state0.clone()
     lat, apply_ms, arcs, per_size = [], [], [], {}
+    relayouts = 0
     torch.cuda.synchronize()
     for k in range(total):
         if k == args.warmup:
@@ -138,7 +169,14 @@ def main():
             t_region = time.perf_counter()
         b = dbatches[k]
         t = time.perf_counter()
-        lib.apply_batch(g, b)
+        try:
+            lib.apply_batch(g, b)
+        except lib.LouvainError as ex:  # a row ran out of slack: re-lay out, retry
+            if ex.code != lib.LV_ENOSLACK:
+                raise
+            g = g.relayout(slack_frac=0.5, slack_min=16)
+            relayouts += 1
+            lib.apply_batch(g, b)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         state, s = lib.louvain_df(g, b, state, prm)
@@ -185,6 +223,7 @@ def main():
         "df_latency_ms_p99": pct(lat, 99),
         "df_latency_ms_by_batch_size": {str(k): float(np.median(v)) for k, v in sorted(per_size.items())},
         "apply_batch_ms_p50": pct(apply_ms, 50),
+        "relayouts": relayouts,
         "df_edges_scanned_per_s": df_arcs / (np.sum(lat) / 1e3),
         "static_latency_ms": float(np.median(static_ms)),
         "static_edges_scanned_per_s": static_eps,

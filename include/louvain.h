@@ -130,6 +130,8 @@ typedef struct {
   int32_t blocks_hub;        /* persistent grid size of the workgroup kernel */
   int32_t async_rounds_log2; /* LV_ASYNC: each iteration runs 2^k hash-partitioned sub-rounds */
   int32_t async_rounds_min_frontier; /* ... when the frontier may exceed this many vertices */
+  int32_t async_round_order; /* sub-rounds by 0: hash of the vertex id; 1: contiguous id ranges;
+                                2: degree classes (highest first), hashed within a class */
 } lv_tuning;
 
 /* The paper's parameter values (Section 5.1.2). */

@@ -10,7 +10,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "lv_internal.hpp"
 
@@ -18,7 +20,7 @@ namespace lv {
 namespace {
 
 thread_local std::string g_last_error;
-lv_tuning g_tuning = {256, 2048, 2048, 512, 3, 4096};
+lv_tuning g_tuning = {256, 2048, 2560, 1280, 7, 4096, 2};
 
 lv_status fail(lv_status code, const char* msg) {
   g_last_error = msg;
@@ -131,15 +133,79 @@ lv_tuning effective_tuning() {
   if (t.wave_max_degree < 32) t.wave_max_degree = 32;
   if (t.wave_max_degree > kWaveTableMaxDegree) t.wave_max_degree = kWaveTableMaxDegree;
   if (t.blocks_small <= 0) t.blocks_small = 2048;
-  if (t.blocks_wave <= 0) t.blocks_wave = 2048;
-  if (t.blocks_hub <= 0) t.blocks_hub = 512;
+  if (t.blocks_wave <= 0) t.blocks_wave = 2560;
+  if (t.blocks_hub <= 0) t.blocks_hub = 1280;
   if (t.async_rounds_log2 < 0) t.async_rounds_log2 = 0;
-  if (t.async_rounds_log2 > 5) t.async_rounds_log2 = 5;
+  if (t.async_rounds_log2 > 7) t.async_rounds_log2 = 7;
+  if (t.async_round_order < 0 || t.async_round_order > 2) t.async_round_order = 0;
   if (t.async_rounds_min_frontier < 0) t.async_rounds_min_frontier = 0;
   return t;
 }
 
 enum Approach { A_STATIC, A_ND, A_DS, A_DF };
+
+// The sub-rounds of one ASYNC iteration.  Splitting the frontier lets a
+// vertex see most of its neighbours' moves (the paper's loop is nearly
+// sequential per thread); SYNC and small frontiers run one round.
+//  - level 0 (the input graph), order 2: four degree classes, highest
+//    first, each hashed into 2^(k-2) rounds, so hubs settle before the many
+//    low-degree vertices that hang off them;
+//  - order 0 / 1: 2^k rounds by id hash / by contiguous id ranges;
+//  - super-vertex levels (dense): 2^min(k, 4) rounds by id hash.
+std::vector<SubRound> sub_rounds(int32_t mode, int32_t pass, int64_t est_frontier, int32_t n, const lv_tuning& tu) {
+  std::vector<SubRound> out;
+  SubRound all;
+  all.id_hi = n;
+  const bool split = mode == LV_ASYNC && (pass > 0 || est_frontier > tu.async_rounds_min_frontier);
+  if (!split || tu.async_rounds_log2 <= 0) {
+    out.push_back(all);
+    return out;
+  }
+  // conflicts scale with the frontier's density: a sparse frontier (small
+  // DF batches) has few adjacent members, so it gets proportionally fewer
+  // rounds (2^k for a full sweep)
+  int k = tu.async_rounds_log2;
+  const double density = n > 0 ? static_cast<double>(std::min<int64_t>(est_frontier, n)) / n : 1.0;
+  while (k > 0 && static_cast<double>(int64_t(1) << tu.async_rounds_log2) * density < static_cast<double>(int64_t(1) << k))
+    --k;
+  if (k <= 0) {
+    out.push_back(all);
+    return out;
+  }
+  if (pass > 0 || tu.async_round_order == 0 || (tu.async_round_order == 2 && k < 2)) {
+    const int kk = pass > 0 ? std::min(k, 4) : k;
+    for (int r = 0; r < (1 << kk); ++r) {
+      SubRound s = all;
+      s.hash_round = static_cast<uint32_t>(r);
+      s.hash_shift = 32u - static_cast<uint32_t>(kk);
+      out.push_back(s);
+    }
+  } else if (tu.async_round_order == 1) {
+    const int64_t R = int64_t(1) << k;
+    for (int64_t r = 0; r < R; ++r) {
+      SubRound s = all;
+      s.id_lo = static_cast<int32_t>(n * r / R);
+      s.id_hi = static_cast<int32_t>(n * (r + 1) / R);
+      out.push_back(s);
+    }
+  } else {
+    static const int32_t cls_lo[4] = {1025, 129, 17, 0};
+    static const int32_t cls_hi[4] = {0x7fffffff, 1024, 128, 16};
+    const int kh = k - 2;
+    for (int c = 0; c < 4; ++c)
+      for (int r = 0; r < (1 << kh); ++r) {
+        SubRound s = all;
+        s.deg_lo = cls_lo[c];
+        s.deg_hi = cls_hi[c];
+        if (kh > 0) {
+          s.hash_round = static_cast<uint32_t>(r);
+          s.hash_shift = 32u - static_cast<uint32_t>(kh);
+        }
+        out.push_back(s);
+      }
+  }
+  return out;
+}
 
 struct DsTables {
   uint64_t* keys;
@@ -321,18 +387,26 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     for (int32_t it = 0; it < p->max_iterations; ++it) {
       a.cur = cur;
       a.next = next;
+      a.est = est_frontier;
+      // large frontiers pull the next frontier (reads) instead of pushing it
+      // (one atomic per arc of every mover)
+      const bool pull = est_frontier > L.n / 4;
+      a.push = pull ? 0 : 1;
+      a.moved = (pull || p->mode == LV_SYNC) ? ws.moved : nullptr;
       LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_ITER_END, st));
-      // sub-rounds pay off when many vertices decide at once, and always on
-      // super-vertex levels, whose graphs are dense
-      const bool rounds = pass > 0 || est_frontier > tu.async_rounds_min_frontier;
-      const int rl2 = (p->mode == LV_ASYNC && rounds) ? tu.async_rounds_log2 : 0;
-      for (int r = 0; r < (1 << rl2); ++r) {
+      if (a.moved) LV_HIP(hipMemsetAsync(ws.moved, 0, sizeof(uint32_t) * words_l, st));
+      const std::vector<SubRound> plan = sub_rounds(p->mode, pass, est_frontier, L.n, tu);
+      // a sub-round holds at most about 4 / rounds of the frontier (four
+      // degree classes); grids are sized for that
+      a.est = std::max<int64_t>(64, est_frontier * 4 / static_cast<int64_t>(plan.size()));
+      for (size_t r = 0; r < plan.size(); ++r) {
         if (r > 0)  // fresh bin counts, unit counts and table pool for the sub-round
           LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_ROUND_END, st));
-        launch_bin_frontier(a, ws, r, rl2, st);
-        launch_move(a, ws, tu, st);
+        launch_bin_frontier(a, ws, plan[r], st);
+        launch_move(a, ws, tu, bins_for_degrees(plan[r].deg_lo, plan[r].deg_hi, a.wave_max), st);
       }
       if (p->mode == LV_SYNC) launch_apply_moves(a, ws, st);
+      if (pull) launch_pull_expand(a, ws, st);
       LV_CHECK_LAUNCH();
       LV_HIP(hipMemsetAsync(cur, 0, sizeof(uint32_t) * words_l, st));
       std::swap(cur, next);
@@ -432,13 +506,13 @@ size_t carve_workspace(Workspace& ws, void* base, int32_t n, int64_t cap) {
   ws.range = take<uint32_t>(cur, total, base, ws.words);
   ws.dE = take<uint32_t>(cur, total, base, ws.words);
   ws.dC = take<uint32_t>(cur, total, base, ws.words);
+  ws.moved = take<uint32_t>(cur, total, base, ws.words);
   for (int b = 0; b < NBINS; ++b) ws.bins[b] = take<int32_t>(cur, total, base, un);
   ws.hub_off = take<int64_t>(cur, total, base, un);
   ws.hub_kid = take<int64_t>(cur, total, base, un);
   ws.hub_moved = take<int32_t>(cur, total, base, un);
   ws.hub_cbase = take<int64_t>(cur, total, base, un);
   ws.hub_cnum = take<int32_t>(cur, total, base, un);
-  ws.mv_v = take<int32_t>(cur, total, base, un);
   ws.mv_c = take<int32_t>(cur, total, base, un);
   ws.size = take<int32_t>(cur, total, base, un);
   ws.lC = take<int32_t>(cur, total, base, un);

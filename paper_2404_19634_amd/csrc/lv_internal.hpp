@@ -73,6 +73,7 @@ struct Workspace {
   uint32_t* range = nullptr;  // DS affected range
   uint32_t* dE = nullptr;     // DS: neighbours-affected flags
   uint32_t* dC = nullptr;     // DS: community-affected flags
+  uint32_t* moved = nullptr;  // vertices moved in this iteration (pull expansion)
   int32_t* bins[NBINS] = {};
   int64_t* hub_off = nullptr;  // global-table offset of each hub item
   int64_t* hub_kid = nullptr;  // hub items: weight into the vertex's own community
@@ -81,8 +82,7 @@ struct Workspace {
   int32_t* hub_cnum = nullptr;
   int64_t* unit_g = nullptr;     // per table-slot unit: best gain and community
   int32_t* unit_c = nullptr;
-  int32_t* mv_v = nullptr;     // sync movers: vertex, target community
-  int32_t* mv_c = nullptr;
+  int32_t* mv_c = nullptr;     // SYNC: target community of each mover (by vertex)
   int32_t* size = nullptr;     // community sizes (swap guard)
   int32_t* lC = nullptr;       // level >= 1 membership, weights, totals
   int64_t* lK = nullptr;
@@ -249,14 +249,29 @@ struct MoveArgs {
   uint32_t* next;
   const uint32_t* range;  // nullptr: every vertex in range
   uint32_t* ever;         // nullptr: not tracked
+  uint32_t* moved;        // movers bitmask (SYNC always; ASYNC when pulling)
+  int32_t push;           // 1: movers push the next frontier; 0: it is pulled afterwards
   int64_t two_m;
+  int64_t est;            // upper bound of the vertices processed (grid sizes)
   int32_t mode;
   int32_t guard;
   int32_t wave_max;
 };
-void launch_bin_frontier(const MoveArgs& a, Workspace& ws, int round, int rounds_log2, hipStream_t st);
-void launch_move(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, hipStream_t st);
+// One ASYNC sub-round: vertices whose id hash matches (hash_shift = 32: all),
+// ids in [id_lo, id_hi), row lengths in [deg_lo, deg_hi].
+struct SubRound {
+  uint32_t hash_round = 0;
+  uint32_t hash_shift = 32;
+  int32_t id_lo = 0;
+  int32_t id_hi = 0;
+  int32_t deg_lo = 0;
+  int32_t deg_hi = 0x7fffffff;
+};
+void launch_bin_frontier(const MoveArgs& a, Workspace& ws, const SubRound& r, hipStream_t st);
+uint32_t bins_for_degrees(int32_t lo, int32_t hi, int32_t wave_max);
+void launch_move(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, uint32_t bin_mask, hipStream_t st);
 void launch_apply_moves(const MoveArgs& a, Workspace& ws, hipStream_t st);
+void launch_pull_expand(const MoveArgs& a, Workspace& ws, hipStream_t st);
 
 // aggregate.hip
 void launch_mark_exists(const int32_t* C, int32_t n, int32_t* flags, hipStream_t st);

@@ -44,8 +44,9 @@ struct Dev {
   int64_t* Sigma;
   int32_t* size;
   uint32_t* next;
-  int32_t* mv_v;
+  uint32_t* moved;
   int32_t* mv_c;
+  int32_t push;
   int64_t* ctr;
   int64_t two_m;
   int32_t mode;
@@ -63,8 +64,9 @@ Dev make_dev(const MoveArgs& a, Workspace& ws) {
   d.Sigma = a.Sigma;
   d.size = a.size;
   d.next = a.next;
-  d.mv_v = ws.mv_v;
+  d.moved = a.moved;
   d.mv_c = ws.mv_c;
+  d.push = a.push;
   d.ctr = ws.ctr;
   d.two_m = a.two_m;
   d.mode = a.mode;
@@ -89,13 +91,13 @@ __device__ __forceinline__ bool decide_move(const Dev& D, int32_t d, int32_t c, 
   return true;
 }
 
-// Records (SYNC) or applies (ASYNC) one move -- one lane per mover.
+// Records (SYNC: target by vertex plus the movers bitmask) or applies
+// (ASYNC) one move -- one lane per mover.  Nothing here waits on a shared
+// counter.
 __device__ __forceinline__ void commit_move(const Dev& D, int32_t i, int32_t d, int32_t c, int64_t Ki) {
+  if (D.moved) set_bit(D.moved, i);
   if (D.mode == LV_SYNC) {
-    const int64_t pos =
-        static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&D.ctr[CTR_MOVERS]), 1ull));
-    D.mv_v[pos] = i;
-    D.mv_c[pos] = c;
+    D.mv_c[i] = c;
     return;
   }
   D.C[i] = c;
@@ -115,14 +117,14 @@ __device__ __forceinline__ void flush_totals(const Dev& D, int64_t gain, int64_t
   if (lane_id() == 0 && moved) {
     atomic_add_i64(&D.ctr[CTR_GAIN], gain);
     atomic_add_i64(&D.ctr[CTR_EXPAND], arcs);
-    if (D.mode != LV_SYNC) atomic_add_i64(&D.ctr[CTR_MOVERS], moved);
+    atomic_add_i64(&D.ctr[CTR_MOVERS], moved);
   }
 }
 
 // Vertices of word k that belong to sub-round `round` (ASYNC mode splits
 // each iteration into 2^(32 - shift) sub-rounds by a multiplicative hash of
-// the vertex id, so that a vertex sees most neighbours' moves already
-// applied; shift = 32 means a single round).
+// the vertex id, or by contiguous id ranges, so that a vertex sees most
+// neighbours' moves already applied; shift = 32 means a single round).
 __device__ __forceinline__ uint32_t round_mask(uint32_t k, uint32_t round, uint32_t shift) {
   uint32_t m = 0;
 #pragma unroll 8
@@ -131,6 +133,17 @@ __device__ __forceinline__ uint32_t round_mask(uint32_t k, uint32_t round, uint3
     if (((i * 0x9E3779B1u) >> shift) == round) m |= 1u << b;
   }
   return m;
+}
+
+// Vertices of word k with ids in [lo, hi) (ASYNC sub-rounds over id ranges).
+__device__ __forceinline__ uint32_t range_mask(int64_t k, int32_t lo, int32_t hi) {
+  const int64_t first = k * 32;
+  const int64_t a = max(static_cast<int64_t>(lo) - first, int64_t(0));
+  const int64_t b = min(static_cast<int64_t>(hi) - first, int64_t(32));
+  if (a >= b) return 0u;
+  const uint32_t upto_b = b >= 32 ? 0xFFFFFFFFu : ((1u << b) - 1u);
+  const uint32_t upto_a = (1u << a) - 1u;
+  return upto_b & ~upto_a;
 }
 
 struct Bins {
@@ -190,6 +203,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(const uint32_t* __restr
                                                         uint32_t* __restrict__ ever,
                                                         const int32_t* __restrict__ row_len, int32_t n,
                                                         int32_t wave_max, uint32_t round, uint32_t round_shift,
+                                                        int32_t id_lo, int32_t id_hi, int32_t deg_lo, int32_t deg_hi,
                                                         Bins bins, HubOut H, int64_t* __restrict__ ctr) {
   __shared__ int32_t s_cnt[NBINS];
   __shared__ int64_t s_base[NBINS];
@@ -205,6 +219,16 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(const uint32_t* __restr
       bits = cur[k];
       if (range) bits &= range[k];
       if (round_shift < 32 && bits) bits &= round_mask(static_cast<uint32_t>(k), round, round_shift);
+      if (bits) bits &= range_mask(k, id_lo, id_hi);
+      if (bits && (deg_lo > 0 || deg_hi < INT_MAX)) {  // this round's degree class only
+        uint32_t keep = 0;
+        for (uint32_t r = bits; r; r &= r - 1) {
+          const int b = __ffs(r) - 1;
+          const int32_t deg = row_len[k * 32 + b];
+          if (deg >= deg_lo && deg <= deg_hi) keep |= 1u << b;
+        }
+        bits = keep;
+      }
       if (ever && bits) ever[k] |= bits;
     }
     int32_t cnt[NBINS];
@@ -317,21 +341,13 @@ __global__ void __launch_bounds__(kBlock) k_move_small(Dev D, const int32_t* __r
     const bool lead = valid && k == 0;
     bool mv = false;
     if (valid) mv = decide_move(D, d, bc, bg);
-    if (D.mode == LV_SYNC) {
-      const int64_t pos = wave_append(lead && mv, &D.ctr[CTR_MOVERS]);
-      if (pos >= 0) {
-        D.mv_v[pos] = i;
-        D.mv_c[pos] = bc;
-      }
-    } else if (lead && mv) {
-      commit_move(D, i, d, bc, Ki);
-    }
     if (lead && mv) {
+      commit_move(D, i, d, bc, Ki);
       gain_acc += bg;
       moved += 1;
       marcs += deg;
     }
-    if (mv && has) set_bit(D.next, j);
+    if (mv && has && D.push) set_bit(D.next, j);
   }
   flush_totals(D, gain_acc, moved, marcs);
 }
@@ -422,10 +438,11 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __re
         moved += 1;
         marcs += deg;
       }
-      for (int32_t b = lane; b < deg; b += kWave) {
-        const int32_t j = D.col[start + b];
-        if (j != i) set_bit(D.next, j);
-      }
+      if (D.push)
+        for (int32_t b = lane; b < deg; b += kWave) {
+          const int32_t j = D.col[start + b];
+          if (j != i) set_bit(D.next, j);
+        }
     }
   }
   flush_totals(D, gain_acc, moved, marcs);
@@ -529,10 +546,11 @@ __global__ void __launch_bounds__(kBlock) k_move_block(Dev D, const int32_t* __r
         moved += 1;
         marcs += deg;
       }
-      for (int32_t k = threadIdx.x; k < deg; k += kBlock) {
-        const int32_t j = D.col[start + k];
-        if (j != i) set_bit(D.next, j);
-      }
+      if (D.push)
+        for (int32_t k = threadIdx.x; k < deg; k += kBlock) {
+          const int32_t j = D.col[start + k];
+          if (j != i) set_bit(D.next, j);
+        }
     }
     __syncthreads();
   }
@@ -734,7 +752,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_final(Dev D, const int32_t* __re
 __global__ void __launch_bounds__(kBlock) k_hub_expand(Dev D, const int32_t* __restrict__ list,
                                                       const int32_t* __restrict__ u_b, const int64_t* __restrict__ u_a,
                                                       const int32_t* __restrict__ hub_moved) {
-  const int64_t count = D.ctr[CTR_HUB_UNITS];
+  const int64_t count = D.push ? D.ctr[CTR_HUB_UNITS] : 0;
   for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
     const int32_t h = u_b[u];
     if (!hub_moved[h]) continue;
@@ -749,27 +767,107 @@ __global__ void __launch_bounds__(kBlock) k_hub_expand(Dev D, const int32_t* __r
 }
 
 // --------------------------------------------------------------------------
-// SYNC: apply the recorded moves after every decision was taken.
+// SYNC: apply the recorded moves after every decision was taken; one thread
+// per word of the movers bitmask.
 // --------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_apply_moves(int32_t* __restrict__ C, const int64_t* __restrict__ K,
                                                        int64_t* __restrict__ Sigma, int32_t* __restrict__ size,
-                                                       const int32_t* __restrict__ mv_v,
-                                                       const int32_t* __restrict__ mv_c,
-                                                       const int64_t* __restrict__ ctr) {
-  const int64_t count = ctr[CTR_MOVERS];
-  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < count;
-       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int32_t i = mv_v[t];
-    const int32_t c = mv_c[t];
-    const int32_t d = C[i];
-    const int64_t Ki = K[i];
-    C[i] = c;
-    atomic_add_i64(&Sigma[d], -Ki);
-    atomic_add_i64(&Sigma[c], Ki);
-    if (size) {
-      atomicSub(&size[d], 1);
-      atomicAdd(&size[c], 1);
+                                                       const uint32_t* __restrict__ moved,
+                                                       const int32_t* __restrict__ target, int32_t n) {
+  const int64_t words = (static_cast<int64_t>(n) + 31) / 32;
+  for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < words;
+       k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    for (uint32_t r = moved[k]; r; r &= r - 1) {
+      const int32_t i = static_cast<int32_t>(k * 32 + (__ffs(r) - 1));
+      const int32_t c = target[i];
+      const int32_t d = C[i];
+      const int64_t Ki = K[i];
+      C[i] = c;
+      atomic_add_i64(&Sigma[d], -Ki);
+      atomic_add_i64(&Sigma[c], Ki);
+      if (size) {
+        atomicSub(&size[d], 1);
+        atomicAdd(&size[c], 1);
+      }
     }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Pull expansion: vertex j joins the next frontier iff a neighbour i != j
+// moved.  The graph is symmetric, so this is the same set the movers would
+// push, without one atomic per arc.  A wavefront owns one 32-vertex word
+// (4 groups of 16 lanes, 8 rows each) and stores it whole; rows longer
+// than kPullGroupMax are left to a workgroup each, which ORs its bit in.
+// --------------------------------------------------------------------------
+constexpr int kPullGroup = 16;
+constexpr int kPullGroupMax = 2048;
+
+__global__ void __launch_bounds__(kBlock) k_pull_words(const int64_t* __restrict__ row_start,
+                                                      const int32_t* __restrict__ row_len,
+                                                      const int32_t* __restrict__ col, int32_t n,
+                                                      const uint32_t* __restrict__ moved, uint32_t* __restrict__ next,
+                                                      int32_t* __restrict__ longlist, int64_t* __restrict__ ctr) {
+  const int lane = lane_id();
+  const int grp = lane / kPullGroup;
+  const int sub = lane % kPullGroup;
+  const int64_t words = (static_cast<int64_t>(n) + 31) / 32;
+  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+  for (int64_t w = wave; w < words; w += nwaves) {
+    uint32_t word = 0;
+    for (int r = 0; r < 8; ++r) {
+      const int bit = grp * 8 + r;
+      const int64_t j = w * 32 + bit;
+      bool hit = false;
+      if (j < n) {
+        const int32_t len = row_len[j];
+        if (len > kPullGroupMax) {
+          if (sub == 0) {
+            const int64_t pos = static_cast<int64_t>(
+                atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_AUX1]), 1ull));
+            longlist[pos] = static_cast<int32_t>(j);
+          }
+        } else {
+          const int64_t s = row_start[j];
+          for (int32_t k = sub; k < len && !hit; k += kPullGroup) {
+            const int32_t i = col[s + k];
+            hit = i != j && test_bit(moved, i);
+          }
+        }
+      }
+      // any lane of the group found a moved neighbour
+      const uint64_t m = __ballot(hit);
+      if ((m >> (grp * kPullGroup)) & 0xFFFFull) word |= 1u << bit;
+    }
+    // groups hold disjoint bits of the word
+    word |= __shfl_xor(word, 16);
+    word |= __shfl_xor(word, 32);
+    if (lane == 0) next[w] = word;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_pull_long(const int64_t* __restrict__ row_start,
+                                                     const int32_t* __restrict__ row_len,
+                                                     const int32_t* __restrict__ col,
+                                                     const uint32_t* __restrict__ moved, uint32_t* __restrict__ next,
+                                                     const int32_t* __restrict__ longlist, const int64_t* __restrict__ ctr) {
+  __shared__ int s_hit;
+  const int64_t count = ctr[CTR_AUX1];
+  for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+    const int32_t j = longlist[idx];
+    if (threadIdx.x == 0) s_hit = 0;
+    __syncthreads();
+    const int64_t s = row_start[j];
+    const int32_t len = row_len[j];
+    for (int32_t k = threadIdx.x; k < len; k += kBlock) {
+      if (s_hit) break;
+      const int32_t i = col[s + k];
+      if (i != j && test_bit(moved, i)) s_hit = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_hit) set_bit(next, j);
+    __syncthreads();
   }
 }
 
@@ -781,25 +879,51 @@ int table_slots_for(int wave_max) {
 
 }  // namespace
 
-void launch_bin_frontier(const MoveArgs& a, Workspace& ws, int round, int rounds_log2, hipStream_t st) {
+void launch_bin_frontier(const MoveArgs& a, Workspace& ws, const SubRound& r, hipStream_t st) {
   const int64_t words = (static_cast<int64_t>(a.g.n) + 31) / 32;
-  const uint32_t shift = rounds_log2 > 0 ? 32u - static_cast<uint32_t>(rounds_log2) : 32u;
   Bins b;
   for (int k = 0; k < NBINS; ++k) b.list[k] = ws.bins[k];
   HubOut H{ws.hub_off, ws.hub_cbase, ws.hub_cnum, ws.u_ins_b, ws.u_ins_a, ws.u_emit_b, ws.u_emit_s};
   hipLaunchKernelGGL(k_bin_frontier, dim3(grid_for(words, kBlock, 4096)), dim3(kBlock), 0, st, a.cur, a.range,
-                     a.ever, a.g.row_len, a.g.n, a.wave_max, static_cast<uint32_t>(round), shift, b, H, ws.ctr);
+                     a.ever, a.g.row_len, a.g.n, a.wave_max, r.hash_round, r.hash_shift, r.id_lo, r.id_hi, r.deg_lo,
+                     r.deg_hi, b, H, ws.ctr);
 }
 
-void launch_move(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, hipStream_t st) {
+// Bins whose degree range meets [lo, hi].
+uint32_t bins_for_degrees(int32_t lo, int32_t hi, int32_t wave_max) {
+  const int32_t blo[NBINS] = {1, 5, 9, 17, 33, wave_max + 1, kBlockMaxDegree + 1};
+  const int32_t bhi[NBINS] = {4, 8, 16, 32, wave_max, kBlockMaxDegree, INT_MAX};
+  uint32_t m = 0;
+  for (int k = 0; k < NBINS; ++k)
+    if (blo[k] <= hi && bhi[k] >= lo) m |= 1u << k;
+  return m;
+}
+
+// Persistent grids sized by the frontier bound: full sweeps fill the chip,
+// small DF frontiers launch few blocks.
+int grid_by_est(int64_t est, int64_t items_per_block, int max_blocks) {
+  const int64_t b = (est + items_per_block - 1) / items_per_block;
+  return static_cast<int>(b < 1 ? 1 : (b > max_blocks ? max_blocks : b));
+}
+
+void launch_move(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, uint32_t bin_mask, hipStream_t st) {
   const Dev D = make_dev(a, ws);
-  const int bs = tu.blocks_small, bw = tu.blocks_wave, bh = tu.blocks_hub;
-  hipLaunchKernelGGL(k_move_small<4>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G4], int(BIN_G4));
-  hipLaunchKernelGGL(k_move_small<8>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G8], int(BIN_G8));
-  hipLaunchKernelGGL(k_move_small<16>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G16], int(BIN_G16));
-  hipLaunchKernelGGL(k_move_small<32>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G32], int(BIN_G32));
+  const int64_t est = a.est > 0 ? a.est : 1;
+  const int bs = grid_by_est(est, 64, tu.blocks_small);      // 16 rows per wave at G = 4
+  const int bw = grid_by_est(est, 4, tu.blocks_wave);        // one row per wavefront
+  const int bh = grid_by_est(est, 1, tu.blocks_hub);         // one row / unit per workgroup
+  if (bin_mask & (1u << BIN_G4))
+    hipLaunchKernelGGL(k_move_small<4>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G4], int(BIN_G4));
+  if (bin_mask & (1u << BIN_G8))
+    hipLaunchKernelGGL(k_move_small<8>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G8], int(BIN_G8));
+  if (bin_mask & (1u << BIN_G16))
+    hipLaunchKernelGGL(k_move_small<16>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G16], int(BIN_G16));
+  if (bin_mask & (1u << BIN_G32))
+    hipLaunchKernelGGL(k_move_small<32>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G32], int(BIN_G32));
   const int ts = table_slots_for(a.wave_max);
-  if (ts <= 128)
+  if (!(bin_mask & (1u << BIN_WAVE)))
+    ;
+  else if (ts <= 128)
     hipLaunchKernelGGL(k_move_wave<128>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
   else if (ts <= 256)
     hipLaunchKernelGGL(k_move_wave<256>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
@@ -807,7 +931,9 @@ void launch_move(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, hipStrea
     hipLaunchKernelGGL(k_move_wave<512>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
   else
     hipLaunchKernelGGL(k_move_wave<1024>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
-  hipLaunchKernelGGL(k_move_block, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_BLOCK]);
+  if (bin_mask & (1u << BIN_BLOCK))
+    hipLaunchKernelGGL(k_move_block, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_BLOCK]);
+  if (!(bin_mask & (1u << BIN_HUB))) return;
   // hub rows
   hipLaunchKernelGGL(k_hub_clear, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off, ws.u_emit_b,
                      ws.u_emit_s, ws.pool_keys, ws.pool_vals, ws.hub_kid, ws.hub_moved, ws.pool_slots);
@@ -822,9 +948,19 @@ void launch_move(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, hipStrea
                      ws.hub_moved);
 }
 
+void launch_pull_expand(const MoveArgs& a, Workspace& ws, hipStream_t st) {
+  const int64_t words = (static_cast<int64_t>(a.g.n) + 31) / 32;
+  (void)hipMemsetAsync(ws.ctr + CTR_AUX1, 0, sizeof(int64_t), st);
+  hipLaunchKernelGGL(k_pull_words, dim3(grid_for(words * kWave, kBlock, 8192)), dim3(kBlock), 0, st, a.g.row_start,
+                     a.g.row_len, a.g.col, a.g.n, a.moved, a.next, ws.bins[NBINS - 1] + 0, ws.ctr);
+  hipLaunchKernelGGL(k_pull_long, dim3(1024), dim3(kBlock), 0, st, a.g.row_start, a.g.row_len, a.g.col, a.moved,
+                     a.next, ws.bins[NBINS - 1] + 0, ws.ctr);
+}
+
 void launch_apply_moves(const MoveArgs& a, Workspace& ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_apply_moves, dim3(grid_for(a.g.n, kBlock, 2048)), dim3(kBlock), 0, st, a.C, a.K, a.Sigma,
-                     a.size, ws.mv_v, ws.mv_c, ws.ctr);
+  const int64_t words = (static_cast<int64_t>(a.g.n) + 31) / 32;
+  hipLaunchKernelGGL(k_apply_moves, dim3(grid_for(words, kBlock, 2048)), dim3(kBlock), 0, st, a.C, a.K, a.Sigma,
+                     a.size, a.moved, ws.mv_c, a.g.n);
 }
 
 }  // namespace lv

@@ -81,7 +81,7 @@ class Stats(ct.Structure):
 class Tuning(ct.Structure):
     _fields_ = [("wave_max_degree", ct.c_int32), ("blocks_small", ct.c_int32), ("blocks_wave", ct.c_int32),
                 ("blocks_hub", ct.c_int32), ("async_rounds_log2", ct.c_int32),
-                ("async_rounds_min_frontier", ct.c_int32)]
+                ("async_rounds_min_frontier", ct.c_int32), ("async_round_order", ct.c_int32)]
 
 
 _lib = None
@@ -147,7 +147,7 @@ def params(tolerance=1e-2, tolerance_drop=10.0, aggregation_tolerance=0.8, max_i
                   int(max_passes), m, int(swap_guard))
 
 
-DEFAULT_ASYNC_ROUNDS_LOG2 = 3
+DEFAULT_ASYNC_ROUNDS_LOG2 = 7
 
 
 DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER = 4096
@@ -155,9 +155,9 @@ DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER = 4096
 
 def set_tuning(wave_max_degree=0, blocks_small=0, blocks_wave=0, blocks_hub=0,
                async_rounds_log2=DEFAULT_ASYNC_ROUNDS_LOG2,
-               async_rounds_min_frontier=DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER):
+               async_rounds_min_frontier=DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER, async_round_order=2):
     load().lv_set_tuning(ct.byref(Tuning(wave_max_degree, blocks_small, blocks_wave, blocks_hub,
-                                         async_rounds_log2, async_rounds_min_frontier)))
+                                         async_rounds_log2, async_rounds_min_frontier, async_round_order)))
 
 
 def get_tuning() -> dict:
