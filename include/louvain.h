@@ -81,11 +81,20 @@ typedef struct {
 } lv_edges;
 
 /* Community membership C, weighted degrees K, community totals Sigma
- * (Sigma indexed by community id).  Device arrays of length n. */
+ * (Sigma indexed by community id).  Device arrays of length n.
+ *
+ * `size` is optional (NULL allowed): the member count of every community
+ * id, size[c] = |{i : C_i = c}|.  Like Sigma it is auxiliary information
+ * carried from one batch to the next (Section 4.1 keeps K and Sigma for
+ * the same reason): the swap guard needs it, and recounting it costs a
+ * pass over all n vertices per call.  When non-NULL, the dynamic entry
+ * points trust it on entry and return it updated; louvain_static fills it.
+ * When NULL, the library counts it in the workspace as needed. */
 typedef struct {
   int32_t* C;
   int64_t* K;
   int64_t* Sigma;
+  int32_t* size;
 } lv_state;
 
 /* Parameters; lv_default_params() gives the paper's values (Section
@@ -179,7 +188,7 @@ lv_status apply_batch(lv_graph* g, const lv_edges* del, const lv_edges* ins, voi
  * louvain_static -- Louvain from singleton communities (the paper's static
  * baseline, Alg. 4 with every vertex affected): K is computed from the
  * graph, Sigma = K, then passes of local-moving (Alg. 5) and aggregation
- * (Alg. 6).  Writes C, K, Sigma of `out`.
+ * (Alg. 6).  Writes C, K, Sigma (and size, when non-NULL) of `out`.
  */
 lv_status louvain_static(const lv_graph* g, const lv_params* p, lv_state* out, void* ws, size_t ws_bytes,
                          lv_stats* stats, void* stream);
@@ -188,7 +197,8 @@ lv_status louvain_static(const lv_graph* g, const lv_params* p, lv_state* out, v
  * louvain_nd / louvain_ds / louvain_df -- dynamic Louvain after a batch
  * (Alg. 2 / Alg. 3 / Alg. 1).  `g` is G^t (apply_batch already ran);
  * `del` and `ins` are the batch.  `state` holds C^{t-1}, K^{t-1},
- * Sigma^{t-1} on entry and C^t, K^t, Sigma^t on return.  K and Sigma are
+ * Sigma^{t-1} (and the matching size, when non-NULL) on entry and C^t,
+ * K^t, Sigma^t (size^t) on return.  K and Sigma are
  * updated from the batch (Alg. 7) rather than recomputed; the initial
  * affected set is every vertex (ND), the delta-screening set (DS) or the
  * endpoints of intra-community deletions and cross-community insertions

@@ -1,19 +1,33 @@
 // In-place batch update of the slack CSR (Section 3.4: a batch holds edge
-// deletions Δ- and insertions Δ+; Section 5.1.4: batches are undirected).
+// deletions Δ- and insertions Δ+; Section 5.1.4: batches are undirected, so
+// every update touches the arc in both directions).
 //
-// Phase 1 (no writes to the graph): validate ids, weights and repeated
-//   pairs; locate every deletion's two arcs; classify every insertion arc
-//   as a merge into a surviving arc or an append; check row capacities and
-//   the 2m bound.  The host reads the error slot once.
-// Phase 2 (only when phase 1 found nothing): subtract deletions, compact
-//   the rows that lost arcs (stable, one wavefront per row), add merges,
-//   append new arcs into the slack, update 2m.
+// The work is organised by ROW, not by update: rows are unsorted, so
+// finding an arc means scanning its row, and in a skewed graph many updates
+// land on the same hub rows.  Each touched row is therefore scanned once,
+// in chunks of kChunk arcs, against a small per-chunk filter of the
+// partners the batch names for that row; filter hits are resolved in a
+// hashtable of the batch's undirected pairs.
+//
+// Phase 1 (reads the graph only): validate ids, weights and repeated pairs;
+//   collect the touched rows; locate every update's two arcs; classify
+//   insertion arcs as merges (the arc survives the deletions) or appends;
+//   check row capacities and the 2m bound.  Errors go to the error counter.
+// Phase 2 (every kernel returns at once if phase 1 set an error, so a bad
+//   batch leaves the graph untouched without a host round trip in between):
+//   subtract deletions and add merges at the located positions; refill the
+//   holes left by arcs that reached weight 0 with the surviving arcs of the
+//   row's tail (O(holes) per row, not O(row length); rows stay unsorted);
+//   append new arcs into the slack; update 2m.
 #include "lv_internal.hpp"
 
 namespace lv {
 namespace {
 
 constexpr uint64_t kEmpty = ~0ull;
+constexpr int kChunk = 1024;        // arcs per scan unit (one wavefront)
+constexpr int kFilterBits = 4096;   // per-wavefront partner filter
+constexpr int kScanWaves = kBlock / kWave;
 
 __device__ __forceinline__ uint64_t canon(int32_t a, int32_t b) {
   const uint32_t lo = static_cast<uint32_t>(min(a, b)), hi = static_cast<uint32_t>(max(a, b));
@@ -27,58 +41,137 @@ __device__ __forceinline__ uint32_t hash64(uint64_t key, uint32_t mask) {
   return static_cast<uint32_t>(key) & mask;
 }
 
-// Inserts key; returns false when it was already present.
-__device__ __forceinline__ bool set_insert(uint64_t* keys, uint32_t size, uint64_t key, uint32_t* slot) {
+// Inserts key; returns its slot.
+__device__ __forceinline__ uint32_t pair_insert(uint64_t* keys, uint32_t size, uint64_t key) {
   const uint32_t mask = size - 1;
   uint32_t h = hash64(key, mask);
   while (true) {
     const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long*>(&keys[h]), kEmpty, key);
-    if (old == kEmpty) {
-      *slot = h;
-      return true;
-    }
-    if (old == key) {
-      *slot = h;
-      return false;
-    }
+    if (old == kEmpty || old == key) return h;
     h = (h + 1) & mask;
   }
 }
 
-__device__ __forceinline__ int64_t set_find(const uint64_t* keys, uint32_t size, uint64_t key) {
+__device__ __forceinline__ int32_t pair_find(const uint64_t* keys, uint32_t size, uint64_t key) {
   const uint32_t mask = size - 1;
   uint32_t h = hash64(key, mask);
   while (true) {
     const uint64_t k = keys[h];
-    if (k == key) return h;
+    if (k == key) return static_cast<int32_t>(h);
     if (k == kEmpty) return -1;
     h = (h + 1) & mask;
   }
 }
 
-__global__ void k_validate(const int32_t* __restrict__ du, const int32_t* __restrict__ dv,
-                           const int32_t* __restrict__ dw, int64_t nd, const int32_t* __restrict__ iu,
-                           const int32_t* __restrict__ iv, const int32_t* __restrict__ iw, int64_t ni, int32_t n,
-                           BatchScratch b, int64_t* __restrict__ ctr) {
+// Endpoints of direction e: directions 2k, 2k+1 belong to deletion k
+// (k < nd), then 2(nd + k), 2(nd + k) + 1 to insertion k.  Direction
+// 2k is the arc u -> v, 2k + 1 the arc v -> u.
+struct Upd {
+  const int32_t *du, *dv, *dw;
+  int64_t nd;
+  const int32_t *iu, *iv, *iw;
+  int64_t ni;
+  __device__ __forceinline__ bool is_del(int64_t e) const { return e < 2 * nd; }
+  __device__ __forceinline__ int64_t update(int64_t e) const { return e >> 1; }  // index into [del | ins]
+  __device__ __forceinline__ void ends(int64_t e, int32_t& a, int32_t& c) const {
+    const int64_t k = e >> 1;
+    const int32_t x = k < nd ? du[k] : iu[k - nd];
+    const int32_t y = k < nd ? dv[k] : iv[k - nd];
+    a = (e & 1) ? y : x;
+    c = (e & 1) ? x : y;
+  }
+  __device__ __forceinline__ int32_t weight(int64_t e) const {
+    const int64_t k = e >> 1;
+    return k < nd ? dw[k] : iw[k - nd];
+  }
+};
+
+// Wave-aggregated reservation of `count` consecutive entries of *total.
+__device__ __forceinline__ int64_t wave_reserve(int64_t count, int64_t* total) {
+  const int lane = lane_id();
+  int64_t incl = count;
+  for (int s = 1; s < kWave; s <<= 1) {
+    const int64_t t = __shfl_up(incl, s);
+    if (lane >= s) incl += t;
+  }
+  int64_t base = 0;
+  if (lane == kWave - 1 && incl)
+    base = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(total),
+                                          static_cast<unsigned long long>(incl)));
+  base = __shfl(base, kWave - 1);
+  return base + incl - count;
+}
+
+__device__ __forceinline__ bool failed(const int64_t* ctr) {
+  return *reinterpret_cast<const volatile int64_t*>(&ctr[CTR_ERR]) != 0;
+}
+
+__global__ void k_init(BatchScratch b, int64_t words, int64_t* __restrict__ ctr) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t t0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  for (int64_t i = t0; i < b.size; i += stride) {
+    b.keys[i] = kEmpty;
+    b.dw[i] = 0;
+    b.iw[i] = 0;
+    b.pos[2 * i] = -1;
+    b.pos[2 * i + 1] = -1;
+  }
+  for (int64_t i = t0; i < b.dirs; i += stride) {
+    b.r_cnt[i] = 0;
+    b.r_zero[i] = 0;
+    b.r_app[i] = 0;
+    b.r_hole[i] = 0;
+  }
+  for (int64_t i = t0; i < words; i += stride) b.tag[i] = 0;
+  for (int64_t i = t0; i < CTR_COUNT; i += stride) ctr[i] = 0;
+}
+
+// Validation, the pair table, and the list of touched rows.
+__global__ void k_validate(Upd U, int32_t n, BatchScratch b, int64_t* __restrict__ ctr) {
   int64_t si = 0, sd = 0;
-  for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < nd + ni;
-       k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const bool del = k < nd;
-    const int32_t a = del ? du[k] : iu[k - nd];
-    const int32_t c = del ? dv[k] : iv[k - nd];
-    const int32_t x = del ? dw[k] : iw[k - nd];
-    if (a < 0 || c < 0 || a >= n || c >= n || a == c || x <= 0) {
-      set_error(ctr, LV_EINVAL);
-      continue;
+  const int64_t total = U.nd + U.ni;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  // whole waves iterate together (wave-aggregated row reservation)
+  for (int64_t k0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + (threadIdx.x & ~(kWave - 1)); k0 < total;
+       k0 += stride) {
+    const int64_t k = k0 + lane_id();
+    bool ok = false;
+    int32_t a = 0, c = 0;
+    if (k < total) {
+      const bool del = k < U.nd;
+      a = del ? U.du[k] : U.iu[k - U.nd];
+      c = del ? U.dv[k] : U.iv[k - U.nd];
+      const int32_t x = del ? U.dw[k] : U.iw[k - U.nd];
+      ok = a >= 0 && c >= 0 && a < n && c < n && a != c && x > 0;
+      int32_t h = -1;
+      if (ok) {
+        h = static_cast<int32_t>(pair_insert(b.keys, b.size, canon(a, c)));
+        if (atomicCAS(del ? &b.dw[h] : &b.iw[h], 0, x) != 0) ok = false;  // pair repeated on this side
+      }
+      if (ok) {
+        if (del)
+          sd += x;
+        else
+          si += x;
+      }
+      if (!ok) {
+        set_error(ctr, LV_EINVAL);
+        h = -1;
+      }
+      b.slot[k] = h;
     }
-    uint32_t slot;
-    if (del) {
-      if (!set_insert(b.del_keys, b.del_size, canon(a, c), &slot)) set_error(ctr, LV_EINVAL);
-      else b.del_vals[slot] = x;
-      sd += x;
-    } else {
-      if (!set_insert(b.ins_keys, b.ins_size, canon(a, c), &slot)) set_error(ctr, LV_EINVAL);
-      si += x;
+    for (int side = 0; side < 2; ++side) {
+      const int32_t r = side ? c : a;
+      bool first = false;
+      if (ok) {
+        const uint32_t bit = 1u << (r & 31);
+        first = (atomicOr(&b.tag[r >> 5], bit) & bit) == 0;
+      }
+      const int64_t slot = wave_append(first, &ctr[CTR_B_ROWS]);
+      if (first) {
+        b.row_slot[r] = static_cast<int32_t>(slot);
+        b.row_of[slot] = r;
+      }
     }
   }
   si = wave_sum_i64(si);
@@ -89,206 +182,270 @@ __global__ void k_validate(const int32_t* __restrict__ du, const int32_t* __rest
   }
 }
 
-// Position of arc (a -> c) in row a, or -1; one wavefront scans the row.
-__device__ __forceinline__ int64_t wave_find_arc(const int64_t* row_start, const int32_t* row_len,
-                                                 const int32_t* col, int32_t a, int32_t c) {
-  const int lane = lane_id();
-  const int64_t s = row_start[a];
-  const int32_t l = row_len[a];
-  for (int32_t b0 = 0; b0 < l; b0 += kWave) {
-    const int32_t k = b0 + lane;
-    const uint64_t m = __ballot(k < l && col[s + k] == c);
-    if (m) return s + b0 + (__ffsll(static_cast<unsigned long long>(m)) - 1);
+// rank of every direction among the directions of its row
+__global__ void k_rank(Upd U, BatchScratch b) {
+  const int64_t dirs = 2 * (U.nd + U.ni);
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < dirs;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    if (b.slot[U.update(e)] < 0) {
+      b.d_rank[e] = -1;
+      continue;
+    }
+    int32_t a, c;
+    U.ends(e, a, c);
+    b.d_rank[e] = atomicAdd(&b.r_cnt[b.row_slot[a]], 1);
   }
-  return -1;
 }
 
-// one wavefront per (update, direction)
-__global__ void k_find(const int64_t* __restrict__ row_start, const int32_t* __restrict__ row_len,
-                       const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
-                       const int32_t* __restrict__ du, const int32_t* __restrict__ dv, const int32_t* __restrict__ dw,
-                       int64_t nd, const int32_t* __restrict__ iu, const int32_t* __restrict__ iv, int64_t ni,
-                       BatchScratch b, int64_t* __restrict__ ctr) {
-  const int lane = lane_id();
-  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
-  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
-  const int64_t total = 2 * (nd + ni);
-  for (int64_t e = wave; e < total; e += nwaves) {
-    const int64_t k = e >> 1;
-    const bool del = k < nd;
-    int32_t a, c;
-    if (del) {
-      a = (e & 1) ? dv[k] : du[k];
-      c = (e & 1) ? du[k] : dv[k];
-    } else {
-      a = (e & 1) ? iv[k - nd] : iu[k - nd];
-      c = (e & 1) ? iu[k - nd] : iv[k - nd];
+// per touched row: its length, its range in the partner list, its chunks
+__global__ void k_rows(const int32_t* __restrict__ row_len, BatchScratch b, int64_t* __restrict__ ctr) {
+  const int64_t rows = ctr[CTR_B_ROWS];
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t r0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + (threadIdx.x & ~(kWave - 1)); r0 < rows;
+       r0 += stride) {
+    const int64_t r = r0 + lane_id();
+    int32_t len = 0, cnt = 0;
+    if (r < rows) {
+      len = row_len[b.row_of[r]];
+      cnt = b.r_cnt[r];
+      b.r_len[r] = len;
     }
-    const int64_t pos = wave_find_arc(row_start, row_len, col, a, c);
-    if (lane != 0) continue;
-    if (del) {
-      if (pos < 0 || wt[pos] < dw[k]) {
+    const int64_t nch = (len + kChunk - 1) / kChunk;
+    const int64_t pbase = wave_reserve(cnt, &ctr[CTR_B_PART]);
+    const int64_t cbase = wave_reserve(nch, &ctr[CTR_B_CHUNKS]);
+    if (r < rows) {
+      b.r_pbase[r] = static_cast<int32_t>(pbase);
+      for (int64_t j = 0; j < nch; ++j) {
+        b.ch_row[cbase + j] = static_cast<int32_t>(r);
+        b.ch_off[cbase + j] = static_cast<int32_t>(j * kChunk);
+      }
+    }
+  }
+}
+
+__global__ void k_place(Upd U, BatchScratch b) {
+  const int64_t dirs = 2 * (U.nd + U.ni);
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < dirs;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int32_t rk = b.d_rank[e];
+    if (rk < 0) continue;
+    int32_t a, c;
+    U.ends(e, a, c);
+    b.part[b.r_pbase[b.row_slot[a]] + rk] = c;
+  }
+}
+
+// One wavefront per chunk: filter of the row's partners in LDS, then every
+// arc of the chunk is tested; hits are looked up in the pair table and
+// their positions recorded per (pair, direction).
+__global__ void __launch_bounds__(kBlock) k_scan(const int64_t* __restrict__ row_start,
+                                                 const int32_t* __restrict__ col, BatchScratch b,
+                                                 const int64_t* __restrict__ ctr) {
+  __shared__ uint32_t filt[kScanWaves][kFilterBits / 32];
+  const int lane = lane_id();
+  const int wv = threadIdx.x / kWave;
+  uint32_t* F = filt[wv];
+  const int64_t chunks = ctr[CTR_B_CHUNKS];
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * kScanWaves;
+  for (int64_t ch = blockIdx.x * static_cast<int64_t>(kScanWaves) + wv; ch < chunks; ch += nwaves) {
+    const int32_t r = b.ch_row[ch];
+    const int32_t a = b.row_of[r];
+    const int32_t cnt = b.r_cnt[r];
+    const int32_t pbase = b.r_pbase[r];
+    const int32_t off = b.ch_off[ch];
+    const int32_t end = min(b.r_len[r], off + kChunk);
+    const int64_t s = row_start[a];
+    for (int i = lane; i < kFilterBits / 32; i += kWave) F[i] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int32_t j = lane; j < cnt; j += kWave) {
+      const uint32_t h = hash_slot(static_cast<uint32_t>(b.part[pbase + j]), kFilterBits);
+      atomicOr(&F[h >> 5], 1u << (h & 31));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int32_t k = off + lane; k < end; k += kWave) {
+      const int32_t c = col[s + k];
+      const uint32_t h = hash_slot(static_cast<uint32_t>(c), kFilterBits);
+      if (!((F[h >> 5] >> (h & 31)) & 1u)) continue;
+      const int32_t p = pair_find(b.keys, b.size, canon(a, c));
+      if (p >= 0) b.pos[2 * static_cast<int64_t>(p) + (a > c ? 1 : 0)] = s + k;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// Deletions must find their arc with enough weight; insertions merge into
+// an arc that survives the deletions, else append.
+__global__ void k_check(Upd U, const int32_t* __restrict__ wt, BatchScratch b, int64_t* __restrict__ ctr) {
+  const int64_t dirs = 2 * (U.nd + U.ni);
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < dirs;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int32_t h = b.slot[U.update(e)];
+    if (h < 0) continue;
+    int32_t a, c;
+    U.ends(e, a, c);
+    const int64_t p = b.pos[2 * static_cast<int64_t>(h) + (a > c ? 1 : 0)];
+    const int32_t r = b.row_slot[a];
+    const int32_t dwh = b.dw[h];
+    if (U.is_del(e)) {
+      if (p < 0 || wt[p] < dwh) {
         set_error(ctr, LV_ENOEDGE);
-        b.del_pos[e] = -1;
         continue;
       }
-      b.del_pos[e] = pos;
-      if (wt[pos] == dw[k]) atomicAdd(&b.row_zeroed[a], 1);
+      if (wt[p] == dwh) atomicAdd(&b.r_zero[r], 1);
     } else {
-      bool merge = pos >= 0;
-      if (merge) {  // an arc removed whole by this batch's deletions is re-appended
-        const int64_t h = set_find(b.del_keys, b.del_size, canon(a, c));
-        if (h >= 0 && b.del_vals[h] == wt[pos]) merge = false;
-      }
-      b.ins_kind[e - 2 * nd] = merge ? 1 : 0;
-      if (!merge) atomicAdd(&b.row_app[a], 1);
+      const bool merge = p >= 0 && !(dwh > 0 && dwh == wt[p]);
+      b.kind[e - 2 * U.nd] = merge ? 1 : 0;
+      if (!merge) atomicAdd(&b.r_app[r], 1);
     }
   }
 }
 
-__global__ void k_capacity(const int64_t* __restrict__ row_start, const int32_t* __restrict__ row_len,
-                           const int32_t* __restrict__ du, const int32_t* __restrict__ dv, int64_t nd,
-                           const int32_t* __restrict__ iu, const int32_t* __restrict__ iv, int64_t ni,
-                           const int64_t* __restrict__ two_m, BatchScratch b, int64_t* __restrict__ ctr) {
-  const int64_t total = 2 * (nd + ni);
+__global__ void k_capacity(const int64_t* __restrict__ row_start, const int64_t* __restrict__ two_m, BatchScratch b,
+                           int64_t* __restrict__ ctr) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const int64_t nm = *two_m + 2 * ctr[CTR_AUX2] - 2 * ctr[CTR_AUX3];
     if (nm >= (int64_t(1) << 31)) set_error(ctr, LV_EOVERFLOW);
   }
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t k = e >> 1;
-    int32_t a;
-    if (k < nd)
-      a = (e & 1) ? dv[k] : du[k];
-    else
-      a = (e & 1) ? iv[k - nd] : iu[k - nd];
-    const int64_t need = static_cast<int64_t>(row_len[a]) - b.row_zeroed[a] + b.row_app[a];
+  const int64_t rows = ctr[CTR_B_ROWS];
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < rows;
+       r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int32_t a = b.row_of[r];
+    const int64_t need = static_cast<int64_t>(b.r_len[r]) - b.r_zero[r] + b.r_app[r];
     if (need > row_start[a + 1] - row_start[a]) set_error(ctr, LV_ENOSLACK);
   }
 }
 
-__global__ void k_apply_del(int32_t* __restrict__ wt, const int32_t* __restrict__ dw, int64_t nd, BatchScratch b) {
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < 2 * nd;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    wt[b.del_pos[e]] -= dw[e >> 1];
+// ---- phase 2 ---------------------------------------------------------------
+
+__global__ void k_apply(Upd U, int32_t* __restrict__ wt, int64_t* __restrict__ two_m, BatchScratch b,
+                        const int64_t* __restrict__ ctr) {
+  if (failed(ctr)) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *two_m += 2 * ctr[CTR_AUX2] - 2 * ctr[CTR_AUX3];
+  const int64_t dirs = 2 * (U.nd + U.ni);
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < dirs;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int32_t h = b.slot[U.update(e)];
+    int32_t a, c;
+    U.ends(e, a, c);
+    const int64_t p = b.pos[2 * static_cast<int64_t>(h) + (a > c ? 1 : 0)];
+    if (U.is_del(e))
+      atomicSub(&wt[p], U.weight(e));  // a pair deleted and merged back gets two updates
+    else if (b.kind[e - 2 * U.nd])
+      atomicAdd(&wt[p], U.weight(e));
+  }
 }
 
-// stable removal of zero-weight arcs; the first wavefront that claims a row
-// compacts it
-__global__ void k_compact(const int64_t* __restrict__ row_start, int32_t* __restrict__ row_len,
-                          int32_t* __restrict__ col, int32_t* __restrict__ wt, const int32_t* __restrict__ du,
-                          const int32_t* __restrict__ dv, int64_t nd, BatchScratch b) {
+// One wavefront per row with zeroed arcs: the new length is L' = L - zeroed;
+// the arcs of the tail [L', L) that survive are copied out (they refill the
+// holes of the head [0, L') in k_fill) and the row is cut to L'.
+__global__ void __launch_bounds__(kBlock) k_tail(const int64_t* __restrict__ row_start, int32_t* __restrict__ row_len,
+                                                 const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
+                                                 BatchScratch b, int64_t* __restrict__ ctr) {
+  if (failed(ctr)) return;
   const int lane = lane_id();
-  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
-  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
-  for (int64_t e = wave; e < 2 * nd; e += nwaves) {
-    const int64_t k = e >> 1;
-    const int32_t a = (e & 1) ? dv[k] : du[k];
-    int32_t claim = 0;
-    if (lane == 0) claim = atomicExch(&b.row_zeroed[a], 0);
-    claim = __shfl(claim, 0);
-    if (claim == 0) continue;
+  const int64_t rows = ctr[CTR_B_ROWS];
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
+  for (int64_t r = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave; r < rows; r += nwaves) {
+    const int32_t z = b.r_zero[r];
+    if (z == 0) continue;
+    const int32_t a = b.row_of[r];
+    const int32_t L = b.r_len[r], Lp = L - z;
     const int64_t s = row_start[a];
-    const int32_t l = row_len[a];
+    int64_t base = 0;
+    if (lane == 0) base = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_B_TMP]),
+                                                         static_cast<unsigned long long>(z)));
+    base = __shfl(base, 0);
     int32_t out = 0;
-    for (int32_t b0 = 0; b0 < l; b0 += kWave) {
-      const int32_t k2 = b0 + lane;
-      int32_t cc = 0, ww = 0;
-      if (k2 < l) {
-        cc = col[s + k2];
-        ww = wt[s + k2];
-      }
-      const bool keep = k2 < l && ww > 0;
+    for (int32_t k0 = Lp; k0 < L; k0 += kWave) {
+      const int32_t k = k0 + lane;
+      const bool keep = k < L && wt[s + k] > 0;
       const uint64_t m = __ballot(keep);
       if (keep) {
-        const int32_t p = out + __popcll(m & ((1ull << lane) - 1ull));
-        col[s + p] = cc;
-        wt[s + p] = ww;
+        const int64_t q = base + out + __popcll(m & ((1ull << lane) - 1ull));
+        b.tcol[q] = col[s + k];
+        b.tw[q] = wt[s + k];
       }
       out += __popcll(m);
     }
-    if (lane == 0) row_len[a] = out;
+    if (lane == 0) {
+      b.r_tbase[r] = static_cast<int32_t>(base);
+      row_len[a] = Lp;
+    }
   }
 }
 
-__global__ void k_merge_ins(const int64_t* __restrict__ row_start, const int32_t* __restrict__ row_len,
-                            const int32_t* __restrict__ col, int32_t* __restrict__ wt, const int32_t* __restrict__ iu,
-                            const int32_t* __restrict__ iv, const int32_t* __restrict__ iw, int64_t ni,
-                            BatchScratch b) {
-  const int lane = lane_id();
-  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
-  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
-  for (int64_t e = wave; e < 2 * ni; e += nwaves) {
-    if (b.ins_kind[e] != 1) continue;
-    const int64_t k = e >> 1;
-    const int32_t a = (e & 1) ? iv[k] : iu[k];
-    const int32_t c = (e & 1) ? iu[k] : iv[k];
-    const int64_t pos = wave_find_arc(row_start, row_len, col, a, c);
-    if (lane == 0 && pos >= 0) wt[pos] += iw[k];
-  }
-}
-
-__global__ void k_append_ins(const int64_t* __restrict__ row_start, int32_t* __restrict__ row_len,
-                             int32_t* __restrict__ col, int32_t* __restrict__ wt, const int32_t* __restrict__ iu,
-                             const int32_t* __restrict__ iv, const int32_t* __restrict__ iw, int64_t ni,
-                             BatchScratch b) {
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < 2 * ni;
+// Zeroed head arcs take the row's tail survivors; insertions that do not
+// merge are appended after the (cut) row.
+__global__ void k_fill(Upd U, const int64_t* __restrict__ row_start, int32_t* __restrict__ row_len,
+                       int32_t* __restrict__ col, int32_t* __restrict__ wt, BatchScratch b,
+                       const int64_t* __restrict__ ctr) {
+  if (failed(ctr)) return;
+  const int64_t dirs = 2 * (U.nd + U.ni);
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < dirs;
        e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    if (b.ins_kind[e] != 0) continue;
-    const int64_t k = e >> 1;
-    const int32_t a = (e & 1) ? iv[k] : iu[k];
-    const int32_t c = (e & 1) ? iu[k] : iv[k];
-    const int64_t p = row_start[a] + atomicAdd(&row_len[a], 1);
-    col[p] = c;
-    wt[p] = iw[k];
+    int32_t a, c;
+    U.ends(e, a, c);
+    const int32_t r = b.row_slot[a];
+    const int64_t s = row_start[a];
+    if (U.is_del(e)) {
+      const int32_t h = b.slot[U.update(e)];
+      const int64_t p = b.pos[2 * static_cast<int64_t>(h) + (a > c ? 1 : 0)];
+      const int32_t Lp = b.r_len[r] - b.r_zero[r];
+      if (p - s >= Lp || wt[p] != 0) continue;  // tail arc, or weight left
+      const int32_t j = atomicAdd(&b.r_hole[r], 1);
+      col[p] = b.tcol[b.r_tbase[r] + j];
+      wt[p] = b.tw[b.r_tbase[r] + j];
+    } else if (!b.kind[e - 2 * U.nd]) {
+      const int64_t q = s + atomicAdd(&row_len[a], 1);
+      col[q] = c;
+      wt[q] = U.weight(e);
+    }
   }
 }
 
-__global__ void k_update_two_m(int64_t* __restrict__ two_m, const int64_t* __restrict__ ctr) {
-  *two_m += 2 * ctr[CTR_AUX2] - 2 * ctr[CTR_AUX3];
+Upd upd(const lv_edges& del, const lv_edges& ins) {
+  return Upd{del.u, del.v, del.w, del.count, ins.u, ins.v, ins.w, ins.count};
 }
 
 }  // namespace
 
-void launch_batch_validate(const lv_edges& del, const lv_edges& ins, int32_t n, const BatchScratch& b, int64_t* ctr,
-                           hipStream_t st) {
-  const int64_t total = del.count + ins.count;
-  if (total == 0) return;
-  hipLaunchKernelGGL(k_validate, dim3(grid_for(total, kBlock, 4096)), dim3(kBlock), 0, st, del.u, del.v, del.w,
-                     del.count, ins.u, ins.v, ins.w, ins.count, n, b, ctr);
+int64_t batch_chunks_bound(int64_t dirs, int64_t cap) { return dirs + cap / kChunk + 1; }
+
+void launch_batch_phase1(const lv_graph& g, const lv_edges& del, const lv_edges& ins, const BatchScratch& b,
+                         int64_t words, int64_t* ctr, hipStream_t st) {
+  const Upd U = upd(del, ins);
+  const int64_t total = del.count + ins.count, dirs = 2 * total;
+  hipLaunchKernelGGL(k_init, dim3(grid_for(std::max<int64_t>(std::max<int64_t>(b.size, dirs), words), kBlock, 2048)),
+                     dim3(kBlock), 0, st, b, words, ctr);
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(total, kBlock, 4096)), dim3(kBlock), 0, st, U, g.n, b, ctr);
+  hipLaunchKernelGGL(k_rank, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, U, b);
+  hipLaunchKernelGGL(k_rows, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, g.row_len, b, ctr);
+  hipLaunchKernelGGL(k_place, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, U, b);
+  // chunks: one per touched row plus one per kChunk arcs of long rows; the
+  // grid covers a few per touched row and strides over the rest
+  hipLaunchKernelGGL(k_scan, dim3(grid_for(std::min<int64_t>(4 * dirs + 64, 32768) * kWave, kBlock, 8192)),
+                     dim3(kBlock), 0, st, g.row_start, g.col, b, ctr);
+  hipLaunchKernelGGL(k_check, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, U, g.w, b, ctr);
+  hipLaunchKernelGGL(k_capacity, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, g.row_start, g.two_m, b,
+                     ctr);
 }
 
-void launch_batch_find(const lv_graph& g, const lv_edges& del, const lv_edges& ins, const BatchScratch& b,
-                       int64_t* ctr, hipStream_t st) {
-  const int64_t total = 2 * (del.count + ins.count);
-  if (total == 0) return;
-  hipLaunchKernelGGL(k_find, dim3(grid_for(total * kWave, kBlock, 8192)), dim3(kBlock), 0, st, g.row_start,
-                     g.row_len, g.col, g.w, del.u, del.v, del.w, del.count, ins.u, ins.v, ins.count, b, ctr);
-}
-
-void launch_batch_capacity(const lv_graph& g, const lv_edges& del, const lv_edges& ins, const BatchScratch& b,
-                           int64_t* ctr, hipStream_t st) {
-  const int64_t total = 2 * (del.count + ins.count);
-  hipLaunchKernelGGL(k_capacity, dim3(grid_for(total, kBlock, 4096)), dim3(kBlock), 0, st, g.row_start, g.row_len,
-                     del.u, del.v, del.count, ins.u, ins.v, ins.count, g.two_m, b, ctr);
-}
-
-void launch_batch_apply(const lv_graph& g, const lv_edges& del, const lv_edges& ins, const BatchScratch& b,
-                        int64_t* ctr, hipStream_t st) {
-  if (del.count) {
-    hipLaunchKernelGGL(k_apply_del, dim3(grid_for(2 * del.count, kBlock, 4096)), dim3(kBlock), 0, st, g.w, del.w,
-                       del.count, b);
-    hipLaunchKernelGGL(k_compact, dim3(grid_for(2 * del.count * kWave, kBlock, 8192)), dim3(kBlock), 0, st,
-                       g.row_start, g.row_len, g.col, g.w, del.u, del.v, del.count, b);
-  }
-  if (ins.count) {
-    hipLaunchKernelGGL(k_merge_ins, dim3(grid_for(2 * ins.count * kWave, kBlock, 8192)), dim3(kBlock), 0, st,
-                       g.row_start, g.row_len, g.col, g.w, ins.u, ins.v, ins.w, ins.count, b);
-    hipLaunchKernelGGL(k_append_ins, dim3(grid_for(2 * ins.count, kBlock, 4096)), dim3(kBlock), 0, st, g.row_start,
-                       g.row_len, g.col, g.w, ins.u, ins.v, ins.w, ins.count, b);
-  }
-  hipLaunchKernelGGL(k_update_two_m, dim3(1), dim3(1), 0, st, g.two_m, ctr);
+void launch_batch_phase2(const lv_graph& g, const lv_edges& del, const lv_edges& ins, const BatchScratch& b,
+                         int64_t* ctr, hipStream_t st) {
+  const Upd U = upd(del, ins);
+  const int64_t dirs = 2 * (del.count + ins.count);
+  hipLaunchKernelGGL(k_apply, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, U, g.w, g.two_m, b, ctr);
+  if (del.count)
+    hipLaunchKernelGGL(k_tail, dim3(grid_for(dirs * kWave, kBlock, 4096)), dim3(kBlock), 0, st, g.row_start,
+                       g.row_len, g.col, g.w, b, ctr);
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, U, g.row_start, g.row_len,
+                     g.col, g.w, b, ctr);
 }
 
 }  // namespace lv

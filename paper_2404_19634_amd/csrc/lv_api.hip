@@ -307,8 +307,12 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
   L0.col = g->col;
   L0.w = g->w;
   bool use_range = false;
+  // member counts of level-0 communities: the caller's carried array when
+  // given (kept exact by the moves), else counted here for the swap guard
+  int32_t* size0 = state->size ? state->size : (p->swap_guard ? ws.size : nullptr);
   if (ap == A_STATIC) {
-    launch_row_sums(L0, nullptr, state->K, state->Sigma, state->C, ws.size, ws.bins[5], ws.ctr, st);
+    launch_row_sums(L0, nullptr, state->K, state->Sigma, state->C, size0 ? size0 : ws.size, ws.bins[5], ws.ctr,
+                    st);
     launch_set_all_bits(ws.fr_a, N, st);
   } else {
     switch (ap) {
@@ -347,7 +351,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
         break;
     }
     launch_update_weights(D, I, state->C, state->K, state->Sigma, st);
-    if (p->swap_guard) launch_community_sizes(state->C, N, ws.size, st);
+    if (p->swap_guard && !state->size) launch_community_sizes(state->C, N, ws.size, st);
   }
   LV_CHECK_LAUNCH();
   LV_HIP(hipEventRecord(ev[1], st));
@@ -357,7 +361,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
   int32_t* Cl = state->C;
   int64_t* Kl = state->K;
   int64_t* Sl = state->Sigma;
-  int32_t* size = p->swap_guard ? ws.size : nullptr;
+  int32_t* size = size0;
   uint32_t* cur = ws.fr_a;
   uint32_t* next = ws.fr_b;
   double tau = p->tolerance;
@@ -473,6 +477,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
   if (aggregated) {
     launch_lookup(state->C, N, Cl, st);
     launch_sigma_from_members(state->C, state->K, N, state->Sigma, st);
+    if (state->size) launch_community_sizes(state->C, N, state->size, st);
   }
   LV_HIP(hipMemsetAsync(ws.ctr + CTR_AUX0, 0, sizeof(int64_t), st));
   hipLaunchKernelGGL(k_popcount, dim3(grid_for(ws.words, kBlock, 1024)), dim3(kBlock), 0, st, ws.ever, ws.words,
@@ -637,32 +642,50 @@ lv_status apply_batch(lv_graph* g, const lv_edges* del, const lv_edges* ins, voi
   int64_t* host = nullptr;
   if ((s = pinned(&host))) return s;
   if (del->count + ins->count == 0) return LV_OK;
+  const int64_t U = del->count + ins->count, E = 2 * U;
   BatchScratch b;
-  b.del_size = pow2_at_least(2 * del->count + 2);
-  b.ins_size = pow2_at_least(2 * ins->count + 2);
-  size_t need = align_up(8ull * b.del_size) + align_up(4ull * b.del_size) + align_up(8ull * b.ins_size) +
-                align_up(16ull * del->count + 8) + align_up(8ull * ins->count + 8);
+  b.size = static_cast<int64_t>(pow2_at_least(2 * U + 2));
+  b.dirs = E;
+  const int64_t chunks = batch_chunks_bound(E, g->cap);
+  size_t need = 0;
+  auto room = [&](size_t bytes) { need += align_up(bytes); };
+  room(8ull * b.size);
+  room(4ull * b.size);
+  room(4ull * b.size);
+  room(16ull * b.size);
+  room(4ull * U);
+  for (int k = 0; k < 10; ++k) room(4ull * E);
+  room(8ull * ins->count + 4);
+  room(4ull * chunks);
+  room(4ull * chunks);
+  room(8ull * del->count + 4);
+  room(8ull * del->count + 4);
   if (need > static_cast<size_t>(ws.pool_slots) * 4) return fail(LV_EWORKSPACE, "batch too large for the workspace pool");
   char* p = reinterpret_cast<char*>(ws.pool_keys);
-  b.del_keys = reinterpret_cast<uint64_t*>(p);
-  p += align_up(8ull * b.del_size);
-  b.del_vals = reinterpret_cast<int32_t*>(p);
-  p += align_up(4ull * b.del_size);
-  b.ins_keys = reinterpret_cast<uint64_t*>(p);
-  p += align_up(8ull * b.ins_size);
-  b.del_pos = reinterpret_cast<int64_t*>(p);
-  p += align_up(16ull * del->count + 8);
-  b.ins_kind = reinterpret_cast<int32_t*>(p);
-  b.row_zeroed = ws.ccount;
-  b.row_app = ws.coff;
-  LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_COUNT, st));
-  LV_HIP(hipMemsetAsync(b.del_keys, 0xFF, 8ull * b.del_size, st));
-  LV_HIP(hipMemsetAsync(b.ins_keys, 0xFF, 8ull * b.ins_size, st));
-  LV_HIP(hipMemsetAsync(b.row_zeroed, 0, sizeof(int32_t) * static_cast<size_t>(g->n), st));
-  LV_HIP(hipMemsetAsync(b.row_app, 0, sizeof(int32_t) * static_cast<size_t>(g->n), st));
-  launch_batch_validate(*del, *ins, g->n, b, ws.ctr, st);
-  launch_batch_find(*g, *del, *ins, b, ws.ctr, st);
-  launch_batch_capacity(*g, *del, *ins, b, ws.ctr, st);
+  auto grab = [&](size_t bytes) {
+    char* q = p;
+    p += align_up(bytes);
+    return q;
+  };
+  b.keys = reinterpret_cast<uint64_t*>(grab(8ull * b.size));
+  b.dw = reinterpret_cast<int32_t*>(grab(4ull * b.size));
+  b.iw = reinterpret_cast<int32_t*>(grab(4ull * b.size));
+  b.pos = reinterpret_cast<int64_t*>(grab(16ull * b.size));
+  b.slot = reinterpret_cast<int32_t*>(grab(4ull * U));
+  int32_t** per_dir[10] = {&b.row_of, &b.r_len, &b.r_cnt, &b.r_pbase, &b.r_zero,
+                           &b.r_app,  &b.r_hole, &b.r_tbase, &b.d_rank, &b.part};
+  for (int k = 0; k < 10; ++k) *per_dir[k] = reinterpret_cast<int32_t*>(grab(4ull * E));
+  b.kind = reinterpret_cast<int32_t*>(grab(8ull * ins->count + 4));
+  b.ch_row = reinterpret_cast<int32_t*>(grab(4ull * chunks));
+  b.ch_off = reinterpret_cast<int32_t*>(grab(4ull * chunks));
+  b.tcol = reinterpret_cast<int32_t*>(grab(8ull * del->count + 4));
+  b.tw = reinterpret_cast<int32_t*>(grab(8ull * del->count + 4));
+  b.tag = ws.dE;
+  b.row_slot = ws.ccount;
+  // phase 2 is gated on the device by the error slot, so the whole update
+  // is enqueued at once and the host waits a single time
+  launch_batch_phase1(*g, *del, *ins, b, ws.words, ws.ctr, st);
+  launch_batch_phase2(*g, *del, *ins, b, ws.ctr, st);
   LV_CHECK_LAUNCH();
   if ((s = read_counters(host, ws, CTR_COUNT, st))) return s;
   if (host[CTR_ERR]) {
@@ -673,8 +696,6 @@ lv_status apply_batch(lv_graph* g, const lv_edges* del, const lv_edges* ins, voi
                                              : "bad id, self-loop, non-positive weight or repeated pair";
     return fail(code, msg);
   }
-  launch_batch_apply(*g, *del, *ins, b, ws.ctr, st);
-  LV_CHECK_LAUNCH();
   return LV_OK;
 }
 

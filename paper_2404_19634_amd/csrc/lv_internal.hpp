@@ -30,6 +30,10 @@ constexpr int kHubClearSlots = 4096;      // table slots per clear unit of a hub
 // Device counters (int64 slots of Workspace::ctr).
 enum Ctr {
   CTR_BIN0 = 0,        // .. CTR_BIN0 + NBINS - 1: items per bin
+  CTR_B_ROWS = 0,      // apply_batch: touched rows (these four reuse the
+  CTR_B_CHUNKS = 1,    //   round slots, which apply_batch does not use)
+  CTR_B_PART = 2,      //   partner entries reserved
+  CTR_B_TMP = 3,       //   tail-survivor entries reserved
   CTR_POOL = 7,        // global hashtable slots handed out
   CTR_HUB_UNITS = 8,   // hub work units (insert / expand)
   CTR_HUB_CUNITS = 9,  // hub table-clear units
@@ -200,24 +204,38 @@ void launch_sum_squares(const int64_t* v, int32_t n, int64_t* out, hipStream_t s
 
 // batch.hip
 struct BatchScratch {
-  uint64_t* del_keys;   // canonical pair -> deletion weight
-  int32_t* del_vals;
-  uint32_t del_size;
-  uint64_t* ins_keys;   // canonical pair set of insertions
-  uint32_t ins_size;
-  int64_t* del_pos;     // 2 per deletion: arc positions of (u,v) and (v,u)
-  int32_t* ins_kind;    // 2 per insertion: 1 = merge into an existing arc, 0 = append
-  int32_t* row_zeroed;  // n: arcs of the row reaching weight 0
-  int32_t* row_app;     // n: arcs appended to the row
+  // table of the batch's undirected pairs (canonical key lo << 32 | hi)
+  uint64_t* keys;
+  int32_t* dw;      // deletion weight of the pair, 0 if none
+  int32_t* iw;      // insertion weight of the pair, 0 if none
+  int64_t* pos;     // 2 per slot: arc positions of lo -> hi and hi -> lo, -1 if absent
+  int64_t size;     // slots (power of two)
+  int32_t* slot;    // per update (deletions, then insertions): pair slot, -1 if invalid
+  int64_t dirs;     // 2 * updates: arc directions
+  // touched rows (at most dirs)
+  uint32_t* tag;    // n bits: row already listed
+  int32_t* row_slot;  // n: index of a listed row (read only where tagged)
+  int32_t* row_of;  // row index -> vertex
+  int32_t* r_len;   // length before the batch
+  int32_t* r_cnt;   // update directions on the row
+  int32_t* r_pbase; // first partner in `part`
+  int32_t* r_zero;  // arcs reaching weight 0
+  int32_t* r_app;   // arcs appended
+  int32_t* r_hole;  // head holes refilled so far
+  int32_t* r_tbase; // first tail survivor in tcol / tw
+  int32_t* d_rank;  // per direction: rank among its row's directions, -1 if invalid
+  int32_t* part;    // partners (other endpoints) grouped by row
+  int32_t* kind;    // per insertion direction: 1 merge, 0 append
+  int32_t* ch_row;  // scan chunk -> row index
+  int32_t* ch_off;  // scan chunk -> first arc
+  int32_t* tcol;    // tail survivors (at most 2 * deletions)
+  int32_t* tw;
 };
-void launch_batch_validate(const lv_edges& del, const lv_edges& ins, int32_t n, const BatchScratch& b,
-                           int64_t* ctr, hipStream_t st);
-void launch_batch_find(const lv_graph& g, const lv_edges& del, const lv_edges& ins, const BatchScratch& b,
-                       int64_t* ctr, hipStream_t st);
-void launch_batch_capacity(const lv_graph& g, const lv_edges& del, const lv_edges& ins, const BatchScratch& b,
-                           int64_t* ctr, hipStream_t st);
-void launch_batch_apply(const lv_graph& g, const lv_edges& del, const lv_edges& ins, const BatchScratch& b,
-                        int64_t* ctr, hipStream_t st);
+int64_t batch_chunks_bound(int64_t dirs, int64_t cap);
+void launch_batch_phase1(const lv_graph& g, const lv_edges& del, const lv_edges& ins, const BatchScratch& b,
+                         int64_t words, int64_t* ctr, hipStream_t st);
+void launch_batch_phase2(const lv_graph& g, const lv_edges& del, const lv_edges& ins, const BatchScratch& b,
+                         int64_t* ctr, hipStream_t st);
 
 // mark.hip
 void launch_mark_df(const lv_edges& del, const lv_edges& ins, const int32_t* C, uint32_t* fr,

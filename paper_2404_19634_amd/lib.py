@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes as ct
 import os
 from dataclasses import dataclass
+from typing import Optional
 
 import numpy as np
 import torch
@@ -45,7 +46,7 @@ class CEdges(ct.Structure):
 
 
 class CState(ct.Structure):
-    _fields_ = [("C", ct.c_void_p), ("K", ct.c_void_p), ("Sigma", ct.c_void_p)]
+    _fields_ = [("C", ct.c_void_p), ("K", ct.c_void_p), ("Sigma", ct.c_void_p), ("size", ct.c_void_p)]
 
 
 class Params(ct.Structure):
@@ -285,14 +286,21 @@ class Graph:
 
 @dataclass
 class State:
+    """C, K, Sigma on the device, plus the optional member count per
+    community (`size`).  A state returned by louvain_static carries `size`,
+    and the dynamic calls keep it exact; a state built from host arrays has
+    none, and the library then counts member sizes itself on every call."""
     C: torch.Tensor
     K: torch.Tensor
     Sigma: torch.Tensor
+    size: Optional[torch.Tensor] = None
 
     @classmethod
-    def empty(cls, n, device="cuda"):
+    def empty(cls, n, device="cuda", with_size=True):
+        """Output buffers for louvain_static (which fills all four)."""
         return cls(torch.zeros(n, dtype=torch.int32, device=device), torch.zeros(n, dtype=torch.int64, device=device),
-                   torch.zeros(n, dtype=torch.int64, device=device))
+                   torch.zeros(n, dtype=torch.int64, device=device),
+                   torch.zeros(n, dtype=torch.int32, device=device) if with_size else None)
 
     @classmethod
     def from_host(cls, C, K, S, device="cuda"):
@@ -301,13 +309,15 @@ class State:
                    torch.from_numpy(np.asarray(S, np.int64).copy()).to(device))
 
     def clone(self) -> "State":
-        return State(self.C.clone(), self.K.clone(), self.Sigma.clone())
+        return State(self.C.clone(), self.K.clone(), self.Sigma.clone(),
+                     None if self.size is None else self.size.clone())
 
     def host(self):
         return self.C.cpu().numpy(), self.K.cpu().numpy(), self.Sigma.cpu().numpy()
 
     def c(self) -> CState:
-        return CState(self.C.data_ptr(), self.K.data_ptr(), self.Sigma.data_ptr())
+        return CState(self.C.data_ptr(), self.K.data_ptr(), self.Sigma.data_ptr(),
+                      None if self.size is None else self.size.data_ptr())
 
 
 def apply_batch(g: Graph, b: Batch, stream=None):

@@ -133,8 +133,13 @@ def test_static_single_iteration(lib, case):
     _same_stats(gs, os_)
 
 
+def _sizes(C, n):
+    return np.bincount(np.asarray(C, np.int64), minlength=n).astype(np.int32)
+
+
+@pytest.mark.parametrize("carry_size", [False, True])
 @pytest.mark.parametrize("approach", ["nd", "ds", "df"])
-def test_dynamic_sync_bit_exact(lib, case, approach):
+def test_dynamic_sync_bit_exact(lib, case, approach, carry_size):
     name, e = case
     b = W.random_batch(e, max(10, e.m // 200), 77)
     G = _orc(e)
@@ -149,12 +154,16 @@ def test_dynamic_sync_bit_exact(lib, case, approach):
     assert np.array_equal(off, o_off) and np.array_equal(col, o_col) and np.array_equal(w, o_w)
     assert g.two_m == G.two_m
     st = lib.State.from_host(*state0)
+    if carry_size:  # member counts carried in from the previous state
+        st.size = torch.from_numpy(_sizes(state0[0], e.n)).cuda()
     st, gs = getattr(lib, "louvain_" + approach)(g, bb, st, mode="sync")
     C, K, S = st.host()
     assert np.array_equal(K, Kd)
     assert np.array_equal(C, Cd)
     assert np.array_equal(S, Sd)
     _same_stats(gs, os_)
+    if carry_size:
+        assert np.array_equal(st.size.cpu().numpy(), _sizes(C, e.n))
 
 
 @pytest.mark.parametrize("approach", ["static", "nd", "ds", "df"])
@@ -275,5 +284,53 @@ def test_chained_batches_df_sync(lib):
         sg, gs = lib.louvain_df(g, bb, sg, mode="sync")
         C, K, S = sg.host()
         assert np.array_equal(C, Co) and np.array_equal(K, Ko) and np.array_equal(S, Sto)
+        assert np.array_equal(sg.size.cpu().numpy(), _sizes(C, e.n))
         _same_stats(gs, os_)
         so = (Co, Ko, Sto)
+
+
+def test_static_fills_sizes(lib, case):
+    name, e = case
+    g = lib.Graph.from_edges(e)
+    for mode in ("sync", "async"):
+        st, _ = lib.louvain_static(g, mode=mode)
+        assert np.array_equal(st.size.cpu().numpy(), _sizes(st.host()[0], e.n))
+
+
+def _hub_batches(e, seed):
+    """Batches that hit the two hubs of the star graph hard: many whole and
+    partial deletions on one row (holes in its head and its tail), merges,
+    appends, and pairs deleted whole and re-inserted in the same batch."""
+    rng = np.random.default_rng(seed)
+    m = e.m
+    hub = np.flatnonzero((e.u == 0) | (e.u == 1))
+    pick = rng.choice(hub, size=len(hub) * 2 // 5, replace=False)
+    d_w = e.w[pick].copy()
+    part = rng.random(len(pick)) < 0.2
+    d_w[part & (d_w > 1)] -= 1
+    # re-insert a third of the whole deletions, append new pairs at the hub
+    whole = pick[~part | (e.w[pick] == 1)]
+    back = whole[: len(whole) // 3]
+    present = set(zip(e.u.tolist(), e.v.tolist()))
+    fresh = [(0, v) for v in range(3001, e.n) if (0, v) not in present][:150]
+    merge = rng.choice(np.setdiff1d(np.arange(m), pick), size=80, replace=False)
+    iu = np.concatenate([e.v[back], np.array([p[1] for p in fresh], np.int64), e.u[merge]]).astype(np.int32)
+    iv = np.concatenate([e.u[back], np.array([p[0] for p in fresh], np.int64), e.v[merge]]).astype(np.int32)
+    iw = rng.integers(1, 4, len(iu)).astype(np.int32)
+    return W.Batch(e.u[pick].copy(), e.v[pick].copy(), d_w, iu, iv, iw)
+
+
+def test_apply_batch_hub_rows(lib):
+    """Row-centric batch editing on rows of thousands of arcs, applied twice
+    in a row: CSR and 2m equal the oracle's after each batch."""
+    e = _star_plus(11)
+    G = _orc(e)
+    g = lib.Graph.from_edges(e, slack_frac=0.5, slack_min=8)
+    cur = e
+    for t in range(2):
+        b = _hub_batches(cur, 40 + t)
+        assert G.apply_batch(b) == 0
+        lib.apply_batch(g, lib.Batch.from_host(b))
+        assert all(np.array_equal(x, y) for x, y in zip(g.csr_host(), G.csr()))
+        assert g.two_m == G.two_m
+        cur = W.apply_batch_np(cur, b)
