@@ -22,7 +22,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "DF Louvain update latency p50/p99 & edges scanned/s vs GPU Static Louvain"
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published peak
+PROFILES = os.path.join(ROOT, "profiles")
+
+# Algorithmic bytes of the local-moving scan (Alg. 5): per scanned arc the
+# neighbour id, the weight and the neighbour's community (4 + 4 + 4 B); per
+# processed vertex its row start and length, K_i and C_i (8 + 4 + 8 + 4 B).
+# The frontier binning kernel reads one 4 B frontier word per 32 vertices
+# and, per active vertex, its row length and one list entry (4 + 4 B).
+SCAN_BYTES_PER_ARC = 12
+SCAN_BYTES_PER_VERTEX = 24
+BIN_BYTES_PER_WORD = 4
+BIN_BYTES_PER_VERTEX = 8
 
 
 def log(*a):
@@ -73,6 +84,57 @@ class ProfilerRegion:
     def pause(self):
         if self.lib is not None:
             self.lib.roctxRangePop()
+
+
+class KernelMeter:
+    """Per-kernel launches, event time and algorithmic bytes, summed over
+    the louvain_* calls it is fed (lv_stats of each call)."""
+
+    def __init__(self, lib, n):
+        self.lib, self.n = lib, n
+        self.launches = [0] * lib.NTIMED
+        self.ms = [0.0] * lib.NTIMED
+        self.bytes = [0] * lib.NTIMED
+        self.work_launches = [0] * lib.NTIMED
+
+    def add(self, s):
+        L = self.lib
+        for k in range(L.NTIMED):
+            self.launches[k] += s["timed_launches"][k]
+            self.ms[k] += s["timed_ms"][k]
+        for b in range(L.NBINS):
+            self.bytes[b] += SCAN_BYTES_PER_ARC * s["bin_arcs"][b] + SCAN_BYTES_PER_VERTEX * s["bin_vertices"][b]
+            self.work_launches[b] += s["bin_launches"][b]
+        # binning runs once per sub-round; its launches are known when timed
+        words = (self.n + 31) // 32
+        nbin = s["timed_launches"][L.TIME_BINNING]
+        self.bytes[L.TIME_BINNING] += BIN_BYTES_PER_WORD * words * nbin + BIN_BYTES_PER_VERTEX * sum(s["bin_vertices"])
+        self.work_launches[L.TIME_BINNING] += nbin
+
+    def dominant(self):
+        return max(range(self.lib.NTIMED), key=lambda k: self.ms[k])
+
+
+def traffic_for(kernel_name):
+    """HBM bytes per launch of `kernel_name` from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there
+    is none or the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(PROFILES, f"traffic_{kernel_name}_rmat22_df.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2404_19634_amd", "csrc", "move.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv.get("move_hip_sha256_16"):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def pct(x, q):
@@ -185,13 +247,20 @@ def main():
     log(f"static: {np.median(static_ms):.2f} ms, arcs scanned {static_arcs[-1]}, Q={q_static:.6f}, "
         f"passes {static_stats['passes']} iters {static_stats['iterations']}")
 
-    # DF steps
+    # DF steps.  The warmup times every scan kernel (HIP events) to find the
+    # one that dominates; the timed region brackets only that kernel.
     state = state0.clone()
     lat, apply_ms, arcs, per_size = [], [], [], {}
     relayouts = 0
+    warm = KernelMeter(lib, e.n)
+    meter = KernelMeter(lib, e.n)
+    lib.set_timing(range(lib.NTIMED))
     torch.cuda.synchronize()
+    dom = None
     for k in range(total):
         if k == args.warmup:
+            dom = warm.dominant() if args.warmup else lib.TIME_BINNING
+            lib.set_timing([dom])
             torch.cuda.synchronize()
             region.resume()
             t_region = time.perf_counter()
@@ -210,6 +279,7 @@ def main():
         state, s = lib.louvain_df(g, b, state, prm)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        (meter if k >= args.warmup else warm).add(s)
         if k >= args.warmup:
             apply_ms.append((t1 - t) * 1e3)
             lat.append((t2 - t1) * 1e3)
@@ -218,6 +288,7 @@ def main():
     torch.cuda.synchronize()
     region_s = time.perf_counter() - t_region
     region.pause()
+    lib.set_timing(())
     q_df = lib.modularity(g, state.C)
 
     # static Louvain on the final graph, same mode (quality and time reference)
@@ -260,6 +331,21 @@ def main():
         "modularity": {"static_initial": q_static, "df_final": q_df, "static_final": q_static_final},
         "static_final_ms": static_final_ms,
     }
+    names = [f"k_move_small<{g}>" for g in (4, 8, 16, 32)] + ["k_move_wave", "k_move_block", "k_hub_insert",
+                                                             "k_bin_frontier"]
+    short = ["move_small4", "move_small8", "move_small16", "move_small32", "move_wave", "move_block", "hub_insert",
+             "bin_frontier"]
+    nl = meter.launches[dom]
+    if nl and meter.ms[dom] > 0:
+        per_launch = meter.bytes[dom] / max(1, meter.work_launches[dom])
+        achieved = per_launch / (meter.ms[dom] / nl * 1e-3) / 1e9
+        tr = traffic_for(short[dom])
+        out["roofline"] = {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": names[dom],
+            "launches": nl, "avg_launch_us": meter.ms[dom] / nl * 1e3, "bytes_per_launch": per_launch,
+            "warmup_kernel_ms": {lib.TIMED[k]: round(warm.ms[k], 4) for k in range(lib.NTIMED)},
+        }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(e, batches[2])

@@ -110,6 +110,15 @@ typedef struct {
   int32_t swap_guard;           /* 1: a singleton never joins a singleton of larger id */
 } lv_params;
 
+/* Degree bins of the local-moving scan: rows of up to 4, 8, 16, 32 arcs
+ * (lane groups), up to the wavefront threshold (one wavefront, LDS table),
+ * up to 2048 arcs (one workgroup, LDS table), and longer hub rows (several
+ * workgroups, global table). */
+enum { LV_BIN_G4 = 0, LV_BIN_G8, LV_BIN_G16, LV_BIN_G32, LV_BIN_WAVE, LV_BIN_BLOCK, LV_BIN_HUB, LV_NBINS };
+/* Kernels the measurement hook can time: the scan kernel of each bin (for
+ * hub rows, the insert kernel) and the frontier binning kernel. */
+enum { LV_TIME_BINNING = LV_NBINS, LV_NTIMED };
+
 /* Per-run statistics.  The first block matches the oracle's layout. */
 typedef struct {
   int32_t passes;
@@ -127,6 +136,17 @@ typedef struct {
   float ms_aggregate;  /* renumber, lookup, aggregation */
   float ms_other;      /* output consistency, setup */
   int64_t arcs_aggregated; /* arcs read by aggregation */
+  /* Local-moving work per degree bin (index LV_BIN_*): vertices processed,
+   * arcs scanned, launches of the bin's scan kernel (for hub rows: the
+   * insert kernel).  Summed over every iteration, pass and sub-round. */
+  int64_t bin_vertices[LV_NBINS];
+  int64_t bin_arcs[LV_NBINS];
+  int32_t bin_launches[LV_NBINS];
+  /* Launches bracketed by timing events (lv_set_timing) and their summed
+   * GPU time, per timed kernel (index LV_BIN_* or LV_TIME_BINNING); zero
+   * for kernels that are not timed. */
+  int32_t timed_launches[LV_NTIMED];
+  double timed_ms[LV_NTIMED];
 } lv_stats;
 
 /* Tunables chosen by the autotuner (degree-bin thresholds and launch
@@ -221,6 +241,15 @@ lv_status modularity(const lv_graph* g, const int32_t* C, double* q_host, void* 
                      void* stream);
 
 /* Set or read the tuning table used by the calls above (process-wide). */
+/* Measurement hook.  lv_set_timing(mask) makes every later louvain_* call
+ * bracket each launch of the kernels whose bit k is set in `mask` (k =
+ * LV_BIN_* or LV_TIME_BINNING) with a pair of HIP events on the call's
+ * stream, and report their count and summed time in lv_stats.  Each event
+ * adds a little time between launches, so a latency measurement should
+ * time one kernel at most.  Up to 4096 launches per call are timed; mask 0
+ * turns timing off.  Process-wide setting; LV_EINVAL for unknown bits. */
+lv_status lv_set_timing(uint32_t mask);
+
 void lv_set_tuning(const lv_tuning* t);
 void lv_get_tuning(lv_tuning* t);
 

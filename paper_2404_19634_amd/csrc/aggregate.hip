@@ -60,33 +60,51 @@ __global__ void k_member_degrees(const int32_t* __restrict__ cmem, const int32_t
 }
 
 // Split communities by volume; big ones get a global table (their insert /
-// emit units are written by k_big_units).
-__global__ void k_bin_communities(const int64_t* __restrict__ out_start, int32_t nc, int32_t* __restrict__ small,
-                                  int32_t* __restrict__ medium, int32_t* __restrict__ big,
-                                  int64_t* __restrict__ big_off, int32_t* __restrict__ out_len,
-                                  int64_t* __restrict__ Kout, int64_t* __restrict__ Sout, int64_t* __restrict__ ctr) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t c0 = blockIdx.x * static_cast<int64_t>(blockDim.x); c0 < nc; c0 += stride) {
-    const int64_t c = c0 + threadIdx.x;
-    const bool valid = c < nc;
-    int64_t vol = 0;
-    if (valid) {
-      vol = out_start[c + 1] - out_start[c];
+// emit units are written by k_big_units).  Each thread takes kBinItems
+// consecutive communities and each workgroup reserves its list entries with
+// one atomic per list.
+constexpr int kBinItems = 16;
+__global__ void __launch_bounds__(kBlock) k_bin_communities(const int64_t* __restrict__ out_start, int32_t nc,
+                                  int32_t* __restrict__ small, int32_t* __restrict__ medium,
+                                  int32_t* __restrict__ big, int64_t* __restrict__ big_off,
+                                  int32_t* __restrict__ out_len, int64_t* __restrict__ Kout,
+                                  int64_t* __restrict__ Sout, int64_t* __restrict__ ctr) {
+  __shared__ int64_t lds[kBlock / kWave + 1];
+  const int64_t span = static_cast<int64_t>(kBlock) * kBinItems;
+  for (int64_t c0 = blockIdx.x * span; c0 < nc; c0 += static_cast<int64_t>(gridDim.x) * span) {
+    const int64_t first = c0 + static_cast<int64_t>(threadIdx.x) * kBinItems;
+    int64_t ns = 0, nm = 0, nb = 0, pool = 0;
+    for (int q = 0; q < kBinItems && first + q < nc; ++q) {
+      const int64_t c = first + q;
+      const int64_t vol = out_start[c + 1] - out_start[c];
       if (vol == 0 || vol > kAggBlockVol) {  // empty rows and big rows start from zero
         out_len[c] = 0;
         Kout[c] = 0;
         Sout[c] = 0;
       }
+      ns += (vol > 0 && vol <= kAggWaveVol) ? 1 : 0;
+      nm += (vol > kAggWaveVol && vol <= kAggBlockVol) ? 1 : 0;
+      if (vol > kAggBlockVol) {
+        nb += 1;
+        pool += big_slots(vol, nc);
+      }
     }
-    const int64_t ps = wave_append(valid && vol > 0 && vol <= kAggWaveVol, &ctr[CTR_AGG_SMALL]);
-    if (ps >= 0) small[ps] = static_cast<int32_t>(c);
-    const int64_t pm = wave_append(valid && vol > kAggWaveVol && vol <= kAggBlockVol, &ctr[CTR_AGG_MEDIUM]);
-    if (pm >= 0) medium[pm] = static_cast<int32_t>(c);
-    const int64_t pb = wave_append(valid && vol > kAggBlockVol, &ctr[CTR_AGG_BIG]);
-    if (pb >= 0) {
-      big[pb] = static_cast<int32_t>(c);
-      big_off[pb] = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_POOL]),
-                                                   static_cast<unsigned long long>(big_slots(vol, nc))));
+    int64_t ps = block_reserve(ns, &ctr[CTR_AGG_SMALL], lds);
+    int64_t pm = block_reserve(nm, &ctr[CTR_AGG_MEDIUM], lds);
+    int64_t pb = block_reserve(nb, &ctr[CTR_AGG_BIG], lds);
+    int64_t pp = block_reserve(pool, &ctr[CTR_POOL], lds);
+    for (int q = 0; q < kBinItems && first + q < nc; ++q) {
+      const int64_t c = first + q;
+      const int64_t vol = out_start[c + 1] - out_start[c];
+      if (vol > 0 && vol <= kAggWaveVol) {
+        small[ps++] = static_cast<int32_t>(c);
+      } else if (vol > kAggWaveVol && vol <= kAggBlockVol) {
+        medium[pm++] = static_cast<int32_t>(c);
+      } else if (vol > kAggBlockVol) {
+        big[pb] = static_cast<int32_t>(c);
+        big_off[pb++] = pp;
+        pp += big_slots(vol, nc);
+      }
     }
   }
 }
@@ -534,9 +552,10 @@ void launch_aggregate(const LevelGraph& g, const int32_t* C, int32_t nc, LevelGr
                      g.n, ws.i64tmp);
   exclusive_scan_i64(ws.i64tmp, ws.vol, g.n, ws, st);
   out.n = nc;
-  (void)hipMemsetAsync(ws.ctr + CTR_AGG_SMALL, 0, sizeof(int64_t) * 5, st);
+  (void)hipMemsetAsync(ws.ctr + CTR_AGG_SMALL, 0, sizeof(int64_t) * 5 * kCtrLine, st);
   (void)hipMemsetAsync(ws.ctr + CTR_POOL, 0, sizeof(int64_t), st);
-  hipLaunchKernelGGL(k_bin_communities, dim3(grid_for(nc, kBlock, 4096)), dim3(kBlock), 0, st, out.row_start, nc,
+  hipLaunchKernelGGL(k_bin_communities, dim3(grid_for(nc, kBlock * kBinItems, 4096)), dim3(kBlock), 0, st,
+                     out.row_start, nc,
                      ws.bins[0], ws.bins[1], ws.bins[2], ws.hub_off, out.row_len, Kout, Sout, ws.ctr);
   hipLaunchKernelGGL(k_merge_wave, dim3(tu.blocks_wave), dim3(kBlock), 0, st, g.row_start, g.row_len, g.col,
                      g.w, C, ws.coff, ws.cmem, ws.bins[0], ws.ctr, out.row_start, out.row_len, out.col, out.w,

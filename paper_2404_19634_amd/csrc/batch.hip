@@ -86,22 +86,6 @@ struct Upd {
   }
 };
 
-// Wave-aggregated reservation of `count` consecutive entries of *total.
-__device__ __forceinline__ int64_t wave_reserve(int64_t count, int64_t* total) {
-  const int lane = lane_id();
-  int64_t incl = count;
-  for (int s = 1; s < kWave; s <<= 1) {
-    const int64_t t = __shfl_up(incl, s);
-    if (lane >= s) incl += t;
-  }
-  int64_t base = 0;
-  if (lane == kWave - 1 && incl)
-    base = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(total),
-                                          static_cast<unsigned long long>(incl)));
-  base = __shfl(base, kWave - 1);
-  return base + incl - count;
-}
-
 __device__ __forceinline__ bool failed(const int64_t* ctr) {
   return *reinterpret_cast<const volatile int64_t*>(&ctr[CTR_ERR]) != 0;
 }
@@ -126,57 +110,52 @@ __global__ void k_init(BatchScratch b, int64_t words, int64_t* __restrict__ ctr)
   for (int64_t i = t0; i < CTR_COUNT; i += stride) ctr[i] = 0;
 }
 
-// Validation, the pair table, and the list of touched rows.
-__global__ void k_validate(Upd U, int32_t n, BatchScratch b, int64_t* __restrict__ ctr) {
+// Validation, the pair table, and the touched rows.  A row is listed
+// under the first direction that reaches it: row_slot[vertex] = that
+// direction's index e, row_of[e] = vertex (-1 for every other direction).
+__global__ void __launch_bounds__(kBlock) k_validate(Upd U, int32_t n, BatchScratch b, int64_t* __restrict__ ctr) {
+  __shared__ int64_t lds[kBlock / kWave];
   int64_t si = 0, sd = 0;
   const int64_t total = U.nd + U.ni;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  // whole waves iterate together (wave-aggregated row reservation)
-  for (int64_t k0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + (threadIdx.x & ~(kWave - 1)); k0 < total;
-       k0 += stride) {
-    const int64_t k = k0 + lane_id();
-    bool ok = false;
-    int32_t a = 0, c = 0;
-    if (k < total) {
-      const bool del = k < U.nd;
-      a = del ? U.du[k] : U.iu[k - U.nd];
-      c = del ? U.dv[k] : U.iv[k - U.nd];
-      const int32_t x = del ? U.dw[k] : U.iw[k - U.nd];
-      ok = a >= 0 && c >= 0 && a < n && c < n && a != c && x > 0;
-      int32_t h = -1;
-      if (ok) {
-        h = static_cast<int32_t>(pair_insert(b.keys, b.size, canon(a, c)));
-        if (atomicCAS(del ? &b.dw[h] : &b.iw[h], 0, x) != 0) ok = false;  // pair repeated on this side
-      }
-      if (ok) {
-        if (del)
-          sd += x;
-        else
-          si += x;
-      }
-      if (!ok) {
-        set_error(ctr, LV_EINVAL);
-        h = -1;
-      }
-      b.slot[k] = h;
+  for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < total;
+       k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const bool del = k < U.nd;
+    const int32_t a = del ? U.du[k] : U.iu[k - U.nd];
+    const int32_t c = del ? U.dv[k] : U.iv[k - U.nd];
+    const int32_t x = del ? U.dw[k] : U.iw[k - U.nd];
+    bool ok = a >= 0 && c >= 0 && a < n && c < n && a != c && x > 0;
+    int32_t h = -1;
+    if (ok) {
+      h = static_cast<int32_t>(pair_insert(b.keys, b.size, canon(a, c)));
+      if (atomicCAS(del ? &b.dw[h] : &b.iw[h], 0, x) != 0) ok = false;  // pair repeated on this side
     }
+    if (ok) {
+      if (del)
+        sd += x;
+      else
+        si += x;
+    } else {
+      set_error(ctr, LV_EINVAL);
+      h = -1;
+    }
+    b.slot[k] = h;
     for (int side = 0; side < 2; ++side) {
       const int32_t r = side ? c : a;
-      bool first = false;
+      const int64_t e = 2 * k + side;
+      int32_t head = -1;
       if (ok) {
         const uint32_t bit = 1u << (r & 31);
-        first = (atomicOr(&b.tag[r >> 5], bit) & bit) == 0;
+        if ((atomicOr(&b.tag[r >> 5], bit) & bit) == 0) {
+          b.row_slot[r] = static_cast<int32_t>(e);
+          head = r;
+        }
       }
-      const int64_t slot = wave_append(first, &ctr[CTR_B_ROWS]);
-      if (first) {
-        b.row_slot[r] = static_cast<int32_t>(slot);
-        b.row_of[slot] = r;
-      }
+      b.row_of[e] = head;
     }
   }
-  si = wave_sum_i64(si);
-  sd = wave_sum_i64(sd);
-  if (lane_id() == 0) {
+  si = block_sum(si, lds);
+  sd = block_sum(sd, lds);
+  if (threadIdx.x == 0) {
     if (si) atomic_add_i64(&ctr[CTR_AUX2], si);
     if (sd) atomic_add_i64(&ctr[CTR_AUX3], sd);
   }
@@ -198,26 +177,38 @@ __global__ void k_rank(Upd U, BatchScratch b) {
 }
 
 // per touched row: its length, its range in the partner list, its chunks
-__global__ void k_rows(const int32_t* __restrict__ row_len, BatchScratch b, int64_t* __restrict__ ctr) {
-  const int64_t rows = ctr[CTR_B_ROWS];
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t r0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + (threadIdx.x & ~(kWave - 1)); r0 < rows;
-       r0 += stride) {
-    const int64_t r = r0 + lane_id();
+// (one packed reservation, chunks << 32 | partners, per workgroup).
+__global__ void __launch_bounds__(kBlock) k_rows(const int64_t* __restrict__ row_start,
+                                                 const int32_t* __restrict__ row_len, BatchScratch b,
+                                                 int64_t* __restrict__ ctr) {
+  __shared__ int64_t lds[kBlock / kWave + 1];
+  for (int64_t r0 = blockIdx.x * static_cast<int64_t>(kBlock); r0 < b.dirs;
+       r0 += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int64_t r = r0 + threadIdx.x;
+    const int32_t a = r < b.dirs ? b.row_of[r] : -1;
     int32_t len = 0, cnt = 0;
-    if (r < rows) {
-      len = row_len[b.row_of[r]];
+    if (a >= 0) {
+      len = row_len[a];
       cnt = b.r_cnt[r];
       b.r_len[r] = len;
     }
     const int64_t nch = (len + kChunk - 1) / kChunk;
-    const int64_t pbase = wave_reserve(cnt, &ctr[CTR_B_PART]);
-    const int64_t cbase = wave_reserve(nch, &ctr[CTR_B_CHUNKS]);
-    if (r < rows) {
-      b.r_pbase[r] = static_cast<int32_t>(pbase);
+    const int64_t at = block_reserve(a >= 0 ? ((nch << 32) | cnt) : 0, &ctr[CTR_B_RESV], lds);
+    if (a >= 0) {
+      const int32_t pbase = static_cast<int32_t>(at & 0xffffffffll);
+      const int64_t cbase = at >> 32;
+      const int64_t s = row_start[a];
+      b.r_pbase[r] = pbase;
       for (int64_t j = 0; j < nch; ++j) {
-        b.ch_row[cbase + j] = static_cast<int32_t>(r);
-        b.ch_off[cbase + j] = static_cast<int32_t>(j * kChunk);
+        BatchScratch::Chunk c;
+        c.s = s;
+        c.a = a;
+        c.off = static_cast<int32_t>(j * kChunk);
+        c.end = static_cast<int32_t>(min(static_cast<int64_t>(len), (j + 1) * kChunk));
+        c.cnt = cnt;
+        c.pbase = pbase;
+        c.pad = 0;
+        b.chunk[cbase + j] = c;
       }
     }
   }
@@ -245,16 +236,12 @@ __global__ void __launch_bounds__(kBlock) k_scan(const int64_t* __restrict__ row
   const int lane = lane_id();
   const int wv = threadIdx.x / kWave;
   uint32_t* F = filt[wv];
-  const int64_t chunks = ctr[CTR_B_CHUNKS];
+  const int64_t chunks = ctr[CTR_B_RESV] >> 32;
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * kScanWaves;
   for (int64_t ch = blockIdx.x * static_cast<int64_t>(kScanWaves) + wv; ch < chunks; ch += nwaves) {
-    const int32_t r = b.ch_row[ch];
-    const int32_t a = b.row_of[r];
-    const int32_t cnt = b.r_cnt[r];
-    const int32_t pbase = b.r_pbase[r];
-    const int32_t off = b.ch_off[ch];
-    const int32_t end = min(b.r_len[r], off + kChunk);
-    const int64_t s = row_start[a];
+    const BatchScratch::Chunk c = b.chunk[ch];
+    const int32_t a = c.a, cnt = c.cnt, pbase = c.pbase, off = c.off, end = c.end;
+    const int64_t s = c.s;
     for (int i = lane; i < kFilterBits / 32; i += kWave) F[i] = 0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -312,10 +299,10 @@ __global__ void k_capacity(const int64_t* __restrict__ row_start, const int64_t*
     const int64_t nm = *two_m + 2 * ctr[CTR_AUX2] - 2 * ctr[CTR_AUX3];
     if (nm >= (int64_t(1) << 31)) set_error(ctr, LV_EOVERFLOW);
   }
-  const int64_t rows = ctr[CTR_B_ROWS];
-  for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < rows;
+  for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < b.dirs;
        r += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int32_t a = b.row_of[r];
+    if (a < 0) continue;
     const int64_t need = static_cast<int64_t>(b.r_len[r]) - b.r_zero[r] + b.r_app[r];
     if (need > row_start[a + 1] - row_start[a]) set_error(ctr, LV_ENOSLACK);
   }
@@ -341,41 +328,56 @@ __global__ void k_apply(Upd U, int32_t* __restrict__ wt, int64_t* __restrict__ t
   }
 }
 
-// One wavefront per row with zeroed arcs: the new length is L' = L - zeroed;
-// the arcs of the tail [L', L) that survive are copied out (they refill the
-// holes of the head [0, L') in k_fill) and the row is cut to L'.
+// Rows with zeroed arcs: the new length is L' = L - zeroed; the arcs of
+// the tail [L', L) that survive are copied out (they refill the holes of
+// the head [0, L') in k_fill) and the row is cut to L'.  The copies go to
+// the row's partner range (zeroed <= partners).  A lane handles a row whose
+// tail is short; longer tails take the whole wavefront.
+constexpr int kTailLane = 16;
 __global__ void __launch_bounds__(kBlock) k_tail(const int64_t* __restrict__ row_start, int32_t* __restrict__ row_len,
                                                  const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
-                                                 BatchScratch b, int64_t* __restrict__ ctr) {
+                                                 BatchScratch b, const int64_t* __restrict__ ctr) {
   if (failed(ctr)) return;
   const int lane = lane_id();
-  const int64_t rows = ctr[CTR_B_ROWS];
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
-  for (int64_t r = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave; r < rows; r += nwaves) {
-    const int32_t z = b.r_zero[r];
-    if (z == 0) continue;
-    const int32_t a = b.row_of[r];
-    const int32_t L = b.r_len[r], Lp = L - z;
-    const int64_t s = row_start[a];
-    int64_t base = 0;
-    if (lane == 0) base = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_B_TMP]),
-                                                         static_cast<unsigned long long>(z)));
-    base = __shfl(base, 0);
-    int32_t out = 0;
-    for (int32_t k0 = Lp; k0 < L; k0 += kWave) {
-      const int32_t k = k0 + lane;
-      const bool keep = k < L && wt[s + k] > 0;
-      const uint64_t m = __ballot(keep);
-      if (keep) {
-        const int64_t q = base + out + __popcll(m & ((1ull << lane) - 1ull));
-        b.tcol[q] = col[s + k];
-        b.tw[q] = wt[s + k];
+  for (int64_t s0 = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave * kWave; s0 < b.dirs;
+       s0 += nwaves * kWave) {
+    const int64_t e = s0 + lane;
+    const int32_t a = e < b.dirs ? b.row_of[e] : -1;
+    const int32_t z = a >= 0 ? b.r_zero[e] : 0;
+    if (z > 0 && z <= kTailLane) {
+      const int32_t L = b.r_len[e], Lp = L - z;
+      const int64_t s = row_start[a];
+      int64_t q = b.r_pbase[e];
+      for (int32_t k = Lp; k < L; ++k) {
+        const int32_t x = wt[s + k];
+        if (x > 0) {
+          b.tcol[q] = col[s + k];
+          b.tw[q] = x;
+          ++q;
+        }
       }
-      out += __popcll(m);
-    }
-    if (lane == 0) {
-      b.r_tbase[r] = static_cast<int32_t>(base);
       row_len[a] = Lp;
+    }
+    for (uint64_t m = __ballot(z > kTailLane); m; m &= m - 1) {
+      const int64_t r = s0 + (__ffsll(static_cast<unsigned long long>(m)) - 1);
+      const int32_t ra = b.row_of[r];
+      const int32_t L = b.r_len[r], Lp = L - b.r_zero[r];
+      const int64_t s = row_start[ra];
+      const int64_t base = b.r_pbase[r];
+      int32_t out = 0;
+      for (int32_t k0 = Lp; k0 < L; k0 += kWave) {
+        const int32_t k = k0 + lane;
+        const bool keep = k < L && wt[s + k] > 0;
+        const uint64_t km = __ballot(keep);
+        if (keep) {
+          const int64_t q = base + out + __popcll(km & ((1ull << lane) - 1ull));
+          b.tcol[q] = col[s + k];
+          b.tw[q] = wt[s + k];
+        }
+        out += __popcll(km);
+      }
+      if (lane == 0) row_len[ra] = Lp;
     }
   }
 }
@@ -399,8 +401,8 @@ __global__ void k_fill(Upd U, const int64_t* __restrict__ row_start, int32_t* __
       const int32_t Lp = b.r_len[r] - b.r_zero[r];
       if (p - s >= Lp || wt[p] != 0) continue;  // tail arc, or weight left
       const int32_t j = atomicAdd(&b.r_hole[r], 1);
-      col[p] = b.tcol[b.r_tbase[r] + j];
-      wt[p] = b.tw[b.r_tbase[r] + j];
+      col[p] = b.tcol[b.r_pbase[r] + j];
+      wt[p] = b.tw[b.r_pbase[r] + j];
     } else if (!b.kind[e - 2 * U.nd]) {
       const int64_t q = s + atomicAdd(&row_len[a], 1);
       col[q] = c;
@@ -423,9 +425,9 @@ void launch_batch_phase1(const lv_graph& g, const lv_edges& del, const lv_edges&
   const int64_t total = del.count + ins.count, dirs = 2 * total;
   hipLaunchKernelGGL(k_init, dim3(grid_for(std::max<int64_t>(std::max<int64_t>(b.size, dirs), words), kBlock, 2048)),
                      dim3(kBlock), 0, st, b, words, ctr);
-  hipLaunchKernelGGL(k_validate, dim3(grid_for(total, kBlock, 4096)), dim3(kBlock), 0, st, U, g.n, b, ctr);
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(total, kBlock, 256)), dim3(kBlock), 0, st, U, g.n, b, ctr);
   hipLaunchKernelGGL(k_rank, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, U, b);
-  hipLaunchKernelGGL(k_rows, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, g.row_len, b, ctr);
+  hipLaunchKernelGGL(k_rows, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, g.row_start, g.row_len, b, ctr);
   hipLaunchKernelGGL(k_place, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, U, b);
   // chunks: one per touched row plus one per kChunk arcs of long rows; the
   // grid covers a few per touched row and strides over the rest
@@ -442,7 +444,7 @@ void launch_batch_phase2(const lv_graph& g, const lv_edges& del, const lv_edges&
   const int64_t dirs = 2 * (del.count + ins.count);
   hipLaunchKernelGGL(k_apply, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, U, g.w, g.two_m, b, ctr);
   if (del.count)
-    hipLaunchKernelGGL(k_tail, dim3(grid_for(dirs * kWave, kBlock, 4096)), dim3(kBlock), 0, st, g.row_start,
+    hipLaunchKernelGGL(k_tail, dim3(grid_for(dirs, kBlock, 1024)), dim3(kBlock), 0, st, g.row_start,
                        g.row_len, g.col, g.w, b, ctr);
   hipLaunchKernelGGL(k_fill, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, U, g.row_start, g.row_len,
                      g.col, g.w, b, ctr);

@@ -6,6 +6,7 @@
 //   ΔQ_iteration = 2 * Σ gains / (2m)^2 <= τ   (FP64 on the host)
 // Between passes the communities are renumbered, the dendrogram looked up
 // and the level graph aggregated (Alg. 6); τ drops by the given factor.
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -57,12 +58,63 @@ thread_local Pinned g_pinned;
 lv_status pinned(int64_t** out) {
   if (!g_pinned.p) {
     void* q = nullptr;
-    LV_HIP(hipHostMalloc(&q, 4096, hipHostMallocDefault));
+    LV_HIP(hipHostMalloc(&q, sizeof(int64_t) * (CTR_COUNT + kCtrLine), hipHostMallocDefault));
     g_pinned.p = static_cast<int64_t*>(q);
   }
   *out = g_pinned.p;
   return LV_OK;
 }
+
+// ---- measurement hook (lv_set_timing) ------------------------------------
+std::atomic<uint32_t> g_timed_mask{0};
+constexpr int kTimerPairs = 4096;
+struct Timer {
+  std::vector<hipEvent_t> ev;   // 2 per launch, created on first use
+  std::vector<int> kernel;      // kernel of each recorded pair
+  int used = 0;                 // pairs recorded since the last collect
+  int open = -1;                // kernel whose first event is recorded
+  ~Timer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+thread_local Timer g_timer;
+
+}  // namespace
+
+void timer_begin(int kernel, hipStream_t st) {
+  if (!((g_timed_mask.load(std::memory_order_relaxed) >> kernel) & 1u)) return;
+  Timer& t = g_timer;
+  if (t.used >= kTimerPairs) return;
+  while (static_cast<int>(t.ev.size()) < 2 * (t.used + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    t.ev.push_back(e);
+  }
+  if (static_cast<int>(t.kernel.size()) < t.used + 1) t.kernel.resize(t.used + 1);
+  if (hipEventRecord(t.ev[2 * t.used], st) == hipSuccess) t.open = kernel;
+}
+
+void timer_end(int kernel, hipStream_t st) {
+  Timer& t = g_timer;
+  if (t.open != kernel) return;
+  t.open = -1;
+  if (hipEventRecord(t.ev[2 * t.used + 1], st) == hipSuccess) t.kernel[t.used++] = kernel;
+}
+
+void timer_collect(int32_t* launches, double* ms) {
+  Timer& t = g_timer;
+  for (int k = 0; k < t.used; ++k) {
+    float x = 0.f;
+    if (hipEventElapsedTime(&x, t.ev[2 * k], t.ev[2 * k + 1]) == hipSuccess) {
+      launches[t.kernel[k]] += 1;
+      ms[t.kernel[k]] += x;
+    }
+  }
+  t.used = 0;
+  t.open = -1;
+}
+
+namespace {
 
 // Timing events, one set per host thread.
 struct Events {
@@ -99,6 +151,13 @@ lv_status read_counters(int64_t* host, const Workspace& ws, int count, hipStream
   LV_HIP(hipMemcpyAsync(host, ws.ctr, sizeof(int64_t) * count, hipMemcpyDeviceToHost, st));
   LV_HIP(hipStreamSynchronize(st));
   return LV_OK;
+}
+
+// A per-iteration statistic summed over its replica lines.
+int64_t stat(const int64_t* host, int st) {
+  int64_t v = 0;
+  for (int r = 0; r < kStatReplicas; ++r) v += host[CTR_STATS + r * kStatStride + st];
+  return v;
 }
 
 lv_status read_i64(int64_t* host, const int64_t* dev, hipStream_t st) {
@@ -246,15 +305,6 @@ __global__ void k_fill_i64(int64_t* p, int64_t v, int64_t n) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
     p[i] = v;
-}
-
-__global__ void k_popcount(const uint32_t* bm, int64_t words, int64_t* out) {
-  int64_t s = 0;
-  for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < words;
-       k += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    s += __popc(bm[k]);
-  s = wave_sum_i64(s);
-  if (lane_id() == 0 && s) atomic_add_i64(out, s);
 }
 
 float ms_between(hipEvent_t a, hipEvent_t b) {
@@ -407,7 +457,9 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
         if (r > 0)  // fresh bin counts, unit counts and table pool for the sub-round
           LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_ROUND_END, st));
         launch_bin_frontier(a, ws, plan[r], st);
-        launch_move(a, ws, tu, bins_for_degrees(plan[r].deg_lo, plan[r].deg_hi, a.wave_max), st);
+        const uint32_t mask = bins_for_degrees(plan[r].deg_lo, plan[r].deg_hi, a.wave_max);
+        launch_move(a, ws, tu, mask, st);
+        for (int b = 0; b < NBINS; ++b) S.bin_launches[b] += (mask >> b) & 1u;
       }
       if (p->mode == LV_SYNC) launch_apply_moves(a, ws, st);
       if (pull) launch_pull_expand(a, ws, st);
@@ -416,10 +468,15 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
       std::swap(cur, next);
       if ((s = read_counters(host, ws, CTR_ITER_END, st))) return s;
       if (host[CTR_ERR]) return fail(static_cast<lv_status>(host[CTR_ERR]), "device error in local-moving");
-      const int64_t movers = host[CTR_MOVERS], gain = host[CTR_GAIN];
-      est_frontier = host[CTR_EXPAND];
+      const int64_t movers = stat(host, ST_MOVERS), gain = stat(host, ST_GAIN);
+      est_frontier = stat(host, ST_EXPAND);
       S.moves += movers;
-      S.arcs_scanned += host[CTR_ARCS];
+      S.arcs_scanned += stat(host, ST_ARCS);
+      S.vertices_affected += stat(host, ST_AFFECTED);
+      for (int b = 0; b < NBINS; ++b) {
+        S.bin_vertices[b] += stat(host, ST_BIN_V0 + b);
+        S.bin_arcs[b] += stat(host, ST_BIN_A0 + b);
+      }
       if (pass < LV_MAX_PASSES && it < LV_MAX_ITERS) {
         S.iter_moves[pass][it] = movers;
         S.iter_gain[pass][it] = gain;
@@ -479,13 +536,10 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     launch_sigma_from_members(state->C, state->K, N, state->Sigma, st);
     if (state->size) launch_community_sizes(state->C, N, state->size, st);
   }
-  LV_HIP(hipMemsetAsync(ws.ctr + CTR_AUX0, 0, sizeof(int64_t), st));
-  hipLaunchKernelGGL(k_popcount, dim3(grid_for(ws.words, kBlock, 1024)), dim3(kBlock), 0, st, ws.ever, ws.words,
-                     ws.ctr + CTR_AUX0);
   LV_CHECK_LAUNCH();
   LV_HIP(hipEventRecord(ev[7], st));
-  if ((s = read_counters(host, ws, CTR_COUNT, st))) return s;
-  S.vertices_affected = host[CTR_AUX0];
+  LV_HIP(hipStreamSynchronize(st));
+  timer_collect(S.timed_launches, S.timed_ms);
   S.ms_mark = ms_between(ev[0], ev[1]);
   S.ms_move = ms_move;
   S.ms_aggregate = ms_agg;
@@ -654,12 +708,9 @@ lv_status apply_batch(lv_graph* g, const lv_edges* del, const lv_edges* ins, voi
   room(4ull * b.size);
   room(16ull * b.size);
   room(4ull * U);
-  for (int k = 0; k < 10; ++k) room(4ull * E);
+  for (int k = 0; k < 11; ++k) room(4ull * E);
   room(8ull * ins->count + 4);
-  room(4ull * chunks);
-  room(4ull * chunks);
-  room(8ull * del->count + 4);
-  room(8ull * del->count + 4);
+  room(sizeof(BatchScratch::Chunk) * chunks);
   if (need > static_cast<size_t>(ws.pool_slots) * 4) return fail(LV_EWORKSPACE, "batch too large for the workspace pool");
   char* p = reinterpret_cast<char*>(ws.pool_keys);
   auto grab = [&](size_t bytes) {
@@ -672,14 +723,11 @@ lv_status apply_batch(lv_graph* g, const lv_edges* del, const lv_edges* ins, voi
   b.iw = reinterpret_cast<int32_t*>(grab(4ull * b.size));
   b.pos = reinterpret_cast<int64_t*>(grab(16ull * b.size));
   b.slot = reinterpret_cast<int32_t*>(grab(4ull * U));
-  int32_t** per_dir[10] = {&b.row_of, &b.r_len, &b.r_cnt, &b.r_pbase, &b.r_zero,
-                           &b.r_app,  &b.r_hole, &b.r_tbase, &b.d_rank, &b.part};
-  for (int k = 0; k < 10; ++k) *per_dir[k] = reinterpret_cast<int32_t*>(grab(4ull * E));
+  int32_t** per_dir[11] = {&b.row_of, &b.r_len,  &b.r_cnt, &b.r_pbase, &b.r_zero, &b.r_app,
+                           &b.r_hole, &b.d_rank, &b.part,  &b.tcol,    &b.tw};
+  for (int k = 0; k < 11; ++k) *per_dir[k] = reinterpret_cast<int32_t*>(grab(4ull * E));
   b.kind = reinterpret_cast<int32_t*>(grab(8ull * ins->count + 4));
-  b.ch_row = reinterpret_cast<int32_t*>(grab(4ull * chunks));
-  b.ch_off = reinterpret_cast<int32_t*>(grab(4ull * chunks));
-  b.tcol = reinterpret_cast<int32_t*>(grab(8ull * del->count + 4));
-  b.tw = reinterpret_cast<int32_t*>(grab(8ull * del->count + 4));
+  b.chunk = reinterpret_cast<BatchScratch::Chunk*>(grab(sizeof(BatchScratch::Chunk) * chunks));
   b.tag = ws.dE;
   b.row_slot = ws.ccount;
   // phase 2 is gated on the device by the error slot, so the whole update
@@ -747,8 +795,14 @@ lv_status modularity(const lv_graph* g, const int32_t* C, double* q_host, void* 
   if (two_m <= 0) return fail(LV_EEMPTY, "graph has no edges (2m = 0)");
   if (two_m >= (int64_t(1) << 31)) return fail(LV_EOVERFLOW, "total arc weight 2m >= 2^31");
   // Q = (2m Σσ_c - Σ_c Σ_c^2) / (2m)^2; the numerator is exact in int64
-  const int64_t qnum = two_m * host[CTR_AUX0] - host[CTR_AUX1];
+  const int64_t qnum = two_m * stat(host, ST_INTRA) - host[CTR_AUX1];
   *q_host = static_cast<double>(qnum) / (static_cast<double>(two_m) * static_cast<double>(two_m));
+  return LV_OK;
+}
+
+lv_status lv_set_timing(uint32_t mask) {
+  if (mask >> LV_NTIMED) return fail(LV_EINVAL, "unknown kernel for timing");
+  g_timed_mask.store(mask);
   return LV_OK;
 }
 

@@ -27,36 +27,52 @@ constexpr int kBlockMaxDegree = 2048;     // largest workgroup-bin row (LDS tabl
 constexpr int kHubUnitArcs = 8192;        // arcs per work unit of a hub row
 constexpr int kHubClearSlots = 4096;      // table slots per clear unit of a hub row
 
-// Device counters (int64 slots of Workspace::ctr).
+// Device counters (int64 slots of Workspace::ctr).  Device-scope atomics
+// on MI355X are executed at the memory side and serialise per 128-byte line
+// (about 12 ns each), so every counter owns a line of its own, and the
+// statistics summed by every workgroup are spread over kStatReplicas lines
+// (replica = workgroup id mod kStatReplicas) that the host adds up.
+constexpr int kCtrLine = 16;        // int64 slots per 128-byte line
+constexpr int kStatReplicas = 32;
+constexpr int kStatStride = 2 * kCtrLine;  // slots per replica (two lines)
 enum Ctr {
-  CTR_BIN0 = 0,        // .. CTR_BIN0 + NBINS - 1: items per bin
-  CTR_B_ROWS = 0,      // apply_batch: touched rows (these four reuse the
-  CTR_B_CHUNKS = 1,    //   round slots, which apply_batch does not use)
-  CTR_B_PART = 2,      //   partner entries reserved
-  CTR_B_TMP = 3,       //   tail-survivor entries reserved
-  CTR_POOL = 7,        // global hashtable slots handed out
-  CTR_HUB_UNITS = 8,   // hub work units (insert / expand)
-  CTR_HUB_CUNITS = 9,  // hub table-clear units
-  CTR_ROUND_END = 10,  // slots [0, CTR_ROUND_END) are cleared every sub-round
-  CTR_MOVERS = 10,     // moves decided this iteration
-  CTR_GAIN = 11,       // sum of movers' gains
-  CTR_ARCS = 12,       // arcs scanned this iteration
-  CTR_PROCESSED = 13,  // vertices processed this iteration
-  CTR_EXPAND = 14,     // arcs of movers (bound on the next frontier)
-  CTR_ERR = 15,        // error code (first nonzero wins)
-  CTR_TOTAL = 16,      // generic total (scans, counts)
-  CTR_AUX0 = 17,
-  CTR_AUX1 = 18,
-  CTR_AUX2 = 19,
-  CTR_AUX3 = 20,
-  CTR_ITER_END = 24,   // slots [0, CTR_ITER_END) are cleared every iteration
-  CTR_AGG_SMALL = 32,  // aggregation: communities per tier and unit counts
-  CTR_AGG_MEDIUM = 33,
-  CTR_AGG_BIG = 34,
-  CTR_UNITS_INS = 35,
-  CTR_UNITS_EMIT = 36,
-  CTR_COUNT = 64
+  CTR_BIN0 = 0,                          // lines 0 .. NBINS-1: items per bin (ctr_bin)
+  CTR_B_RESV = 0 * kCtrLine,             // apply_batch: packed (chunks << 32 | partners) reserved
+  CTR_POOL = 7 * kCtrLine,               // global hashtable slots handed out
+  CTR_HUB_UNITS = 8 * kCtrLine,          // hub work units (insert / expand)
+  CTR_HUB_CUNITS = 9 * kCtrLine,         // hub table-clear units
+  CTR_ROUND_END = 10 * kCtrLine,         // lines below are cleared every sub-round
+  CTR_ERR = 10 * kCtrLine,               // error code (first nonzero wins)
+  CTR_TOTAL = 11 * kCtrLine,             // generic total (scans, counts)
+  CTR_AUX0 = 12 * kCtrLine,
+  CTR_AUX1 = 13 * kCtrLine,
+  CTR_AUX2 = 14 * kCtrLine,
+  CTR_AUX3 = 15 * kCtrLine,
+  CTR_STATS = 16 * kCtrLine,             // kStatReplicas replicas of per-iteration statistics
+  CTR_ITER_END = 16 * kCtrLine + kStatReplicas * kStatStride,  // lines below are cleared every iteration
+  CTR_AGG_SMALL = CTR_ITER_END,          // aggregation: communities per tier and unit counts
+  CTR_AGG_MEDIUM = CTR_ITER_END + 1 * kCtrLine,
+  CTR_AGG_BIG = CTR_ITER_END + 2 * kCtrLine,
+  CTR_UNITS_INS = CTR_ITER_END + 3 * kCtrLine,
+  CTR_UNITS_EMIT = CTR_ITER_END + 4 * kCtrLine,
+  CTR_COUNT = CTR_ITER_END + 8 * kCtrLine
 };
+// per-iteration statistics, slots of every replica line
+enum Stat {
+  ST_MOVERS = 0,  // moves decided
+  ST_GAIN,        // sum of the movers' gains
+  ST_ARCS,        // arcs of processed vertices (edges scanned)
+  ST_PROCESSED,   // vertices processed
+  ST_EXPAND,      // arcs of movers (bound on the next frontier)
+  ST_AFFECTED,    // vertices processed for the first time in the call
+  ST_INTRA,       // modularity: weight of arcs inside communities
+  ST_BIN_V0,      // .. + NBINS - 1: vertices processed per bin
+  ST_BIN_A0 = ST_BIN_V0 + 7,  // .. + NBINS - 1: arcs scanned per bin
+  NSTATS = ST_BIN_A0 + 7
+};
+static_assert(NSTATS <= kStatStride, "statistics exceed a replica");
+constexpr int ctr_bin(int b) { return CTR_BIN0 + b * kCtrLine; }
+
 
 struct LevelGraph {
   int32_t n = 0;
@@ -138,6 +154,12 @@ __device__ __forceinline__ void set_error(int64_t* ctr, int64_t code) {
             static_cast<unsigned long long>(code));
 }
 
+// Adds v to statistic `st` in this workgroup's replica line.
+__device__ __forceinline__ void stat_add(int64_t* ctr, int st, int64_t v) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_STATS + (blockIdx.x % kStatReplicas) * kStatStride + st]),
+            static_cast<unsigned long long>(v));
+}
+
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
   for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s);
   return v;
@@ -162,6 +184,46 @@ __device__ __forceinline__ int64_t wave_append(bool pred, int64_t* count) {
   base = __shfl(base, leader);
   const uint64_t below = mask & ((1ull << lane) - 1ull);
   return pred ? base + __popcll(below) : -1;
+}
+
+// Workgroup-aggregated reservation of `count` consecutive entries of
+// *total (one device atomic per workgroup); every thread of the workgroup
+// must call it.  `lds` holds kBlock / kWave + 1 entries.
+__device__ __forceinline__ int64_t block_reserve(int64_t count, int64_t* total, int64_t* lds) {
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  constexpr int nw = kBlock / kWave;
+  int64_t incl = count;
+  for (int s = 1; s < kWave; s <<= 1) {
+    const int64_t t = __shfl_up(incl, s);
+    if (lane >= s) incl += t;
+  }
+  if (lane == kWave - 1) lds[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int w = 0; w < nw; ++w) {
+      const int64_t x = lds[w];
+      lds[w] = run;
+      run += x;
+    }
+    lds[nw] = run ? static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(total),
+                                                   static_cast<unsigned long long>(run)))
+                  : 0;
+  }
+  __syncthreads();
+  const int64_t base = lds[nw] + lds[wv] + incl - count;
+  __syncthreads();
+  return base;
+}
+
+__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* lds) {
+  v = wave_sum_i64(v);
+  if (lane_id() == 0) lds[threadIdx.x / kWave] = v;
+  __syncthreads();
+  int64_t t = 0;
+  for (int w = 0; w < kBlock / kWave; ++w) t += lds[w];
+  __syncthreads();
+  return t;
 }
 
 // Hash of a community id into [0, size) for the open-addressing tables.
@@ -212,23 +274,26 @@ struct BatchScratch {
   int64_t size;     // slots (power of two)
   int32_t* slot;    // per update (deletions, then insertions): pair slot, -1 if invalid
   int64_t dirs;     // 2 * updates: arc directions
-  // touched rows (at most dirs)
+  // touched rows, each listed under the first direction e that reaches it
+  // (per-row arrays below are indexed by that e; dirs entries each)
   uint32_t* tag;    // n bits: row already listed
-  int32_t* row_slot;  // n: index of a listed row (read only where tagged)
-  int32_t* row_of;  // row index -> vertex
+  int32_t* row_slot;  // n: e of a listed row (read only where tagged)
+  int32_t* row_of;  // e -> vertex if e lists a row, else -1
   int32_t* r_len;   // length before the batch
   int32_t* r_cnt;   // update directions on the row
-  int32_t* r_pbase; // first partner in `part`
+  int32_t* r_pbase; // first partner in `part` (also first tail survivor in tcol / tw)
   int32_t* r_zero;  // arcs reaching weight 0
   int32_t* r_app;   // arcs appended
   int32_t* r_hole;  // head holes refilled so far
-  int32_t* r_tbase; // first tail survivor in tcol / tw
   int32_t* d_rank;  // per direction: rank among its row's directions, -1 if invalid
   int32_t* part;    // partners (other endpoints) grouped by row
   int32_t* kind;    // per insertion direction: 1 merge, 0 append
-  int32_t* ch_row;  // scan chunk -> row index
-  int32_t* ch_off;  // scan chunk -> first arc
-  int32_t* tcol;    // tail survivors (at most 2 * deletions)
+  struct Chunk {     // scan unit: arcs [off, end) of the row of vertex a
+    int64_t s;        // row start
+    int32_t a, off, end, cnt, pbase, pad;
+  };
+  Chunk* chunk;
+  int32_t* tcol;    // tail survivors, in the row's partner range (dirs entries)
   int32_t* tw;
 };
 int64_t batch_chunks_bound(int64_t dirs, int64_t cap);
@@ -285,6 +350,12 @@ struct SubRound {
   int32_t deg_lo = 0;
   int32_t deg_hi = 0x7fffffff;
 };
+// Measurement hook (lv_set_timing): HIP events around every launch of the
+// timed kernel on its stream; collected after the stream is synchronised.
+void timer_begin(int kernel, hipStream_t st);
+void timer_end(int kernel, hipStream_t st);
+void timer_collect(int32_t* launches, double* ms);  // adds per kernel, resets
+
 void launch_bin_frontier(const MoveArgs& a, Workspace& ws, const SubRound& r, hipStream_t st);
 uint32_t bins_for_degrees(int32_t lo, int32_t hi, int32_t wave_max);
 void launch_move(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, uint32_t bin_mask, hipStream_t st);

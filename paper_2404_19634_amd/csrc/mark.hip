@@ -35,23 +35,56 @@ __global__ void k_mark_df(const int32_t* __restrict__ du, const int32_t* __restr
   }
 }
 
-__global__ void k_update_weights(const int32_t* __restrict__ du, const int32_t* __restrict__ dv,
+// Alg. 7: K_u, K_v += w and Sigma[C_u], Sigma[C_v] += w per update (minus
+// for deletions).  Large communities take many of the Sigma updates of a
+// batch, and device atomics on one address serialise, so each workgroup
+// first sums its updates' Sigma deltas per community in LDS and then
+// issues one atomic per distinct community.
+constexpr int kUwItems = 4;                         // updates per thread
+constexpr int kUwSlots = 2048;                      // LDS table slots
+constexpr int kUwProbes = 16;
+__global__ void __launch_bounds__(kBlock) k_update_weights(const int32_t* __restrict__ du, const int32_t* __restrict__ dv,
                                  const int32_t* __restrict__ dw, int64_t nd, const int32_t* __restrict__ iu,
                                  const int32_t* __restrict__ iv, const int32_t* __restrict__ iw, int64_t ni,
                                  const int32_t* __restrict__ C, int64_t* __restrict__ K,
                                  int64_t* __restrict__ Sigma) {
+  __shared__ int32_t tk[kUwSlots];
+  __shared__ unsigned long long tv[kUwSlots];
+  for (int q = threadIdx.x; q < kUwSlots; q += kBlock) {
+    tk[q] = -1;
+    tv[q] = 0;
+  }
+  __syncthreads();
   const int64_t total = nd + ni;
-  for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < total;
-       k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kBlock * kUwItems;
+  for (int it = 0; it < kUwItems; ++it) {
+    const int64_t k = base + static_cast<int64_t>(it) * kBlock + threadIdx.x;
+    if (k >= total) break;
     const bool del = k < nd;
     const int32_t a = del ? du[k] : iu[k - nd];
     const int32_t b = del ? dv[k] : iv[k - nd];
     const int64_t x = del ? -static_cast<int64_t>(dw[k]) : static_cast<int64_t>(iw[k - nd]);
     atomic_add_i64(&K[a], x);
     atomic_add_i64(&K[b], x);
-    atomic_add_i64(&Sigma[C[a]], x);
-    atomic_add_i64(&Sigma[C[b]], x);
+    for (int side = 0; side < 2; ++side) {
+      const int32_t c = C[side ? b : a];
+      uint32_t h = hash_slot(static_cast<uint32_t>(c), kUwSlots);
+      bool done = false;
+      for (int p = 0; p < kUwProbes; ++p) {
+        const int32_t old = atomicCAS(&tk[h], -1, c);
+        if (old == -1 || old == c) {
+          atomicAdd(&tv[h], static_cast<unsigned long long>(x));
+          done = true;
+          break;
+        }
+        h = (h + 1) & (kUwSlots - 1);
+      }
+      if (!done) atomic_add_i64(&Sigma[c], x);
+    }
   }
+  __syncthreads();
+  for (int q = threadIdx.x; q < kUwSlots; q += kBlock)
+    if (tk[q] >= 0 && tv[q]) atomic_add_i64(&Sigma[tk[q]], static_cast<int64_t>(tv[q]));
 }
 
 // ctr[CTR_AUX2] += Σ w of insertions, ctr[CTR_AUX3] += Σ w of deletions
@@ -223,7 +256,8 @@ void launch_update_weights(const lv_edges& del, const lv_edges& ins, const int32
                            hipStream_t st) {
   const int64_t total = del.count + ins.count;
   if (total == 0) return;
-  hipLaunchKernelGGL(k_update_weights, dim3(grid_for(total, kBlock, 4096)), dim3(kBlock), 0, st, del.u, del.v,
+  const int blocks = static_cast<int>((total + kBlock * kUwItems - 1) / (kBlock * kUwItems));
+  hipLaunchKernelGGL(k_update_weights, dim3(blocks), dim3(kBlock), 0, st, del.u, del.v,
                      del.w, del.count, ins.u, ins.v, ins.w, ins.count, C, K, Sigma);
 }
 

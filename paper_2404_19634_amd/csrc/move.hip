@@ -115,9 +115,9 @@ __device__ __forceinline__ void flush_totals(const Dev& D, int64_t gain, int64_t
   moved = wave_sum_i64(moved);
   arcs = wave_sum_i64(arcs);
   if (lane_id() == 0 && moved) {
-    atomic_add_i64(&D.ctr[CTR_GAIN], gain);
-    atomic_add_i64(&D.ctr[CTR_EXPAND], arcs);
-    atomic_add_i64(&D.ctr[CTR_MOVERS], moved);
+    stat_add(D.ctr, ST_GAIN, gain);
+    stat_add(D.ctr, ST_EXPAND, arcs);
+    stat_add(D.ctr, ST_MOVERS, moved);
   }
 }
 
@@ -208,7 +208,10 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(const uint32_t* __restr
   __shared__ int32_t s_cnt[NBINS];
   __shared__ int64_t s_base[NBINS];
   const int64_t words = (static_cast<int64_t>(n) + 31) / 32;
-  int64_t arcs = 0, processed = 0;
+  int64_t arcs = 0, processed = 0, affected = 0;
+  int64_t bin_verts[NBINS], bin_arcs[NBINS];
+#pragma unroll
+  for (int q = 0; q < NBINS; ++q) bin_verts[q] = bin_arcs[q] = 0;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t w0 = blockIdx.x * static_cast<int64_t>(blockDim.x); w0 < words; w0 += stride) {
     if (threadIdx.x < NBINS) s_cnt[threadIdx.x] = 0;
@@ -229,7 +232,11 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(const uint32_t* __restr
         }
         bits = keep;
       }
-      if (ever && bits) ever[k] |= bits;
+      if (ever && bits) {
+        const uint32_t old = ever[k];
+        affected += __popc(bits & ~old);
+        ever[k] = old | bits;
+      }
     }
     int32_t cnt[NBINS];
 #pragma unroll
@@ -241,8 +248,13 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(const uint32_t* __restr
       arcs += deg;
       const int bin = bin_of(deg, wave_max);
 #pragma unroll
-      for (int q = 0; q < NBINS; ++q) cnt[q] += (bin == q) ? 1 : 0;
+      for (int q = 0; q < NBINS; ++q) {
+        cnt[q] += (bin == q) ? 1 : 0;
+        bin_arcs[q] += (bin == q) ? deg : 0;
+      }
     }
+#pragma unroll
+    for (int q = 0; q < NBINS; ++q) bin_verts[q] += cnt[q];
 #pragma unroll
     for (int q = 0; q < NBINS; ++q)
       if (cnt[q]) atomicAdd(&s_cnt[q], cnt[q]);
@@ -250,7 +262,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(const uint32_t* __restr
     if (threadIdx.x < NBINS) {
       const int32_t c = s_cnt[threadIdx.x];
       s_base[threadIdx.x] = c ? static_cast<int64_t>(atomicAdd(
-                                    reinterpret_cast<unsigned long long*>(&ctr[CTR_BIN0 + threadIdx.x]),
+                                    reinterpret_cast<unsigned long long*>(&ctr[ctr_bin(threadIdx.x)]),
                                     static_cast<unsigned long long>(c)))
                               : 0;
       s_cnt[threadIdx.x] = 0;
@@ -269,9 +281,20 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(const uint32_t* __restr
   }
   processed = wave_sum_i64(processed);
   arcs = wave_sum_i64(arcs);
+  affected = wave_sum_i64(affected);
   if (lane_id() == 0) {
-    if (processed) atomic_add_i64(&ctr[CTR_PROCESSED], processed);
-    if (arcs) atomic_add_i64(&ctr[CTR_ARCS], arcs);
+    if (processed) stat_add(ctr, ST_PROCESSED, processed);
+    if (arcs) stat_add(ctr, ST_ARCS, arcs);
+    if (affected) stat_add(ctr, ST_AFFECTED, affected);
+  }
+#pragma unroll
+  for (int q = 0; q < NBINS; ++q) {
+    const int64_t v = wave_sum_i64(bin_verts[q]);
+    const int64_t x = wave_sum_i64(bin_arcs[q]);
+    if (lane_id() == 0 && v) {
+      stat_add(ctr, ST_BIN_V0 + q, v);
+      stat_add(ctr, ST_BIN_A0 + q, x);
+    }
   }
 }
 
@@ -281,7 +304,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(const uint32_t* __restr
 template <int G>
 __global__ void __launch_bounds__(kBlock) k_move_small(Dev D, const int32_t* __restrict__ list, int bin) {
   constexpr int VPW = kWave / G;
-  const int64_t count = D.ctr[CTR_BIN0 + bin];
+  const int64_t count = D.ctr[ctr_bin(bin)];
   const int lane = lane_id();
   const int sub = lane / G;
   const int k = lane % G;
@@ -359,7 +382,7 @@ template <int TS>
 __global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __restrict__ list) {
   __shared__ int32_t s_keys[kBlock / kWave][TS];
   __shared__ int32_t s_vals[kBlock / kWave][TS];
-  const int64_t count = D.ctr[CTR_BIN0 + BIN_WAVE];
+  const int64_t count = D.ctr[ctr_bin(BIN_WAVE)];
   const int lane = lane_id();
   const int wid = threadIdx.x / kWave;
   int32_t* keys = s_keys[wid];
@@ -490,7 +513,7 @@ __global__ void __launch_bounds__(kBlock) k_move_block(Dev D, const int32_t* __r
   __shared__ int64_t r_g[kBlock / kWave];
   __shared__ int32_t r_c[kBlock / kWave];
   __shared__ int64_t r_s[kBlock / kWave];
-  const int64_t count = D.ctr[CTR_BIN0 + BIN_BLOCK];
+  const int64_t count = D.ctr[ctr_bin(BIN_BLOCK)];
   int64_t gain_acc = 0, moved = 0, marcs = 0;
   for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
     const int32_t i = list[idx];
@@ -710,7 +733,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_final(Dev D, const int32_t* __re
                                                      const int64_t* __restrict__ unit_g,
                                                      const int32_t* __restrict__ unit_c,
                                                      int32_t* __restrict__ hub_moved) {
-  const int64_t count = D.ctr[CTR_BIN0 + BIN_HUB];
+  const int64_t count = D.ctr[ctr_bin(BIN_HUB)];
   const int lane = lane_id();
   const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
@@ -884,9 +907,11 @@ void launch_bin_frontier(const MoveArgs& a, Workspace& ws, const SubRound& r, hi
   Bins b;
   for (int k = 0; k < NBINS; ++k) b.list[k] = ws.bins[k];
   HubOut H{ws.hub_off, ws.hub_cbase, ws.hub_cnum, ws.u_ins_b, ws.u_ins_a, ws.u_emit_b, ws.u_emit_s};
+  timer_begin(NBINS, st);
   hipLaunchKernelGGL(k_bin_frontier, dim3(grid_for(words, kBlock, 4096)), dim3(kBlock), 0, st, a.cur, a.range,
                      a.ever, a.g.row_len, a.g.n, a.wave_max, r.hash_round, r.hash_shift, r.id_lo, r.id_hi, r.deg_lo,
                      r.deg_hi, b, H, ws.ctr);
+  timer_end(NBINS, st);
 }
 
 // Bins whose degree range meets [lo, hi].
@@ -912,33 +937,52 @@ void launch_move(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, uint32_t
   const int bs = grid_by_est(est, 64, tu.blocks_small);      // 16 rows per wave at G = 4
   const int bw = grid_by_est(est, 4, tu.blocks_wave);        // one row per wavefront
   const int bh = grid_by_est(est, 1, tu.blocks_hub);         // one row / unit per workgroup
-  if (bin_mask & (1u << BIN_G4))
+  if (bin_mask & (1u << BIN_G4)) {
+    timer_begin(BIN_G4, st);
     hipLaunchKernelGGL(k_move_small<4>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G4], int(BIN_G4));
-  if (bin_mask & (1u << BIN_G8))
+    timer_end(BIN_G4, st);
+  }
+  if (bin_mask & (1u << BIN_G8)) {
+    timer_begin(BIN_G8, st);
     hipLaunchKernelGGL(k_move_small<8>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G8], int(BIN_G8));
-  if (bin_mask & (1u << BIN_G16))
+    timer_end(BIN_G8, st);
+  }
+  if (bin_mask & (1u << BIN_G16)) {
+    timer_begin(BIN_G16, st);
     hipLaunchKernelGGL(k_move_small<16>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G16], int(BIN_G16));
-  if (bin_mask & (1u << BIN_G32))
+    timer_end(BIN_G16, st);
+  }
+  if (bin_mask & (1u << BIN_G32)) {
+    timer_begin(BIN_G32, st);
     hipLaunchKernelGGL(k_move_small<32>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G32], int(BIN_G32));
+    timer_end(BIN_G32, st);
+  }
   const int ts = table_slots_for(a.wave_max);
-  if (!(bin_mask & (1u << BIN_WAVE)))
-    ;
-  else if (ts <= 128)
-    hipLaunchKernelGGL(k_move_wave<128>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
-  else if (ts <= 256)
-    hipLaunchKernelGGL(k_move_wave<256>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
-  else if (ts <= 512)
-    hipLaunchKernelGGL(k_move_wave<512>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
-  else
-    hipLaunchKernelGGL(k_move_wave<1024>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
-  if (bin_mask & (1u << BIN_BLOCK))
+  if (bin_mask & (1u << BIN_WAVE)) {
+    timer_begin(BIN_WAVE, st);
+    if (ts <= 128)
+      hipLaunchKernelGGL(k_move_wave<128>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
+    else if (ts <= 256)
+      hipLaunchKernelGGL(k_move_wave<256>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
+    else if (ts <= 512)
+      hipLaunchKernelGGL(k_move_wave<512>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
+    else
+      hipLaunchKernelGGL(k_move_wave<1024>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
+    timer_end(BIN_WAVE, st);
+  }
+  if (bin_mask & (1u << BIN_BLOCK)) {
+    timer_begin(BIN_BLOCK, st);
     hipLaunchKernelGGL(k_move_block, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_BLOCK]);
+    timer_end(BIN_BLOCK, st);
+  }
   if (!(bin_mask & (1u << BIN_HUB))) return;
   // hub rows
   hipLaunchKernelGGL(k_hub_clear, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off, ws.u_emit_b,
                      ws.u_emit_s, ws.pool_keys, ws.pool_vals, ws.hub_kid, ws.hub_moved, ws.pool_slots);
+  timer_begin(BIN_HUB, st);
   hipLaunchKernelGGL(k_hub_insert, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off, ws.u_ins_b,
                      ws.u_ins_a, ws.pool_keys, ws.pool_vals, ws.hub_kid, ws.pool_slots);
+  timer_end(BIN_HUB, st);
   hipLaunchKernelGGL(k_hub_decide_units, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off,
                      ws.u_emit_b, ws.u_emit_s, ws.pool_keys, ws.pool_vals, ws.hub_kid, ws.unit_g, ws.unit_c,
                      ws.pool_slots);

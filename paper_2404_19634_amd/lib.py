@@ -24,10 +24,16 @@ STATUS = {0: "LV_OK", -1: "LV_EINVAL", -2: "LV_ENOEDGE", -3: "LV_ENOSLACK", -4: 
 LV_EINVAL, LV_ENOEDGE, LV_ENOSLACK, LV_EOVERFLOW, LV_EEMPTY, LV_EHIP, LV_EWORKSPACE = -1, -2, -3, -4, -5, -6, -7
 SYNC, ASYNC = 0, 1
 MAX_PASSES, MAX_ITERS = 16, 32
+# degree bins of the local-moving scan (LV_BIN_*) and the timing selector
+BINS = ("g4", "g8", "g16", "g32", "wave", "block", "hub")
+NBINS = len(BINS)
+TIME_BINNING = NBINS           # timing index of the frontier binning kernel
+NTIMED = NBINS + 1
+TIMED = BINS + ("binning",)
 
 EXPORTS = ["lv_default_params", "lv_workspace_bytes", "lv_graph_capacity_bound", "lv_graph_build",
            "lv_graph_relayout", "apply_batch", "louvain_static", "louvain_nd", "louvain_ds", "louvain_df",
-           "modularity", "lv_set_tuning", "lv_get_tuning", "lv_last_error"]
+           "modularity", "lv_set_tuning", "lv_get_tuning", "lv_set_timing", "lv_last_error"]
 
 
 class LouvainError(RuntimeError):
@@ -61,7 +67,10 @@ class Stats(ct.Structure):
                 ("vertices_affected", ct.c_int64), ("iter_moves", (ct.c_int64 * MAX_ITERS) * MAX_PASSES),
                 ("iter_gain", (ct.c_int64 * MAX_ITERS) * MAX_PASSES), ("seconds", ct.c_double),
                 ("ms_mark", ct.c_float), ("ms_move", ct.c_float), ("ms_aggregate", ct.c_float),
-                ("ms_other", ct.c_float), ("arcs_aggregated", ct.c_int64)]
+                ("ms_other", ct.c_float), ("arcs_aggregated", ct.c_int64),
+                ("bin_vertices", ct.c_int64 * NBINS), ("bin_arcs", ct.c_int64 * NBINS),
+                ("bin_launches", ct.c_int32 * NBINS), ("timed_launches", ct.c_int32 * NTIMED),
+                ("timed_ms", ct.c_double * NTIMED)]
 
     def as_dict(self) -> dict:
         p = self.passes
@@ -76,6 +85,9 @@ class Stats(ct.Structure):
             "seconds": float(self.seconds), "ms_mark": float(self.ms_mark), "ms_move": float(self.ms_move),
             "ms_aggregate": float(self.ms_aggregate), "ms_other": float(self.ms_other),
             "arcs_aggregated": int(self.arcs_aggregated),
+            "bin_vertices": [int(x) for x in self.bin_vertices], "bin_arcs": [int(x) for x in self.bin_arcs],
+            "bin_launches": [int(x) for x in self.bin_launches],
+            "timed_launches": [int(x) for x in self.timed_launches], "timed_ms": [float(x) for x in self.timed_ms],
         }
 
 
@@ -121,6 +133,8 @@ def load():
     L.modularity.argtypes = [GP, P, ct.POINTER(ct.c_double), P, SZ, P]
     L.lv_set_tuning.argtypes = [ct.POINTER(Tuning)]
     L.lv_get_tuning.argtypes = [ct.POINTER(Tuning)]
+    L.lv_set_timing.restype = I32
+    L.lv_set_timing.argtypes = [ct.c_uint32]
     L.lv_last_error.restype = ct.c_char_p
     _lib = L
     return L
@@ -152,6 +166,16 @@ DEFAULT_ASYNC_ROUNDS_LOG2 = 7
 
 
 DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER = 4096
+
+
+def set_timing(kernels=()):
+    """Bracket every launch of the given kernels (indices into TIMED: a bin's
+    scan kernel, or TIME_BINNING) with HIP events; the louvain_* calls then
+    report timed_launches and timed_ms per kernel.  () turns timing off."""
+    mask = 0
+    for k in kernels:
+        mask |= 1 << int(k)
+    _check(load().lv_set_timing(mask))
 
 
 def set_tuning(wave_max_degree=0, blocks_small=0, blocks_wave=0, blocks_hub=0,

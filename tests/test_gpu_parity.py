@@ -334,3 +334,24 @@ def test_apply_batch_hub_rows(lib):
         assert all(np.array_equal(x, y) for x, y in zip(g.csr_host(), G.csr()))
         assert g.two_m == G.two_m
         cur = W.apply_batch_np(cur, b)
+
+
+def test_bin_stats_and_timing_hook(lib):
+    """Per-bin work adds up to the scan totals, and the event hook times
+    exactly the launches it was asked for."""
+    e = W.rmat(12, 16, 0.57, 0.19, 0.19, 5)
+    g = lib.Graph.from_edges(e)
+    _, s = lib.louvain_static(g, mode="sync")
+    assert sum(s["bin_arcs"]) == s["arcs_scanned"]
+    assert all(x == 0 for x in s["timed_launches"])
+    lib.set_timing(range(lib.NTIMED))
+    try:
+        _, t = lib.louvain_static(g, mode="async")
+    finally:
+        lib.set_timing(())
+    for b in range(lib.NBINS):
+        assert t["timed_launches"][b] == t["bin_launches"][b]
+        assert (t["timed_ms"][b] > 0) == (t["timed_launches"][b] > 0)
+    assert t["timed_launches"][lib.TIME_BINNING] >= sum(t["iterations"])
+    _, u = lib.louvain_static(g, mode="async")
+    assert all(x == 0 for x in u["timed_launches"])
