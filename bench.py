@@ -137,6 +137,66 @@ def traffic_for(kernel_name):
         return None
 
 
+def _kname(name):
+    import re
+    name = name.replace("(anonymous namespace)::", "").replace("lv::", "").replace("void ", "")
+    return re.sub(r"\(.*$", "", name)
+
+
+def summarize(db_path, kernel, launches):
+    """Text summary of a rocprofv3 database written by this script.
+
+    A kernel-trace database with the ROCTx range of the timed region gives
+    the per-kernel table of that region.  A counter database (one --pmc
+    counter) gives, for `kernel`, the counter per dispatch averaged over its
+    last `launches` dispatches (the timed region, when the final static run
+    is skipped), and the same counter for the largest device copy (the 1 GiB
+    calibration copy), with the scale factor the copy implies."""
+    import sqlite3
+    db = sqlite3.connect(db_path)
+    tabs = {r[0] for r in db.execute("select name from sqlite_master where type in ('table','view')")}
+    out = []
+    rows = []
+    if "counters_collection" in tabs:
+        rows = db.execute("select dispatch_id, kernel_name, counter_name, sum(value) from counters_collection "
+                          "group by dispatch_id, counter_name order by dispatch_id").fetchall()
+    if rows:
+        counters = sorted({r[2] for r in rows})
+        for cn in counters:
+            mine = [v for d, k, c, v in rows if c == cn and _kname(k) == kernel]
+            copies = [v for d, k, c, v in rows if c == cn and "copyBuffer" in k]
+            tail = mine[-launches:] if launches else mine
+            avg = sum(tail) / len(tail) if tail else float("nan")
+            big = max(copies) if copies else float("nan")
+            scale = (1 << 20) / big if copies and big > 0 else float("nan")
+            out.append(f"{cn}: {kernel} dispatches {len(mine)}, last {len(tail)} average {avg:.1f} KiB")
+            out.append(f"{cn}: largest copy (1 GiB moved) reads {big:.1f} KiB -> scale {scale:.4f}")
+            out.append(f"{cn}_bytes_per_launch: {avg * scale * 1024:.0f}")
+        return "\n".join(out)
+    t0 = t1 = None
+    if "regions" in tabs:
+        r = db.execute("select start, end from regions where category like 'MARKER%'").fetchall()
+        if len(r) == 1:
+            t0, t1 = r[0]
+    q = "select name, duration from kernels" + (" where start >= ? and end <= ?" if t0 is not None else "")
+    rows = db.execute(q, (t0, t1) if t0 is not None else ()).fetchall()
+    agg = {}
+    for name, d in rows:
+        a = agg.setdefault(_kname(name), [0, 0.0, float("inf"), 0.0])
+        a[0] += 1
+        a[1] += d
+        a[2] = min(a[2], d)
+        a[3] = max(a[3], d)
+    tot = sum(a[1] for a in agg.values())
+    if t0 is not None:
+        out.append(f"timed region {(t1 - t0) / 1e6:.3f} ms, {len(rows)} dispatches, kernel time {tot / 1e6:.3f} ms")
+    out.append(f"{'kernel':34s} {'calls':>6s} {'total_ms':>9s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s} {'pct':>6s}")
+    for k, a in sorted(agg.items(), key=lambda x: -x[1][1]):
+        out.append(f"{k[:34]:34s} {a[0]:6d} {a[1] / 1e6:9.3f} {a[1] / a[0] / 1e3:8.2f} {a[2] / 1e3:8.2f} "
+                   f"{a[3] / 1e3:8.2f} {100 * a[1] / tot:6.2f}")
+    return "\n".join(out)
+
+
 def pct(x, q):
     return float(np.percentile(np.asarray(x, dtype=np.float64), q)) if len(x) else None
 
@@ -197,10 +257,21 @@ def main():
     ap.add_argument("--mode", default="async", choices=["async", "sync"])
     ap.add_argument("--static-runs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-final-static", action="store_true",
+                    help="skip the static run on the final graph (counter runs: the timed region's dispatches "
+                         "are then the last ones of each kernel)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with a plain 1 GiB device copy whose counters calibrate FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--summarize", metavar="DB", help="print a summary of a rocprofv3 database and exit")
+    ap.add_argument("--kernel", default="k_hub_insert", help="kernel of --summarize for counter databases")
+    ap.add_argument("--launches", type=int, default=0, help="last dispatches of --kernel to average")
     ap.add_argument("--sweep", type=int, default=0,
                     help="profiling mode: run this many single full local-moving sweeps (SYNC, all vertices "
                          "from singletons) and one 1 GiB device copy for counter calibration, then exit")
     args = ap.parse_args()
+    if args.summarize:
+        print(summarize(args.summarize, args.kernel, args.launches))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the single-GPU line is the result",
               file=sys.stderr)
@@ -292,13 +363,22 @@ def main():
     q_df = lib.modularity(g, state.C)
 
     # static Louvain on the final graph, same mode (quality and time reference)
-    st = lib.State.empty(e.n, dev)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    st, s_final = lib.louvain_static(g, prm, st)
-    torch.cuda.synchronize()
-    static_final_ms = (time.perf_counter() - t) * 1e3
-    q_static_final = lib.modularity(g, st.C)
+    static_final_ms = q_static_final = None
+    if not args.no_final_static:
+        st = lib.State.empty(e.n, dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, s_final = lib.louvain_static(g, prm, st)
+        torch.cuda.synchronize()
+        static_final_ms = (time.perf_counter() - t) * 1e3
+        q_static_final = lib.modularity(g, st.C)
+    if args.calibrate_copy:
+        x = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
 
     df_arcs = int(np.sum(arcs))
     value = df_arcs / region_s

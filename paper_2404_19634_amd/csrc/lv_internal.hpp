@@ -24,7 +24,7 @@ enum Bin { BIN_G4 = 0, BIN_G8, BIN_G16, BIN_G32, BIN_WAVE, BIN_BLOCK, BIN_HUB, N
 
 constexpr int kWaveTableMaxDegree = 512;  // largest wave-bin row the LDS table supports
 constexpr int kBlockMaxDegree = 2048;     // largest workgroup-bin row (LDS table of 4096 slots)
-constexpr int kHubUnitArcs = 8192;        // arcs per work unit of a hub row
+constexpr int kHubUnitArcs = 2048;        // arcs per work unit of a hub row (8 per thread)
 constexpr int kHubClearSlots = 4096;      // table slots per clear unit of a hub row
 
 // Device counters (int64 slots of Workspace::ctr).  Device-scope atomics

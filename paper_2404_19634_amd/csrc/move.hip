@@ -91,22 +91,68 @@ __device__ __forceinline__ bool decide_move(const Dev& D, int32_t d, int32_t c, 
   return true;
 }
 
+// Community-total updates of moves, summed per workgroup in LDS and
+// applied with one device atomic per distinct community when the workgroup
+// ends (agg_end).  Movers crowd into few large communities, and device
+// atomics on one address serialise, so per-move atomics on Sigma and size
+// would queue behind each other.  In ASYNC mode a move's new membership is
+// visible at once; its effect on Sigma and size becomes visible when the
+// workgroup that made it finishes.
+constexpr int kAggSlots = 512;
+constexpr int kAggProbes = 8;
+struct MoveAgg {
+  int32_t key[kAggSlots];
+  int32_t dsize[kAggSlots];
+  unsigned long long dsig[kAggSlots];
+};
+
+__device__ __forceinline__ void agg_begin(MoveAgg* A) {
+  for (int s = threadIdx.x; s < kAggSlots; s += blockDim.x) {
+    A->key[s] = -1;
+    A->dsize[s] = 0;
+    A->dsig[s] = 0;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void agg_add(MoveAgg* A, int64_t* Sigma, int32_t* size, int32_t c, int64_t dk, int32_t ds) {
+  uint32_t h = hash_slot(static_cast<uint32_t>(c), kAggSlots);
+  for (int p = 0; p < kAggProbes; ++p) {
+    const int32_t old = atomicCAS(&A->key[h], -1, c);
+    if (old == -1 || old == c) {
+      atomicAdd(&A->dsig[h], static_cast<unsigned long long>(dk));
+      if (size) atomicAdd(&A->dsize[h], ds);
+      return;
+    }
+    h = (h + 1) & (kAggSlots - 1);
+  }
+  atomic_add_i64(&Sigma[c], dk);
+  if (size) atomicAdd(&size[c], ds);
+}
+
+// every thread of the workgroup calls it once, after its last agg_add
+__device__ __forceinline__ void agg_end(MoveAgg* A, int64_t* Sigma, int32_t* size) {
+  __syncthreads();
+  for (int s = threadIdx.x; s < kAggSlots; s += blockDim.x) {
+    const int32_t c = A->key[s];
+    if (c < 0) continue;
+    if (A->dsig[s]) atomic_add_i64(&Sigma[c], static_cast<int64_t>(A->dsig[s]));
+    if (size && A->dsize[s]) atomicAdd(&size[c], A->dsize[s]);
+  }
+}
+
 // Records (SYNC: target by vertex plus the movers bitmask) or applies
-// (ASYNC) one move -- one lane per mover.  Nothing here waits on a shared
-// counter.
-__device__ __forceinline__ void commit_move(const Dev& D, int32_t i, int32_t d, int32_t c, int64_t Ki) {
+// (ASYNC: membership now, totals through the workgroup's aggregate) one
+// move -- one lane per mover.
+__device__ __forceinline__ void commit_move(const Dev& D, MoveAgg* A, int32_t i, int32_t d, int32_t c, int64_t Ki) {
   if (D.moved) set_bit(D.moved, i);
   if (D.mode == LV_SYNC) {
     D.mv_c[i] = c;
     return;
   }
   D.C[i] = c;
-  atomic_add_i64(&D.Sigma[d], -Ki);
-  atomic_add_i64(&D.Sigma[c], Ki);
-  if (D.size) {
-    atomicSub(&D.size[d], 1);
-    atomicAdd(&D.size[c], 1);
-  }
+  agg_add(A, D.Sigma, D.size, d, -Ki, -1);
+  agg_add(A, D.Sigma, D.size, c, Ki, 1);
 }
 
 // Wavefront totals of gains, moves and mover arcs into the counters.
@@ -311,6 +357,8 @@ __global__ void __launch_bounds__(kBlock) k_move_small(Dev D, const int32_t* __r
   const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
   int64_t gain_acc = 0, moved = 0, marcs = 0;
+  __shared__ MoveAgg agg;
+  agg_begin(&agg);
   for (int64_t base = wave * VPW; base < count; base += nwaves * VPW) {
     const int64_t idx = base + sub;
     const bool valid = idx < count;
@@ -365,7 +413,7 @@ __global__ void __launch_bounds__(kBlock) k_move_small(Dev D, const int32_t* __r
     bool mv = false;
     if (valid) mv = decide_move(D, d, bc, bg);
     if (lead && mv) {
-      commit_move(D, i, d, bc, Ki);
+      commit_move(D, &agg, i, d, bc, Ki);
       gain_acc += bg;
       moved += 1;
       marcs += deg;
@@ -373,6 +421,7 @@ __global__ void __launch_bounds__(kBlock) k_move_small(Dev D, const int32_t* __r
     if (mv && has && D.push) set_bit(D.next, j);
   }
   flush_totals(D, gain_acc, moved, marcs);
+  agg_end(&agg, D.Sigma, D.size);
 }
 
 // --------------------------------------------------------------------------
@@ -390,6 +439,8 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __re
   const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
   int64_t gain_acc = 0, moved = 0, marcs = 0;
+  __shared__ MoveAgg agg;
+  agg_begin(&agg);
   for (int64_t idx = wave; idx < count; idx += nwaves) {
     const int32_t i = list[idx];
     const int64_t start = D.row_start[i];
@@ -456,7 +507,7 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __re
     }
     if (decide_move(D, d, bc, bg)) {
       if (lane == 0) {
-        commit_move(D, i, d, bc, Ki);
+        commit_move(D, &agg, i, d, bc, Ki);
         gain_acc += bg;
         moved += 1;
         marcs += deg;
@@ -469,6 +520,7 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __re
     }
   }
   flush_totals(D, gain_acc, moved, marcs);
+  agg_end(&agg, D.Sigma, D.size);
 }
 
 // --------------------------------------------------------------------------
@@ -515,6 +567,8 @@ __global__ void __launch_bounds__(kBlock) k_move_block(Dev D, const int32_t* __r
   __shared__ int64_t r_s[kBlock / kWave];
   const int64_t count = D.ctr[ctr_bin(BIN_BLOCK)];
   int64_t gain_acc = 0, moved = 0, marcs = 0;
+  __shared__ MoveAgg agg;
+  agg_begin(&agg);
   for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
     const int32_t i = list[idx];
     const int64_t start = D.row_start[i];
@@ -564,7 +618,7 @@ __global__ void __launch_bounds__(kBlock) k_move_block(Dev D, const int32_t* __r
     block_argmax(bg, bc, r_g, r_c);
     if (decide_move(D, d, bc, bg)) {
       if (threadIdx.x == 0) {
-        commit_move(D, i, d, bc, Ki);
+        commit_move(D, &agg, i, d, bc, Ki);
         gain_acc += bg;
         moved += 1;
         marcs += deg;
@@ -578,6 +632,7 @@ __global__ void __launch_bounds__(kBlock) k_move_block(Dev D, const int32_t* __r
     __syncthreads();
   }
   flush_totals(D, gain_acc, moved, marcs);
+  agg_end(&agg, D.Sigma, D.size);
 }
 
 // --------------------------------------------------------------------------
@@ -648,27 +703,38 @@ __global__ void __launch_bounds__(kBlock) k_hub_insert(Dev D, const int32_t* __r
       tv[s] = 0;
     }
     __syncthreads();
-    const int64_t a1 = min(static_cast<int64_t>(deg), u_a[u] + kHubUnitArcs);
+    const int64_t a0 = u_a[u];
+    const int64_t a1 = min(static_cast<int64_t>(deg), a0 + kHubUnitArcs);
     int64_t kid = 0;
-    for (int64_t a = u_a[u] + threadIdx.x; a < a1; a += kBlock) {
-      const int32_t j = D.col[start + a];
-      const int32_t x = D.wt[start + a];
-      if (j == i) continue;
-      const int32_t c = D.C[j];
+    // each thread's arcs: all loads first, then all gathers, then the table
+    constexpr int kPer = kHubUnitArcs / kBlock;
+    int32_t js[kPer], xs[kPer], cs[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int64_t a = a0 + threadIdx.x + static_cast<int64_t>(q) * kBlock;
+      js[q] = a < a1 ? D.col[start + a] : i;
+      xs[q] = a < a1 ? D.wt[start + a] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) cs[q] = js[q] != i ? D.C[js[q]] : d;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      if (js[q] == i) continue;
+      const int32_t c = cs[q], x = xs[q];
       if (c == d) {
         kid += x;
         continue;
       }
-      uint32_t q = hash_slot(static_cast<uint32_t>(c), kHubTS);
+      uint32_t h = hash_slot(static_cast<uint32_t>(c), kHubTS);
       bool done = false;
       for (int p = 0; p < kHubProbes; ++p) {
-        const int32_t old = atomicCAS(&tk[q], -1, c);
+        const int32_t old = atomicCAS(&tk[h], -1, c);
         if (old == -1 || old == c) {
-          atomicAdd(&tv[q], x);
+          atomicAdd(&tv[h], x);
           done = true;
           break;
         }
-        q = (q + 1) & (kHubTS - 1);
+        h = (h + 1) & (kHubTS - 1);
       }
       if (!done) gtable_add(keys + off, vals + off, tsz, c, x);
     }
@@ -738,6 +804,8 @@ __global__ void __launch_bounds__(kBlock) k_hub_final(Dev D, const int32_t* __re
   const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
   int64_t gain_acc = 0, moved = 0, marcs = 0;
+  __shared__ MoveAgg agg;
+  agg_begin(&agg);
   for (int64_t h = wave; h < count; h += nwaves) {
     const int64_t b0 = hub_cbase[h];
     const int32_t nu = hub_cnum[h];
@@ -762,7 +830,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_final(Dev D, const int32_t* __re
       const bool mv = decide_move(D, d, bc, bg);
       hub_moved[h] = mv ? 1 : 0;
       if (mv) {
-        commit_move(D, i, d, bc, D.K[i]);
+        commit_move(D, &agg, i, d, bc, D.K[i]);
         gain_acc += bg;
         moved += 1;
         marcs += D.row_len[i];
@@ -770,6 +838,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_final(Dev D, const int32_t* __re
     }
   }
   flush_totals(D, gain_acc, moved, marcs);
+  agg_end(&agg, D.Sigma, D.size);
 }
 
 __global__ void __launch_bounds__(kBlock) k_hub_expand(Dev D, const int32_t* __restrict__ list,
@@ -797,6 +866,8 @@ __global__ void __launch_bounds__(kBlock) k_apply_moves(int32_t* __restrict__ C,
                                                        int64_t* __restrict__ Sigma, int32_t* __restrict__ size,
                                                        const uint32_t* __restrict__ moved,
                                                        const int32_t* __restrict__ target, int32_t n) {
+  __shared__ MoveAgg agg;
+  agg_begin(&agg);
   const int64_t words = (static_cast<int64_t>(n) + 31) / 32;
   for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < words;
        k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -806,14 +877,11 @@ __global__ void __launch_bounds__(kBlock) k_apply_moves(int32_t* __restrict__ C,
       const int32_t d = C[i];
       const int64_t Ki = K[i];
       C[i] = c;
-      atomic_add_i64(&Sigma[d], -Ki);
-      atomic_add_i64(&Sigma[c], Ki);
-      if (size) {
-        atomicSub(&size[d], 1);
-        atomicAdd(&size[c], 1);
-      }
+      agg_add(&agg, Sigma, size, d, -Ki, -1);
+      agg_add(&agg, Sigma, size, c, Ki, 1);
     }
   }
+  agg_end(&agg, Sigma, size);
 }
 
 // --------------------------------------------------------------------------
