@@ -29,11 +29,16 @@ PROFILES = os.path.join(ROOT, "profiles")
 # neighbour id, the weight and the neighbour's community (4 + 4 + 4 B); per
 # processed vertex its row start and length, K_i and C_i (8 + 4 + 8 + 4 B).
 # The frontier binning kernel reads one 4 B frontier word per 32 vertices
-# and, per active vertex, its row length and one list entry (4 + 4 B).
+# and, per active vertex, its row length and one list entry (4 + 4 B).  A
+# hub row's global table has two 8 B slots per arc, written once by the
+# clear kernel and read once by the decision kernel.
 SCAN_BYTES_PER_ARC = 12
 SCAN_BYTES_PER_VERTEX = 24
 BIN_BYTES_PER_WORD = 4
 BIN_BYTES_PER_VERTEX = 8
+HUB_TABLE_BYTES_PER_ARC = 16
+KERNELS = ("k_move_all", "k_bin_frontier", "k_hub_clear", "k_hub_decide")   # index = LV_TIME_*
+SHORT = ("move_all", "bin_frontier", "hub_clear", "hub_decide")
 
 
 def log(*a):
@@ -87,29 +92,29 @@ class ProfilerRegion:
 
 
 class KernelMeter:
-    """Per-kernel launches, event time and algorithmic bytes, summed over
-    the louvain_* calls it is fed (lv_stats of each call)."""
+    """Per-kernel launches, event time and algorithmic bytes (index
+    LV_TIME_*), summed over the louvain_* calls it is fed (their lv_stats)."""
 
     def __init__(self, lib, n):
         self.lib, self.n = lib, n
         self.launches = [0] * lib.NTIMED
         self.ms = [0.0] * lib.NTIMED
         self.bytes = [0] * lib.NTIMED
-        self.work_launches = [0] * lib.NTIMED
 
     def add(self, s):
         L = self.lib
         for k in range(L.NTIMED):
             self.launches[k] += s["timed_launches"][k]
             self.ms[k] += s["timed_ms"][k]
-        for b in range(L.NBINS):
-            self.bytes[b] += SCAN_BYTES_PER_ARC * s["bin_arcs"][b] + SCAN_BYTES_PER_VERTEX * s["bin_vertices"][b]
-            self.work_launches[b] += s["bin_launches"][b]
+        arcs, verts = s["bin_arcs"], s["bin_vertices"]
+        self.bytes[L.TIME_SCAN] += SCAN_BYTES_PER_ARC * sum(arcs) + SCAN_BYTES_PER_VERTEX * sum(verts)
         # binning runs once per sub-round; its launches are known when timed
         words = (self.n + 31) // 32
         nbin = s["timed_launches"][L.TIME_BINNING]
-        self.bytes[L.TIME_BINNING] += BIN_BYTES_PER_WORD * words * nbin + BIN_BYTES_PER_VERTEX * sum(s["bin_vertices"])
-        self.work_launches[L.TIME_BINNING] += nbin
+        self.bytes[L.TIME_BINNING] += BIN_BYTES_PER_WORD * words * nbin + BIN_BYTES_PER_VERTEX * sum(verts)
+        hub_arcs = arcs[L.BINS.index("hub")]
+        self.bytes[L.TIME_HUB_CLEAR] += HUB_TABLE_BYTES_PER_ARC * hub_arcs
+        self.bytes[L.TIME_HUB_DECIDE] += HUB_TABLE_BYTES_PER_ARC * hub_arcs
 
     def dominant(self):
         return max(range(self.lib.NTIMED), key=lambda k: self.ms[k])
@@ -257,13 +262,14 @@ def main():
     ap.add_argument("--mode", default="async", choices=["async", "sync"])
     ap.add_argument("--static-runs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", default="", help="lv_tuning overrides, e.g. fuse_max_frontier=1024,defer_totals=1")
     ap.add_argument("--no-final-static", action="store_true",
                     help="skip the static run on the final graph (counter runs: the timed region's dispatches "
                          "are then the last ones of each kernel)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 1 GiB device copy whose counters calibrate FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--summarize", metavar="DB", help="print a summary of a rocprofv3 database and exit")
-    ap.add_argument("--kernel", default="k_hub_insert", help="kernel of --summarize for counter databases")
+    ap.add_argument("--kernel", default="k_move_all<512>", help="kernel of --summarize for counter databases")
     ap.add_argument("--launches", type=int, default=0, help="last dispatches of --kernel to average")
     ap.add_argument("--sweep", type=int, default=0,
                     help="profiling mode: run this many single full local-moving sweeps (SYNC, all vertices "
@@ -282,6 +288,8 @@ def main():
     from paper_2404_19634_amd import workloads as W
 
     region = ProfilerRegion()
+    tuning = {k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(",") if kv)}
+    lib.set_tuning(**tuning)
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
@@ -398,7 +406,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"R-MAT scale {args.scale} (edge factor 16, a=0.57 b=0.19 c=0.19), "
                                f"random 80/20 batches of 1e-7..1e-3 |E|",
-                   "vertices": e.n, "undirected_edges": e.m, "batch_sizes": sizes, "mode": args.mode},
+                   "vertices": e.n, "undirected_edges": e.m, "batch_sizes": sizes, "mode": args.mode,
+                   "tuning": lib.get_tuning()},
         "df_latency_ms_p50": pct(lat, 50),
         "df_latency_ms_p99": pct(lat, 99),
         "df_latency_ms_by_batch_size": {str(k): float(np.median(v)) for k, v in sorted(per_size.items())},
@@ -411,18 +420,14 @@ def main():
         "modularity": {"static_initial": q_static, "df_final": q_df, "static_final": q_static_final},
         "static_final_ms": static_final_ms,
     }
-    names = [f"k_move_small<{g}>" for g in (4, 8, 16, 32)] + ["k_move_wave", "k_move_block", "k_hub_insert",
-                                                             "k_bin_frontier"]
-    short = ["move_small4", "move_small8", "move_small16", "move_small32", "move_wave", "move_block", "hub_insert",
-             "bin_frontier"]
     nl = meter.launches[dom]
     if nl and meter.ms[dom] > 0:
-        per_launch = meter.bytes[dom] / max(1, meter.work_launches[dom])
+        per_launch = meter.bytes[dom] / nl
         achieved = per_launch / (meter.ms[dom] / nl * 1e-3) / 1e9
-        tr = traffic_for(short[dom])
+        tr = traffic_for(SHORT[dom])
         out["roofline"] = {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": names[dom],
+            "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": KERNELS[dom],
             "launches": nl, "avg_launch_us": meter.ms[dom] / nl * 1e3, "bytes_per_launch": per_launch,
             "warmup_kernel_ms": {lib.TIMED[k]: round(warm.ms[k], 4) for k in range(lib.NTIMED)},
         }

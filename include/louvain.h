@@ -115,9 +115,10 @@ typedef struct {
  * up to 2048 arcs (one workgroup, LDS table), and longer hub rows (several
  * workgroups, global table). */
 enum { LV_BIN_G4 = 0, LV_BIN_G8, LV_BIN_G16, LV_BIN_G32, LV_BIN_WAVE, LV_BIN_BLOCK, LV_BIN_HUB, LV_NBINS };
-/* Kernels the measurement hook can time: the scan kernel of each bin (for
- * hub rows, the insert kernel) and the frontier binning kernel. */
-enum { LV_TIME_BINNING = LV_NBINS, LV_NTIMED };
+/* Kernels the measurement hook can time: the fused local-moving scan (all
+ * degree bins and the hub-row inserts of a sub-round in one launch), the
+ * frontier binning, and the hub-row table clear and decision kernels. */
+enum { LV_TIME_SCAN = 0, LV_TIME_BINNING, LV_TIME_HUB_CLEAR, LV_TIME_HUB_DECIDE, LV_NTIMED };
 
 /* Per-run statistics.  The first block matches the oracle's layout. */
 typedef struct {
@@ -137,21 +138,22 @@ typedef struct {
   float ms_other;      /* output consistency, setup */
   int64_t arcs_aggregated; /* arcs read by aggregation */
   /* Local-moving work per degree bin (index LV_BIN_*): vertices processed,
-   * arcs scanned, launches of the bin's scan kernel (for hub rows: the
-   * insert kernel).  Summed over every iteration, pass and sub-round. */
+   * arcs scanned, and the sub-rounds whose scan launch served the bin.
+   * Summed over every iteration, pass and sub-round. */
   int64_t bin_vertices[LV_NBINS];
   int64_t bin_arcs[LV_NBINS];
   int32_t bin_launches[LV_NBINS];
   /* Launches bracketed by timing events (lv_set_timing) and their summed
-   * GPU time, per timed kernel (index LV_BIN_* or LV_TIME_BINNING); zero
-   * for kernels that are not timed. */
+   * GPU time, per timed kernel (index LV_TIME_*); zero for kernels that are
+   * not timed. */
   int32_t timed_launches[LV_NTIMED];
   double timed_ms[LV_NTIMED];
 } lv_stats;
 
 /* Tunables chosen by the autotuner (degree-bin thresholds and launch
- * shapes).  Zero fields take built-in defaults, except the two async_rounds
- * fields, where 0 is a value (lv_get_tuning reports the values in use). */
+ * shapes).  Zero fields take built-in defaults, except the async_rounds,
+ * fuse and defer fields, where 0 is a value (lv_get_tuning reports the
+ * values in use). */
 typedef struct {
   int32_t wave_max_degree;   /* rows up to this length go to one wavefront with an LDS table */
   int32_t blocks_small;      /* persistent grid size of the sub-wave kernels */
@@ -161,6 +163,11 @@ typedef struct {
   int32_t async_rounds_min_frontier; /* ... when the frontier may exceed this many vertices */
   int32_t async_round_order; /* sub-rounds by 0: hash of the vertex id; 1: contiguous id ranges;
                                 2: degree classes (highest first), hashed within a class */
+  int32_t fuse_max_frontier; /* a sub-round scans all degree bins in one launch when its frontier
+                                bound is at most this and an eighth of the level's vertices at
+                                most (else one launch per bin); -1: never */
+  int32_t defer_totals;      /* LV_ASYNC: 1 sums a workgroup's Sigma/size changes in LDS and applies
+                                them when it ends; 0 applies each move's changes at once */
 } lv_tuning;
 
 /* The paper's parameter values (Section 5.1.2). */
@@ -243,7 +250,7 @@ lv_status modularity(const lv_graph* g, const int32_t* C, double* q_host, void* 
 /* Set or read the tuning table used by the calls above (process-wide). */
 /* Measurement hook.  lv_set_timing(mask) makes every later louvain_* call
  * bracket each launch of the kernels whose bit k is set in `mask` (k =
- * LV_BIN_* or LV_TIME_BINNING) with a pair of HIP events on the call's
+ * LV_TIME_*) with a pair of HIP events on the call's
  * stream, and report their count and summed time in lv_stats.  Each event
  * adds a little time between launches, so a latency measurement should
  * time one kernel at most.  Up to 4096 launches per call are timed; mask 0

@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_communities(const int64_t* __res
     int64_t ps = block_reserve(ns, &ctr[CTR_AGG_SMALL], lds);
     int64_t pm = block_reserve(nm, &ctr[CTR_AGG_MEDIUM], lds);
     int64_t pb = block_reserve(nb, &ctr[CTR_AGG_BIG], lds);
-    int64_t pp = block_reserve(pool, &ctr[CTR_POOL], lds);
+    int64_t pp = block_reserve(pool, &ctr[CTR_AGG_POOL], lds);
     for (int q = 0; q < kBinItems && first + q < nc; ++q) {
       const int64_t c = first + q;
       const int64_t vol = out_start[c + 1] - out_start[c];
@@ -553,7 +553,7 @@ void launch_aggregate(const LevelGraph& g, const int32_t* C, int32_t nc, LevelGr
   exclusive_scan_i64(ws.i64tmp, ws.vol, g.n, ws, st);
   out.n = nc;
   (void)hipMemsetAsync(ws.ctr + CTR_AGG_SMALL, 0, sizeof(int64_t) * 5 * kCtrLine, st);
-  (void)hipMemsetAsync(ws.ctr + CTR_POOL, 0, sizeof(int64_t), st);
+  (void)hipMemsetAsync(ws.ctr + CTR_AGG_POOL, 0, sizeof(int64_t), st);
   hipLaunchKernelGGL(k_bin_communities, dim3(grid_for(nc, kBlock * kBinItems, 4096)), dim3(kBlock), 0, st,
                      out.row_start, nc,
                      ws.bins[0], ws.bins[1], ws.bins[2], ws.hub_off, out.row_len, Kout, Sout, ws.ctr);

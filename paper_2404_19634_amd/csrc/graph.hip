@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kBlock) k_rows_group(const int64_t* __restrict
     }
   }
   intra = wave_sum_i64(intra);
-  if (lane == 0 && C && intra) stat_add(ctr, ST_INTRA, intra);
+  if (lane == 0 && C && intra) stat_add(ctr + CTR_STATS0, ST_INTRA, intra);
 }
 
 __global__ void __launch_bounds__(kBlock) k_rows_long(const int64_t* __restrict__ row_start,
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(kBlock) k_rows_long(const int64_t* __restrict_
     __syncthreads();
   }
   intra = wave_sum_i64(intra);
-  if (lane == 0 && C && intra) stat_add(ctr, ST_INTRA, intra);
+  if (lane == 0 && C && intra) stat_add(ctr + CTR_STATS0, ST_INTRA, intra);
 }
 
 __global__ void k_sum_squares(const int64_t* __restrict__ v, int32_t n, int64_t* __restrict__ out) {

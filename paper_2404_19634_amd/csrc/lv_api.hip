@@ -21,7 +21,7 @@ namespace lv {
 namespace {
 
 thread_local std::string g_last_error;
-lv_tuning g_tuning = {256, 2048, 2560, 1280, 7, 4096, 2};
+lv_tuning g_tuning = {256, 2048, 2560, 1280, 7, 4096, 2, 8192, 1};
 
 lv_status fail(lv_status code, const char* msg) {
   g_last_error = msg;
@@ -153,11 +153,19 @@ lv_status read_counters(int64_t* host, const Workspace& ws, int count, hipStream
   return LV_OK;
 }
 
-// A per-iteration statistic summed over its replica lines.
-int64_t stat(const int64_t* host, int st) {
+// A per-iteration statistic of one set, summed over its replicas.
+int64_t stat(const int64_t* set, int st) {
   int64_t v = 0;
-  for (int r = 0; r < kStatReplicas; ++r) v += host[CTR_STATS + r * kStatStride + st];
+  for (int r = 0; r < kStatReplicas; ++r) v += set[r * kStatStride + st];
   return v;
+}
+
+lv_status device_error(int64_t code, const char* phase) {
+  if (code == LV_EEMPTY) return fail(LV_EEMPTY, "graph has no edges (2m = 0)");
+  if (code == LV_EOVERFLOW) return fail(LV_EOVERFLOW, "total arc weight 2m >= 2^31");
+  static thread_local char msg[96];
+  std::snprintf(msg, sizeof(msg), "device error in %s", phase);
+  return fail(static_cast<lv_status>(code), msg);
 }
 
 lv_status read_i64(int64_t* host, const int64_t* dev, hipStream_t st) {
@@ -198,6 +206,8 @@ lv_tuning effective_tuning() {
   if (t.async_rounds_log2 > 7) t.async_rounds_log2 = 7;
   if (t.async_round_order < 0 || t.async_round_order > 2) t.async_round_order = 0;
   if (t.async_rounds_min_frontier < 0) t.async_rounds_min_frontier = 0;
+  if (t.fuse_max_frontier < -1) t.fuse_max_frontier = -1;
+  t.defer_totals = t.defer_totals ? 1 : 0;
   return t;
 }
 
@@ -335,21 +345,17 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
   lv_stats& S = stats ? *stats : local;
   std::memset(&S, 0, sizeof(lv_stats));
 
-  int64_t two_m = 0;
-  if ((s = read_i64(&two_m, g->two_m, st))) return s;
-  if (two_m <= 0) return fail(LV_EEMPTY, "graph has no edges (2m = 0)");
-  if (two_m >= (int64_t(1) << 31)) return fail(LV_EOVERFLOW, "total arc weight 2m >= 2^31");
-
   const int32_t N = g->n;
   const lv_edges no_edges = {nullptr, nullptr, nullptr, 0};
   const lv_edges& D = del ? *del : no_edges;
   const lv_edges& I = ins ? *ins : no_edges;
 
+  // The first kernel zeroes counters and frontier bitmasks and checks
+  // 0 < 2m < 2^31 on the device; with 2m out of range every later kernel
+  // leaves the state alone and the first readback reports the error.
   LV_HIP(hipEventRecord(ev[0], st));
-  LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_COUNT, st));
-  LV_HIP(hipMemsetAsync(ws.fr_a, 0, sizeof(uint32_t) * ws.words, st));
-  LV_HIP(hipMemsetAsync(ws.fr_b, 0, sizeof(uint32_t) * ws.words, st));
-  LV_HIP(hipMemsetAsync(ws.ever, 0, sizeof(uint32_t) * ws.words, st));
+  launch_call_begin(ws, g->two_m, st);
+  const int64_t* err = ws.ctr + CTR_ERR;
   LevelGraph L0;
   L0.n = N;
   L0.row_start = g->row_start;
@@ -365,9 +371,10 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
                     st);
     launch_set_all_bits(ws.fr_a, N, st);
   } else {
+    uint32_t* df_frontier = nullptr;
     switch (ap) {
       case A_DF:
-        launch_mark_df(D, I, state->C, ws.fr_a, st);
+        df_frontier = ws.fr_a;  // marked by the updateWeights pass
         break;
       case A_ND:
         launch_set_all_bits(ws.fr_a, N, st);
@@ -400,7 +407,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
       default:
         break;
     }
-    launch_update_weights(D, I, state->C, state->K, state->Sigma, st);
+    launch_update_weights(D, I, state->C, state->K, state->Sigma, df_frontier, err, st);
     if (p->swap_guard && !state->size) launch_community_sizes(state->C, N, ws.size, st);
   }
   LV_CHECK_LAUNCH();
@@ -416,7 +423,9 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
   uint32_t* next = ws.fr_b;
   double tau = p->tolerance;
   bool aggregated = false;
-  const double two_m_d = static_cast<double>(two_m);
+  bool moved_dirty = false;  // cleared by the first kernel, then by the SYNC apply unless pulled
+  int64_t iter_seq = 0, round_seq = 0;  // select the alternating counter sets
+  int64_t two_m = 0;
   float ms_move = 0.f, ms_agg = 0.f;
   int64_t arcs_agg = 0;
   for (int32_t pass = 0; pass < p->max_passes; ++pass) {
@@ -430,7 +439,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     a.size = size;
     a.range = (pass == 0 && use_range) ? ws.range : nullptr;
     a.ever = pass == 0 ? ws.ever : nullptr;
-    a.two_m = two_m;
+    a.two_m = g->two_m;
     a.mode = p->mode;
     a.guard = p->swap_guard;
     a.wave_max = tu.wave_max_degree;
@@ -438,63 +447,72 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     // upper bound of the frontier size, for the choice of sub-rounds
     int64_t est_frontier = L.n;
     if (pass == 0 && ap == A_DF) est_frontier = 2 * (D.count + I.count);
-    for (int32_t it = 0; it < p->max_iterations; ++it) {
+    for (int32_t it = 0; it < p->max_iterations; ++it, ++iter_seq) {
       a.cur = cur;
       a.next = next;
-      a.est = est_frontier;
       // large frontiers pull the next frontier (reads) instead of pushing it
       // (one atomic per arc of every mover)
       const bool pull = est_frontier > L.n / 4;
       a.push = pull ? 0 : 1;
       a.moved = (pull || p->mode == LV_SYNC) ? ws.moved : nullptr;
-      LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_ITER_END, st));
-      if (a.moved) LV_HIP(hipMemsetAsync(ws.moved, 0, sizeof(uint32_t) * words_l, st));
+      if (a.moved && moved_dirty) {
+        LV_HIP(hipMemsetAsync(ws.moved, 0, sizeof(uint32_t) * words_l, st));
+        moved_dirty = false;
+      }
+      int64_t* sc = ws.ctr + CTR_STATS0 + (iter_seq & 1) * kStatSet;
+      int64_t* sc_next = ws.ctr + CTR_STATS0 + ((iter_seq + 1) & 1) * kStatSet;
       const std::vector<SubRound> plan = sub_rounds(p->mode, pass, est_frontier, L.n, tu);
       // a sub-round holds at most about 4 / rounds of the frontier (four
       // degree classes); grids are sized for that
       a.est = std::max<int64_t>(64, est_frontier * 4 / static_cast<int64_t>(plan.size()));
-      for (size_t r = 0; r < plan.size(); ++r) {
-        if (r > 0)  // fresh bin counts, unit counts and table pool for the sub-round
-          LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_ROUND_END, st));
-        launch_bin_frontier(a, ws, plan[r], st);
+      a.sparse = est_frontier * 8 <= L.n ? 1 : 0;
+      for (size_t r = 0; r < plan.size(); ++r, ++round_seq) {
+        a.rc = ws.ctr + CTR_ROUND0 + (round_seq & 1) * kRoundSet;
+        a.rc_next = ws.ctr + CTR_ROUND0 + ((round_seq + 1) & 1) * kRoundSet;
+        a.sc = sc;
+        a.sc_next = r == 0 ? sc_next : nullptr;
+        a.clear_cur = r + 1 == plan.size() ? 1 : 0;
         const uint32_t mask = bins_for_degrees(plan[r].deg_lo, plan[r].deg_hi, a.wave_max);
-        launch_move(a, ws, tu, mask, st);
+        launch_round(a, ws, tu, plan[r], mask, st);
         for (int b = 0; b < NBINS; ++b) S.bin_launches[b] += (mask >> b) & 1u;
       }
-      if (p->mode == LV_SYNC) launch_apply_moves(a, ws, st);
-      if (pull) launch_pull_expand(a, ws, st);
+      if (p->mode == LV_SYNC) launch_apply_moves(a, ws, !pull, st);
+      if (pull) {
+        launch_pull_expand(a, ws, st);
+        moved_dirty = true;
+      }
       LV_CHECK_LAUNCH();
-      LV_HIP(hipMemsetAsync(cur, 0, sizeof(uint32_t) * words_l, st));
       std::swap(cur, next);
-      if ((s = read_counters(host, ws, CTR_ITER_END, st))) return s;
-      if (host[CTR_ERR]) return fail(static_cast<lv_status>(host[CTR_ERR]), "device error in local-moving");
-      const int64_t movers = stat(host, ST_MOVERS), gain = stat(host, ST_GAIN);
-      est_frontier = stat(host, ST_EXPAND);
+      LV_HIP(hipEventRecord(ev[3], st));
+      if ((s = read_counters(host, ws, CTR_ROUND0, st))) return s;
+      if (host[CTR_ERR]) return device_error(host[CTR_ERR], "local-moving");
+      two_m = host[CTR_TWO_M];
+      const int64_t* hs = host + CTR_STATS0 + (iter_seq & 1) * kStatSet;
+      const int64_t movers = stat(hs, ST_MOVERS), gain = stat(hs, ST_GAIN);
+      est_frontier = stat(hs, ST_EXPAND);
       S.moves += movers;
-      S.arcs_scanned += stat(host, ST_ARCS);
-      S.vertices_affected += stat(host, ST_AFFECTED);
+      S.arcs_scanned += stat(hs, ST_ARCS);
+      S.vertices_affected += stat(hs, ST_AFFECTED);
       for (int b = 0; b < NBINS; ++b) {
-        S.bin_vertices[b] += stat(host, ST_BIN_V0 + b);
-        S.bin_arcs[b] += stat(host, ST_BIN_A0 + b);
+        S.bin_vertices[b] += stat(hs, ST_BIN_V0 + b);
+        S.bin_arcs[b] += stat(hs, ST_BIN_A0 + b);
       }
       if (pass < LV_MAX_PASSES && it < LV_MAX_ITERS) {
         S.iter_moves[pass][it] = movers;
         S.iter_gain[pass][it] = gain;
       }
+      const double two_m_d = static_cast<double>(two_m);
       const double dq = (2.0 * static_cast<double>(gain)) / (two_m_d * two_m_d);
       if (dq <= tau) {
         li = it + 1;
+        ++iter_seq;
         break;
       }
     }
-    LV_HIP(hipEventRecord(ev[3], st));
+    ms_move += ms_between(ev[2], ev[3]);
     S.passes = pass + 1;
     S.iterations[pass] = li;
-    if (li <= 1) {
-      LV_HIP(hipStreamSynchronize(st));
-      ms_move += ms_between(ev[2], ev[3]);
-      break;
-    }
+    if (li <= 1) break;
     // renumber communities of this level (ascending old id)
     LV_HIP(hipMemsetAsync(ws.flags, 0, sizeof(int32_t) * (static_cast<size_t>(L.n) + 1), st));
     launch_mark_exists(Cl, L.n, ws.flags, st);
@@ -504,7 +522,6 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     LV_HIP(hipMemcpyAsync(&host[CTR_TOTAL], ws.newid + L.n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     LV_HIP(hipStreamSynchronize(st));
     std::memcpy(&nc32, &host[CTR_TOTAL], sizeof(int32_t));
-    ms_move += ms_between(ev[2], ev[3]);
     const int32_t nc = nc32;
     S.communities[pass] = nc;
     if (static_cast<double>(nc) / static_cast<double>(L.n) > p->aggregation_tolerance) break;
@@ -518,8 +535,8 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     launch_set_all_bits(cur, nc, st);
     LV_HIP(hipEventRecord(ev[5], st));
     LV_HIP(hipMemcpyAsync(&host[CTR_COUNT], out.row_start + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    if ((s = read_counters(host, ws, CTR_ITER_END, st))) return s;
-    if (host[CTR_ERR]) return fail(static_cast<lv_status>(host[CTR_ERR]), "device error in aggregation");
+    if ((s = read_counters(host, ws, CTR_STATS0, st))) return s;
+    if (host[CTR_ERR]) return device_error(host[CTR_ERR], "aggregation");
     ms_agg += ms_between(ev[4], ev[5]);
     arcs_agg += host[CTR_COUNT];
     L = out;
@@ -530,20 +547,20 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     tau = tau / p->tolerance_drop;
     aggregated = true;
   }
-  LV_HIP(hipEventRecord(ev[6], st));
   if (aggregated) {
+    LV_HIP(hipEventRecord(ev[6], st));
     launch_lookup(state->C, N, Cl, st);
     launch_sigma_from_members(state->C, state->K, N, state->Sigma, st);
     if (state->size) launch_community_sizes(state->C, N, state->size, st);
+    LV_CHECK_LAUNCH();
+    LV_HIP(hipEventRecord(ev[7], st));
+    LV_HIP(hipStreamSynchronize(st));
+    S.ms_other = ms_between(ev[6], ev[7]);
   }
-  LV_CHECK_LAUNCH();
-  LV_HIP(hipEventRecord(ev[7], st));
-  LV_HIP(hipStreamSynchronize(st));
   timer_collect(S.timed_launches, S.timed_ms);
   S.ms_mark = ms_between(ev[0], ev[1]);
   S.ms_move = ms_move;
   S.ms_aggregate = ms_agg;
-  S.ms_other = ms_between(ev[6], ev[7]);
   S.arcs_aggregated = arcs_agg;
   S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   return LV_OK;
@@ -795,7 +812,7 @@ lv_status modularity(const lv_graph* g, const int32_t* C, double* q_host, void* 
   if (two_m <= 0) return fail(LV_EEMPTY, "graph has no edges (2m = 0)");
   if (two_m >= (int64_t(1) << 31)) return fail(LV_EOVERFLOW, "total arc weight 2m >= 2^31");
   // Q = (2m Σσ_c - Σ_c Σ_c^2) / (2m)^2; the numerator is exact in int64
-  const int64_t qnum = two_m * stat(host, ST_INTRA) - host[CTR_AUX1];
+  const int64_t qnum = two_m * stat(host + CTR_STATS0, ST_INTRA) - host[CTR_AUX1];
   *q_host = static_cast<double>(qnum) / (static_cast<double>(two_m) * static_cast<double>(two_m));
   return LV_OK;
 }

@@ -30,34 +30,47 @@ constexpr int kHubClearSlots = 4096;      // table slots per clear unit of a hub
 // Device counters (int64 slots of Workspace::ctr).  Device-scope atomics
 // on MI355X are executed at the memory side and serialise per 128-byte line
 // (about 12 ns each), so every counter owns a line of its own, and the
-// statistics summed by every workgroup are spread over kStatReplicas lines
-// (replica = workgroup id mod kStatReplicas) that the host adds up.
+// statistics summed by every workgroup are spread over kStatReplicas
+// replicas (replica = workgroup id mod kStatReplicas) that the host adds up.
+//
+// Sub-round counters (bin sizes, hub units) and per-iteration statistics
+// each come in two sets used alternately, so no clear has to be launched
+// between rounds or iterations: the first kernel of a round zeroes the set
+// the next round will use (the previous round's, already consumed), and the
+// first kernel of an iteration zeroes the statistics set of the iteration
+// after it (the host read it at the end of the previous iteration).
 constexpr int kCtrLine = 16;        // int64 slots per 128-byte line
 constexpr int kStatReplicas = 32;
 constexpr int kStatStride = 2 * kCtrLine;  // slots per replica (two lines)
+constexpr int kStatSet = kStatReplicas * kStatStride;
+constexpr int kRoundSet = 10 * kCtrLine;
 enum Ctr {
-  CTR_BIN0 = 0,                          // lines 0 .. NBINS-1: items per bin (ctr_bin)
-  CTR_B_RESV = 0 * kCtrLine,             // apply_batch: packed (chunks << 32 | partners) reserved
-  CTR_POOL = 7 * kCtrLine,               // global hashtable slots handed out
-  CTR_HUB_UNITS = 8 * kCtrLine,          // hub work units (insert / expand)
-  CTR_HUB_CUNITS = 9 * kCtrLine,         // hub table-clear units
-  CTR_ROUND_END = 10 * kCtrLine,         // lines below are cleared every sub-round
-  CTR_ERR = 10 * kCtrLine,               // error code (first nonzero wins)
-  CTR_TOTAL = 11 * kCtrLine,             // generic total (scans, counts)
-  CTR_AUX0 = 12 * kCtrLine,
-  CTR_AUX1 = 13 * kCtrLine,
-  CTR_AUX2 = 14 * kCtrLine,
-  CTR_AUX3 = 15 * kCtrLine,
-  CTR_STATS = 16 * kCtrLine,             // kStatReplicas replicas of per-iteration statistics
-  CTR_ITER_END = 16 * kCtrLine + kStatReplicas * kStatStride,  // lines below are cleared every iteration
-  CTR_AGG_SMALL = CTR_ITER_END,          // aggregation: communities per tier and unit counts
-  CTR_AGG_MEDIUM = CTR_ITER_END + 1 * kCtrLine,
-  CTR_AGG_BIG = CTR_ITER_END + 2 * kCtrLine,
-  CTR_UNITS_INS = CTR_ITER_END + 3 * kCtrLine,
-  CTR_UNITS_EMIT = CTR_ITER_END + 4 * kCtrLine,
-  CTR_COUNT = CTR_ITER_END + 8 * kCtrLine
+  CTR_ERR = 0 * kCtrLine,        // error code (first nonzero wins)
+  CTR_TOTAL = 1 * kCtrLine,      // generic total (scans, counts)
+  CTR_AUX0 = 2 * kCtrLine,
+  CTR_AUX1 = 3 * kCtrLine,
+  CTR_AUX2 = 4 * kCtrLine,
+  CTR_AUX3 = 5 * kCtrLine,
+  CTR_TWO_M = 6 * kCtrLine,      // 2m as read by the first kernel of a louvain call
+  CTR_AGG_SMALL = 7 * kCtrLine,  // aggregation: communities per tier, unit counts, pool
+  CTR_AGG_MEDIUM = 8 * kCtrLine,
+  CTR_AGG_BIG = 9 * kCtrLine,
+  CTR_UNITS_INS = 10 * kCtrLine,
+  CTR_UNITS_EMIT = 11 * kCtrLine,
+  CTR_AGG_POOL = 12 * kCtrLine,
+  CTR_B_RESV = 13 * kCtrLine,    // apply_batch: packed (chunks << 32 | partners) reserved
+  CTR_STATS0 = 16 * kCtrLine,    // two statistics sets of kStatSet slots
+  CTR_ROUND0 = CTR_STATS0 + 2 * kStatSet,  // two sub-round sets of kRoundSet slots
+  CTR_COUNT = CTR_ROUND0 + 2 * kRoundSet
 };
-// per-iteration statistics, slots of every replica line
+// sub-round counters, offsets inside a round set
+enum RoundCtr {
+  RC_BIN0 = 0,                   // lines 0 .. NBINS-1: items per bin (rc_bin)
+  RC_POOL = 7 * kCtrLine,        // hub table slots handed out
+  RC_HUB_UNITS = 8 * kCtrLine,   // hub insert units
+  RC_HUB_CUNITS = 9 * kCtrLine   // hub table-slot (clear / decide) units
+};
+// per-iteration statistics, slots of every replica
 enum Stat {
   ST_MOVERS = 0,  // moves decided
   ST_GAIN,        // sum of the movers' gains
@@ -71,7 +84,7 @@ enum Stat {
   NSTATS = ST_BIN_A0 + 7
 };
 static_assert(NSTATS <= kStatStride, "statistics exceed a replica");
-constexpr int ctr_bin(int b) { return CTR_BIN0 + b * kCtrLine; }
+constexpr int rc_bin(int b) { return RC_BIN0 + b * kCtrLine; }
 
 
 struct LevelGraph {
@@ -154,9 +167,9 @@ __device__ __forceinline__ void set_error(int64_t* ctr, int64_t code) {
             static_cast<unsigned long long>(code));
 }
 
-// Adds v to statistic `st` in this workgroup's replica line.
-__device__ __forceinline__ void stat_add(int64_t* ctr, int st, int64_t v) {
-  atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_STATS + (blockIdx.x % kStatReplicas) * kStatStride + st]),
+// Adds v to statistic `st` in this workgroup's replica of the set `sc`.
+__device__ __forceinline__ void stat_add(int64_t* sc, int st, int64_t v) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(&sc[(blockIdx.x % kStatReplicas) * kStatStride + st]),
             static_cast<unsigned long long>(v));
 }
 
@@ -303,10 +316,10 @@ void launch_batch_phase2(const lv_graph& g, const lv_edges& del, const lv_edges&
                          int64_t* ctr, hipStream_t st);
 
 // mark.hip
-void launch_mark_df(const lv_edges& del, const lv_edges& ins, const int32_t* C, uint32_t* fr,
-                    hipStream_t st);
+// updateWeights (Alg. 7); with df_frontier given it also marks DF's initial
+// frontier (Alg. 1) in the same pass.  Does nothing if *err is set.
 void launch_update_weights(const lv_edges& del, const lv_edges& ins, const int32_t* C, int64_t* K,
-                           int64_t* Sigma, hipStream_t st);
+                           int64_t* Sigma, uint32_t* df_frontier, const int64_t* err, hipStream_t st);
 void launch_batch_weight_sums(const lv_edges& del, const lv_edges& ins, int64_t* ctr, hipStream_t st);
 void launch_community_sizes(const int32_t* C, int32_t n, int32_t* size, hipStream_t st);
 void launch_ds_deletions(const lv_edges& del, const int32_t* C, uint32_t* dV, uint32_t* dE,
@@ -334,7 +347,13 @@ struct MoveArgs {
   uint32_t* ever;         // nullptr: not tracked
   uint32_t* moved;        // movers bitmask (SYNC always; ASYNC when pulling)
   int32_t push;           // 1: movers push the next frontier; 0: it is pulled afterwards
-  int64_t two_m;
+  const int64_t* two_m;   // device copy of 2m (kernels do nothing unless 0 < 2m < 2^31)
+  int64_t* rc;            // this sub-round's counter set
+  int64_t* rc_next;       // the other set, zeroed by this round's binning for the next round
+  int64_t* sc;            // this iteration's statistics set
+  int64_t* sc_next;       // the other set; zeroed by the first round's binning when non-null
+  int32_t clear_cur;      // 1: binning clears the current frontier as it reads it (last round)
+  int32_t sparse;         // 1: the frontier bound is a small share of the level's vertices
   int64_t est;            // upper bound of the vertices processed (grid sizes)
   int32_t mode;
   int32_t guard;
@@ -356,11 +375,16 @@ void timer_begin(int kernel, hipStream_t st);
 void timer_end(int kernel, hipStream_t st);
 void timer_collect(int32_t* launches, double* ms);  // adds per kernel, resets
 
-void launch_bin_frontier(const MoveArgs& a, Workspace& ws, const SubRound& r, hipStream_t st);
+// One sub-round: binning, hub table clear, the fused scan over the bins in
+// `bin_mask` (and hub inserts), hub decisions.  Four launches.
 uint32_t bins_for_degrees(int32_t lo, int32_t hi, int32_t wave_max);
-void launch_move(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, uint32_t bin_mask, hipStream_t st);
-void launch_apply_moves(const MoveArgs& a, Workspace& ws, hipStream_t st);
+void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const SubRound& r, uint32_t bin_mask,
+                  hipStream_t st);
+void launch_apply_moves(const MoveArgs& a, Workspace& ws, bool clear_moved, hipStream_t st);
 void launch_pull_expand(const MoveArgs& a, Workspace& ws, hipStream_t st);
+// First kernel of a louvain call: zeroes the counters and the frontier
+// bitmasks, copies 2m into CTR_TWO_M and flags LV_EEMPTY / LV_EOVERFLOW.
+void launch_call_begin(Workspace& ws, const int64_t* two_m, hipStream_t st);
 
 // aggregate.hip
 void launch_mark_exists(const int32_t* C, int32_t n, int32_t* flags, hipStream_t st);

@@ -18,22 +18,6 @@
 namespace lv {
 namespace {
 
-__global__ void k_mark_df(const int32_t* __restrict__ du, const int32_t* __restrict__ dv, int64_t nd,
-                          const int32_t* __restrict__ iu, const int32_t* __restrict__ iv, int64_t ni,
-                          const int32_t* __restrict__ C, uint32_t* __restrict__ fr) {
-  const int64_t total = nd + ni;
-  for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < total;
-       k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const bool del = k < nd;
-    const int32_t a = del ? du[k] : iu[k - nd];
-    const int32_t b = del ? dv[k] : iv[k - nd];
-    const bool same = C[a] == C[b];
-    if (same == del) {  // deletion inside a community, or insertion across communities
-      set_bit(fr, a);
-      set_bit(fr, b);
-    }
-  }
-}
 
 // Alg. 7: K_u, K_v += w and Sigma[C_u], Sigma[C_v] += w per update (minus
 // for deletions).  Large communities take many of the Sigma updates of a
@@ -43,11 +27,16 @@ __global__ void k_mark_df(const int32_t* __restrict__ du, const int32_t* __restr
 constexpr int kUwItems = 4;                         // updates per thread
 constexpr int kUwSlots = 2048;                      // LDS table slots
 constexpr int kUwProbes = 16;
+// With `fr` given, the same pass also does DF's initial marking (both read
+// the previous memberships C^{t-1}).  Nothing is done when the call's error
+// slot is already set (2m out of range).
 __global__ void __launch_bounds__(kBlock) k_update_weights(const int32_t* __restrict__ du, const int32_t* __restrict__ dv,
                                  const int32_t* __restrict__ dw, int64_t nd, const int32_t* __restrict__ iu,
                                  const int32_t* __restrict__ iv, const int32_t* __restrict__ iw, int64_t ni,
                                  const int32_t* __restrict__ C, int64_t* __restrict__ K,
-                                 int64_t* __restrict__ Sigma) {
+                                 int64_t* __restrict__ Sigma, uint32_t* __restrict__ fr,
+                                 const int64_t* __restrict__ err) {
+  if (*err) return;
   __shared__ int32_t tk[kUwSlots];
   __shared__ unsigned long long tv[kUwSlots];
   for (int q = threadIdx.x; q < kUwSlots; q += kBlock) {
@@ -57,17 +46,38 @@ __global__ void __launch_bounds__(kBlock) k_update_weights(const int32_t* __rest
   __syncthreads();
   const int64_t total = nd + ni;
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kBlock * kUwItems;
+  // all of a thread's updates are loaded, then their communities gathered,
+  // so the memory latencies overlap
+  int32_t ea[kUwItems], eb[kUwItems], ca[kUwItems], cb[kUwItems];
+  int64_t ex[kUwItems];
+  bool del[kUwItems], ok[kUwItems];
+#pragma unroll
   for (int it = 0; it < kUwItems; ++it) {
     const int64_t k = base + static_cast<int64_t>(it) * kBlock + threadIdx.x;
-    if (k >= total) break;
-    const bool del = k < nd;
-    const int32_t a = del ? du[k] : iu[k - nd];
-    const int32_t b = del ? dv[k] : iv[k - nd];
-    const int64_t x = del ? -static_cast<int64_t>(dw[k]) : static_cast<int64_t>(iw[k - nd]);
+    ok[it] = k < total;
+    del[it] = k < nd;
+    ea[it] = !ok[it] ? 0 : (del[it] ? du[k] : iu[k - nd]);
+    eb[it] = !ok[it] ? 0 : (del[it] ? dv[k] : iv[k - nd]);
+    ex[it] = !ok[it] ? 0 : (del[it] ? -static_cast<int64_t>(dw[k]) : static_cast<int64_t>(iw[k - nd]));
+  }
+#pragma unroll
+  for (int it = 0; it < kUwItems; ++it) {
+    ca[it] = ok[it] ? C[ea[it]] : 0;
+    cb[it] = ok[it] ? C[eb[it]] : 0;
+  }
+#pragma unroll
+  for (int it = 0; it < kUwItems; ++it) {
+    if (!ok[it]) continue;
+    const int32_t a = ea[it], b = eb[it];
+    const int64_t x = ex[it];
     atomic_add_i64(&K[a], x);
     atomic_add_i64(&K[b], x);
+    if (fr && (ca[it] == cb[it]) == del[it]) {  // deletion inside a community, or insertion across
+      set_bit(fr, a);
+      set_bit(fr, b);
+    }
     for (int side = 0; side < 2; ++side) {
-      const int32_t c = C[side ? b : a];
+      const int32_t c = side ? cb[it] : ca[it];
       uint32_t h = hash_slot(static_cast<uint32_t>(c), kUwSlots);
       bool done = false;
       for (int p = 0; p < kUwProbes; ++p) {
@@ -245,20 +255,14 @@ __global__ void k_ds_expand(const int64_t* __restrict__ row_start, const int32_t
 
 }  // namespace
 
-void launch_mark_df(const lv_edges& del, const lv_edges& ins, const int32_t* C, uint32_t* fr, hipStream_t st) {
-  const int64_t total = del.count + ins.count;
-  if (total == 0) return;
-  hipLaunchKernelGGL(k_mark_df, dim3(grid_for(total, kBlock, 4096)), dim3(kBlock), 0, st, del.u, del.v,
-                     del.count, ins.u, ins.v, ins.count, C, fr);
-}
 
 void launch_update_weights(const lv_edges& del, const lv_edges& ins, const int32_t* C, int64_t* K, int64_t* Sigma,
-                           hipStream_t st) {
+                           uint32_t* df_frontier, const int64_t* err, hipStream_t st) {
   const int64_t total = del.count + ins.count;
   if (total == 0) return;
   const int blocks = static_cast<int>((total + kBlock * kUwItems - 1) / (kBlock * kUwItems));
   hipLaunchKernelGGL(k_update_weights, dim3(blocks), dim3(kBlock), 0, st, del.u, del.v,
-                     del.w, del.count, ins.u, ins.v, ins.w, ins.count, C, K, Sigma);
+                     del.w, del.count, ins.u, ins.v, ins.w, ins.count, C, K, Sigma, df_frontier, err);
 }
 
 void launch_batch_weight_sums(const lv_edges& del, const lv_edges& ins, int64_t* ctr, hipStream_t st) {

@@ -16,23 +16,34 @@
 //   rows up to the wave threshold: one wavefront, open-addressing table in
 //     LDS;
 //   rows up to 2048 arcs: one workgroup, open-addressing table in LDS;
-//   hub rows: units of 8192 arcs spread over workgroups; each unit
+//   hub rows: units of 2048 arcs spread over workgroups; each unit
 //     pre-aggregates in LDS and flushes into the row's global table
 //     (2 x deg slots from the workspace pool); units of 4096 table slots
-//     take partial argmaxes, one wavefront per hub picks the best, and
-//     units expand the frontier of moved hubs.
-// LDS tables are sized to the smallest power of two >= 2 x deg.
+//     take partial argmaxes, one wavefront per hub picks the move, and
+//     insert-sized units expand the frontier of moved hubs.
 // Arcs into the vertex's own community d are summed in registers in every
 // tier, which keeps the most frequent key out of the hashtable atomics.
+//
+// A sub-round is binning, then (with hub rows) a hub table clear, the scan,
+// then (with hub rows) hub partial argmaxes, decisions and expansion.  For small
+// frontiers the scan is one fused kernel whose workgroups take the roles
+// of the per-bin kernels (the block ranges of the roles laid end to end in
+// one grid): such launches are bound by launch latency, so the count
+// matters.  Large frontiers run the same kernel once per bin, in order of
+// degree, so that ASYNC moves of one bin are seen by the next.
+//
 // SYNC mode reads the iteration-start state and records movers; a separate
-// kernel applies them.  ASYNC mode applies each move at once.  Both expand
-// the next frontier from the kernel that holds the mover's arcs.
+// kernel applies them.  ASYNC mode applies each move's membership at once.
+// Both expand the next frontier from the kernel that holds the mover's arcs
+// (or leave it to the pull kernels when the frontier is large).
 #include <climits>
 
 #include "lv_internal.hpp"
 
 namespace lv {
 namespace {
+
+constexpr int64_t kTwoMLimit = int64_t(1) << 31;
 
 struct Dev {
   const int64_t* row_start;
@@ -47,13 +58,16 @@ struct Dev {
   uint32_t* moved;
   int32_t* mv_c;
   int32_t push;
+  int64_t* rc;  // sub-round counters
+  int64_t* sc;  // statistics set
   int64_t* ctr;
-  int64_t two_m;
+  const int64_t* two_m;
   int32_t mode;
   int32_t guard;
+  int32_t defer;  // ASYNC: Sigma / size changes through the workgroup aggregate
 };
 
-Dev make_dev(const MoveArgs& a, Workspace& ws) {
+Dev make_dev(const MoveArgs& a, Workspace& ws, const lv_tuning& tu) {
   Dev d;
   d.row_start = a.g.row_start;
   d.row_len = a.g.row_len;
@@ -67,11 +81,21 @@ Dev make_dev(const MoveArgs& a, Workspace& ws) {
   d.moved = a.moved;
   d.mv_c = ws.mv_c;
   d.push = a.push;
+  d.rc = a.rc;
+  d.sc = a.sc;
   d.ctr = ws.ctr;
   d.two_m = a.two_m;
   d.mode = a.mode;
   d.guard = a.guard;
+  d.defer = tu.defer_totals;
   return d;
+}
+
+// 2m of the call; 0 when it is out of range (the first kernel of the call
+// has flagged the error and every move kernel then does nothing).
+__device__ __forceinline__ int64_t load_two_m(const Dev& D) {
+  const int64_t t = *D.two_m;
+  return (t > 0 && t < kTwoMLimit) ? t : 0;
 }
 
 __device__ __forceinline__ bool better(int64_t g1, int32_t c1, int64_t g0, int32_t c0) {
@@ -98,72 +122,88 @@ __device__ __forceinline__ bool decide_move(const Dev& D, int32_t d, int32_t c, 
 // would queue behind each other.  In ASYNC mode a move's new membership is
 // visible at once; its effect on Sigma and size becomes visible when the
 // workgroup that made it finishes.
-constexpr int kAggSlots = 512;
 constexpr int kAggProbes = 8;
-struct MoveAgg {
-  int32_t key[kAggSlots];
-  int32_t dsize[kAggSlots];
-  unsigned long long dsig[kAggSlots];
+template <int SLOTS>
+struct MoveAggT {
+  static constexpr int kSlots = SLOTS;
+  int32_t key[SLOTS];
+  int32_t dsize[SLOTS];
+  unsigned long long dsig[SLOTS];
 };
+using MoveAgg = MoveAggT<512>;       // roles with many movers per workgroup
+using MoveAggSmall = MoveAggT<128>;  // the workgroup-per-row role
 
-__device__ __forceinline__ void agg_begin(MoveAgg* A) {
-  for (int s = threadIdx.x; s < kAggSlots; s += blockDim.x) {
-    A->key[s] = -1;
-    A->dsize[s] = 0;
-    A->dsig[s] = 0;
+template <class A>
+__device__ __forceinline__ void agg_begin(A* a) {
+  for (int s = threadIdx.x; s < A::kSlots; s += blockDim.x) {
+    a->key[s] = -1;
+    a->dsize[s] = 0;
+    a->dsig[s] = 0;
   }
   __syncthreads();
 }
 
-__device__ __forceinline__ void agg_add(MoveAgg* A, int64_t* Sigma, int32_t* size, int32_t c, int64_t dk, int32_t ds) {
-  uint32_t h = hash_slot(static_cast<uint32_t>(c), kAggSlots);
+template <class A>
+__device__ __forceinline__ void agg_add(A* a, int64_t* Sigma, int32_t* size, int32_t c, int64_t dk, int32_t ds) {
+  uint32_t h = hash_slot(static_cast<uint32_t>(c), A::kSlots);
   for (int p = 0; p < kAggProbes; ++p) {
-    const int32_t old = atomicCAS(&A->key[h], -1, c);
+    const int32_t old = atomicCAS(&a->key[h], -1, c);
     if (old == -1 || old == c) {
-      atomicAdd(&A->dsig[h], static_cast<unsigned long long>(dk));
-      if (size) atomicAdd(&A->dsize[h], ds);
+      atomicAdd(&a->dsig[h], static_cast<unsigned long long>(dk));
+      if (size) atomicAdd(&a->dsize[h], ds);
       return;
     }
-    h = (h + 1) & (kAggSlots - 1);
+    h = (h + 1) & (A::kSlots - 1);
   }
   atomic_add_i64(&Sigma[c], dk);
   if (size) atomicAdd(&size[c], ds);
 }
 
 // every thread of the workgroup calls it once, after its last agg_add
-__device__ __forceinline__ void agg_end(MoveAgg* A, int64_t* Sigma, int32_t* size) {
+template <class A>
+__device__ __forceinline__ void agg_end(A* a, int64_t* Sigma, int32_t* size) {
   __syncthreads();
-  for (int s = threadIdx.x; s < kAggSlots; s += blockDim.x) {
-    const int32_t c = A->key[s];
+  for (int s = threadIdx.x; s < A::kSlots; s += blockDim.x) {
+    const int32_t c = a->key[s];
     if (c < 0) continue;
-    if (A->dsig[s]) atomic_add_i64(&Sigma[c], static_cast<int64_t>(A->dsig[s]));
-    if (size && A->dsize[s]) atomicAdd(&size[c], A->dsize[s]);
+    if (a->dsig[s]) atomic_add_i64(&Sigma[c], static_cast<int64_t>(a->dsig[s]));
+    if (size && a->dsize[s]) atomicAdd(&size[c], a->dsize[s]);
   }
 }
 
 // Records (SYNC: target by vertex plus the movers bitmask) or applies
-// (ASYNC: membership now, totals through the workgroup's aggregate) one
-// move -- one lane per mover.
-__device__ __forceinline__ void commit_move(const Dev& D, MoveAgg* A, int32_t i, int32_t d, int32_t c, int64_t Ki) {
+// (ASYNC: membership now, totals through the workgroup's aggregate, or
+// directly when A is null) one move -- one lane per mover.
+template <class Agg>
+__device__ __forceinline__ void commit_move(const Dev& D, Agg* A, int32_t i, int32_t d, int32_t c, int64_t Ki) {
   if (D.moved) set_bit(D.moved, i);
   if (D.mode == LV_SYNC) {
     D.mv_c[i] = c;
     return;
   }
   D.C[i] = c;
-  agg_add(A, D.Sigma, D.size, d, -Ki, -1);
-  agg_add(A, D.Sigma, D.size, c, Ki, 1);
+  if (A && D.defer) {
+    agg_add(A, D.Sigma, D.size, d, -Ki, -1);
+    agg_add(A, D.Sigma, D.size, c, Ki, 1);
+  } else {
+    atomic_add_i64(&D.Sigma[d], -Ki);
+    atomic_add_i64(&D.Sigma[c], Ki);
+    if (D.size) {
+      atomicSub(&D.size[d], 1);
+      atomicAdd(&D.size[c], 1);
+    }
+  }
 }
 
-// Wavefront totals of gains, moves and mover arcs into the counters.
+// Wavefront totals of gains, moves and mover arcs into the statistics.
 __device__ __forceinline__ void flush_totals(const Dev& D, int64_t gain, int64_t moved, int64_t arcs) {
   gain = wave_sum_i64(gain);
   moved = wave_sum_i64(moved);
   arcs = wave_sum_i64(arcs);
   if (lane_id() == 0 && moved) {
-    stat_add(D.ctr, ST_GAIN, gain);
-    stat_add(D.ctr, ST_EXPAND, arcs);
-    stat_add(D.ctr, ST_MOVERS, moved);
+    stat_add(D.sc, ST_GAIN, gain);
+    stat_add(D.sc, ST_EXPAND, arcs);
+    stat_add(D.sc, ST_MOVERS, moved);
   }
 }
 
@@ -211,22 +251,22 @@ struct HubOut {
   int64_t* off;    // global table offset
   int64_t* cbase;  // first clear / decide unit
   int32_t* cnum;   // number of clear / decide units
-  int32_t* u_b;    // insert / expand units: (hub item, first arc)
+  int32_t* u_b;    // insert units: (hub item, first arc)
   int64_t* u_a;
   int32_t* c_b;    // clear / decide units: (hub item, first slot)
   int64_t* c_s;
 };
 
-// Reserves the hub row's global table (2*deg slots) and writes its units.
-__device__ __forceinline__ void hub_setup(const HubOut& H, int64_t pos, int32_t deg, int64_t* ctr) {
-  H.off[pos] = static_cast<int64_t>(
-      atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_POOL]), 2ull * static_cast<unsigned long long>(deg)));
-  const int64_t nu = (deg + kHubUnitArcs - 1) / kHubUnitArcs;
-  const int64_t nc = (2 * static_cast<int64_t>(deg) + kHubClearSlots - 1) / kHubClearSlots;
-  const int64_t bu = static_cast<int64_t>(
-      atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_HUB_UNITS]), static_cast<unsigned long long>(nu)));
-  const int64_t bc = static_cast<int64_t>(
-      atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_HUB_CUNITS]), static_cast<unsigned long long>(nc)));
+__device__ __forceinline__ int64_t hub_units(int32_t deg) { return (deg + kHubUnitArcs - 1) / kHubUnitArcs; }
+__device__ __forceinline__ int64_t hub_cunits(int32_t deg) {
+  return (2 * static_cast<int64_t>(deg) + kHubClearSlots - 1) / kHubClearSlots;
+}
+
+// Writes a hub row's table offset and unit descriptors at the given bases.
+__device__ __forceinline__ void hub_write(const HubOut& H, int64_t pos, int32_t deg, int64_t off, int64_t bu,
+                                         int64_t bc) {
+  const int64_t nu = hub_units(deg), nc = hub_cunits(deg);
+  H.off[pos] = off;
   H.cbase[pos] = bc;
   H.cnum[pos] = static_cast<int32_t>(nc);
   for (int64_t u = 0; u < nu; ++u) {
@@ -239,20 +279,78 @@ __device__ __forceinline__ void hub_setup(const HubOut& H, int64_t pos, int32_t 
   }
 }
 
+// Reserves the hub row's global table (2*deg slots) and its units alone
+// (three device atomics).
+__device__ __forceinline__ void hub_setup(const HubOut& H, int64_t pos, int32_t deg, int64_t* rc) {
+  const int64_t off = static_cast<int64_t>(
+      atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_POOL]), 2ull * static_cast<unsigned long long>(deg)));
+  const int64_t bu = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_HUB_UNITS]),
+                                                    static_cast<unsigned long long>(hub_units(deg))));
+  const int64_t bc = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_HUB_CUNITS]),
+                                                    static_cast<unsigned long long>(hub_cunits(deg))));
+  hub_write(H, pos, deg, off, bu, bc);
+}
+
+// --------------------------------------------------------------------------
+// First kernel of a call: counters, frontier bitmasks, 2m.
+// --------------------------------------------------------------------------
+__global__ void k_call_begin(int64_t* __restrict__ ctr, uint32_t* __restrict__ fr_a, uint32_t* __restrict__ fr_b,
+                             uint32_t* __restrict__ ever, uint32_t* __restrict__ moved, int64_t words,
+                             const int64_t* __restrict__ two_m) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t t0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  for (int64_t k = t0; k < words; k += stride) {
+    fr_a[k] = 0;
+    fr_b[k] = 0;
+    ever[k] = 0;
+    moved[k] = 0;
+  }
+  for (int64_t k = t0; k < CTR_COUNT; k += stride) {
+    int64_t v = 0;
+    if (k == CTR_TWO_M) v = *two_m;
+    if (k == CTR_ERR) {
+      const int64_t t = *two_m;
+      v = t <= 0 ? LV_EEMPTY : (t >= kTwoMLimit ? LV_EOVERFLOW : 0);
+    }
+    ctr[k] = v;
+  }
+}
+
+constexpr int kBinStats = 3 + 2 * NBINS;  // processed, arcs, affected, per-bin vertices and arcs
+constexpr int kBinHubs = 64;              // hubs a workgroup reserves together per pass
+
 // --------------------------------------------------------------------------
 // Frontier -> degree bins.  One thread per 32-vertex bitmask word.  Each
 // workgroup counts its vertices per bin in LDS, reserves one range per bin
-// with a single global atomic, then places them.
+// with a single global atomic, then places them.  Block 0 zeroes the other
+// round set (and, on the first round of an iteration, the other statistics
+// set); on the last round of an iteration each word of the frontier is
+// cleared once read.
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_bin_frontier(const uint32_t* __restrict__ cur,
+__global__ void __launch_bounds__(kBlock) k_bin_frontier(uint32_t* __restrict__ cur,
                                                         const uint32_t* __restrict__ range,
                                                         uint32_t* __restrict__ ever,
                                                         const int32_t* __restrict__ row_len, int32_t n,
                                                         int32_t wave_max, uint32_t round, uint32_t round_shift,
                                                         int32_t id_lo, int32_t id_hi, int32_t deg_lo, int32_t deg_hi,
-                                                        Bins bins, HubOut H, int64_t* __restrict__ ctr) {
+                                                        int32_t clear_cur, Bins bins, HubOut H,
+                                                        int64_t* __restrict__ rc, int64_t* __restrict__ sc,
+                                                        int64_t* __restrict__ rc_next,
+                                                        int64_t* __restrict__ sc_next) {
   __shared__ int32_t s_cnt[NBINS];
   __shared__ int64_t s_base[NBINS];
+  __shared__ unsigned long long s_stat[kBinStats];  // block totals of the statistics
+  __shared__ int32_t s_nh;                          // hubs placed in this pass of the block
+  __shared__ int64_t s_hpos[kBinHubs];
+  __shared__ int32_t s_hdeg[kBinHubs];
+  __shared__ int64_t s_hbase[3];
+  if (threadIdx.x < kBinStats) s_stat[threadIdx.x] = 0;
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < kRoundSet; k += blockDim.x) rc_next[k] = 0;
+  if (sc_next)
+    for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < kStatSet;
+         k += static_cast<int64_t>(gridDim.x) * blockDim.x)
+      sc_next[k] = 0;
   const int64_t words = (static_cast<int64_t>(n) + 31) / 32;
   int64_t arcs = 0, processed = 0, affected = 0;
   int64_t bin_verts[NBINS], bin_arcs[NBINS];
@@ -261,11 +359,13 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(const uint32_t* __restr
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t w0 = blockIdx.x * static_cast<int64_t>(blockDim.x); w0 < words; w0 += stride) {
     if (threadIdx.x < NBINS) s_cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_nh = 0;
     __syncthreads();
     const int64_t k = w0 + threadIdx.x;
     uint32_t bits = 0;
     if (k < words) {
       bits = cur[k];
+      if (clear_cur && bits) cur[k] = 0;
       if (range) bits &= range[k];
       if (round_shift < 32 && bits) bits &= round_mask(static_cast<uint32_t>(k), round, round_shift);
       if (bits) bits &= range_mask(k, id_lo, id_hi);
@@ -308,7 +408,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(const uint32_t* __restr
     if (threadIdx.x < NBINS) {
       const int32_t c = s_cnt[threadIdx.x];
       s_base[threadIdx.x] = c ? static_cast<int64_t>(atomicAdd(
-                                    reinterpret_cast<unsigned long long*>(&ctr[ctr_bin(threadIdx.x)]),
+                                    reinterpret_cast<unsigned long long*>(&rc[rc_bin(threadIdx.x)]),
                                     static_cast<unsigned long long>(c)))
                               : 0;
       s_cnt[threadIdx.x] = 0;
@@ -321,44 +421,89 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(const uint32_t* __restr
       if (bin < 0) continue;
       const int64_t pos = s_base[bin] + atomicAdd(&s_cnt[bin], 1);
       bins.list[bin][pos] = i;
-      if (bin == BIN_HUB) hub_setup(H, pos, deg, ctr);
+      if (bin == BIN_HUB) {  // queued for one reservation per workgroup
+        const int q = atomicAdd(&s_nh, 1);
+        if (q < kBinHubs) {
+          s_hpos[q] = pos;
+          s_hdeg[q] = deg;
+        } else {
+          hub_setup(H, pos, deg, rc);
+        }
+      }
+    }
+    __syncthreads();
+    const int nh = min(s_nh, kBinHubs);
+    if (nh > 0) {
+      if (threadIdx.x == 0) {
+        int64_t slots = 0, nu = 0, nc = 0;
+        for (int q = 0; q < nh; ++q) {
+          slots += 2 * static_cast<int64_t>(s_hdeg[q]);
+          nu += hub_units(s_hdeg[q]);
+          nc += hub_cunits(s_hdeg[q]);
+        }
+        s_hbase[0] = static_cast<int64_t>(
+            atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_POOL]), static_cast<unsigned long long>(slots)));
+        s_hbase[1] = static_cast<int64_t>(
+            atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_HUB_UNITS]), static_cast<unsigned long long>(nu)));
+        s_hbase[2] = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_HUB_CUNITS]),
+                                                    static_cast<unsigned long long>(nc)));
+      }
+      __syncthreads();
+      if (threadIdx.x < nh) {
+        int64_t off = s_hbase[0], bu = s_hbase[1], bc = s_hbase[2];
+        for (int q = 0; q < static_cast<int>(threadIdx.x); ++q) {
+          off += 2 * static_cast<int64_t>(s_hdeg[q]);
+          bu += hub_units(s_hdeg[q]);
+          bc += hub_cunits(s_hdeg[q]);
+        }
+        hub_write(H, s_hpos[threadIdx.x], s_hdeg[threadIdx.x], off, bu, bc);
+      }
     }
     __syncthreads();
   }
-  processed = wave_sum_i64(processed);
-  arcs = wave_sum_i64(arcs);
-  affected = wave_sum_i64(affected);
-  if (lane_id() == 0) {
-    if (processed) stat_add(ctr, ST_PROCESSED, processed);
-    if (arcs) stat_add(ctr, ST_ARCS, arcs);
-    if (affected) stat_add(ctr, ST_AFFECTED, affected);
-  }
+  // statistics: wavefront sums, then workgroup sums, then one atomic each
+  {
+    int64_t v[kBinStats];
+    v[0] = processed;
+    v[1] = arcs;
+    v[2] = affected;
 #pragma unroll
-  for (int q = 0; q < NBINS; ++q) {
-    const int64_t v = wave_sum_i64(bin_verts[q]);
-    const int64_t x = wave_sum_i64(bin_arcs[q]);
-    if (lane_id() == 0 && v) {
-      stat_add(ctr, ST_BIN_V0 + q, v);
-      stat_add(ctr, ST_BIN_A0 + q, x);
+    for (int q = 0; q < NBINS; ++q) {
+      v[3 + q] = bin_verts[q];
+      v[3 + NBINS + q] = bin_arcs[q];
     }
+#pragma unroll
+    for (int q = 0; q < kBinStats; ++q) {
+      const int64_t t = wave_sum_i64(v[q]);
+      if (lane_id() == 0 && t) atomicAdd(&s_stat[q], static_cast<unsigned long long>(t));
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kBinStats && s_stat[threadIdx.x]) {
+    const int q = threadIdx.x;
+    const int slot = q == 0 ? ST_PROCESSED : q == 1 ? ST_ARCS : q == 2 ? ST_AFFECTED
+                   : q < 3 + NBINS ? ST_BIN_V0 + (q - 3) : ST_BIN_A0 + (q - 3 - NBINS);
+    stat_add(sc, slot, static_cast<int64_t>(s_stat[q]));
   }
 }
 
 // --------------------------------------------------------------------------
-// Rows of at most G arcs: groups of G lanes, one arc per lane.
+// Roles of the fused scan kernel.  Each takes its own block index range
+// (rb in [0, nb)) and the workgroup's LDS.
 // --------------------------------------------------------------------------
+
+// Rows of at most G arcs: groups of G lanes, one arc per lane.
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_move_small(Dev D, const int32_t* __restrict__ list, int bin) {
+__device__ __forceinline__ void role_small(const Dev& D, int64_t two_m, const int32_t* __restrict__ list, int bin,
+                                           int64_t rb, int64_t nb, MoveAgg* agg) {
   constexpr int VPW = kWave / G;
-  const int64_t count = D.ctr[ctr_bin(bin)];
+  const int64_t count = D.rc[rc_bin(bin)];
   const int lane = lane_id();
   const int sub = lane / G;
   const int k = lane % G;
-  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
-  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+  const int64_t wave = (rb * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = nb * blockDim.x / kWave;
   int64_t gain_acc = 0, moved = 0, marcs = 0;
-  __shared__ MoveAgg agg;
-  agg_begin(&agg);
   for (int64_t base = wave * VPW; base < count; base += nwaves * VPW) {
     const int64_t idx = base + sub;
     const bool valid = idx < count;
@@ -397,7 +542,7 @@ __global__ void __launch_bounds__(kBlock) k_move_small(Dev D, const int32_t* __r
     if (valid) Ki = D.K[i];
     if (cand) {
       const int64_t Sd = D.Sigma[d];
-      bg = gain_of(D.two_m, kc, kid, Ki, D.Sigma[c], Sd);
+      bg = gain_of(two_m, kc, kid, Ki, D.Sigma[c], Sd);
       bc = c;
     }
 #pragma unroll
@@ -413,7 +558,7 @@ __global__ void __launch_bounds__(kBlock) k_move_small(Dev D, const int32_t* __r
     bool mv = false;
     if (valid) mv = decide_move(D, d, bc, bg);
     if (lead && mv) {
-      commit_move(D, &agg, i, d, bc, Ki);
+      commit_move(D, agg, i, d, bc, Ki);
       gain_acc += bg;
       moved += 1;
       marcs += deg;
@@ -421,26 +566,20 @@ __global__ void __launch_bounds__(kBlock) k_move_small(Dev D, const int32_t* __r
     if (mv && has && D.push) set_bit(D.next, j);
   }
   flush_totals(D, gain_acc, moved, marcs);
-  agg_end(&agg, D.Sigma, D.size);
 }
 
-// --------------------------------------------------------------------------
 // Rows up to the wave threshold: one wavefront, LDS table of TS slots.
-// --------------------------------------------------------------------------
 template <int TS>
-__global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __restrict__ list) {
-  __shared__ int32_t s_keys[kBlock / kWave][TS];
-  __shared__ int32_t s_vals[kBlock / kWave][TS];
-  const int64_t count = D.ctr[ctr_bin(BIN_WAVE)];
+__device__ __forceinline__ void role_wave(const Dev& D, int64_t two_m, const int32_t* __restrict__ list, int64_t rb,
+                                          int64_t nb, int32_t* s_keys, int32_t* s_vals, MoveAgg* agg) {
+  const int64_t count = D.rc[rc_bin(BIN_WAVE)];
   const int lane = lane_id();
   const int wid = threadIdx.x / kWave;
-  int32_t* keys = s_keys[wid];
-  int32_t* vals = s_vals[wid];
-  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
-  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+  int32_t* keys = s_keys + wid * TS;
+  int32_t* vals = s_vals + wid * TS;
+  const int64_t wave = (rb * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = nb * blockDim.x / kWave;
   int64_t gain_acc = 0, moved = 0, marcs = 0;
-  __shared__ MoveAgg agg;
-  agg_begin(&agg);
   for (int64_t idx = wave; idx < count; idx += nwaves) {
     const int32_t i = list[idx];
     const int64_t start = D.row_start[i];
@@ -455,27 +594,35 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __re
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // a lane's arcs (deg <= TS/2): all loads, then all gathers, then the
+    // table, so the memory latencies overlap instead of adding up
+    constexpr int U = TS / (2 * kWave);
     int32_t kid = 0;
-    for (int32_t b = 0; b < deg; b += kWave) {
-      const int32_t k = b + lane;
-      if (k < deg) {
-        const int32_t j = D.col[start + k];
-        const int32_t x = D.wt[start + k];
-        if (j != i) {
-          const int32_t c = D.C[j];
-          if (c == d) {
-            kid += x;
-          } else {
-            uint32_t h = hash_slot(static_cast<uint32_t>(c), ts);
-            while (true) {
-              const int32_t old = atomicCAS(&keys[h], -1, c);
-              if (old == -1 || old == c) {
-                atomicAdd(&vals[h], x);
-                break;
-              }
-              h = (h + 1) & (ts - 1);
-            }
+    {
+      int32_t js[U], xs[U], cs[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int32_t k = lane + q * kWave;
+        js[q] = k < deg ? D.col[start + k] : i;
+        xs[q] = k < deg ? D.wt[start + k] : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) cs[q] = js[q] != i ? D.C[js[q]] : d;
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        if (js[q] == i) continue;
+        if (cs[q] == d) {
+          kid += xs[q];
+          continue;
+        }
+        uint32_t h = hash_slot(static_cast<uint32_t>(cs[q]), ts);
+        while (true) {
+          const int32_t old = atomicCAS(&keys[h], -1, cs[q]);
+          if (old == -1 || old == cs[q]) {
+            atomicAdd(&vals[h], xs[q]);
+            break;
           }
+          h = (h + 1) & (ts - 1);
         }
       }
     }
@@ -487,15 +634,27 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __re
     const int64_t Sd = D.Sigma[d];
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
-    for (uint32_t t = lane; t < ts; t += kWave) {
-      const int32_t c = keys[t];
-      if (c >= 0) {
-        const int64_t g = gain_of(D.two_m, vals[t], kid, Ki, D.Sigma[c], Sd);
-        if (better(g, c, bg, bc)) {
-          bg = g;
-          bc = c;
-        }
+    {
+      constexpr int V = TS / kWave;
+      int32_t cc[V], vv[V];
+      int64_t sg[V];
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        const uint32_t t = lane + q * kWave;
+        cc[q] = t < ts ? keys[t] : -1;
+        vv[q] = t < ts ? vals[t] : 0;
       }
+#pragma unroll
+      for (int q = 0; q < V; ++q) sg[q] = cc[q] >= 0 ? D.Sigma[cc[q]] : 0;
+#pragma unroll
+      for (int q = 0; q < V; ++q)
+        if (cc[q] >= 0) {
+          const int64_t g = gain_of(two_m, vv[q], kid, Ki, sg[q], Sd);
+          if (better(g, cc[q], bg, bc)) {
+            bg = g;
+            bc = cc[q];
+          }
+        }
     }
     for (int s = 1; s < kWave; s <<= 1) {
       const int64_t og = __shfl_xor(bg, s);
@@ -507,7 +666,7 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __re
     }
     if (decide_move(D, d, bc, bg)) {
       if (lane == 0) {
-        commit_move(D, &agg, i, d, bc, Ki);
+        commit_move(D, agg, i, d, bc, Ki);
         gain_acc += bg;
         moved += 1;
         marcs += deg;
@@ -518,14 +677,14 @@ __global__ void __launch_bounds__(kBlock) k_move_wave(Dev D, const int32_t* __re
           if (j != i) set_bit(D.next, j);
         }
     }
+    // the next row's table clear must not overtake this row's reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   flush_totals(D, gain_acc, moved, marcs);
-  agg_end(&agg, D.Sigma, D.size);
 }
 
-// --------------------------------------------------------------------------
-// Rows up to kBlockMaxDegree: one workgroup, LDS table of 4096 slots.
-// --------------------------------------------------------------------------
 constexpr int kBlockTS = 2 * kBlockMaxDegree;
 
 __device__ __forceinline__ void block_argmax(int64_t& bg, int32_t& bc, int64_t* r_g, int32_t* r_c) {
@@ -550,7 +709,7 @@ __device__ __forceinline__ void block_argmax(int64_t& bg, int32_t& bc, int64_t* 
     }
 }
 
-__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* r) {
+__device__ __forceinline__ int64_t block_total(int64_t v, int64_t* r) {
   v = wave_sum_i64(v);
   if (lane_id() == 0) r[threadIdx.x / kWave] = v;
   __syncthreads();
@@ -559,17 +718,21 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* r) {
   return s;
 }
 
-__global__ void __launch_bounds__(kBlock) k_move_block(Dev D, const int32_t* __restrict__ list) {
-  __shared__ int32_t keys[kBlockTS];
-  __shared__ int32_t vals[kBlockTS];
-  __shared__ int64_t r_g[kBlock / kWave];
-  __shared__ int32_t r_c[kBlock / kWave];
-  __shared__ int64_t r_s[kBlock / kWave];
-  const int64_t count = D.ctr[ctr_bin(BIN_BLOCK)];
+// Small per-workgroup scratch of the block and hub roles (with a small move
+// aggregate: a workgroup of the block role commits a few moves at most).
+struct Red {
+  int64_t g[kBlock / kWave];
+  int32_t c[kBlock / kWave];
+  int64_t s[kBlock / kWave];
+  MoveAggSmall agg;
+};
+
+// Rows up to kBlockMaxDegree: one workgroup, LDS table of up to 4096 slots.
+__device__ __forceinline__ void role_block(const Dev& D, int64_t two_m, const int32_t* __restrict__ list, int64_t rb,
+                                           int64_t nb, int32_t* keys, int32_t* vals, Red* red) {
+  const int64_t count = D.rc[rc_bin(BIN_BLOCK)];
   int64_t gain_acc = 0, moved = 0, marcs = 0;
-  __shared__ MoveAgg agg;
-  agg_begin(&agg);
-  for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+  for (int64_t idx = rb; idx < count; idx += nb) {
     const int32_t i = list[idx];
     const int64_t start = D.row_start[i];
     const int32_t deg = D.row_len[i];
@@ -580,45 +743,68 @@ __global__ void __launch_bounds__(kBlock) k_move_block(Dev D, const int32_t* __r
       vals[t] = 0;
     }
     __syncthreads();
+    // a thread's arcs and table slots are loaded, then gathered, in batches
+    constexpr int U = kBlockMaxDegree / kBlock;
     int64_t kid = 0;
-    for (int32_t k = threadIdx.x; k < deg; k += kBlock) {
-      const int32_t j = D.col[start + k];
-      const int32_t x = D.wt[start + k];
-      if (j == i) continue;
-      const int32_t c = D.C[j];
-      if (c == d) {
-        kid += x;
-        continue;
+    {
+      int32_t js[U], xs[U], cs[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int32_t k = threadIdx.x + q * kBlock;
+        js[q] = k < deg ? D.col[start + k] : i;
+        xs[q] = k < deg ? D.wt[start + k] : 0;
       }
-      uint32_t h = hash_slot(static_cast<uint32_t>(c), ts);
-      while (true) {
-        const int32_t old = atomicCAS(&keys[h], -1, c);
-        if (old == -1 || old == c) {
-          atomicAdd(&vals[h], x);
-          break;
+#pragma unroll
+      for (int q = 0; q < U; ++q) cs[q] = js[q] != i ? D.C[js[q]] : d;
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        if (js[q] == i) continue;
+        if (cs[q] == d) {
+          kid += xs[q];
+          continue;
         }
-        h = (h + 1) & (ts - 1);
+        uint32_t h = hash_slot(static_cast<uint32_t>(cs[q]), ts);
+        while (true) {
+          const int32_t old = atomicCAS(&keys[h], -1, cs[q]);
+          if (old == -1 || old == cs[q]) {
+            atomicAdd(&vals[h], xs[q]);
+            break;
+          }
+          h = (h + 1) & (ts - 1);
+        }
       }
     }
-    kid = block_sum(kid, r_s);
+    kid = block_total(kid, red->s);
     const int64_t Ki = D.K[i];
     const int64_t Sd = D.Sigma[d];
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
-    for (uint32_t t = threadIdx.x; t < ts; t += kBlock) {
-      const int32_t c = keys[t];
-      if (c >= 0) {
-        const int64_t g = gain_of(D.two_m, vals[t], kid, Ki, D.Sigma[c], Sd);
-        if (better(g, c, bg, bc)) {
-          bg = g;
-          bc = c;
-        }
+    {
+      constexpr int V = kBlockTS / kBlock;
+      int32_t cc[V], vv[V];
+      int64_t sg[V];
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        const uint32_t t = threadIdx.x + q * kBlock;
+        cc[q] = t < ts ? keys[t] : -1;
+        vv[q] = t < ts ? vals[t] : 0;
       }
+#pragma unroll
+      for (int q = 0; q < V; ++q) sg[q] = cc[q] >= 0 ? D.Sigma[cc[q]] : 0;
+#pragma unroll
+      for (int q = 0; q < V; ++q)
+        if (cc[q] >= 0) {
+          const int64_t g = gain_of(two_m, vv[q], kid, Ki, sg[q], Sd);
+          if (better(g, cc[q], bg, bc)) {
+            bg = g;
+            bc = cc[q];
+          }
+        }
     }
-    block_argmax(bg, bc, r_g, r_c);
+    block_argmax(bg, bc, red->g, red->c);
     if (decide_move(D, d, bc, bg)) {
       if (threadIdx.x == 0) {
-        commit_move(D, &agg, i, d, bc, Ki);
+        commit_move(D, &red->agg, i, d, bc, Ki);
         gain_acc += bg;
         moved += 1;
         marcs += deg;
@@ -632,12 +818,10 @@ __global__ void __launch_bounds__(kBlock) k_move_block(Dev D, const int32_t* __r
     __syncthreads();
   }
   flush_totals(D, gain_acc, moved, marcs);
-  agg_end(&agg, D.Sigma, D.size);
 }
 
-// --------------------------------------------------------------------------
-// Hub rows: clear, insert (units), argmax (one workgroup per hub), expand.
-// --------------------------------------------------------------------------
+// Hub rows, insert units: LDS pre-aggregation of 2048 arcs, flushed into
+// the hub's global table.
 constexpr int kHubTS = 4096;     // LDS pre-aggregation slots per unit
 constexpr int kHubProbes = 8;
 
@@ -653,48 +837,29 @@ __device__ __forceinline__ void gtable_add(int32_t* keys, int32_t* vals, uint32_
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_hub_clear(Dev D, const int32_t* __restrict__ list,
-                                                     const int64_t* __restrict__ hub_off,
-                                                     const int32_t* __restrict__ c_b, const int64_t* __restrict__ c_s,
-                                                     int32_t* __restrict__ keys, int32_t* __restrict__ vals,
-                                                     int64_t* __restrict__ hub_kid, int32_t* __restrict__ hub_moved,
-                                                     int64_t pool_slots) {
-  const int64_t count = D.ctr[CTR_HUB_CUNITS];
-  for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
-    const int32_t h = c_b[u];
-    const int64_t tsz = 2 * static_cast<int64_t>(D.row_len[list[h]]);
-    const int64_t off = hub_off[h];
-    if (off + tsz > pool_slots) continue;  // reported by the insert kernel
-    if (c_s[u] == 0 && threadIdx.x == 0) {
-      hub_kid[h] = 0;
-      hub_moved[h] = 0;
-    }
-    const int64_t s1 = min(tsz, c_s[u] + kHubClearSlots);
-    for (int64_t s = c_s[u] + threadIdx.x; s < s1; s += kBlock) {
-      keys[off + s] = -1;
-      vals[off + s] = 0;
-    }
-  }
-}
+struct HubIn {
+  const int32_t* list;
+  const int64_t* off;
+  const int32_t* u_b;
+  const int64_t* u_a;
+  int32_t* keys;
+  int32_t* vals;
+  int64_t* kid;
+  int64_t pool_slots;
+};
 
-__global__ void __launch_bounds__(kBlock) k_hub_insert(Dev D, const int32_t* __restrict__ list,
-                                                      const int64_t* __restrict__ hub_off,
-                                                      const int32_t* __restrict__ u_b, const int64_t* __restrict__ u_a,
-                                                      int32_t* __restrict__ keys, int32_t* __restrict__ vals,
-                                                      int64_t* __restrict__ hub_kid, int64_t pool_slots) {
-  __shared__ int32_t tk[kHubTS];
-  __shared__ int32_t tv[kHubTS];
-  __shared__ int64_t r_s[kBlock / kWave];
-  const int64_t count = D.ctr[CTR_HUB_UNITS];
-  for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
-    const int32_t h = u_b[u];
-    const int32_t i = list[h];
+__device__ __forceinline__ void role_hub_insert(const Dev& D, const HubIn& H, int64_t rb, int64_t nb, int32_t* tk,
+                                                int32_t* tv, Red* red) {
+  const int64_t count = D.rc[RC_HUB_UNITS];
+  for (int64_t u = rb; u < count; u += nb) {
+    const int32_t h = H.u_b[u];
+    const int32_t i = H.list[h];
     const int64_t start = D.row_start[i];
     const int32_t deg = D.row_len[i];
     const int32_t d = D.C[i];
     const uint32_t tsz = 2u * static_cast<uint32_t>(deg);
-    const int64_t off = hub_off[h];
-    if (off + static_cast<int64_t>(tsz) > pool_slots) {
+    const int64_t off = H.off[h];
+    if (off + static_cast<int64_t>(tsz) > H.pool_slots) {
       if (threadIdx.x == 0) set_error(D.ctr, LV_EWORKSPACE);
       continue;
     }
@@ -703,7 +868,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_insert(Dev D, const int32_t* __r
       tv[s] = 0;
     }
     __syncthreads();
-    const int64_t a0 = u_a[u];
+    const int64_t a0 = H.u_a[u];
     const int64_t a1 = min(static_cast<int64_t>(deg), a0 + kHubUnitArcs);
     int64_t kid = 0;
     // each thread's arcs: all loads first, then all gathers, then the table
@@ -725,40 +890,122 @@ __global__ void __launch_bounds__(kBlock) k_hub_insert(Dev D, const int32_t* __r
         kid += x;
         continue;
       }
-      uint32_t h = hash_slot(static_cast<uint32_t>(c), kHubTS);
+      uint32_t p = hash_slot(static_cast<uint32_t>(c), kHubTS);
       bool done = false;
-      for (int p = 0; p < kHubProbes; ++p) {
-        const int32_t old = atomicCAS(&tk[h], -1, c);
+      for (int t = 0; t < kHubProbes; ++t) {
+        const int32_t old = atomicCAS(&tk[p], -1, c);
         if (old == -1 || old == c) {
-          atomicAdd(&tv[h], x);
+          atomicAdd(&tv[p], x);
           done = true;
           break;
         }
-        h = (h + 1) & (kHubTS - 1);
+        p = (p + 1) & (kHubTS - 1);
       }
-      if (!done) gtable_add(keys + off, vals + off, tsz, c, x);
+      if (!done) gtable_add(H.keys + off, H.vals + off, tsz, c, x);
     }
-    kid = block_sum(kid, r_s);
-    if (threadIdx.x == 0 && kid) atomic_add_i64(&hub_kid[h], kid);
+    kid = block_total(kid, red->s);
+    if (threadIdx.x == 0 && kid) atomic_add_i64(&H.kid[h], kid);
     for (int s = threadIdx.x; s < kHubTS; s += kBlock)
-      if (tk[s] >= 0) gtable_add(keys + off, vals + off, tsz, tk[s], tv[s]);
+      if (tk[s] >= 0) gtable_add(H.keys + off, H.vals + off, tsz, tk[s], tv[s]);
     __syncthreads();
   }
 }
 
-// best (gain, community) of each table-slot unit of a hub table
-__global__ void __launch_bounds__(kBlock) k_hub_decide_units(Dev D, const int32_t* __restrict__ list,
-                                                            const int64_t* __restrict__ hub_off,
-                                                            const int32_t* __restrict__ c_b,
-                                                            const int64_t* __restrict__ c_s,
-                                                            const int32_t* __restrict__ keys,
-                                                            const int32_t* __restrict__ vals,
-                                                            const int64_t* __restrict__ hub_kid,
-                                                            int64_t* __restrict__ unit_g, int32_t* __restrict__ unit_c,
-                                                            int64_t pool_slots) {
+// Role block ranges of the fused kernel, laid end to end.
+struct Roles {
+  int64_t end[NBINS];  // exclusive end of each role's block range (hub = insert units)
+};
+
+// LDS of the roles (bytes): a small role uses the move aggregate only, the
+// wavefront role its four tables and the aggregate, the workgroup and hub
+// roles a 4096-slot table and the reduction scratch.
+template <int TS>
+constexpr size_t lds_wave() {
+  return sizeof(MoveAgg) + 2 * sizeof(int32_t) * (kBlock / kWave) * TS;
+}
+constexpr size_t lds_table() { return sizeof(Red) + 2 * sizeof(int32_t) * kBlockTS; }
+
+template <int TS>
+__global__ void __launch_bounds__(kBlock) k_move_all(Dev D, Bins bins, Roles R, HubIn H) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t two_m = load_two_m(D);
+  if (two_m == 0) return;
+  const int64_t b = blockIdx.x;
+  int role = 0;
+  while (role < NBINS - 1 && b >= R.end[role]) ++role;
+  const int64_t lo = role == 0 ? 0 : R.end[role - 1];
+  const int64_t rb = b - lo, nb = R.end[role] - lo;
+  if (role <= BIN_G32) {
+    MoveAgg* agg = reinterpret_cast<MoveAgg*>(smem);
+    agg_begin(agg);
+    switch (role) {
+      case BIN_G4: role_small<4>(D, two_m, bins.list[BIN_G4], BIN_G4, rb, nb, agg); break;
+      case BIN_G8: role_small<8>(D, two_m, bins.list[BIN_G8], BIN_G8, rb, nb, agg); break;
+      case BIN_G16: role_small<16>(D, two_m, bins.list[BIN_G16], BIN_G16, rb, nb, agg); break;
+      default: role_small<32>(D, two_m, bins.list[BIN_G32], BIN_G32, rb, nb, agg); break;
+    }
+    agg_end(agg, D.Sigma, D.size);
+  } else if (role == BIN_WAVE) {
+    MoveAgg* agg = reinterpret_cast<MoveAgg*>(smem);
+    int32_t* keys = reinterpret_cast<int32_t*>(smem + sizeof(MoveAgg));
+    int32_t* vals = keys + (kBlock / kWave) * TS;
+    agg_begin(agg);
+    role_wave<TS>(D, two_m, bins.list[BIN_WAVE], rb, nb, keys, vals, agg);
+    agg_end(agg, D.Sigma, D.size);
+  } else if (role == BIN_BLOCK) {
+    Red* red = reinterpret_cast<Red*>(smem);
+    int32_t* keys = reinterpret_cast<int32_t*>(smem + sizeof(Red));
+    agg_begin(&red->agg);
+    role_block(D, two_m, bins.list[BIN_BLOCK], rb, nb, keys, keys + kBlockTS, red);
+    agg_end(&red->agg, D.Sigma, D.size);
+  } else {
+    Red* red = reinterpret_cast<Red*>(smem);
+    int32_t* tk = reinterpret_cast<int32_t*>(smem + sizeof(Red));
+    role_hub_insert(D, H, rb, nb, tk, tk + kHubTS, red);
+  }
+}
+
+// --------------------------------------------------------------------------
+// Hub rows: table clear (before the fused kernel), then decisions.
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_hub_clear(Dev D, const int32_t* __restrict__ list,
+                                                     const int64_t* __restrict__ hub_off,
+                                                     const int32_t* __restrict__ c_b, const int64_t* __restrict__ c_s,
+                                                     int32_t* __restrict__ keys, int32_t* __restrict__ vals,
+                                                     int64_t* __restrict__ hub_kid, int64_t pool_slots) {
+  const int64_t count = D.rc[RC_HUB_CUNITS];
+  for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
+    const int32_t h = c_b[u];
+    const int64_t tsz = 2 * static_cast<int64_t>(D.row_len[list[h]]);
+    const int64_t off = hub_off[h];
+    if (off + tsz > pool_slots) continue;  // reported by the insert role
+    if (c_s[u] == 0 && threadIdx.x == 0) hub_kid[h] = 0;
+    const int64_t s1 = min(tsz, c_s[u] + kHubClearSlots);
+    for (int64_t s = c_s[u] + threadIdx.x; s < s1; s += kBlock) {
+      keys[off + s] = -1;
+      vals[off + s] = 0;
+    }
+  }
+}
+
+// One workgroup per unit of 4096 table slots publishes the unit's best
+// (gain, community).  (A completion count with a device-scope fence would
+// let the last unit decide, but on a multi-XCD part that fence writes back
+// the L2 and costs more than a launch.)
+__global__ void __launch_bounds__(kBlock) k_hub_decide(Dev D, const int32_t* __restrict__ list,
+                                                      const int64_t* __restrict__ hub_off,
+                                                      const int32_t* __restrict__ c_b,
+                                                      const int64_t* __restrict__ c_s,
+                                                      const int32_t* __restrict__ keys,
+                                                      const int32_t* __restrict__ vals,
+                                                      const int64_t* __restrict__ hub_kid,
+                                                      int64_t* __restrict__ unit_g, int32_t* __restrict__ unit_c,
+                                                      int64_t pool_slots) {
   __shared__ int64_t r_g[kBlock / kWave];
   __shared__ int32_t r_c[kBlock / kWave];
-  const int64_t count = D.ctr[CTR_HUB_CUNITS];
+  const int64_t two_m = load_two_m(D);
+  if (two_m == 0) return;
+  const int64_t count = D.rc[RC_HUB_CUNITS];
   for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
     const int32_t h = c_b[u];
     const int32_t i = list[h];
@@ -768,20 +1015,30 @@ __global__ void __launch_bounds__(kBlock) k_hub_decide_units(Dev D, const int32_
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
     if (off + tsz <= pool_slots) {
-      const int64_t kid = hub_kid[h];
       const int64_t Ki = D.K[i];
+      const int64_t kid = hub_kid[h];
       const int64_t Sd = D.Sigma[d];
       const int64_t s1 = min(tsz, c_s[u] + kHubClearSlots);
-      for (int64_t t = c_s[u] + threadIdx.x; t < s1; t += kBlock) {
-        const int32_t c = keys[off + t];
-        if (c >= 0) {
-          const int64_t g = gain_of(D.two_m, vals[off + t], kid, Ki, D.Sigma[c], Sd);
-          if (better(g, c, bg, bc)) {
+      constexpr int V = kHubClearSlots / kBlock;
+      int32_t cc[V], vv[V];
+      int64_t sg[V];
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        const int64_t t = c_s[u] + threadIdx.x + q * kBlock;
+        cc[q] = t < s1 ? keys[off + t] : -1;
+        vv[q] = t < s1 ? vals[off + t] : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < V; ++q) sg[q] = cc[q] >= 0 ? D.Sigma[cc[q]] : 0;
+#pragma unroll
+      for (int q = 0; q < V; ++q)
+        if (cc[q] >= 0) {
+          const int64_t g = gain_of(two_m, vv[q], kid, Ki, sg[q], Sd);
+          if (better(g, cc[q], bg, bc)) {
             bg = g;
-            bc = c;
+            bc = cc[q];
           }
         }
-      }
     }
     block_argmax(bg, bc, r_g, r_c);
     if (threadIdx.x == 0) {
@@ -792,20 +1049,19 @@ __global__ void __launch_bounds__(kBlock) k_hub_decide_units(Dev D, const int32_
   }
 }
 
-// one wavefront per hub: best over its units, then the move decision
+// One wavefront per hub: best over its units, then the move decision.
 __global__ void __launch_bounds__(kBlock) k_hub_final(Dev D, const int32_t* __restrict__ list,
                                                      const int64_t* __restrict__ hub_cbase,
                                                      const int32_t* __restrict__ hub_cnum,
                                                      const int64_t* __restrict__ unit_g,
                                                      const int32_t* __restrict__ unit_c,
                                                      int32_t* __restrict__ hub_moved) {
-  const int64_t count = D.ctr[ctr_bin(BIN_HUB)];
+  if (load_two_m(D) == 0) return;
+  const int64_t count = D.rc[rc_bin(BIN_HUB)];
   const int lane = lane_id();
   const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
   const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
   int64_t gain_acc = 0, moved = 0, marcs = 0;
-  __shared__ MoveAgg agg;
-  agg_begin(&agg);
   for (int64_t h = wave; h < count; h += nwaves) {
     const int64_t b0 = hub_cbase[h];
     const int32_t nu = hub_cnum[h];
@@ -830,7 +1086,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_final(Dev D, const int32_t* __re
       const bool mv = decide_move(D, d, bc, bg);
       hub_moved[h] = mv ? 1 : 0;
       if (mv) {
-        commit_move(D, &agg, i, d, bc, D.K[i]);
+        commit_move(D, static_cast<MoveAggSmall*>(nullptr), i, d, bc, D.K[i]);
         gain_acc += bg;
         moved += 1;
         marcs += D.row_len[i];
@@ -838,13 +1094,14 @@ __global__ void __launch_bounds__(kBlock) k_hub_final(Dev D, const int32_t* __re
     }
   }
   flush_totals(D, gain_acc, moved, marcs);
-  agg_end(&agg, D.Sigma, D.size);
 }
 
+// Neighbours of moved hubs join the next frontier, one insert unit of arcs
+// per workgroup (a hub row can hold over 10^5 arcs).
 __global__ void __launch_bounds__(kBlock) k_hub_expand(Dev D, const int32_t* __restrict__ list,
                                                       const int32_t* __restrict__ u_b, const int64_t* __restrict__ u_a,
                                                       const int32_t* __restrict__ hub_moved) {
-  const int64_t count = D.push ? D.ctr[CTR_HUB_UNITS] : 0;
+  const int64_t count = D.rc[RC_HUB_UNITS];
   for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
     const int32_t h = u_b[u];
     if (!hub_moved[h]) continue;
@@ -864,14 +1121,17 @@ __global__ void __launch_bounds__(kBlock) k_hub_expand(Dev D, const int32_t* __r
 // --------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_apply_moves(int32_t* __restrict__ C, const int64_t* __restrict__ K,
                                                        int64_t* __restrict__ Sigma, int32_t* __restrict__ size,
-                                                       const uint32_t* __restrict__ moved,
-                                                       const int32_t* __restrict__ target, int32_t n) {
+                                                       uint32_t* __restrict__ moved,
+                                                       const int32_t* __restrict__ target, int32_t n,
+                                                       int32_t clear) {
   __shared__ MoveAgg agg;
   agg_begin(&agg);
   const int64_t words = (static_cast<int64_t>(n) + 31) / 32;
   for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < words;
        k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    for (uint32_t r = moved[k]; r; r &= r - 1) {
+    const uint32_t bits = moved[k];
+    if (clear && bits) moved[k] = 0;  // nothing reads the movers after this kernel
+    for (uint32_t r = bits; r; r &= r - 1) {
       const int32_t i = static_cast<int32_t>(k * 32 + (__ffs(r) - 1));
       const int32_t c = target[i];
       const int32_t d = C[i];
@@ -968,18 +1228,22 @@ int table_slots_for(int wave_max) {
   return ts;
 }
 
+int grid_by_est(int64_t est, int64_t items_per_block, int max_blocks) {
+  const int64_t b = (est + items_per_block - 1) / items_per_block;
+  return static_cast<int>(b < 1 ? 1 : (b > max_blocks ? max_blocks : b));
+}
+
+template <int TS>
+void launch_move_all(const Dev& D, const Bins& b, const Roles& R, const HubIn& H, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL(k_move_all<TS>, dim3(static_cast<unsigned>(R.end[NBINS - 1])), dim3(kBlock), lds, st, D, b, R,
+                     H);
+}
+
 }  // namespace
 
-void launch_bin_frontier(const MoveArgs& a, Workspace& ws, const SubRound& r, hipStream_t st) {
-  const int64_t words = (static_cast<int64_t>(a.g.n) + 31) / 32;
-  Bins b;
-  for (int k = 0; k < NBINS; ++k) b.list[k] = ws.bins[k];
-  HubOut H{ws.hub_off, ws.hub_cbase, ws.hub_cnum, ws.u_ins_b, ws.u_ins_a, ws.u_emit_b, ws.u_emit_s};
-  timer_begin(NBINS, st);
-  hipLaunchKernelGGL(k_bin_frontier, dim3(grid_for(words, kBlock, 4096)), dim3(kBlock), 0, st, a.cur, a.range,
-                     a.ever, a.g.row_len, a.g.n, a.wave_max, r.hash_round, r.hash_shift, r.id_lo, r.id_hi, r.deg_lo,
-                     r.deg_hi, b, H, ws.ctr);
-  timer_end(NBINS, st);
+void launch_call_begin(Workspace& ws, const int64_t* two_m, hipStream_t st) {
+  hipLaunchKernelGGL(k_call_begin, dim3(grid_for(std::max<int64_t>(ws.words, CTR_COUNT), kBlock, 2048)),
+                     dim3(kBlock), 0, st, ws.ctr, ws.fr_a, ws.fr_b, ws.ever, ws.moved, ws.words, two_m);
 }
 
 // Bins whose degree range meets [lo, hi].
@@ -992,72 +1256,78 @@ uint32_t bins_for_degrees(int32_t lo, int32_t hi, int32_t wave_max) {
   return m;
 }
 
-// Persistent grids sized by the frontier bound: full sweeps fill the chip,
-// small DF frontiers launch few blocks.
-int grid_by_est(int64_t est, int64_t items_per_block, int max_blocks) {
-  const int64_t b = (est + items_per_block - 1) / items_per_block;
-  return static_cast<int>(b < 1 ? 1 : (b > max_blocks ? max_blocks : b));
-}
+void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const SubRound& r, uint32_t bin_mask,
+                  hipStream_t st) {
+  const Dev D = make_dev(a, ws, tu);
+  const int64_t words = (static_cast<int64_t>(a.g.n) + 31) / 32;
+  Bins b;
+  for (int k = 0; k < NBINS; ++k) b.list[k] = ws.bins[k];
+  HubOut HO{ws.hub_off, ws.hub_cbase, ws.hub_cnum, ws.u_ins_b, ws.u_ins_a, ws.u_emit_b, ws.u_emit_s};
+  timer_begin(LV_TIME_BINNING, st);
+  hipLaunchKernelGGL(k_bin_frontier, dim3(grid_for(words, kBlock, 4096)), dim3(kBlock), 0, st,
+                     const_cast<uint32_t*>(a.cur), a.range, a.ever, a.g.row_len, a.g.n, a.wave_max, r.hash_round,
+                     r.hash_shift, r.id_lo, r.id_hi, r.deg_lo, r.deg_hi, a.clear_cur, b, HO, a.rc, a.sc, a.rc_next,
+                     a.sc_next);
+  timer_end(LV_TIME_BINNING, st);
 
-void launch_move(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, uint32_t bin_mask, hipStream_t st) {
-  const Dev D = make_dev(a, ws);
   const int64_t est = a.est > 0 ? a.est : 1;
-  const int bs = grid_by_est(est, 64, tu.blocks_small);      // 16 rows per wave at G = 4
-  const int bw = grid_by_est(est, 4, tu.blocks_wave);        // one row per wavefront
-  const int bh = grid_by_est(est, 1, tu.blocks_hub);         // one row / unit per workgroup
-  if (bin_mask & (1u << BIN_G4)) {
-    timer_begin(BIN_G4, st);
-    hipLaunchKernelGGL(k_move_small<4>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G4], int(BIN_G4));
-    timer_end(BIN_G4, st);
+  const int bs = grid_by_est(est, 64, tu.blocks_small);  // 16 rows per wave at G = 4
+  const int bw = grid_by_est(est, 4, tu.blocks_wave);    // one row per wavefront
+  const int bh = grid_by_est(est, 1, tu.blocks_hub);     // one row / unit per workgroup
+  const bool hubs = bin_mask & (1u << BIN_HUB);
+  if (hubs) {
+    timer_begin(LV_TIME_HUB_CLEAR, st);
+    hipLaunchKernelGGL(k_hub_clear, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off, ws.u_emit_b,
+                       ws.u_emit_s, ws.pool_keys, ws.pool_vals, ws.hub_kid, ws.pool_slots);
+    timer_end(LV_TIME_HUB_CLEAR, st);
   }
-  if (bin_mask & (1u << BIN_G8)) {
-    timer_begin(BIN_G8, st);
-    hipLaunchKernelGGL(k_move_small<8>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G8], int(BIN_G8));
-    timer_end(BIN_G8, st);
-  }
-  if (bin_mask & (1u << BIN_G16)) {
-    timer_begin(BIN_G16, st);
-    hipLaunchKernelGGL(k_move_small<16>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G16], int(BIN_G16));
-    timer_end(BIN_G16, st);
-  }
-  if (bin_mask & (1u << BIN_G32)) {
-    timer_begin(BIN_G32, st);
-    hipLaunchKernelGGL(k_move_small<32>, dim3(bs), dim3(kBlock), 0, st, D, ws.bins[BIN_G32], int(BIN_G32));
-    timer_end(BIN_G32, st);
-  }
+
+  // The scan: for a small, sparse frontier one launch whose role ranges lie
+  // end to end; otherwise a launch per bin in increasing degree order, so
+  // that (in ASYNC mode) each bin sees the moves of the bins before it (on
+  // dense frontiers that ordering is worth modularity).
+  const int per[NBINS] = {bs, bs, bs, bs, bw, bh, bh};
   const int ts = table_slots_for(a.wave_max);
-  if (bin_mask & (1u << BIN_WAVE)) {
-    timer_begin(BIN_WAVE, st);
+  const size_t lw = ts <= 128 ? lds_wave<128>() : ts <= 256 ? lds_wave<256>() : ts <= 512 ? lds_wave<512>()
+                                                                                        : lds_wave<1024>();
+  const HubIn H{ws.bins[BIN_HUB], ws.hub_off, ws.u_ins_b, ws.u_ins_a, ws.pool_keys, ws.pool_vals, ws.hub_kid,
+                ws.pool_slots};
+  const bool fuse = a.sparse && a.est <= tu.fuse_max_frontier;
+  for (int first = 0; first < NBINS; ++first) {
+    const uint32_t m = fuse ? bin_mask : (bin_mask & (1u << first));
+    if (!m) continue;
+    Roles R;
+    int64_t end = 0;
+    for (int k = 0; k < NBINS; ++k) {
+      if (m & (1u << k)) end += per[k];
+      R.end[k] = end;
+    }
+    size_t lds = sizeof(MoveAgg);
+    if (m & (1u << BIN_WAVE)) lds = std::max(lds, lw);
+    if (m & ((1u << BIN_BLOCK) | (1u << BIN_HUB))) lds = std::max(lds, lds_table());
+    timer_begin(LV_TIME_SCAN, st);
     if (ts <= 128)
-      hipLaunchKernelGGL(k_move_wave<128>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
+      launch_move_all<128>(D, b, R, H, lds, st);
     else if (ts <= 256)
-      hipLaunchKernelGGL(k_move_wave<256>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
+      launch_move_all<256>(D, b, R, H, lds, st);
     else if (ts <= 512)
-      hipLaunchKernelGGL(k_move_wave<512>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
+      launch_move_all<512>(D, b, R, H, lds, st);
     else
-      hipLaunchKernelGGL(k_move_wave<1024>, dim3(bw), dim3(kBlock), 0, st, D, ws.bins[BIN_WAVE]);
-    timer_end(BIN_WAVE, st);
+      launch_move_all<1024>(D, b, R, H, lds, st);
+    timer_end(LV_TIME_SCAN, st);
+    if (fuse) break;
   }
-  if (bin_mask & (1u << BIN_BLOCK)) {
-    timer_begin(BIN_BLOCK, st);
-    hipLaunchKernelGGL(k_move_block, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_BLOCK]);
-    timer_end(BIN_BLOCK, st);
+  if (hubs) {
+    timer_begin(LV_TIME_HUB_DECIDE, st);
+    hipLaunchKernelGGL(k_hub_decide, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off, ws.u_emit_b,
+                       ws.u_emit_s, ws.pool_keys, ws.pool_vals, ws.hub_kid, ws.unit_g, ws.unit_c, ws.pool_slots);
+    timer_end(LV_TIME_HUB_DECIDE, st);
+    hipLaunchKernelGGL(k_hub_final, dim3(64), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_cbase, ws.hub_cnum,
+                       ws.unit_g, ws.unit_c, ws.hub_moved);
+    if (a.push)
+      hipLaunchKernelGGL(k_hub_expand, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.u_ins_b, ws.u_ins_a,
+                         ws.hub_moved);
   }
-  if (!(bin_mask & (1u << BIN_HUB))) return;
-  // hub rows
-  hipLaunchKernelGGL(k_hub_clear, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off, ws.u_emit_b,
-                     ws.u_emit_s, ws.pool_keys, ws.pool_vals, ws.hub_kid, ws.hub_moved, ws.pool_slots);
-  timer_begin(BIN_HUB, st);
-  hipLaunchKernelGGL(k_hub_insert, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off, ws.u_ins_b,
-                     ws.u_ins_a, ws.pool_keys, ws.pool_vals, ws.hub_kid, ws.pool_slots);
-  timer_end(BIN_HUB, st);
-  hipLaunchKernelGGL(k_hub_decide_units, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off,
-                     ws.u_emit_b, ws.u_emit_s, ws.pool_keys, ws.pool_vals, ws.hub_kid, ws.unit_g, ws.unit_c,
-                     ws.pool_slots);
-  hipLaunchKernelGGL(k_hub_final, dim3(64), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_cbase, ws.hub_cnum,
-                     ws.unit_g, ws.unit_c, ws.hub_moved);
-  hipLaunchKernelGGL(k_hub_expand, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.u_ins_b, ws.u_ins_a,
-                     ws.hub_moved);
 }
 
 void launch_pull_expand(const MoveArgs& a, Workspace& ws, hipStream_t st) {
@@ -1069,10 +1339,10 @@ void launch_pull_expand(const MoveArgs& a, Workspace& ws, hipStream_t st) {
                      a.next, ws.bins[NBINS - 1] + 0, ws.ctr);
 }
 
-void launch_apply_moves(const MoveArgs& a, Workspace& ws, hipStream_t st) {
+void launch_apply_moves(const MoveArgs& a, Workspace& ws, bool clear_moved, hipStream_t st) {
   const int64_t words = (static_cast<int64_t>(a.g.n) + 31) / 32;
   hipLaunchKernelGGL(k_apply_moves, dim3(grid_for(words, kBlock, 2048)), dim3(kBlock), 0, st, a.C, a.K, a.Sigma,
-                     a.size, a.moved, ws.mv_c, a.g.n);
+                     a.size, a.moved, ws.mv_c, a.g.n, clear_moved ? 1 : 0);
 }
 
 }  // namespace lv

@@ -27,9 +27,10 @@ MAX_PASSES, MAX_ITERS = 16, 32
 # degree bins of the local-moving scan (LV_BIN_*) and the timing selector
 BINS = ("g4", "g8", "g16", "g32", "wave", "block", "hub")
 NBINS = len(BINS)
-TIME_BINNING = NBINS           # timing index of the frontier binning kernel
-NTIMED = NBINS + 1
-TIMED = BINS + ("binning",)
+# kernels the timing hook can bracket (LV_TIME_*)
+TIMED = ("scan", "binning", "hub_clear", "hub_decide")
+TIME_SCAN, TIME_BINNING, TIME_HUB_CLEAR, TIME_HUB_DECIDE = range(4)
+NTIMED = len(TIMED)
 
 EXPORTS = ["lv_default_params", "lv_workspace_bytes", "lv_graph_capacity_bound", "lv_graph_build",
            "lv_graph_relayout", "apply_batch", "louvain_static", "louvain_nd", "louvain_ds", "louvain_df",
@@ -94,7 +95,8 @@ class Stats(ct.Structure):
 class Tuning(ct.Structure):
     _fields_ = [("wave_max_degree", ct.c_int32), ("blocks_small", ct.c_int32), ("blocks_wave", ct.c_int32),
                 ("blocks_hub", ct.c_int32), ("async_rounds_log2", ct.c_int32),
-                ("async_rounds_min_frontier", ct.c_int32), ("async_round_order", ct.c_int32)]
+                ("async_rounds_min_frontier", ct.c_int32), ("async_round_order", ct.c_int32),
+                ("fuse_max_frontier", ct.c_int32), ("defer_totals", ct.c_int32)]
 
 
 _lib = None
@@ -165,13 +167,14 @@ def params(tolerance=1e-2, tolerance_drop=10.0, aggregation_tolerance=0.8, max_i
 DEFAULT_ASYNC_ROUNDS_LOG2 = 7
 
 
+DEFAULT_FUSE_MAX_FRONTIER = 8192
 DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER = 4096
 
 
 def set_timing(kernels=()):
-    """Bracket every launch of the given kernels (indices into TIMED: a bin's
-    scan kernel, or TIME_BINNING) with HIP events; the louvain_* calls then
-    report timed_launches and timed_ms per kernel.  () turns timing off."""
+    """Bracket every launch of the given kernels (indices into TIMED) with
+    HIP events; the louvain_* calls then report timed_launches and timed_ms
+    per kernel.  () turns timing off."""
     mask = 0
     for k in kernels:
         mask |= 1 << int(k)
@@ -180,9 +183,11 @@ def set_timing(kernels=()):
 
 def set_tuning(wave_max_degree=0, blocks_small=0, blocks_wave=0, blocks_hub=0,
                async_rounds_log2=DEFAULT_ASYNC_ROUNDS_LOG2,
-               async_rounds_min_frontier=DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER, async_round_order=2):
+               async_rounds_min_frontier=DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER, async_round_order=2,
+               fuse_max_frontier=DEFAULT_FUSE_MAX_FRONTIER, defer_totals=1):
     load().lv_set_tuning(ct.byref(Tuning(wave_max_degree, blocks_small, blocks_wave, blocks_hub,
-                                         async_rounds_log2, async_rounds_min_frontier, async_round_order)))
+                                         async_rounds_log2, async_rounds_min_frontier, async_round_order,
+                                         fuse_max_frontier, defer_totals)))
 
 
 def get_tuning() -> dict:

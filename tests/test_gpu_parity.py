@@ -349,9 +349,11 @@ def test_bin_stats_and_timing_hook(lib):
         _, t = lib.louvain_static(g, mode="async")
     finally:
         lib.set_timing(())
-    for b in range(lib.NBINS):
-        assert t["timed_launches"][b] == t["bin_launches"][b]
-        assert (t["timed_ms"][b] > 0) == (t["timed_launches"][b] > 0)
-    assert t["timed_launches"][lib.TIME_BINNING] >= sum(t["iterations"])
+    rounds = t["timed_launches"][lib.TIME_BINNING]
+    assert rounds >= sum(t["iterations"])
+    assert rounds <= t["timed_launches"][lib.TIME_SCAN] <= lib.NBINS * rounds  # fused, or one per bin
+    assert t["timed_launches"][lib.TIME_HUB_DECIDE] == t["bin_launches"][lib.BINS.index("hub")]
+    assert t["timed_launches"][lib.TIME_HUB_CLEAR] == t["bin_launches"][lib.BINS.index("hub")]
+    assert all((t["timed_ms"][k] > 0) == (t["timed_launches"][k] > 0) for k in range(lib.NTIMED))
     _, u = lib.louvain_static(g, mode="async")
     assert all(x == 0 for x in u["timed_launches"])
