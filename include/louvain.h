@@ -47,6 +47,7 @@ typedef int32_t lv_status;
 #define LV_EEMPTY (-5)      /* graph without edges (2m = 0) */
 #define LV_EHIP (-6)        /* a HIP runtime call failed */
 #define LV_EWORKSPACE (-7)  /* workspace smaller than lv_workspace_bytes() */
+#define LV_ETOOLARGE (-8)   /* louvain_df_many: item outside the batched kernel's limits */
 
 #define LV_SYNC 0   /* Jacobi moves: every vertex decides on the iteration-start state */
 #define LV_ASYNC 1  /* moves applied as they are decided (racy, as in the paper's loop) */
@@ -248,6 +249,49 @@ lv_status modularity(const lv_graph* g, const int32_t* C, double* q_host, void* 
                      void* stream);
 
 /* Set or read the tuning table used by the calls above (process-wide). */
+/*
+ * louvain_df_many -- apply_batch followed by louvain_df (Section 3.4,
+ * Alg. 1) on many independent graphs at once, in one persistent launch:
+ * a workgroup takes a graph, edits it in place, updates K and Sigma, marks
+ * the DF frontier and runs the local-moving iterations of pass 0.  A graph
+ * whose pass 0 needs more than one iteration (so Alg. 4 aggregates and
+ * goes on) continues on the single-graph path afterwards, as does an item
+ * outside the kernel's limits (rows longer than 2048 arcs after its batch).
+ * Results are those of apply_batch + louvain_df on each graph alone
+ * (bit-exact in LV_SYNC mode).
+ *
+ *   items      host array of `count` items; each names its graph, its state
+ *              (size is required: member counts carried with the state),
+ *              its batch, and its scratch: lv_many_scratch_bytes(n,
+ *              max_updates) bytes of device memory, zero before its first
+ *              use; each call leaves it ready for the next (keep one per
+ *              graph); del.count + ins.count must not exceed max_updates.
+ *   desc       device buffer of lv_many_desc_bytes(count) bytes (item
+ *              descriptors and results).
+ *   ws         a workspace for the single-graph path, lv_workspace_bytes()
+ *              of the largest graph that may need it; may be NULL, and then
+ *              such items report LV_EWORKSPACE.
+ *   status     host array of `count`: LV_OK or the item's own error
+ *              (LV_EINVAL, LV_ENOEDGE, LV_ENOSLACK, LV_EOVERFLOW: nothing of
+ *              that graph was changed; LV_EEMPTY after the edit).
+ *   stats      host array of `count` lv_stats, or NULL.
+ * Returns LV_OK unless a HIP call failed or an argument is invalid.
+ * Synchronises `stream`.  Items must name distinct graphs.
+ */
+typedef struct {
+  lv_graph g;
+  lv_state state;
+  lv_edges del;
+  lv_edges ins;
+  void* scratch;
+  int32_t max_updates;
+} lv_item;
+
+size_t lv_many_scratch_bytes(int32_t n, int32_t max_updates);
+size_t lv_many_desc_bytes(int32_t count);
+lv_status louvain_df_many(const lv_item* items, int32_t count, const lv_params* p, void* desc, size_t desc_bytes,
+                          void* ws, size_t ws_bytes, int32_t* status, lv_stats* stats, void* stream);
+
 /* Measurement hook.  lv_set_timing(mask) makes every later louvain_* call
  * bracket each launch of the kernels whose bit k is set in `mask` (k =
  * LV_TIME_*) with a pair of HIP events on the call's

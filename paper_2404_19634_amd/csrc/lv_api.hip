@@ -323,9 +323,12 @@ float ms_between(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
+// resume_li > 0: the local-moving iterations of pass 0 already ran (the
+// batched kernel did them, with that l_i); the call goes on from the end of
+// pass 0 with the state as it is (Alg. 4: renumber, aggregate, passes >= 1).
 lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const lv_edges* ins,
                       const lv_params* p, lv_state* state, void* wsp, size_t ws_bytes, lv_stats* stats,
-                      void* stream) {
+                      void* stream, int32_t resume_li = 0) {
   const auto t_start = std::chrono::steady_clock::now();
   if (!graph_ok(g)) return fail(LV_EINVAL, "invalid graph");
   if (!params_ok(p)) return fail(LV_EINVAL, "invalid parameters");
@@ -366,7 +369,9 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
   // member counts of level-0 communities: the caller's carried array when
   // given (kept exact by the moves), else counted here for the swap guard
   int32_t* size0 = state->size ? state->size : (p->swap_guard ? ws.size : nullptr);
-  if (ap == A_STATIC) {
+  if (resume_li > 0) {
+    // nothing to mark: pass 0's moves are done
+  } else if (ap == A_STATIC) {
     launch_row_sums(L0, nullptr, state->K, state->Sigma, state->C, size0 ? size0 : ws.size, ws.bins[5], ws.ctr,
                     st);
     launch_set_all_bits(ws.fr_a, N, st);
@@ -447,7 +452,11 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     // upper bound of the frontier size, for the choice of sub-rounds
     int64_t est_frontier = L.n;
     if (pass == 0 && ap == A_DF) est_frontier = 2 * (D.count + I.count);
-    for (int32_t it = 0; it < p->max_iterations; ++it, ++iter_seq) {
+    if (pass == 0 && resume_li > 0) {
+      li = resume_li;
+      LV_HIP(hipEventRecord(ev[3], st));
+    }
+    for (int32_t it = 0; it < p->max_iterations && !(pass == 0 && resume_li > 0); ++it, ++iter_seq) {
       a.cur = cur;
       a.next = next;
       // large frontiers pull the next frontier (reads) instead of pushing it
@@ -782,6 +791,101 @@ lv_status louvain_ds(const lv_graph* g, const lv_edges* del, const lv_edges* ins
 lv_status louvain_df(const lv_graph* g, const lv_edges* del, const lv_edges* ins, const lv_params* p,
                      lv_state* state, void* ws, size_t ws_bytes, lv_stats* stats, void* stream) {
   return run_louvain(A_DF, g, del, ins, p, state, ws, ws_bytes, stats, stream);
+}
+
+size_t lv_many_scratch_bytes(int32_t n, int32_t max_updates) { return many_scratch_bytes(n, max_updates); }
+
+size_t lv_many_desc_bytes(int32_t count) { return sizeof(ManyItem) * static_cast<size_t>(count > 0 ? count : 1); }
+
+lv_status louvain_df_many(const lv_item* items, int32_t count, const lv_params* p, void* desc, size_t desc_bytes,
+                          void* ws, size_t ws_bytes, int32_t* status, lv_stats* stats, void* stream) {
+  if (count < 0 || (count > 0 && (!items || !status || !desc))) return fail(LV_EINVAL, "invalid arguments");
+  if (!params_ok(p)) return fail(LV_EINVAL, "invalid parameters");
+  if (desc_bytes < lv_many_desc_bytes(count)) return fail(LV_EWORKSPACE, "descriptor buffer too small");
+  if (count == 0) return LV_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const auto t_start = std::chrono::steady_clock::now();
+  std::vector<ManyItem> h(static_cast<size_t>(count));
+  for (int32_t k = 0; k < count; ++k) {
+    const lv_item& x = items[k];
+    ManyItem& m = h[k];
+    std::memset(&m, 0, sizeof(ManyItem));
+    if (!graph_ok(&x.g) || !x.state.C || !x.state.K || !x.state.Sigma || !x.state.size || !edges_ok(&x.del) ||
+        !edges_ok(&x.ins) || !x.scratch)
+      return fail(LV_EINVAL, "invalid item");
+    m.row_start = x.g.row_start;
+    m.row_len = x.g.row_len;
+    m.col = x.g.col;
+    m.w = x.g.w;
+    m.two_m = x.g.two_m;
+    m.n = x.g.n;
+    m.max_updates = x.max_updates;
+    m.C = x.state.C;
+    m.K = x.state.K;
+    m.Sigma = x.state.Sigma;
+    m.size = x.state.size;
+    m.du = x.del.u;
+    m.dv = x.del.v;
+    m.dw = x.del.w;
+    m.iu = x.ins.u;
+    m.iv = x.ins.v;
+    m.iw = x.ins.w;
+    m.nd = static_cast<int32_t>(x.del.count);
+    m.ni = static_cast<int32_t>(x.ins.count);
+    m.scratch = x.scratch;
+    // outside the kernel's limits: the single-graph path takes it
+    if (x.del.count + x.ins.count > x.max_updates || x.max_updates <= 0 || x.g.n <= 0) m.status = LV_ETOOLARGE;
+  }
+  ManyItem* d = static_cast<ManyItem*>(desc);
+  LV_HIP(hipMemcpyAsync(d, h.data(), sizeof(ManyItem) * h.size(), hipMemcpyHostToDevice, st));
+  launch_many_df(d, count, *p, st);
+  LV_CHECK_LAUNCH();
+  LV_HIP(hipMemcpyAsync(h.data(), d, sizeof(ManyItem) * h.size(), hipMemcpyDeviceToHost, st));
+  LV_HIP(hipStreamSynchronize(st));
+  const double batched_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  for (int32_t k = 0; k < count; ++k) {
+    const ManyItem& m = h[k];
+    const lv_item& x = items[k];
+    lv_stats local;
+    lv_stats& S = stats ? stats[k] : local;
+    std::memset(&S, 0, sizeof(lv_stats));
+    status[k] = m.status;
+    if (m.status == LV_ETOOLARGE) {  // single-graph path from the start
+      if (!ws) {
+        status[k] = LV_EWORKSPACE;
+        continue;
+      }
+      lv_graph g = x.g;
+      lv_state state = x.state;
+      lv_status s = apply_batch(&g, &x.del, &x.ins, ws, ws_bytes, stream);
+      if (s == LV_OK) s = run_louvain(A_DF, &g, &x.del, &x.ins, p, &state, ws, ws_bytes, &S, stream);
+      status[k] = s;
+      continue;
+    }
+    if (m.status != LV_OK) continue;
+    if (m.iterations > 1) {  // aggregation and further passes (Alg. 4)
+      if (!ws) {
+        status[k] = LV_EWORKSPACE;
+        continue;
+      }
+      lv_graph g = x.g;
+      lv_state state = x.state;
+      const lv_status s = run_louvain(A_DF, &g, &x.del, &x.ins, p, &state, ws, ws_bytes, &S, stream, m.iterations);
+      status[k] = s;
+    } else {
+      S.passes = 1;
+    }
+    S.iterations[0] = m.iterations;
+    S.moves += m.moves;
+    S.arcs_scanned += m.arcs_scanned;
+    S.vertices_affected = m.vertices_affected;
+    for (int t = 0; t < m.iterations && t < kManyIters && t < LV_MAX_ITERS; ++t) {
+      S.iter_moves[0][t] = m.iter_moves[t];
+      S.iter_gain[0][t] = m.iter_gain[t];
+    }
+    S.seconds += batched_s;
+  }
+  return LV_OK;
 }
 
 lv_status modularity(const lv_graph* g, const int32_t* C, double* q_host, void* wsp, size_t ws_bytes, void* stream) {

@@ -334,6 +334,43 @@ void launch_ds_mark_sources(const uint64_t* skeys, const int32_t* sbestc, uint32
 void launch_ds_expand(const LevelGraph& g, const lv_edges& del, const lv_edges& ins, const int32_t* C,
                       const uint32_t* dE, const uint32_t* dC, uint32_t* dV, hipStream_t st);
 
+// many.hip -- DF for many graphs in one persistent launch
+constexpr int kManyWaveDeg = 256;    // rows up to this length: one wavefront
+constexpr int kManyBlockDeg = 2048;  // rows up to this length: one workgroup (longer: not batched)
+constexpr int kManyIters = 32;
+struct ManyItem {
+  int64_t* row_start;
+  int32_t* row_len;
+  int32_t* col;
+  int32_t* w;
+  int64_t* two_m;
+  int32_t n;
+  int32_t max_updates;  // capacity of the scratch
+  int32_t* C;
+  int64_t* K;
+  int64_t* Sigma;
+  int32_t* size;
+  const int32_t* du;
+  const int32_t* dv;
+  const int32_t* dw;
+  const int32_t* iu;
+  const int32_t* iv;
+  const int32_t* iw;
+  int32_t nd;
+  int32_t ni;
+  void* scratch;
+  // results
+  int32_t status;
+  int32_t iterations;  // pass 0 (l_i)
+  int64_t moves;
+  int64_t arcs_scanned;
+  int64_t vertices_affected;
+  int64_t iter_moves[kManyIters];
+  int64_t iter_gain[kManyIters];
+};
+size_t many_scratch_bytes(int32_t n, int32_t max_updates);
+void launch_many_df(ManyItem* items, int32_t count, const lv_params& p, hipStream_t st);
+
 // move.hip
 struct MoveArgs {
   LevelGraph g;

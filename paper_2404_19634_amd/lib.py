@@ -20,8 +20,9 @@ LIB_PATH = os.path.join(PKG, "liblouvain_hip.so")
 
 LV_OK = 0
 STATUS = {0: "LV_OK", -1: "LV_EINVAL", -2: "LV_ENOEDGE", -3: "LV_ENOSLACK", -4: "LV_EOVERFLOW",
-          -5: "LV_EEMPTY", -6: "LV_EHIP", -7: "LV_EWORKSPACE"}
+          -5: "LV_EEMPTY", -6: "LV_EHIP", -7: "LV_EWORKSPACE", -8: "LV_ETOOLARGE"}
 LV_EINVAL, LV_ENOEDGE, LV_ENOSLACK, LV_EOVERFLOW, LV_EEMPTY, LV_EHIP, LV_EWORKSPACE = -1, -2, -3, -4, -5, -6, -7
+LV_ETOOLARGE = -8
 SYNC, ASYNC = 0, 1
 MAX_PASSES, MAX_ITERS = 16, 32
 # degree bins of the local-moving scan (LV_BIN_*) and the timing selector
@@ -34,7 +35,8 @@ NTIMED = len(TIMED)
 
 EXPORTS = ["lv_default_params", "lv_workspace_bytes", "lv_graph_capacity_bound", "lv_graph_build",
            "lv_graph_relayout", "apply_batch", "louvain_static", "louvain_nd", "louvain_ds", "louvain_df",
-           "modularity", "lv_set_tuning", "lv_get_tuning", "lv_set_timing", "lv_last_error"]
+           "modularity", "lv_set_tuning", "lv_get_tuning", "lv_set_timing", "lv_last_error",
+           "lv_many_scratch_bytes", "lv_many_desc_bytes", "louvain_df_many"]
 
 
 class LouvainError(RuntimeError):
@@ -92,6 +94,11 @@ class Stats(ct.Structure):
         }
 
 
+class CItem(ct.Structure):
+    _fields_ = [("g", CGraph), ("state", CState), ("dels", CEdges), ("ins", CEdges), ("scratch", ct.c_void_p),
+                ("max_updates", ct.c_int32)]
+
+
 class Tuning(ct.Structure):
     _fields_ = [("wave_max_degree", ct.c_int32), ("blocks_small", ct.c_int32), ("blocks_wave", ct.c_int32),
                 ("blocks_hub", ct.c_int32), ("async_rounds_log2", ct.c_int32),
@@ -135,6 +142,12 @@ def load():
     L.modularity.argtypes = [GP, P, ct.POINTER(ct.c_double), P, SZ, P]
     L.lv_set_tuning.argtypes = [ct.POINTER(Tuning)]
     L.lv_get_tuning.argtypes = [ct.POINTER(Tuning)]
+    L.lv_many_scratch_bytes.restype = SZ
+    L.lv_many_scratch_bytes.argtypes = [I32, I32]
+    L.lv_many_desc_bytes.restype = SZ
+    L.lv_many_desc_bytes.argtypes = [I32]
+    L.louvain_df_many.restype = I32
+    L.louvain_df_many.argtypes = [ct.POINTER(CItem), I32, PP, P, SZ, P, SZ, ct.POINTER(I32), STP, P]
     L.lv_set_timing.restype = I32
     L.lv_set_timing.argtypes = [ct.c_uint32]
     L.lv_last_error.restype = ct.c_char_p
@@ -388,6 +401,39 @@ def louvain_ds(g, b, state, prm=None, stream=None, **kw):
 
 def louvain_df(g, b, state, prm=None, stream=None, **kw):
     return _dynamic("louvain_df", g, b, state, prm, stream, kw)
+
+
+def many_scratch(n: int, max_updates: int, device="cuda") -> torch.Tensor:
+    """Zeroed scratch for one graph of louvain_df_many (kept per graph; each
+    call leaves it ready for the next)."""
+    nbytes = int(load().lv_many_scratch_bytes(int(n), int(max_updates)))
+    return torch.zeros(nbytes, dtype=torch.uint8, device=device)
+
+
+def louvain_df_many(graphs, batches, states, scratches, max_updates, prm=None, ws=None, desc=None, stream=None,
+                    **kw):
+    """apply_batch + louvain_df on every (graph, batch, state) in one
+    persistent launch.  `max_updates` is the capacity each scratch was sized
+    for (an int, or one per graph); `ws` is a workspace tensor for graphs
+    that continue on the single-graph path (None: they report
+    LV_EWORKSPACE).  Returns (status list, stats list)."""
+    L = load()
+    count = len(graphs)
+    prm = prm if prm is not None else params(**kw)
+    caps = list(max_updates) if hasattr(max_updates, "__len__") else [int(max_updates)] * count
+    items = (CItem * max(count, 1))()
+    for k in range(count):
+        items[k] = CItem(graphs[k].c(), states[k].c(), batches[k].dels.c(), batches[k].ins.c(),
+                         scratches[k].data_ptr(), int(caps[k]))
+    need = int(L.lv_many_desc_bytes(count))
+    if desc is None or desc.numel() < need:
+        desc = torch.empty(need, dtype=torch.uint8, device=graphs[0].device if count else "cuda")
+    status = (ct.c_int32 * max(count, 1))()
+    stats = (Stats * max(count, 1))()
+    wp, wb = (ct.c_void_p(ws.data_ptr()), ws.numel()) if ws is not None else (None, 0)
+    _check(L.louvain_df_many(items, count, ct.byref(prm), ct.c_void_p(desc.data_ptr()), desc.numel(), wp, wb,
+                             status, stats, _stream(stream)))
+    return [int(status[k]) for k in range(count)], [stats[k].as_dict() for k in range(count)]
 
 
 def modularity(g: Graph, C: torch.Tensor, stream=None) -> float:

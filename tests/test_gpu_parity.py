@@ -357,3 +357,83 @@ def test_bin_stats_and_timing_hook(lib):
     assert all((t["timed_ms"][k] > 0) == (t["timed_launches"][k] > 0) for k in range(lib.NTIMED))
     _, u = lib.louvain_static(g, mode="async")
     assert all(x == 0 for x in u["timed_launches"])
+
+
+# ---- many graphs in one launch ------------------------------------------------
+
+def _many_cases():
+    """Graphs of different sizes and shapes, each with its own batch; the
+    star has a row longer than the batched kernel takes (single-graph path),
+    and the big SBM batch makes pass 0 run several iterations (continuation
+    with aggregation on the single-graph path)."""
+    out = []
+    for k, e in enumerate([W.config1_sbm(seed=5), W.rmat(11, 8, 0.57, 0.19, 0.19, 31),
+                           W.random_small_graph(777, 3000, 41, max_w=5), W.ring_of_cliques(12, 5),
+                           _star_plus(17), W.sbm([40] * 25, 0.3, 0.01, 8)]):
+        size = max(6, e.m // 100) if k != 5 else e.m // 3
+        out.append((e, W.random_batch(e, size, 500 + k)))
+    return out
+
+
+@pytest.mark.parametrize("mode,tol", [("sync", 1e-2), ("sync", 1e-4), ("async", 1e-2)])
+def test_many_graphs_match_single_graph_results(lib, mode, tol):
+    cases = _many_cases()
+    cap = max(b.size for _, b in cases)
+    graphs, batches, states, scratches, expect = [], [], [], [], []
+    for e, b in cases:
+        G = _orc(e)
+        s0 = G.louvain("static", mode="sync")[:3]
+        assert G.apply_batch(b) == 0
+        Co, Ko, So, os_ = G.louvain("df", batch=b, state=s0, mode="sync", tolerance=tol)
+        expect.append((G, Co, Ko, So, os_))
+        g = lib.Graph.from_edges(e, slack_frac=1.0, slack_min=32)
+        st = lib.State.from_host(*s0)
+        st.size = torch.from_numpy(_sizes(s0[0], e.n)).cuda()
+        graphs.append(g)
+        batches.append(lib.Batch.from_host(b))
+        states.append(st)
+        scratches.append(lib.many_scratch(e.n, cap))
+    ws = max(graphs, key=lambda g: g.n * 4 + g.cap).workspace
+    status, stats = lib.louvain_df_many(graphs, batches, states, scratches, cap, ws=ws, mode=mode, tolerance=tol)
+    assert status == [0] * len(cases), status
+    if tol < 1e-2:  # pass 0 of the R-MAT graph iterates, so it continues with aggregation
+        assert stats[1]["passes"] > 1
+    for (G, Co, Ko, So, os_), g, st, s, (e, _) in zip(expect, graphs, states, stats, cases):
+        assert all(np.array_equal(x, y) for x, y in zip(g.csr_host(), G.csr()))
+        assert g.two_m == G.two_m
+        C, K, S = st.host()
+        assert np.array_equal(K, Ko)
+        assert np.array_equal(st.size.cpu().numpy(), _sizes(C, e.n))
+        assert np.array_equal(S, np.bincount(C, weights=K, minlength=e.n).astype(np.int64))
+        if mode == "sync":
+            assert np.array_equal(C, Co) and np.array_equal(S, So)
+            _same_stats(s, os_)
+        else:
+            q = lib.modularity(g, st.C)
+            assert q >= G.modularity(Co) - 2e-3
+    # the call restores what the scratch needs: a second round on the same graphs works too
+    b2 = [lib.Batch.from_host(W.random_batch(W.apply_batch_np(e, b), 8, 900 + k))
+          for k, (e, b) in enumerate(cases)]
+    status, _ = lib.louvain_df_many(graphs, b2, states, scratches, cap, ws=ws, mode=mode, tolerance=tol)
+    assert status == [0] * len(cases), status
+
+
+def test_many_graphs_isolate_bad_batches(lib):
+    good = [W.random_small_graph(300, 900, 60 + k) for k in range(3)]
+    z = np.zeros(0, np.int32)
+    e = good[1]
+    bad = W.Batch(e.u[:1], e.v[:1], e.w[:1] + 1, z, z, z)  # deletes more weight than present
+    batches_h = [W.random_batch(good[0], 20, 70), bad, W.random_batch(good[2], 20, 72)]
+    graphs = [lib.Graph.from_edges(x) for x in good]
+    before = graphs[1].csr_host()
+    states = []
+    for g, x in zip(graphs, good):
+        st, _ = lib.louvain_static(g, mode="sync")
+        states.append(st)
+    C1 = states[1].C.clone()
+    scratches = [lib.many_scratch(x.n, 32) for x in good]
+    status, _ = lib.louvain_df_many(graphs, [lib.Batch.from_host(b) for b in batches_h], states, scratches, 32,
+                                    mode="sync")
+    assert status == [0, lib.LV_ENOEDGE, 0]
+    assert all(np.array_equal(x, y) for x, y in zip(before, graphs[1].csr_host()))
+    assert torch.equal(C1, states[1].C)
