@@ -1,0 +1,251 @@
+"""Serving loop: streaming batch updates on device-resident graphs.
+
+Requests name a graph and a batch of edge updates (Section 3.4).  Graphs
+and their community state (C, K, Sigma, member counts) stay resident in
+HBM between requests; each request is apply_batch + DF Louvain on its
+graph (Alg. 1).  The loop batches continuously: worker threads each own a
+HIP stream and repeatedly take up to `slots` waiting requests on distinct
+graphs, admit their graphs into HBM (evicting idle graphs to host memory
+when the byte budget would be exceeded), and run them in one persistent
+launch (`louvain_df_many`).  Requests that arrive while a launch is on the
+GPU are picked up by the next free worker, so launches overlap on the
+device.  Latency is arrival to completion; the summary reports p50/p99
+and requests per second.
+
+Only argument marshalling and bookkeeping happen here; every step of the
+update runs in the HIP library.
+"""
+from __future__ import annotations
+
+import collections
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import lib
+
+
+@dataclass
+class Request:
+    gid: int
+    batch: object          # workloads.Batch (host arrays)
+    t_arrival: float
+    rid: int = 0
+    t_start: float = 0.0
+    t_done: float = 0.0
+    status: int = 1        # 1 pending, else the library status
+    stats: dict = field(default_factory=dict)
+
+
+class Resident:
+    """A graph, its state and its batched-kernel scratch on the device."""
+
+    def __init__(self, graph: lib.Graph, state: lib.State, scratch: torch.Tensor):
+        self.graph, self.state, self.scratch = graph, state, scratch
+        self.busy = False
+        self.last_used = 0.0
+
+    @property
+    def nbytes(self) -> int:
+        g, s = self.graph, self.state
+        t = [g.row_start, g.row_len, g.col, g.w, g.two_m_t, s.C, s.K, s.Sigma, s.size, self.scratch]
+        return sum(x.numel() * x.element_size() for x in t)
+
+
+class GraphStore:
+    """Graphs by id; at most `budget_bytes` of them resident in HBM.
+
+    A graph enters HBM when a request needs it (built from its edge list
+    and given a static Louvain state the first time, copied back from the
+    host after an eviction) and leaves, least recently used first, when an
+    admission would exceed the budget."""
+
+    def __init__(self, budget_bytes: int, max_updates: int, device="cuda", mode="async", slack_frac=0.5,
+                 slack_min=16):
+        self.budget = int(budget_bytes)
+        self.max_updates = int(max_updates)
+        self.device = torch.device(device)
+        self.mode = mode
+        self.slack = (slack_frac, slack_min)
+        self.edges = {}        # gid -> workloads.Edges (never-admitted graphs)
+        self.host = {}         # gid -> evicted device arrays, on the host
+        self.res = {}          # gid -> Resident
+        self.lock = threading.Lock()
+        self.resident_bytes = 0
+        self.evictions = 0
+        self.admissions = 0
+
+    def add(self, gid: int, edges) -> None:
+        self.edges[gid] = edges
+
+    def _build(self, gid) -> Resident:
+        if gid in self.host:
+            h = self.host.pop(gid)
+            g = lib.Graph(h["n"], h["cap"], self.device)
+            for name in ("row_start", "row_len", "col", "w", "two_m_t"):
+                getattr(g, name).copy_(h[name], non_blocking=False)
+            st = lib.State(h["C"].to(self.device), h["K"].to(self.device), h["Sigma"].to(self.device),
+                           h["size"].to(self.device))
+        else:
+            e = self.edges[gid]
+            g = lib.Graph.from_edges(e, slack_frac=self.slack[0], slack_min=self.slack[1], device=self.device)
+            st, _ = lib.louvain_static(g, mode=self.mode)
+            g._ws = None  # the build workspace is not kept; louvain_df_many needs none per graph
+        scratch = lib.many_scratch(g.n, self.max_updates, self.device)
+        return Resident(g, st, scratch)
+
+    def _evict_one(self) -> bool:
+        idle = [(r.last_used, gid) for gid, r in self.res.items() if not r.busy]
+        if not idle:
+            return False
+        _, gid = min(idle)
+        r = self.res.pop(gid)
+        g, s = r.graph, r.state
+        self.host[gid] = {"n": g.n, "cap": g.cap, "row_start": g.row_start.cpu(), "row_len": g.row_len.cpu(),
+                          "col": g.col.cpu(), "w": g.w.cpu(), "two_m_t": g.two_m_t.cpu(), "C": s.C.cpu(),
+                          "K": s.K.cpu(), "Sigma": s.Sigma.cpu(), "size": s.size.cpu()}
+        self.resident_bytes -= r.nbytes
+        self.evictions += 1
+        return True
+
+    def acquire(self, gids) -> list:
+        """Marks the graphs busy and makes them resident.  Called with the
+        store lock held by the caller's scheduling step."""
+        out = []
+        for gid in gids:
+            r = self.res.get(gid)
+            if r is None:
+                r = self._build(gid)
+                while self.resident_bytes + r.nbytes > self.budget and self._evict_one():
+                    pass
+                self.res[gid] = r
+                self.resident_bytes += r.nbytes
+                self.admissions += 1
+            r.busy = True
+            out.append(r)
+        return out
+
+    def release(self, gids) -> None:
+        now = time.perf_counter()
+        for gid in gids:
+            r = self.res[gid]
+            r.busy = False
+            r.last_used = now
+
+
+class Server:
+    """Continuous batching over a GraphStore (see the module docstring)."""
+
+    def __init__(self, store: GraphStore, slots=1024, workers=2, **params):
+        self.store = store
+        self.slots = int(slots)
+        self.workers = int(workers)
+        self.params = lib.params(mode=store.mode, **params)
+        self.queue = collections.deque()
+        self.done = []
+        self.cv = threading.Condition(store.lock)
+        self.closed = False
+        self.launches = 0
+        self._next_rid = 0
+        self._threads = []
+
+    def submit(self, gid: int, batch, t_arrival=None) -> Request:
+        with self.cv:
+            r = Request(gid, batch, time.perf_counter() if t_arrival is None else t_arrival, self._next_rid)
+            self._next_rid += 1
+            self.queue.append(r)
+            self.cv.notify()
+        return r
+
+    def start(self):
+        for k in range(self.workers):
+            t = threading.Thread(target=self._worker, args=(k,), daemon=True)
+            t.start()
+            self._threads.append(t)
+
+    def close(self):
+        with self.cv:
+            self.closed = True
+            self.cv.notify_all()
+        for t in self._threads:
+            t.join()
+
+    def _take(self):
+        """Up to `slots` waiting requests on distinct idle graphs, oldest
+        first (a graph's requests stay in arrival order)."""
+        picked, seen, keep = [], set(), collections.deque()
+        while self.queue and len(picked) < self.slots:
+            r = self.queue.popleft()
+            res = self.store.res.get(r.gid)
+            if r.gid in seen or (res is not None and res.busy):
+                keep.append(r)
+                seen.add(r.gid)
+                continue
+            seen.add(r.gid)
+            picked.append(r)
+        keep.extend(self.queue)
+        self.queue.clear()
+        self.queue.extend(keep)
+        return picked
+
+    def _worker(self, k):
+        stream = torch.cuda.Stream(device=self.store.device)
+        desc = torch.empty(int(lib.load().lv_many_desc_bytes(self.slots)), dtype=torch.uint8,
+                           device=self.store.device)
+        ws = None
+        while True:
+            with self.cv:
+                while not self.queue and not self.closed:
+                    self.cv.wait()
+                if not self.queue and self.closed:
+                    return
+                picked = self._take()
+                if not picked:
+                    self.cv.wait(0.001)
+                    continue
+                with torch.cuda.stream(stream):
+                    residents = self.store.acquire([r.gid for r in picked])
+            t0 = time.perf_counter()
+            with torch.cuda.stream(stream):
+                batches = [lib.Batch.from_host(r.batch, self.store.device) for r in picked]
+                big = max(residents, key=lambda x: x.graph.n * 4 + x.graph.cap)
+                need = int(lib.load().lv_workspace_bytes(big.graph.n, big.graph.cap))
+                if ws is None or ws.numel() < need:
+                    ws = torch.empty(need, dtype=torch.uint8, device=self.store.device)
+                status, stats = lib.louvain_df_many([x.graph for x in residents], batches,
+                                                    [x.state for x in residents], [x.scratch for x in residents],
+                                                    self.store.max_updates, prm=self.params, ws=ws, desc=desc,
+                                                    stream=stream)
+            t1 = time.perf_counter()
+            with self.cv:
+                self.launches += 1
+                for r, s, st in zip(picked, status, stats):
+                    r.t_start, r.t_done, r.status, r.stats = t0, t1, s, st
+                    self.done.append(r)
+                self.store.release([r.gid for r in picked])
+                self.cv.notify_all()
+
+    def wait(self, count: int, timeout: float = 600.0) -> None:
+        """Blocks until `count` requests are done."""
+        end = time.perf_counter() + timeout
+        with self.cv:
+            while len(self.done) < count:
+                left = end - time.perf_counter()
+                if left <= 0:
+                    raise TimeoutError(f"{len(self.done)} of {count} requests done")
+                self.cv.wait(left)
+
+    def summary(self) -> dict:
+        lat = np.array([r.t_done - r.t_arrival for r in self.done]) * 1e3
+        if not len(lat):
+            return {}
+        t0 = min(r.t_arrival for r in self.done)
+        t1 = max(r.t_done for r in self.done)
+        return {"requests": len(self.done), "latency_ms_p50": float(np.percentile(lat, 50)),
+                "latency_ms_p99": float(np.percentile(lat, 99)), "requests_per_s": len(self.done) / (t1 - t0),
+                "launches": self.launches, "admissions": self.store.admissions,
+                "evictions": self.store.evictions,
+                "failed": sum(1 for r in self.done if r.status != 0)}

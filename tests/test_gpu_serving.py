@@ -1,0 +1,97 @@
+"""Serving loop: each request's result is the same alone and in the mix.
+
+Many small graphs each receive a chain of batches.  In the mix, two worker
+streams batch whatever requests are waiting into persistent launches, under
+an HBM budget that forces evictions to host memory and re-admissions.
+Alone, each graph's chain runs by itself.  SYNC mode must agree bit for bit
+(and with the sequential oracle); ASYNC mode must give consistent states
+of the same modularity within 2e-3."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2404_19634_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2404_19634_amd import lib as L
+    L.load()
+    L.set_tuning()
+    return L
+
+
+def _workload(count=24, chain=3, seed=77):
+    specs = W.multi_sbm_specs(count, seed, n_lo=300, n_hi=6000, b_lo=10, b_hi=400)
+    graphs, chains = [], []
+    for k, (n, b, s) in enumerate(specs):
+        e = W.multi_sbm_graph(int(n), int(b), int(s))
+        cur, bs = e, []
+        for t in range(chain):
+            bt = W.random_batch(cur, max(5, cur.m // 100), 1000 * k + t)
+            bs.append(bt)
+            cur = W.apply_batch_np(cur, bt)
+        graphs.append(e)
+        chains.append(bs)
+    return graphs, chains
+
+
+def _run(lib, graphs, chains, mode, budget, workers, slots, order):
+    from paper_2404_19634_amd import serve
+    store = serve.GraphStore(budget, max_updates=max(b.size for c in chains for b in c), mode=mode)
+    for gid, e in enumerate(graphs):
+        store.add(gid, e)
+    srv = serve.Server(store, slots=slots, workers=workers)
+    srv.start()
+    try:
+        for gid, t in order:
+            srv.submit(gid, chains[gid][t])
+        srv.wait(len(order))
+    finally:
+        srv.close()
+    assert all(r.status == 0 for r in srv.done), [r.status for r in srv.done if r.status]
+    out = {}
+    for gid in range(len(graphs)):
+        r = store.acquire([gid])[0]
+        store.release([gid])
+        s = r.state
+        out[gid] = (s.C.cpu().numpy(), s.K.cpu().numpy(), s.Sigma.cpu().numpy(), s.size.cpu().numpy(),
+                    r.graph.csr_host(), lib.modularity(r.graph, s.C))
+    return out, srv.summary()
+
+
+@pytest.mark.parametrize("mode", ["sync", "async"])
+def test_results_alone_and_in_the_mix(lib, mode):
+    graphs, chains = _workload()
+    chain = len(chains[0])
+    # interleaved arrivals: every graph's first batch, then every second...
+    order = [(gid, t) for t in range(chain) for gid in range(len(graphs))]
+    mix, summ = _run(lib, graphs, chains, mode, budget=2 << 20, workers=2, slots=8, order=order)
+    assert summ["evictions"] > 0 and summ["launches"] > 1
+    alone = {}
+    for gid in range(len(graphs)):
+        one, _ = _run(lib, [graphs[gid]], [chains[gid]], mode, budget=1 << 40, workers=1, slots=1,
+                      order=[(0, t) for t in range(chain)])
+        alone[gid] = one[0]
+    for gid in range(len(graphs)):
+        a, b = mix[gid], alone[gid]
+        assert all(np.array_equal(x, y) for x, y in zip(a[4], b[4]))  # the graph itself
+        assert np.array_equal(a[1], b[1])  # K
+        for C, K, S, size, _, _ in (a, b):
+            assert np.array_equal(S, np.bincount(C, weights=K, minlength=len(C)).astype(np.int64))
+            assert np.array_equal(size, np.bincount(C, minlength=len(C)))
+        if mode == "sync":
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+        else:
+            assert abs(a[5] - b[5]) <= 2e-3
+    if mode == "sync":  # and the chain agrees with the sequential oracle
+        import oracle
+        for gid in range(0, len(graphs), 6):
+            G = oracle.Graph.from_edges(graphs[gid])
+            C, K, S, _ = G.louvain("static", mode="sync")
+            for b in chains[gid]:
+                assert G.apply_batch(b) == 0
+                C, K, S, _ = G.louvain("df", batch=b, state=(C, K, S), mode="sync")
+            assert np.array_equal(C, mix[gid][0]) and np.array_equal(S, mix[gid][2])
