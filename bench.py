@@ -253,6 +253,83 @@ def sweep(g, e, runs):
     log("copy: 1 GiB read + 1 GiB written")
 
 
+def _gen_graph(spec):
+    from paper_2404_19634_amd import workloads as W
+    n, b, seed = spec
+    e = W.multi_sbm_graph(int(n), int(b), int(seed))
+    b1 = W.random_batch(e, W.batch_size(1e-3, e.m), int(seed) % (1 << 30))
+    e1 = W.apply_batch_np(e, b1)
+    b2 = W.random_batch(e1, W.batch_size(1e-3, e1.m), (int(seed) + 1) % (1 << 30))
+    return e, b1, b2
+
+
+def serve_bench(args):
+    """Many independent SBM graphs (vertex counts log-uniform in [1e3, 2e5],
+    block sizes log-uniform in [20, 2000], expected intra/inter degree
+    12/3), each with 1e-3|E| 80/20 batches, served from HBM.  Phase 1 sends
+    every graph's first batch at once (the batched persistent launch at
+    saturation); phase 2 sends the second batches with Poisson arrivals at
+    a fraction of that rate and reports latency percentiles."""
+    import multiprocessing as mp
+    import torch
+    from paper_2404_19634_amd import lib, serve
+    from paper_2404_19634_amd import workloads as W
+    lib.load()
+    specs = W.multi_sbm_specs(args.serve_graphs, 1244)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        data = pool.map(_gen_graph, specs, chunksize=4)
+    sum_n = sum(e.n for e, _, _ in data)
+    sum_m = sum(e.m for e, _, _ in data)
+    log(f"{len(data)} graphs, {sum_n} vertices, {sum_m} edges generated in {time.perf_counter() - t0:.1f} s")
+    cap = max(max(b1.size, b2.size) for _, b1, b2 in data)
+    free, _ = torch.cuda.mem_get_info()
+    store = serve.GraphStore(int(free * 0.8), max_updates=cap, mode=args.mode)
+    for gid, (e, _, _) in enumerate(data):
+        store.add(gid, e)
+    t0 = time.perf_counter()
+    with store.lock:
+        store.acquire(list(range(len(data))))
+    store.release(list(range(len(data))))
+    torch.cuda.synchronize()
+    log(f"resident: {store.resident_bytes / 1e9:.2f} GB after {time.perf_counter() - t0:.1f} s "
+        f"(build + static Louvain per graph)")
+    srv = serve.Server(store, slots=args.serve_slots, workers=2)
+    srv.start()
+    t0 = time.perf_counter()
+    for gid, (_, b1, _) in enumerate(data):
+        srv.submit(gid, b1, t_arrival=t0)
+    srv.wait(len(data))
+    burst_s = time.perf_counter() - t0
+    burst = srv.summary()
+    sat = len(data) / burst_s
+    log(f"burst: {len(data)} updates in {burst_s * 1e3:.1f} ms ({sat:.0f} graphs/s), {burst}")
+    srv.done.clear()
+    srv.launches = 0
+    rate = args.serve_load * sat
+    rng = np.random.default_rng(5)
+    gaps = rng.exponential(1.0 / rate, len(data))
+    order = rng.permutation(len(data))
+    t = time.perf_counter()
+    for gid, gap in zip(order, gaps):
+        t += gap
+        while time.perf_counter() < t:
+            pass
+        srv.submit(int(gid), data[int(gid)][2], t_arrival=t)
+    srv.wait(len(data))
+    srv.close()
+    poisson = srv.summary()
+    out = {"metric": "batched DF update latency p50/p99 and graphs/s, many-graph serving", "unit": "graphs/s",
+           "value": sat, "higher_is_better": True, "n_gpus": 1, "data": "synthetic", "dtype": "int64",
+           "config": {"workload": f"{len(data)} SBM graphs (n log-uniform 1e3..2e5, blocks log-uniform 20..2000, "
+                                  f"degree 12/3), 1e-3|E| 80/20 batches", "graphs": len(data),
+                      "vertices": sum_n, "undirected_edges": sum_m, "mode": args.mode, "slots": args.serve_slots},
+           "burst": {"graphs_per_s": sat, "ms": burst_s * 1e3, **burst},
+           "poisson": {"offered_rate_per_s": rate, "load": args.serve_load, **poisson},
+           "resident_gb": store.resident_bytes / 1e9}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +348,10 @@ def main():
     ap.add_argument("--summarize", metavar="DB", help="print a summary of a rocprofv3 database and exit")
     ap.add_argument("--kernel", default="k_move_all<512>", help="kernel of --summarize for counter databases")
     ap.add_argument("--launches", type=int, default=0, help="last dispatches of --kernel to average")
+    ap.add_argument("--serve", action="store_true", help="many-graph serving benchmark instead of the R-MAT line")
+    ap.add_argument("--serve-graphs", type=int, default=4096)
+    ap.add_argument("--serve-slots", type=int, default=4096)
+    ap.add_argument("--serve-load", type=float, default=0.5, help="Poisson rate as a fraction of the burst rate")
     ap.add_argument("--sweep", type=int, default=0,
                     help="profiling mode: run this many single full local-moving sweeps (SYNC, all vertices "
                          "from singletons) and one 1 GiB device copy for counter calibration, then exit")
@@ -287,6 +368,9 @@ def main():
     from paper_2404_19634_amd import lib
     from paper_2404_19634_amd import workloads as W
 
+    if args.serve:
+        serve_bench(args)
+        return
     region = ProfilerRegion()
     tuning = {k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(",") if kv)}
     lib.set_tuning(**tuning)

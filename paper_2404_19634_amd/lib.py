@@ -247,6 +247,23 @@ class Batch:
         z = np.zeros(0, np.int32)
         return cls(Edges(z, z, z, device), Edges(z, z, z, device))
 
+    @classmethod
+    def many_from_host(cls, batches, device="cuda"):
+        """Device copies of many host batches through one transfer (views
+        into a single device buffer)."""
+        parts = []
+        for b in batches:
+            parts += [b.del_u, b.del_v, b.del_w, b.ins_u, b.ins_v, b.ins_w]
+        sizes = [len(x) for x in parts]
+        flat = np.concatenate([np.asarray(x, np.int32) for x in parts]) if parts else np.zeros(0, np.int32)
+        dev = torch.from_numpy(flat).pin_memory().to(device, non_blocking=True)
+        views, o = [], 0
+        for k in sizes:
+            views.append(dev[o:o + k])
+            o += k
+        return [cls(Edges(*views[6 * j:6 * j + 3], device), Edges(*views[6 * j + 3:6 * j + 6], device))
+                for j in range(len(batches))]
+
 
 class Graph:
     """Slack-padded CSR on the device plus its workspace."""

@@ -210,7 +210,7 @@ class Server:
                     residents = self.store.acquire([r.gid for r in picked])
             t0 = time.perf_counter()
             with torch.cuda.stream(stream):
-                batches = [lib.Batch.from_host(r.batch, self.store.device) for r in picked]
+                batches = lib.Batch.many_from_host([r.batch for r in picked], self.store.device)
                 big = max(residents, key=lambda x: x.graph.n * 4 + x.graph.cap)
                 need = int(lib.load().lv_workspace_bytes(big.graph.n, big.graph.cap))
                 if ws is None or ws.numel() < need:
