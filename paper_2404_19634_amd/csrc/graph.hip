@@ -2,9 +2,31 @@
 // the paper's aggregation phase, Alg. 6, reused for in-place batch
 // updates), relayout with more slack, weighted degrees (Section 3), and the
 // per-arc / per-community terms of modularity (Eq. 1).
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "lv_internal.hpp"
 
 namespace lv {
+
+int64_t resident_blocks(const void* kernel, int block, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, int, size_t>, int64_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return INT32_MAX;
+  const auto key = std::make_tuple(dev, kernel, block, lds);
+  std::lock_guard<std::mutex> lock(mu);
+  const auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  int64_t r = INT32_MAX;  // unknown: no cap
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && per_cu > 0 && cus > 0)
+    r = static_cast<int64_t>(per_cu) * cus;
+  cache[key] = r;
+  return r;
+}
 
 int grid_for(int64_t items, int per_block, int max_blocks) {
   int64_t b = (items + per_block - 1) / per_block;

@@ -133,8 +133,9 @@ struct Workspace {
   int32_t* u_emit_b = nullptr;   // table-slot units of big items (item, first slot)
   int64_t* u_emit_s = nullptr;
   int64_t units_max = 0;
-  int32_t* pool_keys = nullptr;  // global hashtables
-  int32_t* pool_vals = nullptr;
+  int32_t* pool_keys = nullptr;  // global hashtables: keys then values, or
+  int32_t* pool_vals = nullptr;  // (as pool_pairs) packed key:value slots
+  uint64_t* pool_pairs = nullptr;
   int64_t pool_slots = 0;
   int64_t* scan_part = nullptr;  // per-block partial sums of the scans
   int64_t scan_part_len = 0;
@@ -249,6 +250,9 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t key, uint32_t size) {
 // Launchers (host).  All enqueue on `st`; none synchronises.
 // --------------------------------------------------------------------------
 int grid_for(int64_t items, int per_block, int max_blocks = 65535 * 4);
+// Workgroups of `kernel` (with `lds` bytes of dynamic LDS) that the current
+// device holds at once: occupancy per compute unit times the unit count.
+int64_t resident_blocks(const void* kernel, int block, size_t lds);
 
 // scan.hip
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, Workspace& ws, hipStream_t st);

@@ -568,6 +568,9 @@ __device__ __forceinline__ void role_small(const Dev& D, int64_t two_m, const in
   flush_totals(D, gain_acc, moved, marcs);
 }
 
+// Table slots (and arcs) a lane holds at once in the gather phases.
+constexpr int kDecideSlots = 4;
+
 // Rows up to the wave threshold: one wavefront, LDS table of TS slots.
 template <int TS>
 __device__ __forceinline__ void role_wave(const Dev& D, int64_t two_m, const int32_t* __restrict__ list, int64_t rb,
@@ -634,20 +637,21 @@ __device__ __forceinline__ void role_wave(const Dev& D, int64_t two_m, const int
     const int64_t Sd = D.Sigma[d];
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
-    {
-      constexpr int V = TS / kWave;
-      int32_t cc[V], vv[V];
-      int64_t sg[V];
+    // the table in chunks of kDecideSlots slots per lane (the gathers of a
+    // chunk overlap; the chunk bounds the registers the phase holds)
+    for (uint32_t t0 = 0; t0 < ts; t0 += kDecideSlots * kWave) {
+      int32_t cc[kDecideSlots], vv[kDecideSlots];
+      int64_t sg[kDecideSlots];
 #pragma unroll
-      for (int q = 0; q < V; ++q) {
-        const uint32_t t = lane + q * kWave;
+      for (int q = 0; q < kDecideSlots; ++q) {
+        const uint32_t t = t0 + lane + q * kWave;
         cc[q] = t < ts ? keys[t] : -1;
         vv[q] = t < ts ? vals[t] : 0;
       }
 #pragma unroll
-      for (int q = 0; q < V; ++q) sg[q] = cc[q] >= 0 ? D.Sigma[cc[q]] : 0;
+      for (int q = 0; q < kDecideSlots; ++q) sg[q] = cc[q] >= 0 ? D.Sigma[cc[q]] : 0;
 #pragma unroll
-      for (int q = 0; q < V; ++q)
+      for (int q = 0; q < kDecideSlots; ++q)
         if (cc[q] >= 0) {
           const int64_t g = gain_of(two_m, vv[q], kid, Ki, sg[q], Sd);
           if (better(g, cc[q], bg, bc)) {
@@ -743,14 +747,14 @@ __device__ __forceinline__ void role_block(const Dev& D, int64_t two_m, const in
       vals[t] = 0;
     }
     __syncthreads();
-    // a thread's arcs and table slots are loaded, then gathered, in batches
-    constexpr int U = kBlockMaxDegree / kBlock;
+    // a thread's arcs and table slots are loaded, then gathered, in chunks
+    constexpr int U = kDecideSlots;
     int64_t kid = 0;
-    {
+    for (int32_t k0 = 0; k0 < deg; k0 += U * kBlock) {
       int32_t js[U], xs[U], cs[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
-        const int32_t k = threadIdx.x + q * kBlock;
+        const int32_t k = k0 + threadIdx.x + q * kBlock;
         js[q] = k < deg ? D.col[start + k] : i;
         xs[q] = k < deg ? D.wt[start + k] : 0;
       }
@@ -779,20 +783,19 @@ __device__ __forceinline__ void role_block(const Dev& D, int64_t two_m, const in
     const int64_t Sd = D.Sigma[d];
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
-    {
-      constexpr int V = kBlockTS / kBlock;
-      int32_t cc[V], vv[V];
-      int64_t sg[V];
+    for (uint32_t t0 = 0; t0 < ts; t0 += kDecideSlots * kBlock) {
+      int32_t cc[kDecideSlots], vv[kDecideSlots];
+      int64_t sg[kDecideSlots];
 #pragma unroll
-      for (int q = 0; q < V; ++q) {
-        const uint32_t t = threadIdx.x + q * kBlock;
+      for (int q = 0; q < kDecideSlots; ++q) {
+        const uint32_t t = t0 + threadIdx.x + q * kBlock;
         cc[q] = t < ts ? keys[t] : -1;
         vv[q] = t < ts ? vals[t] : 0;
       }
 #pragma unroll
-      for (int q = 0; q < V; ++q) sg[q] = cc[q] >= 0 ? D.Sigma[cc[q]] : 0;
+      for (int q = 0; q < kDecideSlots; ++q) sg[q] = cc[q] >= 0 ? D.Sigma[cc[q]] : 0;
 #pragma unroll
-      for (int q = 0; q < V; ++q)
+      for (int q = 0; q < kDecideSlots; ++q)
         if (cc[q] >= 0) {
           const int64_t g = gain_of(two_m, vv[q], kid, Ki, sg[q], Sd);
           if (better(g, cc[q], bg, bc)) {
@@ -821,16 +824,25 @@ __device__ __forceinline__ void role_block(const Dev& D, int64_t two_m, const in
 }
 
 // Hub rows, insert units: LDS pre-aggregation of 2048 arcs, flushed into
-// the hub's global table.
+// the hub's global table.  A global slot packs key (high half) and value
+// (low half) in 64 bits, so one compare-and-swap inserts a new key with
+// its weight; a hit adds the weight to the low half (a sum of arc weights
+// of one row stays below 2m < 2^31, so it never carries into the key).
 constexpr int kHubTS = 4096;     // LDS pre-aggregation slots per unit
 constexpr int kHubProbes = 8;
+constexpr unsigned long long kEmptyPair = 0xFFFFFFFF00000000ull;  // key -1, value 0
 
-__device__ __forceinline__ void gtable_add(int32_t* keys, int32_t* vals, uint32_t tsz, int32_t c, int32_t x) {
+__device__ __forceinline__ unsigned long long pack_pair(int32_t c, int32_t x) {
+  return (static_cast<unsigned long long>(static_cast<uint32_t>(c)) << 32) | static_cast<uint32_t>(x);
+}
+
+__device__ __forceinline__ void gtable_add(unsigned long long* tab, uint32_t tsz, int32_t c, int32_t x) {
   uint32_t h = hash_slot(static_cast<uint32_t>(c), tsz);
   while (true) {
-    const int32_t old = atomicCAS(&keys[h], -1, c);
-    if (old == -1 || old == c) {
-      atomicAdd(&vals[h], x);
+    const unsigned long long old = atomicCAS(&tab[h], kEmptyPair, pack_pair(c, x));
+    if (old == kEmptyPair) return;
+    if (static_cast<int32_t>(old >> 32) == c) {
+      atomicAdd(&tab[h], static_cast<unsigned long long>(static_cast<uint32_t>(x)));
       return;
     }
     h = (h + 1 == tsz) ? 0 : h + 1;
@@ -842,8 +854,7 @@ struct HubIn {
   const int64_t* off;
   const int32_t* u_b;
   const int64_t* u_a;
-  int32_t* keys;
-  int32_t* vals;
+  unsigned long long* tab;
   int64_t* kid;
   int64_t pool_slots;
 };
@@ -863,6 +874,7 @@ __device__ __forceinline__ void role_hub_insert(const Dev& D, const HubIn& H, in
       if (threadIdx.x == 0) set_error(D.ctr, LV_EWORKSPACE);
       continue;
     }
+    unsigned long long* tab = H.tab + off;
     for (int s = threadIdx.x; s < kHubTS; s += kBlock) {
       tk[s] = -1;
       tv[s] = 0;
@@ -901,12 +913,45 @@ __device__ __forceinline__ void role_hub_insert(const Dev& D, const HubIn& H, in
         }
         p = (p + 1) & (kHubTS - 1);
       }
-      if (!done) gtable_add(H.keys + off, H.vals + off, tsz, c, x);
+      if (!done) gtable_add(tab, tsz, c, x);
     }
     kid = block_total(kid, red->s);
     if (threadIdx.x == 0 && kid) atomic_add_i64(&H.kid[h], kid);
-    for (int s = threadIdx.x; s < kHubTS; s += kBlock)
-      if (tk[s] >= 0) gtable_add(H.keys + off, H.vals + off, tsz, tk[s], tv[s]);
+    // Flush in rounds: every pending slot of the thread tries its current
+    // table slot (the compare-and-swaps of a round are in flight
+    // together); hits add their weight, collisions probe on.
+    constexpr int F = 8;
+    for (int s0 = 0; s0 < kHubTS; s0 += F * kBlock) {
+      int32_t fk[F], fv[F];
+      uint32_t fp[F];
+      uint32_t pend = 0;
+#pragma unroll
+      for (int q = 0; q < F; ++q) {
+        const int sl = s0 + threadIdx.x + q * kBlock;
+        fk[q] = tk[sl];
+        fv[q] = tv[sl];
+        fp[q] = fk[q] >= 0 ? hash_slot(static_cast<uint32_t>(fk[q]), tsz) : 0;
+        if (fk[q] >= 0) pend |= 1u << q;
+      }
+      while (pend) {
+        unsigned long long old[F];
+#pragma unroll
+        for (int q = 0; q < F; ++q)
+          old[q] = (pend >> q) & 1u ? atomicCAS(&tab[fp[q]], kEmptyPair, pack_pair(fk[q], fv[q])) : kEmptyPair;
+#pragma unroll
+        for (int q = 0; q < F; ++q) {
+          if (!((pend >> q) & 1u)) continue;
+          if (old[q] == kEmptyPair) {
+            pend &= ~(1u << q);
+          } else if (static_cast<int32_t>(old[q] >> 32) == fk[q]) {
+            atomicAdd(&tab[fp[q]], static_cast<unsigned long long>(static_cast<uint32_t>(fv[q])));
+            pend &= ~(1u << q);
+          } else {
+            fp[q] = fp[q] + 1 == tsz ? 0 : fp[q] + 1;
+          }
+        }
+      }
+    }
     __syncthreads();
   }
 }
@@ -925,17 +970,26 @@ constexpr size_t lds_wave() {
 }
 constexpr size_t lds_table() { return sizeof(Red) + 2 * sizeof(int32_t) * kBlockTS; }
 
-template <int TS>
+// ONLY == NBINS: the fused kernel, whose workgroups find their role from the
+// block ranges laid end to end.  ONLY < NBINS: that role alone over the
+// whole grid (its own register and LDS budget, so a higher occupancy).
+template <int TS, int ONLY>
 __global__ void __launch_bounds__(kBlock) k_move_all(Dev D, Bins bins, Roles R, HubIn H) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t two_m = load_two_m(D);
   if (two_m == 0) return;
-  const int64_t b = blockIdx.x;
-  int role = 0;
-  while (role < NBINS - 1 && b >= R.end[role]) ++role;
-  const int64_t lo = role == 0 ? 0 : R.end[role - 1];
-  const int64_t rb = b - lo, nb = R.end[role] - lo;
-  if (role <= BIN_G32) {
+  constexpr bool kAny = ONLY == NBINS;
+  int role = ONLY;
+  int64_t rb = blockIdx.x, nb = gridDim.x;
+  if constexpr (kAny) {
+    const int64_t b = blockIdx.x;
+    role = 0;
+    while (role < NBINS - 1 && b >= R.end[role]) ++role;
+    const int64_t lo = role == 0 ? 0 : R.end[role - 1];
+    rb = b - lo;
+    nb = R.end[role] - lo;
+  }
+  if ((kAny || ONLY <= BIN_G32) && role <= BIN_G32) {
     MoveAgg* agg = reinterpret_cast<MoveAgg*>(smem);
     agg_begin(agg);
     switch (role) {
@@ -945,20 +999,20 @@ __global__ void __launch_bounds__(kBlock) k_move_all(Dev D, Bins bins, Roles R, 
       default: role_small<32>(D, two_m, bins.list[BIN_G32], BIN_G32, rb, nb, agg); break;
     }
     agg_end(agg, D.Sigma, D.size);
-  } else if (role == BIN_WAVE) {
+  } else if ((kAny || ONLY == BIN_WAVE) && role == BIN_WAVE) {
     MoveAgg* agg = reinterpret_cast<MoveAgg*>(smem);
     int32_t* keys = reinterpret_cast<int32_t*>(smem + sizeof(MoveAgg));
     int32_t* vals = keys + (kBlock / kWave) * TS;
     agg_begin(agg);
     role_wave<TS>(D, two_m, bins.list[BIN_WAVE], rb, nb, keys, vals, agg);
     agg_end(agg, D.Sigma, D.size);
-  } else if (role == BIN_BLOCK) {
+  } else if ((kAny || ONLY == BIN_BLOCK) && role == BIN_BLOCK) {
     Red* red = reinterpret_cast<Red*>(smem);
     int32_t* keys = reinterpret_cast<int32_t*>(smem + sizeof(Red));
     agg_begin(&red->agg);
     role_block(D, two_m, bins.list[BIN_BLOCK], rb, nb, keys, keys + kBlockTS, red);
     agg_end(&red->agg, D.Sigma, D.size);
-  } else {
+  } else if (kAny || ONLY == BIN_HUB) {
     Red* red = reinterpret_cast<Red*>(smem);
     int32_t* tk = reinterpret_cast<int32_t*>(smem + sizeof(Red));
     role_hub_insert(D, H, rb, nb, tk, tk + kHubTS, red);
@@ -971,7 +1025,7 @@ __global__ void __launch_bounds__(kBlock) k_move_all(Dev D, Bins bins, Roles R, 
 __global__ void __launch_bounds__(kBlock) k_hub_clear(Dev D, const int32_t* __restrict__ list,
                                                      const int64_t* __restrict__ hub_off,
                                                      const int32_t* __restrict__ c_b, const int64_t* __restrict__ c_s,
-                                                     int32_t* __restrict__ keys, int32_t* __restrict__ vals,
+                                                     unsigned long long* __restrict__ tab,
                                                      int64_t* __restrict__ hub_kid, int64_t pool_slots) {
   const int64_t count = D.rc[RC_HUB_CUNITS];
   for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
@@ -981,10 +1035,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_clear(Dev D, const int32_t* __re
     if (off + tsz > pool_slots) continue;  // reported by the insert role
     if (c_s[u] == 0 && threadIdx.x == 0) hub_kid[h] = 0;
     const int64_t s1 = min(tsz, c_s[u] + kHubClearSlots);
-    for (int64_t s = c_s[u] + threadIdx.x; s < s1; s += kBlock) {
-      keys[off + s] = -1;
-      vals[off + s] = 0;
-    }
+    for (int64_t s = c_s[u] + threadIdx.x; s < s1; s += kBlock) tab[off + s] = kEmptyPair;
   }
 }
 
@@ -996,8 +1047,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_decide(Dev D, const int32_t* __r
                                                       const int64_t* __restrict__ hub_off,
                                                       const int32_t* __restrict__ c_b,
                                                       const int64_t* __restrict__ c_s,
-                                                      const int32_t* __restrict__ keys,
-                                                      const int32_t* __restrict__ vals,
+                                                      const unsigned long long* __restrict__ tab,
                                                       const int64_t* __restrict__ hub_kid,
                                                       int64_t* __restrict__ unit_g, int32_t* __restrict__ unit_c,
                                                       int64_t pool_slots) {
@@ -1025,8 +1075,9 @@ __global__ void __launch_bounds__(kBlock) k_hub_decide(Dev D, const int32_t* __r
 #pragma unroll
       for (int q = 0; q < V; ++q) {
         const int64_t t = c_s[u] + threadIdx.x + q * kBlock;
-        cc[q] = t < s1 ? keys[off + t] : -1;
-        vv[q] = t < s1 ? vals[off + t] : 0;
+        const unsigned long long e = t < s1 ? tab[off + t] : kEmptyPair;
+        cc[q] = static_cast<int32_t>(e >> 32);
+        vv[q] = static_cast<int32_t>(static_cast<uint32_t>(e));
       }
 #pragma unroll
       for (int q = 0; q < V; ++q) sg[q] = cc[q] >= 0 ? D.Sigma[cc[q]] : 0;
@@ -1235,8 +1286,33 @@ int grid_by_est(int64_t est, int64_t items_per_block, int max_blocks) {
 
 template <int TS>
 void launch_move_all(const Dev& D, const Bins& b, const Roles& R, const HubIn& H, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL(k_move_all<TS>, dim3(static_cast<unsigned>(R.end[NBINS - 1])), dim3(kBlock), lds, st, D, b, R,
+  hipLaunchKernelGGL((k_move_all<TS, NBINS>), dim3(static_cast<unsigned>(R.end[NBINS - 1])), dim3(kBlock), lds, st,
+                     D, b, R, H);
+}
+
+// One role over its own grid, capped at the workgroups the device holds at
+// once (a grid-stride loop on a larger grid leaves a tail of late
+// workgroups behind the resident ones).
+template <int TS, int ONLY>
+void launch_role(const Dev& D, const Bins& b, const HubIn& H, size_t lds, int64_t grid, hipStream_t st) {
+  const auto fn = k_move_all<TS, ONLY>;
+  grid = std::min<int64_t>(grid, resident_blocks(reinterpret_cast<const void*>(fn), kBlock, lds));
+  Roles R{};
+  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(std::max<int64_t>(grid, 1))), dim3(kBlock), lds, st, D, b, R,
                      H);
+}
+
+template <int TS>
+void launch_one_role(int role, const Dev& D, const Bins& b, const HubIn& H, int64_t grid, hipStream_t st) {
+  switch (role) {
+    case BIN_G4: launch_role<128, BIN_G4>(D, b, H, sizeof(MoveAgg), grid, st); break;
+    case BIN_G8: launch_role<128, BIN_G8>(D, b, H, sizeof(MoveAgg), grid, st); break;
+    case BIN_G16: launch_role<128, BIN_G16>(D, b, H, sizeof(MoveAgg), grid, st); break;
+    case BIN_G32: launch_role<128, BIN_G32>(D, b, H, sizeof(MoveAgg), grid, st); break;
+    case BIN_WAVE: launch_role<TS, BIN_WAVE>(D, b, H, lds_wave<TS>(), grid, st); break;
+    case BIN_BLOCK: launch_role<128, BIN_BLOCK>(D, b, H, lds_table(), grid, st); break;
+    default: launch_role<128, BIN_HUB>(D, b, H, lds_table(), grid, st); break;
+  }
 }
 
 }  // namespace
@@ -1278,7 +1354,7 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
   if (hubs) {
     timer_begin(LV_TIME_HUB_CLEAR, st);
     hipLaunchKernelGGL(k_hub_clear, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off, ws.u_emit_b,
-                       ws.u_emit_s, ws.pool_keys, ws.pool_vals, ws.hub_kid, ws.pool_slots);
+                       ws.u_emit_s, reinterpret_cast<unsigned long long*>(ws.pool_pairs), ws.hub_kid, ws.pool_slots);
     timer_end(LV_TIME_HUB_CLEAR, st);
   }
 
@@ -1290,21 +1366,19 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
   const int ts = table_slots_for(a.wave_max);
   const size_t lw = ts <= 128 ? lds_wave<128>() : ts <= 256 ? lds_wave<256>() : ts <= 512 ? lds_wave<512>()
                                                                                         : lds_wave<1024>();
-  const HubIn H{ws.bins[BIN_HUB], ws.hub_off, ws.u_ins_b, ws.u_ins_a, ws.pool_keys, ws.pool_vals, ws.hub_kid,
-                ws.pool_slots};
+  const HubIn H{ws.bins[BIN_HUB], ws.hub_off, ws.u_ins_b, ws.u_ins_a,
+                reinterpret_cast<unsigned long long*>(ws.pool_pairs), ws.hub_kid, ws.pool_slots};
   const bool fuse = a.sparse && a.est <= tu.fuse_max_frontier;
-  for (int first = 0; first < NBINS; ++first) {
-    const uint32_t m = fuse ? bin_mask : (bin_mask & (1u << first));
-    if (!m) continue;
+  if (fuse) {
     Roles R;
     int64_t end = 0;
     for (int k = 0; k < NBINS; ++k) {
-      if (m & (1u << k)) end += per[k];
+      if (bin_mask & (1u << k)) end += per[k];
       R.end[k] = end;
     }
     size_t lds = sizeof(MoveAgg);
-    if (m & (1u << BIN_WAVE)) lds = std::max(lds, lw);
-    if (m & ((1u << BIN_BLOCK) | (1u << BIN_HUB))) lds = std::max(lds, lds_table());
+    if (bin_mask & (1u << BIN_WAVE)) lds = std::max(lds, lw);
+    if (bin_mask & ((1u << BIN_BLOCK) | (1u << BIN_HUB))) lds = std::max(lds, lds_table());
     timer_begin(LV_TIME_SCAN, st);
     if (ts <= 128)
       launch_move_all<128>(D, b, R, H, lds, st);
@@ -1315,12 +1389,26 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
     else
       launch_move_all<1024>(D, b, R, H, lds, st);
     timer_end(LV_TIME_SCAN, st);
-    if (fuse) break;
+  } else {
+    for (int k = 0; k < NBINS; ++k) {
+      if (!(bin_mask & (1u << k))) continue;
+      timer_begin(LV_TIME_SCAN, st);
+      if (ts <= 128)
+        launch_one_role<128>(k, D, b, H, per[k], st);
+      else if (ts <= 256)
+        launch_one_role<256>(k, D, b, H, per[k], st);
+      else if (ts <= 512)
+        launch_one_role<512>(k, D, b, H, per[k], st);
+      else
+        launch_one_role<1024>(k, D, b, H, per[k], st);
+      timer_end(LV_TIME_SCAN, st);
+    }
   }
   if (hubs) {
     timer_begin(LV_TIME_HUB_DECIDE, st);
     hipLaunchKernelGGL(k_hub_decide, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off, ws.u_emit_b,
-                       ws.u_emit_s, ws.pool_keys, ws.pool_vals, ws.hub_kid, ws.unit_g, ws.unit_c, ws.pool_slots);
+                       ws.u_emit_s, reinterpret_cast<const unsigned long long*>(ws.pool_pairs), ws.hub_kid, ws.unit_g,
+                       ws.unit_c, ws.pool_slots);
     timer_end(LV_TIME_HUB_DECIDE, st);
     hipLaunchKernelGGL(k_hub_final, dim3(64), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_cbase, ws.hub_cnum,
                        ws.unit_g, ws.unit_c, ws.hub_moved);
