@@ -256,7 +256,9 @@ lv_status modularity(const lv_graph* g, const int32_t* C, double* q_host, void* 
  * the DF frontier and runs the local-moving iterations of pass 0.  A graph
  * whose pass 0 needs more than one iteration (so Alg. 4 aggregates and
  * goes on) continues on the single-graph path afterwards, as does an item
- * outside the kernel's limits (rows longer than 2048 arcs after its batch).
+ * outside the kernel's limits (rows longer than 2048 arcs after its batch,
+ * or a batch of more than LV_MANY_MAX_UPDATES updates, whose frontier is
+ * too large for one workgroup).
  * Results are those of apply_batch + louvain_df on each graph alone
  * (bit-exact in LV_SYNC mode).
  *
@@ -278,6 +280,8 @@ lv_status modularity(const lv_graph* g, const int32_t* C, double* q_host, void* 
  * Returns LV_OK unless a HIP call failed or an argument is invalid.
  * Synchronises `stream`.  Items must name distinct graphs.
  */
+#define LV_MANY_MAX_UPDATES 4096
+
 typedef struct {
   lv_graph g;
   lv_state state;

@@ -835,7 +835,9 @@ lv_status louvain_df_many(const lv_item* items, int32_t count, const lv_params* 
     m.ni = static_cast<int32_t>(x.ins.count);
     m.scratch = x.scratch;
     // outside the kernel's limits: the single-graph path takes it
-    if (x.del.count + x.ins.count > x.max_updates || x.max_updates <= 0 || x.g.n <= 0) m.status = LV_ETOOLARGE;
+    if (x.del.count + x.ins.count > x.max_updates || x.del.count + x.ins.count > LV_MANY_MAX_UPDATES ||
+        x.max_updates <= 0 || x.g.n <= 0)
+      m.status = LV_ETOOLARGE;
   }
   ManyItem* d = static_cast<ManyItem*>(desc);
   LV_HIP(hipMemcpyAsync(d, h.data(), sizeof(ManyItem) * h.size(), hipMemcpyHostToDevice, st));

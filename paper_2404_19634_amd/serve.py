@@ -111,6 +111,14 @@ class GraphStore:
         self.evictions += 1
         return True
 
+    def grow(self, r: Resident, slack_frac: float, slack_min: int) -> None:
+        """Lays a resident graph out again with more slack per row."""
+        before = r.nbytes
+        r.graph = r.graph.relayout(slack_frac=slack_frac, slack_min=slack_min)
+        r.graph._ws = None  # the relayout workspace is not kept
+        with self.lock:
+            self.resident_bytes += r.nbytes - before
+
     def acquire(self, gids) -> list:
         """Marks the graphs busy and makes them resident.  Called with the
         store lock held by the caller's scheduling step."""
@@ -219,6 +227,24 @@ class Server:
                                                     [x.state for x in residents], [x.scratch for x in residents],
                                                     self.store.max_updates, prm=self.params, ws=ws, desc=desc,
                                                     stream=stream)
+                # a batch that does not fit its rows' slack left the graph as
+                # it was: lay the graph out again with more slack and rerun
+                for attempt in range(3):
+                    redo = [j for j, st in enumerate(status) if st == lib.LV_ENOSLACK]
+                    if not redo:
+                        break
+                    for j in redo:
+                        self.store.grow(residents[j], 0.5 * 2 ** attempt, 16 << attempt)
+                    big = max((residents[j] for j in redo), key=lambda x: x.graph.n * 4 + x.graph.cap)
+                    need = int(lib.load().lv_workspace_bytes(big.graph.n, big.graph.cap))
+                    if ws.numel() < need:
+                        ws = torch.empty(need, dtype=torch.uint8, device=self.store.device)
+                    st2, sts2 = lib.louvain_df_many([residents[j].graph for j in redo], [batches[j] for j in redo],
+                                                    [residents[j].state for j in redo],
+                                                    [residents[j].scratch for j in redo], self.store.max_updates,
+                                                    prm=self.params, ws=ws, desc=desc, stream=stream)
+                    for j, a, b in zip(redo, st2, sts2):
+                        status[j], stats[j] = a, b
             t1 = time.perf_counter()
             with self.cv:
                 self.launches += 1

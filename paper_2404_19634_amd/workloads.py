@@ -28,8 +28,8 @@ import numpy as np
 __all__ = [
     "Edges", "Batch", "sbm", "config1_sbm", "rmat", "config2_rmat",
     "random_batch", "batch_size", "two_cliques_bridge", "ring_of_cliques",
-    "random_small_graph", "apply_batch_np", "chung_lu", "pa_temporal_stream",
-    "multi_sbm_specs",
+    "random_small_graph", "apply_batch_np", "chung_lu", "config3_chung_lu", "pa_temporal_stream",
+    "temporal_workload", "config4_temporal", "multi_sbm_specs",
 ]
 
 
@@ -355,88 +355,153 @@ def random_small_graph(n: int, m: int, seed: int, max_w: int = 1) -> Edges:
 # Larger configurations (power-law, temporal, many graphs)
 # ---------------------------------------------------------------------------
 
-def chung_lu(n: int, gamma: float, mean_degree: float, seed: int,
-             m_target: int | None = None, chunk: int = 1 << 24) -> Edges:
+def chung_lu(n: int, gamma: float, mean_degree: float, seed: int, m_target: int | None = None,
+             device: str = "cpu", chunk: int = 1 << 26) -> Edges:
     """Chung-Lu power-law graph: expected weights w_i ~ (i+1)^(-1/(gamma-1)),
     capped at sqrt(sum w) and rescaled so their mean is ``mean_degree``;
     endpoints drawn proportional to w, self pairs and repeats dropped until
-    ``m_target`` distinct edges (default n*mean_degree/2); unit weights."""
-    rng = np.random.default_rng(seed)
+    ``m_target`` distinct edges (default n*mean_degree/2); unit weights.
+
+    The draws run in torch on ``device`` (seeded generator), so the
+    hundreds of millions of draws of the 20M-vertex configuration take
+    seconds on a GPU; the edge list comes back as numpy arrays."""
+    import torch
     expo = -1.0 / (gamma - 1.0)
     base = np.power(np.arange(1, n + 1, dtype=np.float64), expo)
+    total = base.sum()
 
-    def weights(scale):
-        wv = base * scale
-        cap = math.sqrt(wv.sum())
-        return np.minimum(wv, cap)
+    def mean_at(scale):
+        return np.minimum(base * scale, math.sqrt(total * scale)).mean()
 
     lo, hi = 1e-6, 1e6
-    for _ in range(200):   # bisection on the scale so that mean(w) hits the target
+    for _ in range(80):   # bisection on the scale so that mean(w) hits the target
         mid = math.sqrt(lo * hi)
-        if weights(mid).mean() < mean_degree:
+        if mean_at(mid) < mean_degree:
             lo = mid
         else:
             hi = mid
-    wv = weights(hi)
+    wv = np.minimum(base * hi, math.sqrt(total * hi))
     cdf = np.cumsum(wv)
     cdf /= cdf[-1]
+    dev = torch.device(device)
+    tcdf = torch.from_numpy(cdf).to(dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed))
     m_target = int(m_target if m_target is not None else round(n * mean_degree / 2))
-    got = np.zeros(0, dtype=np.int64)
-    while got.shape[0] < m_target:
-        need = m_target - got.shape[0]
-        cnt = min(chunk, int(need * 1.15) + 1024)
-        a = np.searchsorted(cdf, rng.random(cnt), side="right").astype(np.int64)
-        b = np.searchsorted(cdf, rng.random(cnt), side="right").astype(np.int64)
-        a = np.minimum(a, n - 1)
-        b = np.minimum(b, n - 1)
-        ok = a != b
-        key = np.minimum(a[ok], b[ok]) * n + np.maximum(a[ok], b[ok])
-        got = np.unique(np.concatenate([got, key]))
-    if got.shape[0] > m_target:
-        keep = rng.choice(got.shape[0], m_target, replace=False)
-        got = np.sort(got[keep])
-    return _from_keys(got, n)
+    keys = torch.zeros(0, dtype=torch.int64, device=dev)
+    while keys.numel() < m_target:
+        need = m_target - keys.numel()
+        cnt = int(need * 1.15) + 1024
+        parts = [keys]
+        for off in range(0, cnt, chunk):
+            c = min(chunk, cnt - off)
+            a = torch.searchsorted(tcdf, torch.rand(c, generator=gen, device=dev, dtype=torch.float64), right=True)
+            b = torch.searchsorted(tcdf, torch.rand(c, generator=gen, device=dev, dtype=torch.float64), right=True)
+            a.clamp_(max=n - 1)
+            b.clamp_(max=n - 1)
+            ok = a != b
+            a, b = a[ok], b[ok]
+            parts.append(torch.minimum(a, b) * n + torch.maximum(a, b))
+            del a, b, ok
+        keys = torch.unique(torch.cat(parts))
+        del parts
+    if keys.numel() > m_target:
+        keep = torch.randperm(keys.numel(), generator=gen, device=dev)[:m_target]
+        keys = torch.sort(keys[keep]).values
+    u = (keys // n).to(torch.int32).cpu().numpy()
+    v = (keys % n).to(torch.int32).cpu().numpy()
+    return Edges(int(n), u, v, np.ones(u.shape[0], dtype=np.int32))
 
 
-def pa_temporal_stream(n: int, targets: int, seed: int):
-    """Preferential-attachment growth: vertex t (t >= targets+1) links to
-    ``targets`` distinct earlier vertices chosen with probability
-    proportional to degree+1.  Returns (u, v) int32 arrays of the edges in
-    creation order (the temporal order)."""
+def config3_chung_lu(device: str = "cpu") -> Edges:
+    """Chung-Lu, 20M vertices, degree exponent 2.1, mean degree 50."""
+    return chung_lu(20_000_000, 2.1, 50.0, 1237, device=device)
+
+
+def pa_temporal_stream(n: int, targets: int, seed: int, block: int = 1024):
+    """Preferential-attachment growth: every vertex t >= targets+1 links to
+    ``targets`` distinct earlier vertices, drawn with probability
+    proportional to degree + 1.  Vertices join in blocks of up to ``block``
+    (a quarter of the vertices so far while the graph is small); a block's
+    vertices draw from the degrees as they stood when the block began, and
+    each takes a uniform choice of ``targets`` among its distinct draws.
+    Returns (u, v) int32 arrays in creation order (the temporal order)."""
     rng = np.random.default_rng(seed)
     k = targets
     seed_n = k + 1
-    us, vs = [], []
-    # seed clique
     a, b = np.triu_indices(seed_n, 1)
-    us.append(b.astype(np.int64))
-    vs.append(a.astype(np.int64))
-    # endpoint pool: sampling uniformly from the arc list is degree-proportional;
-    # the +1 smoothing is an extra uniform draw over existing vertices.
-    pool = np.concatenate([a, b]).astype(np.int64)
-    pool_buf = np.zeros(2 * k * n + pool.shape[0], dtype=np.int64)
-    pool_buf[: pool.shape[0]] = pool
-    plen = pool.shape[0]
-    for t in range(seed_n, n):
-        chosen = set()
-        while len(chosen) < k:
-            need = k - len(chosen)
-            tot = plen + t
-            r = rng.integers(0, tot, 2 * need)
-            for x in r:
-                x = int(x)
-                c = int(pool_buf[x]) if x < plen else x - plen
-                if c != t:
-                    chosen.add(c)
-                    if len(chosen) == k:
-                        break
-        cs = np.fromiter(chosen, dtype=np.int64, count=k)
-        us.append(np.full(k, t, dtype=np.int64))
-        vs.append(cs)
-        pool_buf[plen:plen + k] = t
-        pool_buf[plen + k:plen + 2 * k] = cs
-        plen += 2 * k
+    us, vs = [b.astype(np.int64)], [a.astype(np.int64)]
+    # endpoint pool: a uniform draw from it is degree-proportional; the +1
+    # smoothing is a uniform draw over the existing vertices
+    pool = np.zeros(2 * k * n + 2 * a.shape[0], dtype=np.int64)
+    pool[: 2 * a.shape[0]] = np.concatenate([a, b])
+    plen = 2 * a.shape[0]
+    t = seed_n
+    R = 3 * k + 8
+    while t < n:
+        B = min(block, max(1, t // 4), n - t)
+        chosen = np.zeros((B, k), dtype=np.int64)
+        todo = np.arange(B)
+        while todo.shape[0]:
+            x = rng.integers(0, plen + t, (todo.shape[0], R))
+            cand = np.where(x < plen, pool[np.minimum(x, plen - 1)], x - plen)
+            srt = np.sort(cand, axis=1)
+            dup = np.zeros_like(srt, dtype=bool)
+            dup[:, 1:] = srt[:, 1:] == srt[:, :-1]
+            ok = (~dup).sum(axis=1) >= k
+            prio = rng.random(srt.shape)
+            prio[dup] = 2.0
+            pick = np.argsort(prio, axis=1)[:, :k]
+            rows = todo[ok]
+            chosen[rows] = np.take_along_axis(srt[ok], pick[ok], axis=1)
+            todo = todo[~ok]
+        src = np.repeat(np.arange(t, t + B, dtype=np.int64), k)
+        dst = chosen.reshape(-1)
+        us.append(src)
+        vs.append(dst)
+        pool[plen:plen + B * k] = src
+        pool[plen + B * k:plen + 2 * B * k] = dst
+        plen += 2 * B * k
+        t += B
     return _i32(np.concatenate(us)), _i32(np.concatenate(vs))
+
+
+def temporal_workload(n: int, targets: int, seed: int, initial_frac: float = 0.9, batches: int = 100,
+                      window: int | None = None):
+    """A temporal stream cut into an initial graph and consecutive batches.
+
+    The stream's first ``initial_frac`` of edges (in creation order) are the
+    prefix; the graph holds the ``window`` most recent edges of it (all of
+    it when ``window`` is None).  Batch j inserts the next slice of the
+    remaining edges and deletes the edges that drop out of the window.
+    Returns (initial Edges, list of Batch)."""
+    u, v = pa_temporal_stream(n, targets, seed)
+    E = u.shape[0]
+    t0 = int(round(initial_frac * E))
+    window = E if window is None else int(window)
+    lo = max(0, t0 - window)
+    a = np.minimum(u[lo:t0], v[lo:t0]).astype(np.int64)
+    b = np.maximum(u[lo:t0], v[lo:t0]).astype(np.int64)
+    order = np.argsort(a * n + b)
+    g = Edges(int(n), _i32(a[order]), _i32(b[order]), np.ones(t0 - lo, dtype=np.int32))
+    cuts = np.linspace(t0, E, batches + 1).round().astype(np.int64)
+    out = []
+    for j in range(batches):
+        s, e = int(cuts[j]), int(cuts[j + 1])
+        d0, d1 = max(0, s - window), max(0, e - window)
+        one = np.ones(e - s, dtype=np.int32)
+        out.append(Batch(_i32(u[d0:d1]), _i32(v[d0:d1]), np.ones(d1 - d0, dtype=np.int32),
+                         _i32(u[s:e]), _i32(v[s:e]), one))
+    return g, out
+
+
+def config4_temporal(scale: float = 1.0):
+    """Preferential-attachment stream grown to 2M vertices and 30M edges
+    (15 per new vertex); the first 90% form the initial graph, the rest
+    arrive as 100 batches under a sliding window of the 20M newest edges.
+    ``scale`` shrinks vertices and window together for small test cases."""
+    n = max(64, int(round(2_000_000 * scale)))
+    return temporal_workload(n, 15, 1238, window=int(round(20_000_000 * scale)))
 
 
 def multi_sbm_specs(count: int, seed: int, n_lo=1000, n_hi=200000, b_lo=20, b_hi=2000):

@@ -1,0 +1,240 @@
+"""Parity at the full sizes of the paper-shaped workloads, in the launch
+configuration the benchmark times (default tuning, CSR slack 0.1 / 8).
+
+* R-MAT scale 22 (4.2M vertices, 64M edges): a SYNC sweep from singletons
+  and a SYNC DF step after a batch are bit-exact with the sequential oracle
+  over every vertex; ASYNC static + DF over batches of 1e-7..1e-3 |E| keep
+  K, Sigma and the member counts exact and their modularity equal to the
+  oracle's value of the same memberships.
+* Chung-Lu, 20M vertices, mean degree 50 (500M edges, tens of thousands
+  of rows above 2048 arcs, the longest over 10^5): the SYNC sweep's decision of sampled vertices (every row above
+  the workgroup bin and a uniform sample) equals the oracle's decision
+  computed one vertex at a time; ASYNC static + DF at 1e-5 and 1e-4 |E|
+  keep the same invariants.
+* Temporal preferential-attachment stream (2M vertices, 30M edges, 100
+  sliding-window batches): SYNC DF on the first batches is bit-exact with
+  the oracle; the whole stream served by the request loop keeps the
+  invariants and reports per-batch latency.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2404_19634_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BENCH_SLACK = dict(slack_frac=0.1, slack_min=8)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2404_19634_amd import lib as L
+    L.load()
+    L.set_tuning()
+    return L
+
+
+def _degrees(e):
+    """K_i: the weighted degree (Section 3), from the edge list."""
+    w = e.w.astype(np.int64)
+    return np.bincount(e.u, weights=w, minlength=e.n).astype(np.int64) + \
+        np.bincount(e.v, weights=w, minlength=e.n).astype(np.int64)
+
+
+def _check_state(lib, g, st, K_ref, orc):
+    C, K, S = st.host()
+    n = C.shape[0]
+    assert C.min() >= 0 and C.max() < n
+    assert np.array_equal(K, K_ref)
+    assert np.array_equal(S, np.bincount(C, weights=K, minlength=n).astype(np.int64))
+    if st.size is not None:
+        assert np.array_equal(st.size.cpu().numpy(), np.bincount(C, minlength=n))
+    q = lib.modularity(g, st.C)
+    qo = orc.modularity(C)
+    assert abs(q - qo) <= 1e-12, (q, qo)
+    return q
+
+
+def _orc(e):
+    import oracle
+    return oracle.Graph.from_edges(e)
+
+
+def _after(e, b):
+    return W.apply_batch_np(e, b)
+
+
+def _apply(lib, g, b):
+    """apply_batch; a row without room for its insertions leaves the graph
+    unchanged (LV_ENOSLACK), which is then laid out with more slack."""
+    try:
+        lib.apply_batch(g, b)
+        return g
+    except lib.LouvainError as ex:
+        if ex.code != lib.LV_ENOSLACK:
+            raise
+    g = g.relayout(slack_frac=0.5, slack_min=16)
+    lib.apply_batch(g, b)
+    return g
+
+
+# ---------------------------------------------------------------------------
+# R-MAT scale 22
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def rmat22():
+    return W.config2_rmat()
+
+
+@pytest.mark.timeout(600)
+def test_rmat22_sync_sweep_and_df_bit_exact(lib, rmat22):
+    e = rmat22
+    print(f"R-MAT s22 n={e.n} m={e.m}", flush=True)
+    g = lib.Graph.from_edges(e, **BENCH_SLACK)
+    st, s = lib.louvain_static(g, mode="sync", max_iterations=1, max_passes=1)
+    orc = _orc(e)
+    C, K, S, so = orc.louvain("static", mode="sync", max_iterations=1, max_passes=1)
+    Cg, Kg, Sg = st.host()
+    assert np.array_equal(Cg, C) and np.array_equal(Kg, K) and np.array_equal(Sg, S)
+    assert s["iter_moves"] == so["iter_moves"] and s["iter_gain"] == so["iter_gain"]
+    for frac, seed in ((1e-5, 71), (1e-3, 72)):
+        b = W.random_batch(e, W.batch_size(frac, e.m), seed)
+        lib.apply_batch(g, lib.Batch.from_host(b))
+        assert orc.apply_batch(b) == 0
+        st, s = lib.louvain_df(g, lib.Batch.from_host(b), st, mode="sync", max_passes=1)
+        C, K, S, so = orc.louvain("df", batch=b, state=(C, K, S), mode="sync", max_passes=1)
+        Cg, Kg, Sg = st.host()
+        assert np.array_equal(Cg, C) and np.array_equal(Kg, K) and np.array_equal(Sg, S), frac
+        assert s["iterations"] == so["iterations"] and s["iter_gain"] == so["iter_gain"], frac
+        e = _after(e, b)
+
+
+@pytest.mark.timeout(600)
+def test_rmat22_async_bench_configuration(lib, rmat22):
+    e = rmat22
+    g = lib.Graph.from_edges(e, **BENCH_SLACK)
+    orc = _orc(e)
+    st, s = lib.louvain_static(g)
+    q0 = _check_state(lib, g, st, _degrees(e), orc)
+    print(f"static Q={q0:.6f} passes={s['passes']}", flush=True)
+    for k, frac in enumerate((1e-7, 1e-6, 1e-5, 1e-4, 1e-3)):
+        b = W.random_batch(e, W.batch_size(frac, e.m), 900 + k)
+        lib.apply_batch(g, lib.Batch.from_host(b))
+        assert orc.apply_batch(b) == 0
+        st, s = lib.louvain_df(g, lib.Batch.from_host(b), st)
+        e = _after(e, b)
+        q = _check_state(lib, g, st, _degrees(e), orc)
+        print(f"DF {b.size} updates: Q={q:.6f} iterations={s['iterations']}", flush=True)
+    # DF against static Louvain on the final graph (static ASYNC's own spread
+    # over runs is printed beside it)
+    qs = []
+    for r in range(3):
+        st2, _ = lib.louvain_static(g)
+        qs.append(_check_state(lib, g, st2, _degrees(e), orc))
+    print(f"final: DF Q={q:.6f}, static Q {min(qs):.6f}..{max(qs):.6f}", flush=True)
+    assert q >= min(qs) - 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Chung-Lu, 20M vertices, 500M edges
+# ---------------------------------------------------------------------------
+
+@pytest.mark.timeout(900)
+def test_chung_lu_20m_sampled_decisions_and_invariants(lib):
+    t0 = time.perf_counter()
+    e = W.config3_chung_lu(device="cuda")
+    torch.cuda.synchronize()
+    K_ref = _degrees(e)
+    print(f"Chung-Lu n={e.n} m={e.m} max degree {K_ref.max()} ({time.perf_counter() - t0:.1f} s)", flush=True)
+    g = lib.Graph.from_edges(e, **BENCH_SLACK)
+    # one SYNC sweep from singletons: each vertex's decision is a function of
+    # the singleton state, which the oracle evaluates vertex by vertex
+    st, _ = lib.louvain_static(g, mode="sync", max_iterations=1, max_passes=1)
+    C1 = st.C.cpu().numpy()
+    t1 = time.perf_counter()
+    orc = _orc(e)
+    print(f"oracle graph built in {time.perf_counter() - t1:.1f} s", flush=True)
+    rng = np.random.default_rng(5)
+    hubs = np.flatnonzero(K_ref > 2048)
+    verts = np.unique(np.concatenate([hubs, rng.choice(e.n, 20000, replace=False)])).astype(np.int32)
+    ids = np.arange(e.n, dtype=np.int32)
+    oc, og, om = orc.decide(ids, K_ref, K_ref.copy(), np.ones(e.n, np.int32), verts, guard=1)
+    want = np.where(om, oc, verts)
+    assert np.array_equal(C1[verts], want), int((C1[verts] != want).sum())
+    print(f"{verts.shape[0]} sampled decisions ({hubs.shape[0]} hub rows) match", flush=True)
+    # ASYNC, the benchmark's mode
+    st, s = lib.louvain_static(g)
+    q = _check_state(lib, g, st, K_ref, orc)
+    print(f"static Q={q:.6f} passes={s['passes']}", flush=True)
+    for k, frac in enumerate((1e-5, 1e-4)):
+        b = W.random_batch(e, W.batch_size(frac, e.m), 910 + k)
+        g = _apply(lib, g, lib.Batch.from_host(b))
+        assert orc.apply_batch(b) == 0
+        st, s = lib.louvain_df(g, lib.Batch.from_host(b), st)
+        e = _after(e, b)
+        q = _check_state(lib, g, st, _degrees(e), orc)
+        print(f"DF {b.size} updates: Q={q:.6f} iterations={s['iterations']}", flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Temporal stream through the request loop
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def temporal():
+    t0 = time.perf_counter()
+    g0, batches = W.config4_temporal()
+    print(f"temporal: n={g0.n} initial m={g0.m}, {len(batches)} batches of {batches[0].size} "
+          f"({time.perf_counter() - t0:.1f} s)", flush=True)
+    return g0, batches
+
+
+@pytest.mark.timeout(600)
+def test_temporal_sync_df_bit_exact(lib, temporal):
+    e, batches = temporal
+    g = lib.Graph.from_edges(e, **BENCH_SLACK)
+    orc = _orc(e)
+    st, _ = lib.louvain_static(g, mode="sync", max_iterations=1, max_passes=1)
+    C, K, S, _ = orc.louvain("static", mode="sync", max_iterations=1, max_passes=1)
+    for b in batches[:3]:
+        g = _apply(lib, g, lib.Batch.from_host(b))
+        assert orc.apply_batch(b) == 0
+        st, s = lib.louvain_df(g, lib.Batch.from_host(b), st, mode="sync", max_passes=1)
+        C, K, S, so = orc.louvain("df", batch=b, state=(C, K, S), mode="sync", max_passes=1)
+        Cg, Kg, Sg = st.host()
+        assert np.array_equal(Cg, C) and np.array_equal(Kg, K) and np.array_equal(Sg, S)
+        assert s["iter_gain"] == so["iter_gain"]
+
+
+@pytest.mark.timeout(600)
+def test_temporal_stream_served(lib, temporal):
+    from paper_2404_19634_amd import serve
+    e0, batches = temporal
+    store = serve.GraphStore(1 << 40, max_updates=max(b.size for b in batches), mode="async",
+                             **{"slack_frac": 0.1, "slack_min": 8})
+    store.add(0, e0)
+    with store.lock:
+        store.acquire([0])
+    store.release([0])
+    srv = serve.Server(store, slots=1, workers=1)
+    srv.start()
+    lat = []
+    try:
+        for k, b in enumerate(batches):
+            t = time.perf_counter()
+            srv.submit(0, b, t_arrival=t)
+            srv.wait(k + 1)
+            lat.append((srv.done[-1].t_done - t) * 1e3)
+    finally:
+        srv.close()
+    assert all(r.status == 0 for r in srv.done)
+    print(f"per-batch latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms", flush=True)
+    e = e0
+    for b in batches:
+        e = _after(e, b)
+    r = store.res[0]
+    _check_state(lib, r.graph, r.state, _degrees(e), _orc(e))
