@@ -310,12 +310,17 @@ def serve_bench(args):
     rng = np.random.default_rng(5)
     gaps = rng.exponential(1.0 / rate, len(data))
     order = rng.permutation(len(data))
-    t = time.perf_counter()
-    for gid, gap in zip(order, gaps):
-        t += gap
-        while time.perf_counter() < t:
-            pass
-        srv.submit(int(gid), data[int(gid)][2], t_arrival=t)
+    # arrivals at their scheduled times: whatever is due is submitted (with
+    # its scheduled time as arrival), then the submitter sleeps, so that it
+    # does not hold the interpreter lock the workers need
+    due = time.perf_counter() + np.cumsum(gaps)
+    k = 0
+    while k < len(order):
+        now = time.perf_counter()
+        while k < len(order) and due[k] <= now:
+            srv.submit(int(order[k]), data[int(order[k])][2], t_arrival=float(due[k]))
+            k += 1
+        time.sleep(2e-4)
     srv.wait(len(data))
     srv.close()
     poisson = srv.summary()

@@ -248,21 +248,46 @@ class Batch:
         return cls(Edges(z, z, z, device), Edges(z, z, z, device))
 
     @classmethod
-    def many_from_host(cls, batches, device="cuda"):
-        """Device copies of many host batches through one transfer (views
-        into a single device buffer)."""
+    def many_from_host(cls, batches, device="cuda", staging: Optional[torch.Tensor] = None):
+        """Device copies of many host batches through one transfer: every
+        array lands in one device buffer and each batch refers to its part
+        by address.  `staging`, a pinned int32 host tensor, is reused for
+        the transfer when large enough (the caller must not refill it
+        before the copy has completed, e.g. before the stream's next
+        synchronisation)."""
         parts = []
         for b in batches:
             parts += [b.del_u, b.del_v, b.del_w, b.ins_u, b.ins_v, b.ins_w]
-        sizes = [len(x) for x in parts]
-        flat = np.concatenate([np.asarray(x, np.int32) for x in parts]) if parts else np.zeros(0, np.int32)
-        dev = torch.from_numpy(flat).pin_memory().to(device, non_blocking=True)
-        views, o = [], 0
-        for k in sizes:
-            views.append(dev[o:o + k])
-            o += k
-        return [cls(Edges(*views[6 * j:6 * j + 3], device), Edges(*views[6 * j + 3:6 * j + 6], device))
-                for j in range(len(batches))]
+        sizes = np.fromiter((len(x) for x in parts), dtype=np.int64, count=len(parts))
+        total = int(sizes.sum())
+        if staging is None or staging.numel() < total:
+            staging = torch.empty(max(total, 1), dtype=torch.int32, pin_memory=True)
+        host = staging.numpy()[:total]
+        if parts:
+            np.concatenate([np.asarray(x, np.int32) for x in parts], out=host)
+        dev = torch.empty(max(total, 1), dtype=torch.int32, device=device)
+        dev[:total].copy_(staging[:total], non_blocking=True)
+        addr = dev.data_ptr() + 4 * (np.cumsum(sizes) - sizes)
+        out = []
+        for j in range(len(batches)):
+            a = addr[6 * j:6 * j + 6].tolist()
+            nd, ni = int(sizes[6 * j]), int(sizes[6 * j + 3])
+            out.append(cls(_EdgesAt(dev, a[0], a[1], a[2], nd), _EdgesAt(dev, a[3], a[4], a[5], ni)))
+        return out
+
+
+class _EdgesAt:
+    """An update list inside a shared device buffer (addresses only; the
+    buffer is kept alive by reference)."""
+    __slots__ = ("buf", "pu", "pv", "pw", "count")
+
+    def __init__(self, buf, pu, pv, pw, count):
+        self.buf, self.pu, self.pv, self.pw, self.count = buf, pu, pv, pw, count
+
+    def c(self) -> CEdges:
+        if self.count == 0:
+            return CEdges(None, None, None, 0)
+        return CEdges(self.pu, self.pv, self.pw, self.count)
 
 
 class Graph:
@@ -438,19 +463,80 @@ def louvain_df_many(graphs, batches, states, scratches, max_updates, prm=None, w
     count = len(graphs)
     prm = prm if prm is not None else params(**kw)
     caps = list(max_updates) if hasattr(max_updates, "__len__") else [int(max_updates)] * count
-    items = (CItem * max(count, 1))()
-    for k in range(count):
-        items[k] = CItem(graphs[k].c(), states[k].c(), batches[k].dels.c(), batches[k].ins.c(),
-                         scratches[k].data_ptr(), int(caps[k]))
+    items = np.zeros(max(count, 1), dtype=_item_dtype())
+    if count:
+        cols = [g.c() for g in graphs]
+        for f, _ in CGraph._fields_:
+            items["g." + f][:count] = [getattr(x, f) or 0 for x in cols]
+        cols = [x.c() for x in states]
+        for f, _ in CState._fields_:
+            items["state." + f][:count] = [getattr(x, f) or 0 for x in cols]
+        for side in ("dels", "ins"):
+            cols = [getattr(b, side).c() for b in batches]
+            for f, _ in CEdges._fields_:
+                items[side + "." + f][:count] = [getattr(x, f) or 0 for x in cols]
+        items["scratch"][:count] = [x.data_ptr() for x in scratches]
+        items["max_updates"][:count] = caps
     need = int(L.lv_many_desc_bytes(count))
     if desc is None or desc.numel() < need:
         desc = torch.empty(need, dtype=torch.uint8, device=graphs[0].device if count else "cuda")
-    status = (ct.c_int32 * max(count, 1))()
+    status = np.zeros(max(count, 1), dtype=np.int32)
     stats = (Stats * max(count, 1))()
     wp, wb = (ct.c_void_p(ws.data_ptr()), ws.numel()) if ws is not None else (None, 0)
-    _check(L.louvain_df_many(items, count, ct.byref(prm), ct.c_void_p(desc.data_ptr()), desc.numel(), wp, wb,
-                             status, stats, _stream(stream)))
-    return [int(status[k]) for k in range(count)], [stats[k].as_dict() for k in range(count)]
+    _check(L.louvain_df_many(items.ctypes.data_as(ct.POINTER(CItem)), count, ct.byref(prm),
+                             ct.c_void_p(desc.data_ptr()), desc.numel(), wp, wb,
+                             status.ctypes.data_as(ct.POINTER(ct.c_int32)), stats, _stream(stream)))
+    return status[:count].tolist(), StatsList(stats, count)
+
+
+class StatsList:
+    """Per-item statistics of louvain_df_many, converted to dicts when read."""
+
+    def __init__(self, arr, count):
+        self._a, self._n, self._d = arr, count, {}
+
+    def __len__(self):
+        return self._n
+
+    def __getitem__(self, k):
+        if isinstance(k, slice):
+            return [self[j] for j in range(*k.indices(self._n))]
+        if k < 0:
+            k += self._n
+        if not 0 <= k < self._n:
+            raise IndexError(k)
+        if k not in self._d:
+            self._d[k] = self._a[k].as_dict()
+        return self._d[k]
+
+    def __iter__(self):
+        return (self[k] for k in range(self._n))
+
+
+_ITEM_DTYPE = None
+
+
+def _item_dtype() -> np.dtype:
+    """numpy layout of lv_item (field offsets taken from the ctypes
+    declaration, so the two cannot drift apart)."""
+    global _ITEM_DTYPE
+    if _ITEM_DTYPE is None:
+        kinds = {ct.c_int32: np.int32, ct.c_int64: np.int64, ct.c_void_p: np.uint64}
+        names, fmts, offs = [], [], []
+
+        def walk(t, base, prefix):
+            for f, ft in t._fields_:
+                off = base + getattr(t, f).offset
+                if isinstance(ft, type) and issubclass(ft, ct.Structure):
+                    walk(ft, off, prefix + f + ".")
+                else:
+                    names.append(prefix + f)
+                    fmts.append(kinds[ft])
+                    offs.append(off)
+
+        walk(CItem, 0, "")
+        _ITEM_DTYPE = np.dtype({"names": names, "formats": fmts, "offsets": offs, "itemsize": ct.sizeof(CItem)})
+    return _ITEM_DTYPE
 
 
 def modularity(g: Graph, C: torch.Tensor, stream=None) -> float:

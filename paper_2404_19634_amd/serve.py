@@ -20,7 +20,7 @@ from __future__ import annotations
 import collections
 import threading
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 import torch
@@ -37,7 +37,11 @@ class Request:
     t_start: float = 0.0
     t_done: float = 0.0
     status: int = 1        # 1 pending, else the library status
-    stats: dict = field(default_factory=dict)
+    src: tuple = ()        # (per-launch statistics list, index): read on demand
+
+    @property
+    def stats(self) -> dict:
+        return self.src[0][self.src[1]] if self.src else {}
 
 
 class Resident:
@@ -64,11 +68,14 @@ class GraphStore:
     admission would exceed the budget."""
 
     def __init__(self, budget_bytes: int, max_updates: int, device="cuda", mode="async", slack_frac=0.5,
-                 slack_min=16):
+                 slack_min=16, init_mode=None):
         self.budget = int(budget_bytes)
         self.max_updates = int(max_updates)
         self.device = torch.device(device)
         self.mode = mode
+        # mode of the static Louvain run that gives an admitted graph its
+        # first state (SYNC makes it reproducible run to run)
+        self.init_mode = init_mode or mode
         self.slack = (slack_frac, slack_min)
         self.edges = {}        # gid -> workloads.Edges (never-admitted graphs)
         self.host = {}         # gid -> evicted device arrays, on the host
@@ -92,7 +99,7 @@ class GraphStore:
         else:
             e = self.edges[gid]
             g = lib.Graph.from_edges(e, slack_frac=self.slack[0], slack_min=self.slack[1], device=self.device)
-            st, _ = lib.louvain_static(g, mode=self.mode)
+            st, _ = lib.louvain_static(g, mode=self.init_mode)
             g._ws = None  # the build workspace is not kept; louvain_df_many needs none per graph
         scratch = lib.many_scratch(g.n, self.max_updates, self.device)
         return Resident(g, st, scratch)
@@ -204,6 +211,7 @@ class Server:
         desc = torch.empty(int(lib.load().lv_many_desc_bytes(self.slots)), dtype=torch.uint8,
                            device=self.store.device)
         ws = None
+        staging = None  # pinned host buffer of the batches' transfer
         while True:
             with self.cv:
                 while not self.queue and not self.closed:
@@ -218,7 +226,10 @@ class Server:
                     residents = self.store.acquire([r.gid for r in picked])
             t0 = time.perf_counter()
             with torch.cuda.stream(stream):
-                batches = lib.Batch.many_from_host([r.batch for r in picked], self.store.device)
+                need_i32 = sum(r.batch.size * 3 for r in picked)
+                if staging is None or staging.numel() < need_i32:
+                    staging = torch.empty(max(need_i32, 1 << 16) * 2, dtype=torch.int32, pin_memory=True)
+                batches = lib.Batch.many_from_host([r.batch for r in picked], self.store.device, staging)
                 big = max(residents, key=lambda x: x.graph.n * 4 + x.graph.cap)
                 need = int(lib.load().lv_workspace_bytes(big.graph.n, big.graph.cap))
                 if ws is None or ws.numel() < need:
@@ -227,6 +238,7 @@ class Server:
                                                     [x.state for x in residents], [x.scratch for x in residents],
                                                     self.store.max_updates, prm=self.params, ws=ws, desc=desc,
                                                     stream=stream)
+                src = [(stats, j) for j in range(len(picked))]
                 # a batch that does not fit its rows' slack left the graph as
                 # it was: lay the graph out again with more slack and rerun
                 for attempt in range(3):
@@ -243,13 +255,13 @@ class Server:
                                                     [residents[j].state for j in redo],
                                                     [residents[j].scratch for j in redo], self.store.max_updates,
                                                     prm=self.params, ws=ws, desc=desc, stream=stream)
-                    for j, a, b in zip(redo, st2, sts2):
-                        status[j], stats[j] = a, b
+                    for q, (j, a) in enumerate(zip(redo, st2)):
+                        status[j], src[j] = a, (sts2, q)
             t1 = time.perf_counter()
             with self.cv:
                 self.launches += 1
-                for r, s, st in zip(picked, status, stats):
-                    r.t_start, r.t_done, r.status, r.stats = t0, t1, s, st
+                for r, s, sr in zip(picked, status, src):
+                    r.t_start, r.t_done, r.status, r.src = t0, t1, s, sr
                     self.done.append(r)
                 self.store.release([r.gid for r in picked])
                 self.cv.notify_all()
