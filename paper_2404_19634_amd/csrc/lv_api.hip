@@ -221,6 +221,10 @@ enum Approach { A_STATIC, A_ND, A_DS, A_DF };
 //    low-degree vertices that hang off them;
 //  - order 0 / 1: 2^k rounds by id hash / by contiguous id ranges;
 //  - super-vertex levels (dense): 2^min(k, 4) rounds by id hash.
+// Aggregated levels up to this many vertices take the full 2^k ASYNC rounds,
+// each in one fused launch.
+constexpr int32_t kSmallLevel = 4096;
+
 std::vector<SubRound> sub_rounds(int32_t mode, int32_t pass, int64_t est_frontier, int32_t n, const lv_tuning& tu) {
   std::vector<SubRound> out;
   SubRound all;
@@ -242,7 +246,10 @@ std::vector<SubRound> sub_rounds(int32_t mode, int32_t pass, int64_t est_frontie
     return out;
   }
   if (pass > 0 || tu.async_round_order == 0 || (tu.async_round_order == 2 && k < 2)) {
-    const int kk = pass > 0 ? std::min(k, 4) : k;
+    // aggregated levels: 16 rounds, or 2^k when the level is small (its
+    // super-vertices are densely linked, and few per round keep a move from
+    // acting on totals that a neighbour's move in the same round changed)
+    const int kk = pass > 0 ? (n <= kSmallLevel ? k : std::min(k, 4)) : k;
     for (int r = 0; r < (1 << kk); ++r) {
       SubRound s = all;
       s.hash_round = static_cast<uint32_t>(r);
@@ -474,7 +481,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
       // a sub-round holds at most about 4 / rounds of the frontier (four
       // degree classes); grids are sized for that
       a.est = std::max<int64_t>(64, est_frontier * 4 / static_cast<int64_t>(plan.size()));
-      a.sparse = est_frontier * 8 <= L.n ? 1 : 0;
+      a.sparse = (est_frontier * 8 <= L.n || (pass > 0 && L.n <= kSmallLevel)) ? 1 : 0;
       for (size_t r = 0; r < plan.size(); ++r, ++round_seq) {
         a.rc = ws.ctr + CTR_ROUND0 + (round_seq & 1) * kRoundSet;
         a.rc_next = ws.ctr + CTR_ROUND0 + ((round_seq + 1) & 1) * kRoundSet;
@@ -624,7 +631,9 @@ size_t carve_workspace(Workspace& ws, void* base, int32_t n, int64_t cap) {
   ws.u_emit_s = take<int64_t>(cur, total, base, static_cast<size_t>(ws.units_max));
   ws.unit_g = take<int64_t>(cur, total, base, static_cast<size_t>(ws.units_max));
   ws.unit_c = take<int32_t>(cur, total, base, static_cast<size_t>(ws.units_max));
-  ws.pool_slots = 2 * static_cast<int64_t>(ucap) + 4096;
+  // hub tables take 2 slots per arc; rows that aggregate by segment add
+  // their segment offsets, under 1/16 slot per arc
+  ws.pool_slots = 2 * static_cast<int64_t>(ucap) + static_cast<int64_t>(ucap) / 16 + 4096;
   ws.pool_pairs = take<uint64_t>(cur, total, base, static_cast<size_t>(ws.pool_slots));
   ws.pool_keys = reinterpret_cast<int32_t*>(ws.pool_pairs);
   ws.pool_vals = base ? ws.pool_keys + ws.pool_slots : nullptr;

@@ -394,7 +394,8 @@ struct MoveArgs {
   int64_t* sc;            // this iteration's statistics set
   int64_t* sc_next;       // the other set; zeroed by the first round's binning when non-null
   int32_t clear_cur;      // 1: binning clears the current frontier as it reads it (last round)
-  int32_t sparse;         // 1: the frontier bound is a small share of the level's vertices
+  int32_t sparse;         // 1: the scan may run as one fused launch (a frontier bound that is a small
+                          // share of the level's vertices, or a small aggregated level)
   int64_t est;            // upper bound of the vertices processed (grid sizes)
   int32_t mode;
   int32_t guard;

@@ -262,6 +262,24 @@ __device__ __forceinline__ int64_t hub_cunits(int32_t deg) {
   return (2 * static_cast<int64_t>(deg) + kHubClearSlots - 1) / kHubClearSlots;
 }
 
+// Hub rows up to kHubPartMaxDeg arcs aggregate by segment: each insert unit
+// sums its arcs per community in LDS and writes the (community, weight)
+// pairs grouped by segment (a hash range of community ids, one per decide
+// unit); each decide unit then sums its segment's pairs from every insert
+// unit in LDS.  Plain stores replace the global hashtable's atomics.
+// Longer rows use the global table.  A partitioned row's pool reservation
+// holds its pairs (unit u at slot u * kHubUnitArcs) and, after 2 * deg
+// slots, the segment offsets of every unit (hub_cunits + 1 int32 each).
+constexpr int32_t kHubPartMaxDeg = 1 << 18;
+constexpr int kHubMaxSegs = (2 * kHubPartMaxDeg + kHubClearSlots - 1) / kHubClearSlots;
+constexpr int kHubMaxUnits = (kHubPartMaxDeg + kHubUnitArcs - 1) / kHubUnitArcs;
+
+__device__ __forceinline__ bool hub_part(int32_t deg) { return deg <= kHubPartMaxDeg; }
+__device__ __forceinline__ int64_t hub_slots(int32_t deg) {
+  const int64_t base = 2 * static_cast<int64_t>(deg);
+  return hub_part(deg) ? base + (hub_units(deg) * (hub_cunits(deg) + 1) + 1) / 2 : base;
+}
+
 // Writes a hub row's table offset and unit descriptors at the given bases.
 __device__ __forceinline__ void hub_write(const HubOut& H, int64_t pos, int32_t deg, int64_t off, int64_t bu,
                                          int64_t bc) {
@@ -283,7 +301,7 @@ __device__ __forceinline__ void hub_write(const HubOut& H, int64_t pos, int32_t 
 // (three device atomics).
 __device__ __forceinline__ void hub_setup(const HubOut& H, int64_t pos, int32_t deg, int64_t* rc) {
   const int64_t off = static_cast<int64_t>(
-      atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_POOL]), 2ull * static_cast<unsigned long long>(deg)));
+      atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_POOL]), static_cast<unsigned long long>(hub_slots(deg))));
   const int64_t bu = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_HUB_UNITS]),
                                                     static_cast<unsigned long long>(hub_units(deg))));
   const int64_t bc = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_HUB_CUNITS]),
@@ -437,7 +455,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(uint32_t* __restrict__ 
       if (threadIdx.x == 0) {
         int64_t slots = 0, nu = 0, nc = 0;
         for (int q = 0; q < nh; ++q) {
-          slots += 2 * static_cast<int64_t>(s_hdeg[q]);
+          slots += hub_slots(s_hdeg[q]);
           nu += hub_units(s_hdeg[q]);
           nc += hub_cunits(s_hdeg[q]);
         }
@@ -452,7 +470,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(uint32_t* __restrict__ 
       if (threadIdx.x < nh) {
         int64_t off = s_hbase[0], bu = s_hbase[1], bc = s_hbase[2];
         for (int q = 0; q < static_cast<int>(threadIdx.x); ++q) {
-          off += 2 * static_cast<int64_t>(s_hdeg[q]);
+          off += hub_slots(s_hdeg[q]);
           bu += hub_units(s_hdeg[q]);
           bc += hub_cunits(s_hdeg[q]);
         }
@@ -860,7 +878,7 @@ struct HubIn {
 };
 
 __device__ __forceinline__ void role_hub_insert(const Dev& D, const HubIn& H, int64_t rb, int64_t nb, int32_t* tk,
-                                                int32_t* tv, Red* red) {
+                                                int32_t* tv, int32_t* hist, Red* red) {
   const int64_t count = D.rc[RC_HUB_UNITS];
   for (int64_t u = rb; u < count; u += nb) {
     const int32_t h = H.u_b[u];
@@ -869,8 +887,9 @@ __device__ __forceinline__ void role_hub_insert(const Dev& D, const HubIn& H, in
     const int32_t deg = D.row_len[i];
     const int32_t d = D.C[i];
     const uint32_t tsz = 2u * static_cast<uint32_t>(deg);
+    const bool part = hub_part(deg);
     const int64_t off = H.off[h];
-    if (off + static_cast<int64_t>(tsz) > H.pool_slots) {
+    if (off + hub_slots(deg) > H.pool_slots) {
       if (threadIdx.x == 0) set_error(D.ctr, LV_EWORKSPACE);
       continue;
     }
@@ -904,7 +923,9 @@ __device__ __forceinline__ void role_hub_insert(const Dev& D, const HubIn& H, in
       }
       uint32_t p = hash_slot(static_cast<uint32_t>(c), kHubTS);
       bool done = false;
-      for (int t = 0; t < kHubProbes; ++t) {
+      // a partitioned row's unit has at most kHubUnitArcs keys, half the
+      // table: probing always ends
+      for (int t = 0; t < (part ? kHubTS : kHubProbes); ++t) {
         const int32_t old = atomicCAS(&tk[p], -1, c);
         if (old == -1 || old == c) {
           atomicAdd(&tv[p], x);
@@ -917,6 +938,38 @@ __device__ __forceinline__ void role_hub_insert(const Dev& D, const HubIn& H, in
     }
     kid = block_total(kid, red->s);
     if (threadIdx.x == 0 && kid) atomic_add_i64(&H.kid[h], kid);
+    if (part) {
+      // the unit's pairs grouped by segment: a histogram, its prefix sums
+      // (stored as the unit's segment offsets), then the placement
+      const uint32_t ns = static_cast<uint32_t>(hub_cunits(deg));
+      const int64_t ui = a0 / kHubUnitArcs;
+      unsigned long long* pairs = tab + ui * kHubUnitArcs;
+      int32_t* segoff = reinterpret_cast<int32_t*>(tab + 2 * static_cast<int64_t>(deg)) + ui * (ns + 1);
+      for (uint32_t q = threadIdx.x; q <= ns; q += kBlock) hist[q] = 0;
+      __syncthreads();
+      for (int sl = threadIdx.x; sl < kHubTS; sl += kBlock)
+        if (tk[sl] >= 0) atomicAdd(&hist[hash_slot(static_cast<uint32_t>(tk[sl]), ns)], 1);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (uint32_t q = 0; q < ns; ++q) {
+          const int32_t c = hist[q];
+          hist[q] = run;
+          run += c;
+        }
+        hist[ns] = run;
+      }
+      __syncthreads();
+      for (uint32_t q = threadIdx.x; q <= ns; q += kBlock) segoff[q] = hist[q];
+      __syncthreads();
+      for (int sl = threadIdx.x; sl < kHubTS; sl += kBlock)
+        if (tk[sl] >= 0) {
+          const int32_t pos = atomicAdd(&hist[hash_slot(static_cast<uint32_t>(tk[sl]), ns)], 1);
+          pairs[pos] = pack_pair(tk[sl], tv[sl]);
+        }
+      __syncthreads();
+      continue;
+    }
     // Flush in rounds: every pending slot of the thread tries its current
     // table slot (the compare-and-swaps of a round are in flight
     // together); hits add their weight, collisions probe on.
@@ -968,7 +1021,9 @@ template <int TS>
 constexpr size_t lds_wave() {
   return sizeof(MoveAgg) + 2 * sizeof(int32_t) * (kBlock / kWave) * TS;
 }
-constexpr size_t lds_table() { return sizeof(Red) + 2 * sizeof(int32_t) * kBlockTS; }
+constexpr size_t lds_table() {
+  return sizeof(Red) + 2 * sizeof(int32_t) * kBlockTS + sizeof(int32_t) * (kHubMaxSegs + 1);
+}
 
 // ONLY == NBINS: the fused kernel, whose workgroups find their role from the
 // block ranges laid end to end.  ONLY < NBINS: that role alone over the
@@ -1015,7 +1070,7 @@ __global__ void __launch_bounds__(kBlock) k_move_all(Dev D, Bins bins, Roles R, 
   } else if (kAny || ONLY == BIN_HUB) {
     Red* red = reinterpret_cast<Red*>(smem);
     int32_t* tk = reinterpret_cast<int32_t*>(smem + sizeof(Red));
-    role_hub_insert(D, H, rb, nb, tk, tk + kHubTS, red);
+    role_hub_insert(D, H, rb, nb, tk, tk + kHubTS, tk + 2 * kHubTS, red);
   }
 }
 
@@ -1030,19 +1085,57 @@ __global__ void __launch_bounds__(kBlock) k_hub_clear(Dev D, const int32_t* __re
   const int64_t count = D.rc[RC_HUB_CUNITS];
   for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
     const int32_t h = c_b[u];
-    const int64_t tsz = 2 * static_cast<int64_t>(D.row_len[list[h]]);
+    const int32_t deg = D.row_len[list[h]];
+    const int64_t tsz = 2 * static_cast<int64_t>(deg);
     const int64_t off = hub_off[h];
-    if (off + tsz > pool_slots) continue;  // reported by the insert role
+    if (off + hub_slots(deg) > pool_slots) continue;  // reported by the insert role
     if (c_s[u] == 0 && threadIdx.x == 0) hub_kid[h] = 0;
+    if (hub_part(deg)) continue;  // no global table
     const int64_t s1 = min(tsz, c_s[u] + kHubClearSlots);
     for (int64_t s = c_s[u] + threadIdx.x; s < s1; s += kBlock) tab[off + s] = kEmptyPair;
   }
 }
 
-// One workgroup per unit of 4096 table slots publishes the unit's best
-// (gain, community).  (A completion count with a device-scope fence would
-// let the last unit decide, but on a multi-XCD part that fence writes back
-// the L2 and costs more than a launch.)
+// MurmurHash3's 32-bit finalizer: the decide units index their LDS tables
+// with it, independently of the multiplicative hash that chose the segment.
+__device__ __forceinline__ uint32_t mix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// Keys one pass of a decide unit holds in its 4096-slot table; the rest of
+// the table stays free for inserts in flight when the limit is reached.
+constexpr int kDecideMaxKeys = kHubTS - 2 * kBlock;
+
+// Best (gain, community) over table entries held by this thread.
+__device__ __forceinline__ void best_of(const Dev& D, int64_t two_m, int64_t kid, int64_t Ki, int64_t Sd,
+                                        const int32_t* cc, const int32_t* vv, int64_t& bg, int32_t& bc) {
+  int64_t sg[kDecideSlots];
+#pragma unroll
+  for (int q = 0; q < kDecideSlots; ++q) sg[q] = cc[q] >= 0 ? D.Sigma[cc[q]] : 0;
+#pragma unroll
+  for (int q = 0; q < kDecideSlots; ++q)
+    if (cc[q] >= 0) {
+      const int64_t g = gain_of(two_m, vv[q], kid, Ki, sg[q], Sd);
+      if (better(g, cc[q], bg, bc)) {
+        bg = g;
+        bc = cc[q];
+      }
+    }
+}
+
+// One workgroup per decide unit publishes the unit's best (gain,
+// community).  A unit of a partitioned row sums its segment's pairs from
+// every insert unit in an LDS table (in several passes over disjoint key
+// subsets if the segment holds more keys than one pass can); a unit of a
+// long row reads its 4096 slots of the global table.  (A completion count
+// with a device-scope fence would let the last unit decide, but on a
+// multi-XCD part that fence writes back the L2 and costs more than a
+// launch.)
 __global__ void __launch_bounds__(kBlock) k_hub_decide(Dev D, const int32_t* __restrict__ list,
                                                       const int64_t* __restrict__ hub_off,
                                                       const int32_t* __restrict__ c_b,
@@ -1053,6 +1146,12 @@ __global__ void __launch_bounds__(kBlock) k_hub_decide(Dev D, const int32_t* __r
                                                       int64_t pool_slots) {
   __shared__ int64_t r_g[kBlock / kWave];
   __shared__ int32_t r_c[kBlock / kWave];
+  __shared__ int32_t t_key[kHubTS];
+  __shared__ int32_t t_val[kHubTS];
+  __shared__ int32_t s_lo[kHubMaxUnits];
+  __shared__ int32_t s_pre[kHubMaxUnits + 1];
+  __shared__ int32_t s_nkeys;
+  __shared__ int32_t s_ovf;
   const int64_t two_m = load_two_m(D);
   if (two_m == 0) return;
   const int64_t count = D.rc[RC_HUB_CUNITS];
@@ -1060,36 +1159,106 @@ __global__ void __launch_bounds__(kBlock) k_hub_decide(Dev D, const int32_t* __r
     const int32_t h = c_b[u];
     const int32_t i = list[h];
     const int32_t d = D.C[i];
-    const int64_t tsz = 2 * static_cast<int64_t>(D.row_len[i]);
+    const int32_t deg = D.row_len[i];
+    const int64_t tsz = 2 * static_cast<int64_t>(deg);
     const int64_t off = hub_off[h];
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
-    if (off + tsz <= pool_slots) {
+    if (off + hub_slots(deg) <= pool_slots) {
       const int64_t Ki = D.K[i];
       const int64_t kid = hub_kid[h];
       const int64_t Sd = D.Sigma[d];
-      const int64_t s1 = min(tsz, c_s[u] + kHubClearSlots);
-      constexpr int V = kHubClearSlots / kBlock;
-      int32_t cc[V], vv[V];
-      int64_t sg[V];
-#pragma unroll
-      for (int q = 0; q < V; ++q) {
-        const int64_t t = c_s[u] + threadIdx.x + q * kBlock;
-        const unsigned long long e = t < s1 ? tab[off + t] : kEmptyPair;
-        cc[q] = static_cast<int32_t>(e >> 32);
-        vv[q] = static_cast<int32_t>(static_cast<uint32_t>(e));
-      }
-#pragma unroll
-      for (int q = 0; q < V; ++q) sg[q] = cc[q] >= 0 ? D.Sigma[cc[q]] : 0;
-#pragma unroll
-      for (int q = 0; q < V; ++q)
-        if (cc[q] >= 0) {
-          const int64_t g = gain_of(two_m, vv[q], kid, Ki, sg[q], Sd);
-          if (better(g, cc[q], bg, bc)) {
-            bg = g;
-            bc = cc[q];
-          }
+      if (hub_part(deg)) {
+        const uint32_t ns = static_cast<uint32_t>(hub_cunits(deg));
+        const int32_t nu = static_cast<int32_t>(hub_units(deg));
+        const int64_t seg = c_s[u] / kHubClearSlots;
+        const unsigned long long* pairs = tab + off;
+        const int32_t* segoff = reinterpret_cast<const int32_t*>(tab + off + tsz);
+        for (int32_t q = threadIdx.x; q < nu; q += kBlock) {
+          const int32_t lo = segoff[q * (ns + 1) + seg];
+          s_lo[q] = lo;
+          s_pre[q + 1] = segoff[q * (ns + 1) + seg + 1] - lo;
         }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          s_pre[0] = 0;
+          for (int32_t q = 0; q < nu; ++q) s_pre[q + 1] += s_pre[q];
+        }
+        __syncthreads();
+        const int32_t total = s_pre[nu];
+        for (uint32_t log2r = 0;; ++log2r) {
+          bool redo = false;
+          bg = LLONG_MIN;
+          bc = INT_MAX;
+          for (uint32_t r = 0; r < (1u << log2r) && !redo; ++r) {
+            for (int t = threadIdx.x; t < kHubTS; t += kBlock) {
+              t_key[t] = -1;
+              t_val[t] = 0;
+            }
+            if (threadIdx.x == 0) {
+              s_nkeys = 0;
+              s_ovf = 0;
+            }
+            __syncthreads();
+            for (int32_t j = threadIdx.x; j < total; j += kBlock) {
+              int32_t lo = 0, hi = nu;  // the insert unit of flat index j: s_pre[lo] <= j < s_pre[hi]
+              while (hi - lo > 1) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (s_pre[mid] <= j) lo = mid;
+                else hi = mid;
+              }
+              const unsigned long long e = pairs[static_cast<int64_t>(lo) * kHubUnitArcs + s_lo[lo] + (j - s_pre[lo])];
+              const int32_t c = static_cast<int32_t>(e >> 32);
+              const int32_t x = static_cast<int32_t>(static_cast<uint32_t>(e));
+              const uint32_t hk = mix32(static_cast<uint32_t>(c));
+              if (log2r && (hk >> (32 - log2r)) != r) continue;
+              if (__hip_atomic_load(&s_nkeys, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= kDecideMaxKeys) {
+                s_ovf = 1;
+                continue;
+              }
+              uint32_t p = hk & (kHubTS - 1);
+              while (true) {
+                const int32_t old = atomicCAS(&t_key[p], -1, c);
+                if (old == -1 || old == c) {
+                  if (old == -1) atomicAdd(&s_nkeys, 1);
+                  atomicAdd(&t_val[p], x);
+                  break;
+                }
+                p = (p + 1) & (kHubTS - 1);
+              }
+            }
+            __syncthreads();
+            if (s_ovf) {
+              redo = true;
+            } else {
+              for (int t0 = 0; t0 < kHubTS; t0 += kDecideSlots * kBlock) {
+                int32_t cc[kDecideSlots], vv[kDecideSlots];
+#pragma unroll
+                for (int q = 0; q < kDecideSlots; ++q) {
+                  cc[q] = t_key[t0 + threadIdx.x + q * kBlock];
+                  vv[q] = t_val[t0 + threadIdx.x + q * kBlock];
+                }
+                best_of(D, two_m, kid, Ki, Sd, cc, vv, bg, bc);
+              }
+            }
+            __syncthreads();
+          }
+          if (!redo) break;
+        }
+      } else {
+        const int64_t s1 = min(tsz, c_s[u] + kHubClearSlots);
+        for (int64_t t0 = c_s[u]; t0 < s1; t0 += kDecideSlots * kBlock) {
+          int32_t cc[kDecideSlots], vv[kDecideSlots];
+#pragma unroll
+          for (int q = 0; q < kDecideSlots; ++q) {
+            const int64_t t = t0 + threadIdx.x + q * kBlock;
+            const unsigned long long e = t < s1 ? tab[off + t] : kEmptyPair;
+            cc[q] = static_cast<int32_t>(e >> 32);
+            vv[q] = static_cast<int32_t>(static_cast<uint32_t>(e));
+          }
+          best_of(D, two_m, kid, Ki, Sd, cc, vv, bg, bc);
+        }
+      }
     }
     block_argmax(bg, bc, r_g, r_c);
     if (threadIdx.x == 0) {
