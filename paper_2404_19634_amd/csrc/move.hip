@@ -522,17 +522,30 @@ __device__ __forceinline__ void role_small(const Dev& D, int64_t two_m, const in
   const int64_t wave = (rb * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = nb * blockDim.x / kWave;
   int64_t gain_acc = 0, moved = 0, marcs = 0;
+  // the next iteration's row and its metadata are loaded during this one
+  int32_t n_i = 0, n_deg = 0, n_d = -1;
+  int64_t n_start = 0;
+  if (wave * VPW + sub < count) {
+    n_i = list[wave * VPW + sub];
+    n_start = D.row_start[n_i];
+    n_deg = D.row_len[n_i];
+    n_d = D.C[n_i];
+  }
   for (int64_t base = wave * VPW; base < count; base += nwaves * VPW) {
     const int64_t idx = base + sub;
     const bool valid = idx < count;
     int32_t i = 0, deg = 0, d = -1;
     int64_t start = 0;
     if (valid) {
-      i = list[idx];
-      start = D.row_start[i];
-      deg = D.row_len[i];
-      d = D.C[i];
+      i = n_i;
+      start = n_start;
+      deg = n_deg;
+      d = n_d;
     }
+    const int64_t Ki = valid ? D.K[i] : 0;
+    const int64_t Sd = valid && k < deg ? D.Sigma[d] : 0;
+    const int64_t nidx = idx + nwaves * VPW;
+    if (nidx < count) n_i = list[nidx];
     bool has = valid && k < deg;
     int32_t j = -1, x = 0, c = -1;
     if (has) {
@@ -541,6 +554,11 @@ __device__ __forceinline__ void role_small(const Dev& D, int64_t two_m, const in
       if (j == i) has = false;  // self-loop: not a neighbour
     }
     if (has) c = D.C[j];
+    if (nidx < count) {
+      n_start = D.row_start[n_i];
+      n_deg = D.row_len[n_i];
+      n_d = D.C[n_i];
+    }
     // K_{i->c} for this lane's community: all-pairs exchange inside the group
     int32_t kc = has ? x : 0;
     const int32_t xe = has ? x : 0;
@@ -556,10 +574,7 @@ __device__ __forceinline__ void role_small(const Dev& D, int64_t two_m, const in
     const bool cand = has && c != d;
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
-    int64_t Ki = 0;
-    if (valid) Ki = D.K[i];
     if (cand) {
-      const int64_t Sd = D.Sigma[d];
       bg = gain_of(two_m, kc, kid, Ki, D.Sigma[c], Sd);
       bc = c;
     }
@@ -601,11 +616,23 @@ __device__ __forceinline__ void role_wave(const Dev& D, int64_t two_m, const int
   const int64_t wave = (rb * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = nb * blockDim.x / kWave;
   int64_t gain_acc = 0, moved = 0, marcs = 0;
+  // the next row's id and metadata are loaded while this row is scanned
+  int32_t n_i = 0, n_deg = 0, n_d = 0;
+  int64_t n_start = 0;
+  if (wave < count) {
+    n_i = list[wave];
+    n_start = D.row_start[n_i];
+    n_deg = D.row_len[n_i];
+    n_d = D.C[n_i];
+  }
   for (int64_t idx = wave; idx < count; idx += nwaves) {
-    const int32_t i = list[idx];
-    const int64_t start = D.row_start[i];
-    const int32_t deg = D.row_len[i];
-    const int32_t d = D.C[i];
+    const int32_t i = n_i;
+    const int64_t start = n_start;
+    const int32_t deg = n_deg;
+    const int32_t d = n_d;
+    const int64_t Ki = D.K[i];
+    const int64_t Sd = D.Sigma[d];
+    if (idx + nwaves < count) n_i = list[idx + nwaves];
     // table of the smallest power of two >= 2*deg slots (at least 64)
     const uint32_t ts = max(64u, 1u << (32 - __clz(static_cast<uint32_t>(2 * deg - 1))));
     for (uint32_t t = lane; t < ts; t += kWave) {
@@ -650,9 +677,12 @@ __device__ __forceinline__ void role_wave(const Dev& D, int64_t two_m, const int
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (idx + nwaves < count) {
+      n_start = D.row_start[n_i];
+      n_deg = D.row_len[n_i];
+      n_d = D.C[n_i];
+    }
     kid = wave_sum_i32(kid);
-    const int64_t Ki = D.K[i];
-    const int64_t Sd = D.Sigma[d];
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
     // the table in chunks of kDecideSlots slots per lane (the gathers of a
@@ -740,12 +770,32 @@ __device__ __forceinline__ int64_t block_total(int64_t v, int64_t* r) {
   return s;
 }
 
+// Exclusive prefix sums of a[0, n) in place (n <= kBlock), with the total
+// in a[n]; called by the whole workgroup.  wsum: kBlock / kWave ints of LDS.
+__device__ __forceinline__ void block_exscan(int32_t* a, int n, int32_t* wsum) {
+  const int t = threadIdx.x, lane = lane_id();
+  const int32_t own = t < n ? a[t] : 0;
+  int32_t v = own;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t y = __shfl_up(v, o);
+    if (lane >= o) v += y;
+  }
+  if (lane == kWave - 1) wsum[t / kWave] = v;
+  __syncthreads();
+  for (int w = 0; w < t / kWave; ++w) v += wsum[w];
+  if (t < n) a[t] = v - own;
+  if (t == n - 1) a[n] = v;
+  if (n == 0 && t == 0) a[0] = 0;
+  __syncthreads();
+}
+
 // Small per-workgroup scratch of the block and hub roles (with a small move
 // aggregate: a workgroup of the block role commits a few moves at most).
 struct Red {
   int64_t g[kBlock / kWave];
   int32_t c[kBlock / kWave];
   int64_t s[kBlock / kWave];
+  int32_t w[kBlock / kWave];
   MoveAggSmall agg;
 };
 
@@ -754,11 +804,24 @@ __device__ __forceinline__ void role_block(const Dev& D, int64_t two_m, const in
                                            int64_t nb, int32_t* keys, int32_t* vals, Red* red) {
   const int64_t count = D.rc[rc_bin(BIN_BLOCK)];
   int64_t gain_acc = 0, moved = 0, marcs = 0;
+  // the next row's id and metadata are loaded while this row is scanned
+  // (no other workgroup changes C of a row this workgroup holds)
+  int32_t n_i = 0, n_deg = 0, n_d = 0;
+  int64_t n_start = 0;
+  if (rb < count) {
+    n_i = list[rb];
+    n_start = D.row_start[n_i];
+    n_deg = D.row_len[n_i];
+    n_d = D.C[n_i];
+  }
   for (int64_t idx = rb; idx < count; idx += nb) {
-    const int32_t i = list[idx];
-    const int64_t start = D.row_start[i];
-    const int32_t deg = D.row_len[i];
-    const int32_t d = D.C[i];
+    const int32_t i = n_i;
+    const int64_t start = n_start;
+    const int32_t deg = n_deg;
+    const int32_t d = n_d;
+    const int64_t Ki = D.K[i];
+    const int64_t Sd = D.Sigma[d];
+    if (idx + nb < count) n_i = list[idx + nb];
     const uint32_t ts = max(256u, 1u << (32 - __clz(static_cast<uint32_t>(2 * deg - 1))));
     for (uint32_t t = threadIdx.x; t < ts; t += kBlock) {
       keys[t] = -1;
@@ -796,9 +859,12 @@ __device__ __forceinline__ void role_block(const Dev& D, int64_t two_m, const in
         }
       }
     }
+    if (idx + nb < count) {
+      n_start = D.row_start[n_i];
+      n_deg = D.row_len[n_i];
+      n_d = D.C[n_i];
+    }
     kid = block_total(kid, red->s);
-    const int64_t Ki = D.K[i];
-    const int64_t Sd = D.Sigma[d];
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
     for (uint32_t t0 = 0; t0 < ts; t0 += kDecideSlots * kBlock) {
@@ -950,16 +1016,7 @@ __device__ __forceinline__ void role_hub_insert(const Dev& D, const HubIn& H, in
       for (int sl = threadIdx.x; sl < kHubTS; sl += kBlock)
         if (tk[sl] >= 0) atomicAdd(&hist[hash_slot(static_cast<uint32_t>(tk[sl]), ns)], 1);
       __syncthreads();
-      if (threadIdx.x == 0) {
-        int32_t run = 0;
-        for (uint32_t q = 0; q < ns; ++q) {
-          const int32_t c = hist[q];
-          hist[q] = run;
-          run += c;
-        }
-        hist[ns] = run;
-      }
-      __syncthreads();
+      block_exscan(hist, static_cast<int>(ns), red->w);
       for (uint32_t q = threadIdx.x; q <= ns; q += kBlock) segoff[q] = hist[q];
       __syncthreads();
       for (int sl = threadIdx.x; sl < kHubTS; sl += kBlock)
@@ -1152,6 +1209,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_decide(Dev D, const int32_t* __r
   __shared__ int32_t s_pre[kHubMaxUnits + 1];
   __shared__ int32_t s_nkeys;
   __shared__ int32_t s_ovf;
+  __shared__ int32_t s_w[kBlock / kWave];
   const int64_t two_m = load_two_m(D);
   if (two_m == 0) return;
   const int64_t count = D.rc[RC_HUB_CUNITS];
@@ -1177,14 +1235,10 @@ __global__ void __launch_bounds__(kBlock) k_hub_decide(Dev D, const int32_t* __r
         for (int32_t q = threadIdx.x; q < nu; q += kBlock) {
           const int32_t lo = segoff[q * (ns + 1) + seg];
           s_lo[q] = lo;
-          s_pre[q + 1] = segoff[q * (ns + 1) + seg + 1] - lo;
+          s_pre[q] = segoff[q * (ns + 1) + seg + 1] - lo;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-          s_pre[0] = 0;
-          for (int32_t q = 0; q < nu; ++q) s_pre[q + 1] += s_pre[q];
-        }
-        __syncthreads();
+        block_exscan(s_pre, nu, s_w);
         const int32_t total = s_pre[nu];
         for (uint32_t log2r = 0;; ++log2r) {
           bool redo = false;
@@ -1471,6 +1525,13 @@ void launch_role(const Dev& D, const Bins& b, const HubIn& H, size_t lds, int64_
                      H);
 }
 
+// A grid-stride kernel's grid, capped at the workgroups resident at once.
+template <class F>
+unsigned cap_grid(F fn, int64_t grid) {
+  grid = std::min<int64_t>(grid, resident_blocks(reinterpret_cast<const void*>(fn), kBlock, 0));
+  return static_cast<unsigned>(std::max<int64_t>(grid, 1));
+}
+
 template <int TS>
 void launch_one_role(int role, const Dev& D, const Bins& b, const HubIn& H, int64_t grid, hipStream_t st) {
   switch (role) {
@@ -1522,8 +1583,9 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
   const bool hubs = bin_mask & (1u << BIN_HUB);
   if (hubs) {
     timer_begin(LV_TIME_HUB_CLEAR, st);
-    hipLaunchKernelGGL(k_hub_clear, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off, ws.u_emit_b,
-                       ws.u_emit_s, reinterpret_cast<unsigned long long*>(ws.pool_pairs), ws.hub_kid, ws.pool_slots);
+    hipLaunchKernelGGL(k_hub_clear, dim3(cap_grid(k_hub_clear, bh)), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB],
+                       ws.hub_off, ws.u_emit_b, ws.u_emit_s, reinterpret_cast<unsigned long long*>(ws.pool_pairs),
+                       ws.hub_kid, ws.pool_slots);
     timer_end(LV_TIME_HUB_CLEAR, st);
   }
 
@@ -1575,15 +1637,16 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
   }
   if (hubs) {
     timer_begin(LV_TIME_HUB_DECIDE, st);
-    hipLaunchKernelGGL(k_hub_decide, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_off, ws.u_emit_b,
-                       ws.u_emit_s, reinterpret_cast<const unsigned long long*>(ws.pool_pairs), ws.hub_kid, ws.unit_g,
-                       ws.unit_c, ws.pool_slots);
+    hipLaunchKernelGGL(k_hub_decide, dim3(cap_grid(k_hub_decide, bh)), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB],
+                       ws.hub_off, ws.u_emit_b, ws.u_emit_s,
+                       reinterpret_cast<const unsigned long long*>(ws.pool_pairs), ws.hub_kid, ws.unit_g, ws.unit_c,
+                       ws.pool_slots);
     timer_end(LV_TIME_HUB_DECIDE, st);
     hipLaunchKernelGGL(k_hub_final, dim3(64), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_cbase, ws.hub_cnum,
                        ws.unit_g, ws.unit_c, ws.hub_moved);
     if (a.push)
-      hipLaunchKernelGGL(k_hub_expand, dim3(bh), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.u_ins_b, ws.u_ins_a,
-                         ws.hub_moved);
+      hipLaunchKernelGGL(k_hub_expand, dim3(cap_grid(k_hub_expand, bh)), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB],
+                         ws.u_ins_b, ws.u_ins_a, ws.hub_moved);
   }
 }
 
