@@ -21,7 +21,7 @@ namespace lv {
 namespace {
 
 thread_local std::string g_last_error;
-lv_tuning g_tuning = {256, 2048, 2560, 1280, 7, 4096, 2, 8192, 1};
+lv_tuning g_tuning = {256, 2048, 2560, 1280, 7, 4096, 2, 1 << 20, 1};
 
 lv_status fail(lv_status code, const char* msg) {
   g_last_error = msg;

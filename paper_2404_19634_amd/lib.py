@@ -180,7 +180,7 @@ def params(tolerance=1e-2, tolerance_drop=10.0, aggregation_tolerance=0.8, max_i
 DEFAULT_ASYNC_ROUNDS_LOG2 = 7
 
 
-DEFAULT_FUSE_MAX_FRONTIER = 8192
+DEFAULT_FUSE_MAX_FRONTIER = 1 << 20
 DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER = 4096
 
 
