@@ -30,13 +30,14 @@ PROFILES = os.path.join(ROOT, "profiles")
 # processed vertex its row start and length, K_i and C_i (8 + 4 + 8 + 4 B).
 # The frontier binning kernel reads one 4 B frontier word per 32 vertices
 # and, per active vertex, its row length and one list entry (4 + 4 B).  A
-# hub row's global table has two 8 B slots per arc, written once by the
-# clear kernel and read once by the decision kernel.
+# hub row's decision units read at most one 8 B (community, weight) pair
+# per arc; the clear kernel resets per-hub sums (and the global tables of
+# rows above 2^18 arcs, not priced here).
 SCAN_BYTES_PER_ARC = 12
 SCAN_BYTES_PER_VERTEX = 24
 BIN_BYTES_PER_WORD = 4
 BIN_BYTES_PER_VERTEX = 8
-HUB_TABLE_BYTES_PER_ARC = 16
+HUB_PAIR_BYTES_PER_ARC = 8
 KERNELS = ("k_move_all", "k_bin_frontier", "k_hub_clear", "k_hub_decide")   # index = LV_TIME_*
 SHORT = ("move_all", "bin_frontier", "hub_clear", "hub_decide")
 
@@ -113,8 +114,7 @@ class KernelMeter:
         nbin = s["timed_launches"][L.TIME_BINNING]
         self.bytes[L.TIME_BINNING] += BIN_BYTES_PER_WORD * words * nbin + BIN_BYTES_PER_VERTEX * sum(verts)
         hub_arcs = arcs[L.BINS.index("hub")]
-        self.bytes[L.TIME_HUB_CLEAR] += HUB_TABLE_BYTES_PER_ARC * hub_arcs
-        self.bytes[L.TIME_HUB_DECIDE] += HUB_TABLE_BYTES_PER_ARC * hub_arcs
+        self.bytes[L.TIME_HUB_DECIDE] += HUB_PAIR_BYTES_PER_ARC * hub_arcs
 
     def dominant(self):
         return max(range(self.lib.NTIMED), key=lambda k: self.ms[k])
@@ -253,6 +253,90 @@ def sweep(g, e, runs):
     log("copy: 1 GiB read + 1 GiB written")
 
 
+def full_sweep_roofline(lib, g, runs=3):
+    """Roofline of the scan on a full sweep: one SYNC local-moving iteration
+    over every vertex from singletons (static Louvain's first iteration),
+    the scan kernel's launches timed with HIP events.  Bytes are the
+    algorithmic ones (12 B per arc, 24 B per vertex).  The best of `runs`."""
+    import torch
+    prm = lib.params(mode="sync", max_iterations=1, max_passes=1)
+    best = None
+    lib.set_timing([lib.TIME_SCAN])
+    try:
+        for _ in range(runs):
+            st = lib.State.empty(g.n, g.device)
+            torch.cuda.synchronize()
+            st, s = lib.louvain_static(g, prm, st)
+            torch.cuda.synchronize()
+            ms = s["timed_ms"][lib.TIME_SCAN]
+            if best is None or ms < best[0]:
+                best = (ms, s)
+    finally:
+        lib.set_timing(())
+    ms, s = best
+    arcs, verts = sum(s["bin_arcs"]), sum(s["bin_vertices"])
+    nbytes = SCAN_BYTES_PER_ARC * arcs + SCAN_BYTES_PER_VERTEX * verts
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "kernel": "k_move_all (all roles, hub insert units included)",
+            "launches": s["timed_launches"][lib.TIME_SCAN], "scan_ms": ms, "bytes": nbytes,
+            "arcs": arcs, "vertices": verts, "local_moving_ms": s["ms_move"],
+            "local_moving_edges_per_s": arcs / (s["ms_move"] * 1e-3) if s["ms_move"] > 0 else None,
+            "workload": "one SYNC local-moving iteration from singletons over every vertex"}
+
+
+def approaches(lib, e, sizes, reps=2, seed=777):
+    """Update latency of ND, DS and DF Louvain in SYNC and ASYNC mode, and
+    static Louvain in both modes, on the same graph: per (approach, mode) a
+    fresh copy of the graph, its static state, then `reps` rounds of the
+    batch sizes, each apply_batch followed by the approach (timed)."""
+    import torch
+    dev = torch.device("cuda:0")
+    batches = make_batches(e, sizes, reps * len(sizes), seed=seed)
+    out = {"static": {}}
+    for mode in ("sync", "async"):
+        prm = lib.params(mode=mode)
+        g = lib.Graph.from_edges(e, slack_frac=0.1, slack_min=8)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st0, s0 = lib.louvain_static(g, prm, lib.State.empty(e.n, dev))
+        torch.cuda.synchronize()
+        out["static"][mode] = {"latency_ms": (time.perf_counter() - t) * 1e3, "edges_scanned": s0["arcs_scanned"],
+                               "modularity": lib.modularity(g, st0.C)}
+        del g
+        for name in ("nd", "ds", "df"):
+            fn = getattr(lib, "louvain_" + name)
+            g = lib.Graph.from_edges(e, slack_frac=0.1, slack_min=8)
+            st = st0.clone()
+            lat, arcs, by = [], [], {}
+            for b in batches:
+                db = lib.Batch.from_host(b, dev)
+                try:
+                    lib.apply_batch(g, db)
+                except lib.LouvainError as ex:
+                    if ex.code != lib.LV_ENOSLACK:
+                        raise
+                    g = g.relayout(slack_frac=0.5, slack_min=16)
+                    lib.apply_batch(g, db)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                st, s = fn(g, db, st, prm)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t) * 1e3
+                lat.append(ms)
+                arcs.append(s["arcs_scanned"])
+                by.setdefault(str(b.size), []).append(ms)
+            out.setdefault(name, {})[mode] = {
+                "latency_ms_p50": pct(lat, 50), "latency_ms_p99": pct(lat, 99),
+                "by_batch_size": {k: float(np.median(v)) for k, v in by.items()},
+                "edges_scanned_per_s": float(np.sum(arcs)) / (np.sum(lat) * 1e-3),
+                "speedup_vs_static": out["static"][mode]["latency_ms"] / pct(lat, 50),
+                "modularity": lib.modularity(g, st.C)}
+            del g, st
+            torch.cuda.empty_cache()
+    return out
+
+
 def _gen_graph(spec):
     from paper_2404_19634_amd import workloads as W
     n, b, seed = spec
@@ -344,6 +428,8 @@ def main():
     ap.add_argument("--mode", default="async", choices=["async", "sync"])
     ap.add_argument("--static-runs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-approaches", action="store_true",
+                    help="skip the ND/DS/DF x SYNC/ASYNC comparison and the full-sweep roofline")
     ap.add_argument("--tuning", default="", help="lv_tuning overrides, e.g. fuse_max_frontier=1024,defer_totals=1")
     ap.add_argument("--no-final-static", action="store_true",
                     help="skip the static run on the final graph (counter runs: the timed region's dispatches "
@@ -520,6 +606,11 @@ def main():
             "launches": nl, "avg_launch_us": meter.ms[dom] / nl * 1e3, "bytes_per_launch": per_launch,
             "warmup_kernel_ms": {lib.TIMED[k]: round(warm.ms[k], 4) for k in range(lib.NTIMED)},
         }
+    if not args.no_approaches:
+        log("full-sweep roofline ...")
+        out["roofline_full_sweep"] = full_sweep_roofline(lib, g)
+        log("approaches (ND / DS / DF x SYNC / ASYNC) ...")
+        out["approaches"] = approaches(lib, e, sizes)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(e, batches[2])

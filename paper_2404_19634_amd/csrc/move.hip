@@ -1067,8 +1067,11 @@ __device__ __forceinline__ void role_hub_insert(const Dev& D, const HubIn& H, in
 }
 
 // Role block ranges of the fused kernel, laid end to end.
+// The ranges run from the hub role down to the 4-lane role: workgroups are
+// dispatched in index order, so the longest units start first instead of
+// forming the launch's tail.
 struct Roles {
-  int64_t end[NBINS];  // exclusive end of each role's block range (hub = insert units)
+  int64_t end[NBINS];  // exclusive end of range r, which holds role NBINS - 1 - r (hub = insert units)
 };
 
 // LDS of the roles (bytes): a small role uses the move aggregate only, the
@@ -1095,11 +1098,12 @@ __global__ void __launch_bounds__(kBlock) k_move_all(Dev D, Bins bins, Roles R, 
   int64_t rb = blockIdx.x, nb = gridDim.x;
   if constexpr (kAny) {
     const int64_t b = blockIdx.x;
-    role = 0;
-    while (role < NBINS - 1 && b >= R.end[role]) ++role;
-    const int64_t lo = role == 0 ? 0 : R.end[role - 1];
+    int r = 0;
+    while (r < NBINS - 1 && b >= R.end[r]) ++r;
+    const int64_t lo = r == 0 ? 0 : R.end[r - 1];
     rb = b - lo;
-    nb = R.end[role] - lo;
+    nb = R.end[r] - lo;
+    role = NBINS - 1 - r;
   }
   if ((kAny || ONLY <= BIN_G32) && role <= BIN_G32) {
     MoveAgg* agg = reinterpret_cast<MoveAgg*>(smem);
@@ -1603,9 +1607,10 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
   if (fuse) {
     Roles R;
     int64_t end = 0;
-    for (int k = 0; k < NBINS; ++k) {
+    for (int r = 0; r < NBINS; ++r) {
+      const int k = NBINS - 1 - r;
       if (bin_mask & (1u << k)) end += per[k];
-      R.end[k] = end;
+      R.end[r] = end;
     }
     size_t lds = sizeof(MoveAgg);
     if (bin_mask & (1u << BIN_WAVE)) lds = std::max(lds, lw);
