@@ -165,6 +165,19 @@ def summarize(db_path, kernel, launches):
     if "counters_collection" in tabs:
         rows = db.execute("select dispatch_id, kernel_name, counter_name, sum(value) from counters_collection "
                           "group by dispatch_id, counter_name order by dispatch_id").fetchall()
+    if rows and kernel == "all":
+        counters = sorted({r[2] for r in rows})
+        names = sorted({_kname(k) for d, k, c, v in rows})
+        out.append(f"{'kernel (avg per dispatch, last ' + str(launches or 'all') + ')':40s} " +
+                   " ".join(f"{c:>24s}" for c in counters))
+        for nm in names:
+            cells = []
+            for cn in counters:
+                vals = [v for d, k, c, v in rows if c == cn and _kname(k) == nm]
+                tail = vals[-launches:] if launches else vals
+                cells.append(f"{sum(tail) / len(tail):24.1f}" if tail else f"{'-':>24s}")
+            out.append(f"{nm[:40]:40s} " + " ".join(cells))
+        return "\n".join(out)
     if rows:
         counters = sorted({r[2] for r in rows})
         for cn in counters:
@@ -437,7 +450,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain 1 GiB device copy whose counters calibrate FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--summarize", metavar="DB", help="print a summary of a rocprofv3 database and exit")
-    ap.add_argument("--kernel", default="k_move_all<512>", help="kernel of --summarize for counter databases")
+    ap.add_argument("--kernel", default="k_move_all<512, 7>",
+                    help="kernel of --summarize for counter databases ('all': a table of every kernel)")
     ap.add_argument("--launches", type=int, default=0, help="last dispatches of --kernel to average")
     ap.add_argument("--serve", action="store_true", help="many-graph serving benchmark instead of the R-MAT line")
     ap.add_argument("--serve-graphs", type=int, default=4096)
