@@ -1432,11 +1432,29 @@ __global__ void __launch_bounds__(kBlock) k_apply_moves(int32_t* __restrict__ C,
 constexpr int kPullGroup = 16;
 constexpr int kPullGroupMax = 2048;
 
+// Pull or push: the expansion reads every row until it meets a mover
+// (pull), or ORs in the neighbours of every mover (push).  Once the scan is
+// done the iteration's statistics say which costs less: push when the
+// movers' arcs are under an eighth of the arcs scanned.
+constexpr int64_t kPushRatio = 8;
+
+__device__ __forceinline__ int64_t stat_sum(const int64_t* sc, int st) {
+  int64_t v = 0;
+  for (int r = 0; r < kStatReplicas; ++r) v += sc[r * kStatStride + st];
+  return v;
+}
+
+__device__ __forceinline__ bool expand_by_push(const int64_t* sc) {
+  return stat_sum(sc, ST_EXPAND) * kPushRatio < stat_sum(sc, ST_ARCS);
+}
+
 __global__ void __launch_bounds__(kBlock) k_pull_words(const int64_t* __restrict__ row_start,
                                                       const int32_t* __restrict__ row_len,
                                                       const int32_t* __restrict__ col, int32_t n,
                                                       const uint32_t* __restrict__ moved, uint32_t* __restrict__ next,
-                                                      int32_t* __restrict__ longlist, int64_t* __restrict__ ctr) {
+                                                      int32_t* __restrict__ longlist, int64_t* __restrict__ ctr,
+                                                      const int64_t* __restrict__ sc) {
+  if (expand_by_push(sc)) return;
   const int lane = lane_id();
   const int grp = lane / kPullGroup;
   const int sub = lane % kPullGroup;
@@ -1480,8 +1498,10 @@ __global__ void __launch_bounds__(kBlock) k_pull_long(const int64_t* __restrict_
                                                      const int32_t* __restrict__ row_len,
                                                      const int32_t* __restrict__ col,
                                                      const uint32_t* __restrict__ moved, uint32_t* __restrict__ next,
-                                                     const int32_t* __restrict__ longlist, const int64_t* __restrict__ ctr) {
+                                                     const int32_t* __restrict__ longlist, const int64_t* __restrict__ ctr,
+                                                     const int64_t* __restrict__ sc) {
   __shared__ int s_hit;
+  if (expand_by_push(sc)) return;
   const int64_t count = ctr[CTR_AUX1];
   for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
     const int32_t j = longlist[idx];
@@ -1497,6 +1517,72 @@ __global__ void __launch_bounds__(kBlock) k_pull_long(const int64_t* __restrict_
     __syncthreads();
     if (threadIdx.x == 0 && s_hit) set_bit(next, j);
     __syncthreads();
+  }
+}
+
+// Push: one wavefront per word of the movers bitmask ORs in the neighbours
+// of its movers whose rows are short, a lane per arc; longer rows are
+// queued for a workgroup each.
+constexpr int32_t kPushShortMax = 256;
+
+__global__ void __launch_bounds__(kBlock) k_push_words(const int64_t* __restrict__ row_start,
+                                                      const int32_t* __restrict__ row_len,
+                                                      const int32_t* __restrict__ col, int32_t n,
+                                                      const uint32_t* __restrict__ moved, uint32_t* __restrict__ next,
+                                                      int32_t* __restrict__ longlist, int64_t* __restrict__ ctr,
+                                                      const int64_t* __restrict__ sc) {
+  if (!expand_by_push(sc)) return;
+  const int lane = lane_id();
+  const int64_t words = (static_cast<int64_t>(n) + 31) / 32;
+  const int64_t wave = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kWave;
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * blockDim.x / kWave;
+  for (int64_t w = wave; w < words; w += nwaves) {
+    const uint32_t bits = moved[w];
+    if (!bits) continue;
+    // each lane of the first 32 loads one mover's row; then the wavefront
+    // walks the short rows together
+    const int32_t i = static_cast<int32_t>(w * 32 + (lane & 31));
+    const bool mine = lane < 32 && ((bits >> lane) & 1u);
+    int32_t len = 0;
+    int64_t s = 0;
+    if (mine) {
+      len = row_len[i];
+      s = row_start[i];
+      if (len > kPushShortMax) {
+        const int64_t pos =
+            static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_AUX1]), 1ull));
+        longlist[pos] = i;
+        len = 0;
+      }
+    }
+    for (uint32_t r = bits; r; r &= r - 1) {
+      const int b = __ffs(r) - 1;
+      const int32_t v = static_cast<int32_t>(w * 32 + b);
+      const int32_t vl = __shfl(len, b);
+      const int64_t vs = __shfl(s, b);
+      for (int32_t k = lane; k < vl; k += kWave) {
+        const int32_t j = col[vs + k];
+        if (j != v) set_bit(next, j);
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_push_long(const int64_t* __restrict__ row_start,
+                                                     const int32_t* __restrict__ row_len,
+                                                     const int32_t* __restrict__ col, uint32_t* __restrict__ next,
+                                                     const int32_t* __restrict__ longlist,
+                                                     const int64_t* __restrict__ ctr, const int64_t* __restrict__ sc) {
+  if (!expand_by_push(sc)) return;
+  const int64_t count = ctr[CTR_AUX1];
+  for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
+    const int32_t i = longlist[idx];
+    const int64_t s = row_start[i];
+    const int32_t len = row_len[i];
+    for (int32_t k = threadIdx.x; k < len; k += kBlock) {
+      const int32_t j = col[s + k];
+      if (j != i) set_bit(next, j);
+    }
   }
 }
 
@@ -1659,9 +1745,14 @@ void launch_pull_expand(const MoveArgs& a, Workspace& ws, hipStream_t st) {
   const int64_t words = (static_cast<int64_t>(a.g.n) + 31) / 32;
   (void)hipMemsetAsync(ws.ctr + CTR_AUX1, 0, sizeof(int64_t), st);
   hipLaunchKernelGGL(k_pull_words, dim3(grid_for(words * kWave, kBlock, 8192)), dim3(kBlock), 0, st, a.g.row_start,
-                     a.g.row_len, a.g.col, a.g.n, a.moved, a.next, ws.bins[NBINS - 1] + 0, ws.ctr);
+                     a.g.row_len, a.g.col, a.g.n, a.moved, a.next, ws.bins[NBINS - 1] + 0, ws.ctr, a.sc);
   hipLaunchKernelGGL(k_pull_long, dim3(1024), dim3(kBlock), 0, st, a.g.row_start, a.g.row_len, a.g.col, a.moved,
-                     a.next, ws.bins[NBINS - 1] + 0, ws.ctr);
+                     a.next, ws.bins[NBINS - 1] + 0, ws.ctr, a.sc);
+  // (only one of the pair above and the pair below does any work)
+  hipLaunchKernelGGL(k_push_words, dim3(grid_for(words * kWave, kBlock, 8192)), dim3(kBlock), 0, st, a.g.row_start,
+                     a.g.row_len, a.g.col, a.g.n, a.moved, a.next, ws.bins[NBINS - 1] + 0, ws.ctr, a.sc);
+  hipLaunchKernelGGL(k_push_long, dim3(1024), dim3(kBlock), 0, st, a.g.row_start, a.g.row_len, a.g.col, a.next,
+                     ws.bins[NBINS - 1] + 0, ws.ctr, a.sc);
 }
 
 void launch_apply_moves(const MoveArgs& a, Workspace& ws, bool clear_moved, hipStream_t st) {
