@@ -632,8 +632,10 @@ size_t carve_workspace(Workspace& ws, void* base, int32_t n, int64_t cap) {
   ws.unit_g = take<int64_t>(cur, total, base, static_cast<size_t>(ws.units_max));
   ws.unit_c = take<int32_t>(cur, total, base, static_cast<size_t>(ws.units_max));
   // hub tables take 2 slots per arc; rows that aggregate by segment add
-  // their segment offsets, under 1/16 slot per arc
-  ws.pool_slots = 2 * static_cast<int64_t>(ucap) + static_cast<int64_t>(ucap) / 16 + 4096;
+  // their segment offsets: at most d/8 + d/1365 + 2 slots for a row of d
+  // arcs (d <= 2^20 > 2048), so under cap/8 + cap/512 in all
+  ws.pool_slots = 2 * static_cast<int64_t>(ucap) + static_cast<int64_t>(ucap) / 8 +
+                  static_cast<int64_t>(ucap) / 512 + 4096;
   ws.pool_pairs = take<uint64_t>(cur, total, base, static_cast<size_t>(ws.pool_slots));
   ws.pool_keys = reinterpret_cast<int32_t*>(ws.pool_pairs);
   ws.pool_vals = base ? ws.pool_keys + ws.pool_slots : nullptr;

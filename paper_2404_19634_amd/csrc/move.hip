@@ -270,9 +270,12 @@ __device__ __forceinline__ int64_t hub_cunits(int32_t deg) {
 // Longer rows use the global table.  A partitioned row's pool reservation
 // holds its pairs (unit u at slot u * kHubUnitArcs) and, after 2 * deg
 // slots, the segment offsets of every unit (hub_cunits + 1 int32 each).
-constexpr int32_t kHubPartMaxDeg = 1 << 18;
+constexpr int32_t kHubPartMaxDeg = 1 << 20;
 constexpr int kHubMaxSegs = (2 * kHubPartMaxDeg + kHubClearSlots - 1) / kHubClearSlots;
 constexpr int kHubMaxUnits = (kHubPartMaxDeg + kHubUnitArcs - 1) / kHubUnitArcs;
+
+static_assert(kHubMaxSegs + 1 <= 4 * kBlock && kHubMaxUnits + 1 <= 4 * kBlock,
+              "segment offsets and unit counts must fit one workgroup scan");
 
 __device__ __forceinline__ bool hub_part(int32_t deg) { return deg <= kHubPartMaxDeg; }
 __device__ __forceinline__ int64_t hub_slots(int32_t deg) {
@@ -770,12 +773,22 @@ __device__ __forceinline__ int64_t block_total(int64_t v, int64_t* r) {
   return s;
 }
 
-// Exclusive prefix sums of a[0, n) in place (n <= kBlock), with the total
-// in a[n]; called by the whole workgroup.  wsum: kBlock / kWave ints of LDS.
+// Exclusive prefix sums of a[0, n) in place (n <= kScanItems * kBlock),
+// with the total in a[n]; called by the whole workgroup.  Thread t owns
+// a[kScanItems t, kScanItems (t + 1)).  wsum: kBlock / kWave ints of LDS.
+constexpr int kScanItems = 4;
+
 __device__ __forceinline__ void block_exscan(int32_t* a, int n, int32_t* wsum) {
   const int t = threadIdx.x, lane = lane_id();
-  const int32_t own = t < n ? a[t] : 0;
-  int32_t v = own;
+  int32_t own[kScanItems];
+  int32_t sum = 0;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    const int k = t * kScanItems + q;
+    own[q] = k < n ? a[k] : 0;
+    sum += own[q];
+  }
+  int32_t v = sum;
   for (int o = 1; o < kWave; o <<= 1) {
     const int32_t y = __shfl_up(v, o);
     if (lane >= o) v += y;
@@ -783,8 +796,14 @@ __device__ __forceinline__ void block_exscan(int32_t* a, int n, int32_t* wsum) {
   if (lane == kWave - 1) wsum[t / kWave] = v;
   __syncthreads();
   for (int w = 0; w < t / kWave; ++w) v += wsum[w];
-  if (t < n) a[t] = v - own;
-  if (t == n - 1) a[n] = v;
+  int32_t run = v - sum;  // sum of the elements before this thread's
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    const int k = t * kScanItems + q;
+    if (k < n) a[k] = run;
+    run += own[q];
+    if (k == n - 1) a[n] = run;
+  }
   if (n == 0 && t == 0) a[0] = 0;
   __syncthreads();
 }

@@ -336,6 +336,64 @@ def test_apply_batch_hub_rows(lib):
         cur = W.apply_batch_np(cur, b)
 
 
+def _segment_heavy_hub(n=60000, deg=12000, crowd=7000, seed=13):
+    """Vertex 0 adjacent to `deg` others, `crowd` of which hash into the
+    first of its ceil(2 deg / 4096) segments (multiplicative hash of the id,
+    as in a SYNC sweep from singletons the community ids are the vertex
+    ids): that segment then holds more keys than one decide pass takes.
+    Plus a ring and random chords so the other rows have neighbours."""
+    rng = np.random.default_rng(seed)
+    ns = -(-2 * deg // 4096)
+    ids = np.arange(1, n, dtype=np.uint64)
+    h = (ids * np.uint64(0x9E3779B1)) & np.uint64(0xFFFFFFFF)
+    seg = (h * np.uint64(ns)) >> np.uint64(32)
+    first = ids[seg == 0].astype(np.int64)
+    other = ids[seg != 0].astype(np.int64)
+    nb = np.concatenate([rng.choice(first, crowd, replace=False), rng.choice(other, deg - crowd, replace=False)])
+    pairs = {(0, int(v)) for v in nb}
+    for v in range(1, n - 1):
+        pairs.add((v, v + 1))
+    while len(pairs) < deg + n + 20000:
+        a, b = rng.integers(1, n, 2)
+        if a != b:
+            pairs.add((int(min(a, b)), int(max(a, b))))
+    a = np.array(sorted(pairs), dtype=np.int32)
+    return W.Edges(n, a[:, 0].copy(), a[:, 1].copy(), np.ones(a.shape[0], np.int32))
+
+
+def _long_star(leaves=(1 << 20) + 5000, seed=17):
+    """A hub row longer than 2^20 arcs (the global-table path), leaves in a
+    ring with random chords."""
+    rng = np.random.default_rng(seed)
+    n = leaves + 1
+    u = [np.zeros(leaves, np.int64), np.arange(1, n - 1, dtype=np.int64)]
+    v = [np.arange(1, n, dtype=np.int64), np.arange(2, n, dtype=np.int64)]
+    a, b = rng.integers(1, n, 200000), rng.integers(1, n, 200000)
+    u.append(np.minimum(a, b))
+    v.append(np.maximum(a, b))
+    uu, vv = np.concatenate(u), np.concatenate(v)
+    ok = uu != vv
+    keys = np.unique(uu[ok] * n + vv[ok])
+    return W.Edges(n, (keys // n).astype(np.int32), (keys % n).astype(np.int32), np.ones(keys.shape[0], np.int32))
+
+
+@pytest.mark.parametrize("make", [_segment_heavy_hub, _long_star], ids=["segment_overflow", "global_table"])
+def test_hub_paths_sync_bit_exact(lib, make):
+    """The hub decide unit's multi-pass path (a segment with more keys than
+    one pass holds) and the global-table path of rows above 2^20 arcs: one
+    SYNC sweep from singletons and a full SYNC static run match the oracle
+    bit for bit."""
+    e = make()
+    g = lib.Graph.from_edges(e)
+    G = _orc(e)
+    for kw in (dict(max_iterations=1, max_passes=1), dict()):
+        st, gs = lib.louvain_static(g, mode="sync", **kw)
+        C, K, S = st.host()
+        Co, Ko, So, os_ = G.louvain("static", mode="sync", **kw)
+        assert np.array_equal(C, Co) and np.array_equal(K, Ko) and np.array_equal(S, So)
+        _same_stats(gs, os_)
+
+
 def test_bin_stats_and_timing_hook(lib):
     """Per-bin work adds up to the scan totals, and the event hook times
     exactly the launches it was asked for."""
