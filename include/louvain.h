@@ -268,8 +268,12 @@ lv_status modularity(const lv_graph* g, const int32_t* C, double* q_host, void* 
  *              max_updates) bytes of device memory, zero before its first
  *              use; each call leaves it ready for the next (keep one per
  *              graph); del.count + ins.count must not exceed max_updates.
- *   desc       device buffer of lv_many_desc_bytes(count) bytes (item
- *              descriptors and results).
+ *   desc       device buffer of at least lv_many_desc_bytes(count) bytes
+ *              (item count, item descriptors and results).  Keep one per
+ *              calling thread: the call replays a HIP graph captured for
+ *              this buffer (copy in, the persistent kernel, copy out; one
+ *              graph per power-of-two size class of count that fits the
+ *              buffer), and calls on one buffer must not overlap.
  *   ws         a workspace for the single-graph path, lv_workspace_bytes()
  *              of the largest graph that may need it; may be NULL, and then
  *              such items report LV_EWORKSPACE.
@@ -307,6 +311,25 @@ lv_status lv_set_timing(uint32_t mask);
 
 void lv_set_tuning(const lv_tuning* t);
 void lv_get_tuning(lv_tuning* t);
+
+/*
+ * lv_autotune -- picks the degree-bin threshold between the wavefront and
+ * the workgroup mapping of the local-moving scan (Alg. 5) for graph g: for
+ * each wave_max_degree in {64, 128, 256, 512} it times, with HIP events,
+ * `repeats` SYNC local-moving sweeps of g from singletons (every vertex
+ * scanned once) and keeps the fastest.  The other tuning fields stay as
+ * they are.  The result becomes the process-wide tuning (as lv_set_tuning)
+ * and is written to *best when non-null.
+ *   scratch  device C/K/Sigma arrays of g->n entries (contents overwritten;
+ *            size may be NULL)
+ *   ws       lv_workspace_bytes(g->n, g->cap) bytes of device memory
+ * The graph is not modified.  Synchronises `stream`.  Not to be called
+ * while other calls of this library run (they read the tuning).
+ * Returns LV_OK, LV_EINVAL, LV_EWORKSPACE or LV_EHIP (tuning then as
+ * before the call).
+ */
+lv_status lv_autotune(const lv_graph* g, lv_state* scratch, void* ws, size_t ws_bytes, int32_t repeats,
+                      lv_tuning* best, void* stream);
 
 /* Message for the last non-OK status returned on this thread. */
 const char* lv_last_error(void);

@@ -646,6 +646,91 @@ size_t carve_workspace(Workspace& ws, void* base, int32_t n, int64_t cap) {
   return total;
 }
 
+// Batched launches are replayed from captured graphs: copy of the
+// descriptors in, the persistent kernel, copy of the results out.  The
+// kernel reads the item count from the descriptor header, so one graph
+// serves every count up to its size bucket (a power of two); graphs are
+// kept per host thread, keyed by descriptor buffer, bucket and parameters,
+// and copy through one pinned host buffer of that thread.
+struct ManyGraph {
+  void* desc = nullptr;
+  int32_t bucket = 0;
+  lv_params p{};
+  char* host = nullptr;  // the thread's pinned staging buffer
+  hipGraphExec_t exec = nullptr;
+};
+
+struct ManyGraphs {
+  std::vector<ManyGraph> g;
+  char* host = nullptr;
+  size_t host_bytes = 0;
+  hipStream_t cap = nullptr;
+  void drop() {
+    for (auto& x : g) (void)hipGraphExecDestroy(x.exec);
+    g.clear();
+  }
+  ~ManyGraphs() {
+    drop();
+    if (host) (void)hipHostFree(host);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+thread_local ManyGraphs g_many;
+constexpr size_t kManyGraphsMax = 64;
+
+bool same_params(const lv_params& a, const lv_params& b) {
+  return a.tolerance == b.tolerance && a.max_iterations == b.max_iterations && a.mode == b.mode &&
+         a.swap_guard == b.swap_guard;
+}
+
+lv_status many_graph(void* desc, size_t desc_bytes, int32_t count, const lv_params& p, ManyGraph** out) {
+  // the next power of two, within the descriptor buffer (>= count: checked by the caller)
+  const int64_t fit = static_cast<int64_t>((desc_bytes - kManyHeader) / sizeof(ManyItem));
+  int64_t b = 1;
+  while (b < count) b <<= 1;
+  const int32_t bucket = static_cast<int32_t>(std::min<int64_t>(b, fit));
+  const size_t bytes = kManyHeader + sizeof(ManyItem) * static_cast<size_t>(bucket);
+  ManyGraphs& G = g_many;
+  if (bytes > G.host_bytes) {  // a larger staging buffer: graphs that copy through the old one go
+    G.drop();
+    if (G.host) LV_HIP(hipHostFree(G.host));
+    G.host = nullptr;
+    G.host_bytes = 0;
+    void* q = nullptr;
+    LV_HIP(hipHostMalloc(&q, bytes, hipHostMallocDefault));
+    G.host = static_cast<char*>(q);
+    G.host_bytes = bytes;
+  }
+  for (auto& x : G.g)
+    if (x.desc == desc && x.bucket == bucket && same_params(x.p, p)) {
+      *out = &x;
+      return LV_OK;
+    }
+  if (G.g.size() >= kManyGraphsMax) G.drop();
+  if (!G.cap) LV_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+  char* d = static_cast<char*>(desc);
+  hipGraph_t graph = nullptr;
+  LV_HIP(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+  (void)hipMemcpyAsync(d, G.host, bytes, hipMemcpyHostToDevice, G.cap);
+  launch_many_df(reinterpret_cast<const int32_t*>(d), reinterpret_cast<ManyItem*>(d + kManyHeader),
+                 bucket < 4096 ? bucket : 4096, p, G.cap);
+  (void)hipMemcpyAsync(G.host, d, bytes, hipMemcpyDeviceToHost, G.cap);
+  LV_HIP(hipStreamEndCapture(G.cap, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  LV_HIP(e);
+  ManyGraph x;
+  x.desc = desc;
+  x.bucket = bucket;
+  x.p = p;
+  x.host = G.host;
+  x.exec = exec;
+  G.g.push_back(x);
+  *out = &G.g.back();
+  return LV_OK;
+}
+
 }  // namespace lv
 
 using namespace lv;
@@ -807,7 +892,9 @@ lv_status louvain_df(const lv_graph* g, const lv_edges* del, const lv_edges* ins
 
 size_t lv_many_scratch_bytes(int32_t n, int32_t max_updates) { return many_scratch_bytes(n, max_updates); }
 
-size_t lv_many_desc_bytes(int32_t count) { return sizeof(ManyItem) * static_cast<size_t>(count > 0 ? count : 1); }
+size_t lv_many_desc_bytes(int32_t count) {
+  return kManyHeader + sizeof(ManyItem) * static_cast<size_t>(count > 0 ? count : 1);
+}
 
 lv_status louvain_df_many(const lv_item* items, int32_t count, const lv_params* p, void* desc, size_t desc_bytes,
                           void* ws, size_t ws_bytes, int32_t* status, lv_stats* stats, void* stream) {
@@ -850,12 +937,14 @@ lv_status louvain_df_many(const lv_item* items, int32_t count, const lv_params* 
         x.max_updates <= 0 || x.g.n <= 0)
       m.status = LV_ETOOLARGE;
   }
-  ManyItem* d = static_cast<ManyItem*>(desc);
-  LV_HIP(hipMemcpyAsync(d, h.data(), sizeof(ManyItem) * h.size(), hipMemcpyHostToDevice, st));
-  launch_many_df(d, count, *p, st);
-  LV_CHECK_LAUNCH();
-  LV_HIP(hipMemcpyAsync(h.data(), d, sizeof(ManyItem) * h.size(), hipMemcpyDeviceToHost, st));
+  ManyGraph* mg = nullptr;
+  lv_status gs = many_graph(desc, desc_bytes, count, *p, &mg);
+  if (gs) return gs;
+  *reinterpret_cast<int32_t*>(mg->host) = count;
+  std::memcpy(mg->host + kManyHeader, h.data(), sizeof(ManyItem) * h.size());
+  LV_HIP(hipGraphLaunch(mg->exec, st));
   LV_HIP(hipStreamSynchronize(st));
+  std::memcpy(h.data(), mg->host + kManyHeader, sizeof(ManyItem) * h.size());
   const double batched_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   for (int32_t k = 0; k < count; ++k) {
     const ManyItem& m = h[k];
@@ -947,6 +1036,48 @@ void lv_set_tuning(const lv_tuning* t) {
 
 void lv_get_tuning(lv_tuning* t) {
   if (t) *t = effective_tuning();
+}
+
+lv_status lv_autotune(const lv_graph* g, lv_state* scratch, void* ws, size_t ws_bytes, int32_t repeats,
+                      lv_tuning* best, void* stream) {
+  if (!graph_ok(g)) return fail(LV_EINVAL, "invalid graph");
+  if (!scratch || !scratch->C || !scratch->K || !scratch->Sigma) return fail(LV_EINVAL, "invalid scratch state");
+  const lv_tuning base = g_tuning;
+  lv_params p;
+  lv_default_params(&p);
+  p.mode = LV_SYNC;
+  p.max_iterations = 1;
+  p.max_passes = 1;
+  static const int32_t kCandidates[] = {64, 128, 256, 512};
+  float best_ms = 0.f;
+  int32_t best_w = effective_tuning().wave_max_degree;
+  bool have = false;
+  for (const int32_t w : kCandidates) {
+    lv_tuning t = base;
+    t.wave_max_degree = w;
+    g_tuning = t;
+    float ms = 0.f;
+    for (int32_t r = 0; r < std::max(1, repeats); ++r) {
+      lv_stats S;
+      lv_state st = *scratch;
+      const lv_status s = run_louvain(A_STATIC, g, nullptr, nullptr, &p, &st, ws, ws_bytes, &S, stream);
+      if (s != LV_OK) {
+        g_tuning = base;
+        return s;
+      }
+      if (r == 0 || S.ms_move < ms) ms = S.ms_move;
+    }
+    if (!have || ms < best_ms) {
+      have = true;
+      best_ms = ms;
+      best_w = w;
+    }
+  }
+  lv_tuning t = base;
+  t.wave_max_degree = best_w;
+  g_tuning = t;
+  if (best) *best = effective_tuning();
+  return LV_OK;
 }
 
 const char* lv_last_error(void) { return g_last_error.c_str(); }

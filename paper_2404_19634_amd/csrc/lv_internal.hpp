@@ -373,7 +373,10 @@ struct ManyItem {
   int64_t iter_gain[kManyIters];
 };
 size_t many_scratch_bytes(int32_t n, int32_t max_updates);
-void launch_many_df(ManyItem* items, int32_t count, const lv_params& p, hipStream_t st);
+// The descriptor buffer: an int32 item count in a header of kManyHeader
+// bytes, then the items.  The kernel reads the count there.
+constexpr size_t kManyHeader = 256;
+void launch_many_df(const int32_t* count, ManyItem* items, int32_t grid, const lv_params& p, hipStream_t st);
 
 // move.hip
 struct MoveArgs {

@@ -552,9 +552,11 @@ __device__ void build_list(const ManyItem& it, const ItemScratch& s, Shared& sh,
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(kBlock) k_many_df(ManyItem* __restrict__ items, int32_t count, double tol,
-                                                   int32_t max_iterations, int32_t mode, int32_t guard) {
+__global__ void __launch_bounds__(kBlock) k_many_df(const int32_t* __restrict__ count_ptr,
+                                                   ManyItem* __restrict__ items, double tol, int32_t max_iterations,
+                                                   int32_t mode, int32_t guard) {
   __shared__ Shared sh;
+  const int32_t count = *count_ptr;  // the descriptor header: a captured launch serves any count
   for (int32_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
     const ManyItem& it = items[idx];  // uniform: fields come through the scalar cache
     if (it.status != 0) continue;      // rejected by the host (sizes)
@@ -666,9 +668,8 @@ size_t many_scratch_bytes(int32_t n, int32_t max_updates) {
   return 3 * a(4 * words) + 2 * a(4 * un + 4) + a(8 * ps) + 2 * a(4 * ps) + 3 * a(4 * rs) + 2 * a(8 * cap + 4);
 }
 
-void launch_many_df(ManyItem* items, int32_t count, const lv_params& p, hipStream_t st) {
-  const int blocks = count < 4096 ? count : 4096;
-  hipLaunchKernelGGL(k_many_df, dim3(blocks), dim3(kBlock), 0, st, items, count, p.tolerance, p.max_iterations,
+void launch_many_df(const int32_t* count, ManyItem* items, int32_t grid, const lv_params& p, hipStream_t st) {
+  hipLaunchKernelGGL(k_many_df, dim3(grid), dim3(kBlock), 0, st, count, items, p.tolerance, p.max_iterations,
                      p.mode, p.swap_guard);
 }
 

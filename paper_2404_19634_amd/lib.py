@@ -36,7 +36,7 @@ NTIMED = len(TIMED)
 EXPORTS = ["lv_default_params", "lv_workspace_bytes", "lv_graph_capacity_bound", "lv_graph_build",
            "lv_graph_relayout", "apply_batch", "louvain_static", "louvain_nd", "louvain_ds", "louvain_df",
            "modularity", "lv_set_tuning", "lv_get_tuning", "lv_set_timing", "lv_last_error",
-           "lv_many_scratch_bytes", "lv_many_desc_bytes", "louvain_df_many"]
+           "lv_many_scratch_bytes", "lv_many_desc_bytes", "louvain_df_many", "lv_autotune"]
 
 
 class LouvainError(RuntimeError):
@@ -148,6 +148,8 @@ def load():
     L.lv_many_desc_bytes.argtypes = [I32]
     L.louvain_df_many.restype = I32
     L.louvain_df_many.argtypes = [ct.POINTER(CItem), I32, PP, P, SZ, P, SZ, ct.POINTER(I32), STP, P]
+    L.lv_autotune.restype = I32
+    L.lv_autotune.argtypes = [GP, SP, P, SZ, I32, ct.POINTER(Tuning), P]
     L.lv_set_timing.restype = I32
     L.lv_set_timing.argtypes = [ct.c_uint32]
     L.lv_last_error.restype = ct.c_char_p
@@ -201,6 +203,19 @@ def set_tuning(wave_max_degree=0, blocks_small=0, blocks_wave=0, blocks_hub=0,
     load().lv_set_tuning(ct.byref(Tuning(wave_max_degree, blocks_small, blocks_wave, blocks_hub,
                                          async_rounds_log2, async_rounds_min_frontier, async_round_order,
                                          fuse_max_frontier, defer_totals)))
+
+
+def autotune(g: "Graph", repeats: int = 2, stream=None) -> dict:
+    """Picks the wavefront / workgroup degree threshold for graph g by
+    timing full SYNC sweeps (lv_autotune); the choice becomes the
+    process-wide tuning.  Returns the tuning now in force."""
+    L = load()
+    st = State.empty(g.n, g.device, with_size=False)
+    cs, cg = st.c(), g.c()
+    ws, nb = g.ws_args()
+    out = Tuning()
+    _check(L.lv_autotune(ct.byref(cg), ct.byref(cs), ws, nb, int(repeats), ct.byref(out), _stream(stream)))
+    return {f: getattr(out, f) for f, _ in Tuning._fields_}
 
 
 def get_tuning() -> dict:

@@ -394,6 +394,23 @@ def test_hub_paths_sync_bit_exact(lib, make):
         _same_stats(gs, os_)
 
 
+def test_autotune_picks_a_candidate_and_keeps_results(lib):
+    """The autotuner leaves one of its candidate thresholds in force, and
+    SYNC results under it still match the oracle."""
+    e = W.rmat(14, 8, 0.57, 0.19, 0.19, 6)
+    g = lib.Graph.from_edges(e)
+    try:
+        t = lib.autotune(g, repeats=1)
+        assert t["wave_max_degree"] in (64, 128, 256, 512)
+        assert lib.get_tuning()["wave_max_degree"] == t["wave_max_degree"]
+        st, gs = lib.louvain_static(g, mode="sync")
+        Co, Ko, So, os_ = _orc(e).louvain("static", mode="sync")
+        assert np.array_equal(st.C.cpu().numpy(), Co) and np.array_equal(st.Sigma.cpu().numpy(), So)
+        _same_stats(gs, os_)
+    finally:
+        lib.set_tuning()
+
+
 def test_bin_stats_and_timing_hook(lib):
     """Per-bin work adds up to the scan totals, and the event hook times
     exactly the launches it was asked for."""
@@ -474,6 +491,44 @@ def test_many_graphs_match_single_graph_results(lib, mode, tol):
           for k, (e, b) in enumerate(cases)]
     status, _ = lib.louvain_df_many(graphs, b2, states, scratches, cap, ws=ws, mode=mode, tolerance=tol)
     assert status == [0] * len(cases), status
+
+
+def test_many_graph_replays_match_eager_calls(lib):
+    """Batched launches through one descriptor buffer replay a captured
+    graph (the first call captures it).  Over a chain of SYNC batches, with
+    eager apply_batch + louvain_df calls on twin graphs and synchronisations
+    between the replays, every replay's graphs and states equal the twins'."""
+    specs = W.multi_sbm_specs(6, 321, n_lo=500, n_hi=4000, b_lo=20, b_hi=300)
+    edges = [W.multi_sbm_graph(n, b, sd) for n, b, sd in specs]
+    chains, cap = [], 0
+    for k, e in enumerate(edges):
+        cur, bs = e, []
+        for t in range(4):
+            b = W.random_batch(cur, max(4, cur.m // 200), 500 + 10 * k + t)
+            bs.append(b)
+            cap = max(cap, b.size)
+            cur = W.apply_batch_np(cur, b)
+        chains.append(bs)
+    graphs = [lib.Graph.from_edges(e, slack_frac=1.0, slack_min=32) for e in edges]
+    twins = [lib.Graph.from_edges(e, slack_frac=1.0, slack_min=32) for e in edges]
+    states = [lib.louvain_static(g, mode="sync")[0] for g in graphs]
+    twin_states = [st.clone() for st in states]
+    scratches = [lib.many_scratch(g.n, cap) for g in graphs]
+    desc = torch.empty(int(lib.load().lv_many_desc_bytes(len(graphs))), dtype=torch.uint8, device="cuda")
+    ws = max(graphs, key=lambda g: g.n * 4 + g.cap).workspace
+    for t in range(4):
+        bs = [lib.Batch.from_host(c[t]) for c in chains]
+        status, _ = lib.louvain_df_many(graphs, bs, states, scratches, cap, ws=ws, desc=desc, mode="sync")
+        assert status == [0] * len(graphs), (t, status)
+        for k in range(len(graphs)):
+            lib.apply_batch(twins[k], bs[k])
+            twin_states[k], _ = lib.louvain_df(twins[k], bs[k], twin_states[k], mode="sync")
+        torch.cuda.synchronize()
+        for g, tw, st, ts in zip(graphs, twins, states, twin_states):
+            assert all(np.array_equal(x, y) for x, y in zip(g.csr_host(), tw.csr_host())), t
+            for x, y in zip(st.host(), ts.host()):
+                assert np.array_equal(x, y), t
+            assert np.array_equal(st.size.cpu().numpy(), ts.size.cpu().numpy()), t
 
 
 def test_many_graphs_isolate_bad_batches(lib):
