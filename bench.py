@@ -441,6 +441,8 @@ def main():
     ap.add_argument("--mode", default="async", choices=["async", "sync"])
     ap.add_argument("--static-runs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tuning instead of lv_autotune's choice for the graph")
     ap.add_argument("--no-approaches", action="store_true",
                     help="skip the ND/DS/DF x SYNC/ASYNC comparison and the full-sweep roofline")
     ap.add_argument("--tuning", default="", help="lv_tuning overrides, e.g. fuse_max_frontier=1024,defer_totals=1")
@@ -496,6 +498,12 @@ def main():
     if args.sweep:
         sweep(g, e, args.sweep)
         return
+    autotune_ms = None
+    if not args.no_autotune and "wave_max_degree" not in tuning:
+        t = time.perf_counter()
+        lib.autotune(g, repeats=2)
+        autotune_ms = (time.perf_counter() - t) * 1e3
+        log(f"autotune: {lib.get_tuning()} ({autotune_ms:.0f} ms)")
 
     # GPU static Louvain on the initial graph (comparison baseline)
     static_ms, static_arcs, static_stats = [], [], None
@@ -596,7 +604,7 @@ def main():
         "config": {"workload": f"R-MAT scale {args.scale} (edge factor 16, a=0.57 b=0.19 c=0.19), "
                                f"random 80/20 batches of 1e-7..1e-3 |E|",
                    "vertices": e.n, "undirected_edges": e.m, "batch_sizes": sizes, "mode": args.mode,
-                   "tuning": lib.get_tuning()},
+                   "tuning": lib.get_tuning(), "autotuned": autotune_ms is not None, "autotune_ms": autotune_ms},
         "df_latency_ms_p50": pct(lat, 50),
         "df_latency_ms_p99": pct(lat, 99),
         "df_latency_ms_by_batch_size": {str(k): float(np.median(v)) for k, v in sorted(per_size.items())},

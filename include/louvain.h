@@ -317,7 +317,8 @@ void lv_get_tuning(lv_tuning* t);
  * the workgroup mapping of the local-moving scan (Alg. 5) for graph g: for
  * each wave_max_degree in {64, 128, 256, 512} it times, with HIP events,
  * `repeats` SYNC local-moving sweeps of g from singletons (every vertex
- * scanned once) and keeps the fastest.  The other tuning fields stay as
+ * scanned once) and keeps the fastest, unless the threshold in force is
+ * within 3% of it (then that one stays).  The other tuning fields stay as
  * they are.  The result becomes the process-wide tuning (as lv_set_tuning)
  * and is written to *best when non-null.
  *   scratch  device C/K/Sigma arrays of g->n entries (contents overwritten;

@@ -1049,8 +1049,12 @@ lv_status lv_autotune(const lv_graph* g, lv_state* scratch, void* ws, size_t ws_
   p.max_iterations = 1;
   p.max_passes = 1;
   static const int32_t kCandidates[] = {64, 128, 256, 512};
-  float best_ms = 0.f;
-  int32_t best_w = effective_tuning().wave_max_degree;
+  // the threshold in force stays unless a candidate is faster by more than
+  // kAutotuneMargin (run-to-run timing noise is a few per cent)
+  constexpr float kAutotuneMargin = 0.03f;
+  const int32_t current = effective_tuning().wave_max_degree;
+  float best_ms = 0.f, current_ms = -1.f;
+  int32_t best_w = current;
   bool have = false;
   for (const int32_t w : kCandidates) {
     lv_tuning t = base;
@@ -1067,12 +1071,14 @@ lv_status lv_autotune(const lv_graph* g, lv_state* scratch, void* ws, size_t ws_
       }
       if (r == 0 || S.ms_move < ms) ms = S.ms_move;
     }
+    if (w == current) current_ms = ms;
     if (!have || ms < best_ms) {
       have = true;
       best_ms = ms;
       best_w = w;
     }
   }
+  if (current_ms >= 0.f && best_ms > current_ms * (1.f - kAutotuneMargin)) best_w = current;
   lv_tuning t = base;
   t.wave_max_degree = best_w;
   g_tuning = t;
