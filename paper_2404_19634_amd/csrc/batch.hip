@@ -242,6 +242,17 @@ __global__ void __launch_bounds__(kBlock) k_scan(const int64_t* __restrict__ row
     const BatchScratch::Chunk c = b.chunk[ch];
     const int32_t a = c.a, cnt = c.cnt, pbase = c.pbase, off = c.off, end = c.end;
     const int64_t s = c.s;
+    if (end - off <= kWave) {
+      // a chunk of at most one arc per lane looks every arc up directly
+      // (the filter would cost more round trips than it saves)
+      const int32_t k = off + lane;
+      if (k < end) {
+        const int32_t cc = col[s + k];
+        const int32_t p = pair_find(b.keys, b.size, canon(a, cc));
+        if (p >= 0) b.pos[2 * static_cast<int64_t>(p) + (a > cc ? 1 : 0)] = s + k;
+      }
+      continue;
+    }
     for (int i = lane; i < kFilterBits / 32; i += kWave) F[i] = 0;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
