@@ -8,9 +8,11 @@
 //   <= 256   one wavefront, LDS table of 512 slots;
 //   <= 2048  one workgroup, LDS table of 4096 slots;
 //   larger   many workgroups: the community's arc range is cut into units of
-//            8192 arcs; each unit pre-aggregates in an LDS table and flushes
+//            2048 arcs; each unit sums its arcs per neighbour community in an
+//            LDS table (at most 2048 keys in 4096 slots) and flushes the sums
 //            into the community's global table (2 x min(volume, communities)
-//            slots), then emit units compact the table into the row.
+//            slots of packed key:weight pairs), then emit units compact the
+//            table into the row.
 // Arcs into the community itself (its self-loop weight, usually the most
 // frequent key) are summed in registers in every tier.  K''_c = Σ''_c is
 // the row sum.
@@ -23,11 +25,18 @@ constexpr int kAggWaveVol = 256;
 constexpr int kAggWaveTS = 512;
 constexpr int kAggBlockVol = 2048;
 constexpr int kAggBlockTS = 4096;
-constexpr int kUnitArcs = 8192;       // arcs per insert unit of a big community
+constexpr int kUnitArcs = 2048;       // arcs per insert unit of a big community
 constexpr int kArcsPerThread = kUnitArcs / kBlock;
 constexpr int kEmitSlots = 4096;      // table slots per emit unit
 constexpr int kUnitTS = 4096;         // LDS slots for a unit's pre-aggregation
-constexpr int kUnitProbes = 8;
+// A global table slot packs a key (high half) and a weight (low half): one
+// compare-and-swap inserts a new key with its weight; a hit adds to the low
+// half, which never carries (a sum of arc weights stays below 2m < 2^31).
+constexpr unsigned long long kEmptyPair = 0xFFFFFFFF00000000ull;
+
+__device__ __forceinline__ unsigned long long pack_pair(int32_t d, int32_t x) {
+  return (static_cast<unsigned long long>(static_cast<uint32_t>(d)) << 32) | static_cast<uint32_t>(x);
+}
 
 // Global table slots of a big community: distinct neighbour communities are
 // at most min(volume, communities), load factor <= 1/2.
@@ -139,8 +148,8 @@ __global__ void __launch_bounds__(kBlock) k_big_clear(const int32_t* __restrict_
                                                      const int64_t* __restrict__ emit_s,
                                                      const int32_t* __restrict__ big, const int64_t* __restrict__ big_off,
                                                      const int64_t* __restrict__ out_start,
-                                                     const int64_t* __restrict__ ctr, int32_t nc, int32_t* __restrict__ keys,
-                                                     int32_t* __restrict__ vals, int64_t pool_slots) {
+                                                     const int64_t* __restrict__ ctr, int32_t nc,
+                                                     unsigned long long* __restrict__ tab, int64_t pool_slots) {
   const int64_t count = ctr[CTR_UNITS_EMIT];
   for (int64_t u = blockIdx.x; u < count; u += gridDim.x) {
     const int32_t b = emit_b[u];
@@ -149,34 +158,39 @@ __global__ void __launch_bounds__(kBlock) k_big_clear(const int32_t* __restrict_
     const int64_t off = big_off[b];
     if (off + tsz > pool_slots) continue;  // reported by the insert kernel
     const int64_t s1 = min(tsz, emit_s[u] + kEmitSlots);
-    for (int64_t s = emit_s[u] + threadIdx.x; s < s1; s += kBlock) {
-      keys[off + s] = -1;
-      vals[off + s] = 0;
-    }
+    for (int64_t s = emit_s[u] + threadIdx.x; s < s1; s += kBlock) tab[off + s] = kEmptyPair;
   }
 }
 
-__device__ __forceinline__ void global_table_add(int32_t* keys, int32_t* vals, uint32_t tsz, int32_t d, int32_t x) {
+__device__ __forceinline__ void table_add(unsigned long long* tab, uint32_t tsz, int32_t d, int32_t x) {
   uint32_t h = hash_slot(static_cast<uint32_t>(d), tsz);
   while (true) {
-    const int32_t old = atomicCAS(&keys[h], -1, d);
-    if (old == -1 || old == d) {
-      atomicAdd(&vals[h], x);
+    const unsigned long long old = atomicCAS(&tab[h], kEmptyPair, pack_pair(d, x));
+    if (old == kEmptyPair) return;
+    if (static_cast<int32_t>(old >> 32) == d) {
+      atomicAdd(&tab[h], static_cast<unsigned long long>(static_cast<uint32_t>(x)));
       return;
     }
     h = (h + 1 == tsz) ? 0 : h + 1;
   }
 }
 
+// One workgroup per insert unit.  The unit's members' first-arc offsets are
+// staged in LDS; each thread then takes kArcsPerThread consecutive arcs and
+// issues their loads in batches (member rows, arcs, neighbour communities)
+// so the latencies overlap; sums go to the LDS table, and the table is
+// flushed in rounds of compare-and-swaps that are in flight together.
 __global__ void __launch_bounds__(kBlock) k_big_insert(
     const int64_t* __restrict__ row_start, const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
     const int32_t* __restrict__ C, const int32_t* __restrict__ coff, const int32_t* __restrict__ cmem,
     const int64_t* __restrict__ mpre, const int32_t* __restrict__ ins_b, const int64_t* __restrict__ ins_a,
     const int32_t* __restrict__ big, const int64_t* __restrict__ big_off, const int64_t* __restrict__ out_start,
-    int64_t* __restrict__ ctr, int32_t nc, int32_t* __restrict__ keys, int32_t* __restrict__ vals,
-    int64_t pool_slots) {
+    int64_t* __restrict__ ctr, int32_t nc, unsigned long long* __restrict__ tab_all, int64_t pool_slots) {
+  constexpr int A = kArcsPerThread;
   __shared__ int32_t tk[kUnitTS];
   __shared__ int32_t tv[kUnitTS];
+  __shared__ int32_t s_moff[kUnitArcs + 2];  // member first-arc offsets from the unit start
+  __shared__ int32_t s_mlo, s_mcnt;
   __shared__ int64_t r_self[kBlock / kWave];
   const int64_t count = ctr[CTR_UNITS_INS];
   const int lane = lane_id();
@@ -191,68 +205,130 @@ __global__ void __launch_bounds__(kBlock) k_big_insert(
       if (threadIdx.x == 0) set_error(ctr, LV_EWORKSPACE);
       continue;
     }
-    int32_t* gk = keys + off;
-    int32_t* gv = vals + off;
-    for (int s = threadIdx.x; s < kUnitTS; s += kBlock) {
-      tk[s] = -1;
-      tv[s] = 0;
+    unsigned long long* tab = tab_all + off;
+    for (int sl = threadIdx.x; sl < kUnitTS; sl += kBlock) {
+      tk[sl] = -1;
+      tv[sl] = 0;
     }
-    __syncthreads();
-    // this thread's arcs, as offsets into the community's arc range
     const int32_t m0 = coff[c], m1 = coff[c + 1];
     const int64_t base = mpre[m0];
-    const int64_t a_begin = ins_a[u] + static_cast<int64_t>(threadIdx.x) * kArcsPerThread;
-    const int64_t a_end = min(vol, min(ins_a[u] + kUnitArcs, a_begin + kArcsPerThread));
-    int64_t self = 0;
-    if (a_begin < a_end) {
-      // last member whose first arc is <= a_begin
+    const int64_t a_u = ins_a[u];
+    if (threadIdx.x == 0) {  // last member whose first arc is <= the unit's first arc
       int32_t lo = m0, hi = m1 - 1;
       while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
-        if (mpre[mid] - base <= a_begin) lo = mid;
+        if (mpre[mid] - base <= a_u) lo = mid;
         else hi = mid - 1;
       }
-      int32_t k = lo;
-      int64_t k_first = mpre[k] - base, k_next = mpre[k + 1] - base;
-      int64_t rs = row_start[cmem[k]];
-      for (int64_t a = a_begin; a < a_end; ++a) {
-        while (a >= k_next) {
-          ++k;
-          k_first = k_next;
-          k_next = mpre[k + 1] - base;
-          rs = row_start[cmem[k]];
+      s_mlo = lo;
+      // members starting inside the unit number at most kUnitArcs; one more
+      // entry bounds the last one
+      s_mcnt = static_cast<int32_t>(min(static_cast<int64_t>(m1 - lo), static_cast<int64_t>(kUnitArcs + 1)));
+    }
+    __syncthreads();
+    const int32_t mlo = s_mlo, mcnt = s_mcnt;
+    for (int t = threadIdx.x; t <= mcnt; t += kBlock)
+      s_moff[t] = static_cast<int32_t>(min(mpre[mlo + t] - base - a_u, static_cast<int64_t>(kUnitArcs)));
+    __syncthreads();
+    // this thread's arcs: unit offsets [o0, o0 + A)
+    const int32_t o0 = threadIdx.x * A;
+    const int32_t olim = static_cast<int32_t>(min(static_cast<int64_t>(kUnitArcs), vol - a_u));
+    int32_t mt[A];
+#pragma unroll
+    for (int q = 0; q < A; ++q) {
+      const int32_t o = o0 + q;
+      int32_t lo = 0, hi = mcnt - 1;  // last staged member with s_moff <= o
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (s_moff[mid] <= o) lo = mid;
+        else hi = mid - 1;
+      }
+      mt[q] = lo;
+    }
+    // an arc is taken when its member's range holds it (members start at
+    // most kUnitArcs times inside a unit unless some have no arcs, which a
+    // community of more than one vertex never has)
+    bool ok[A];
+#pragma unroll
+    for (int q = 0; q < A; ++q) {
+      ok[q] = o0 + q < olim && o0 + q < s_moff[mt[q] + 1];
+      if (o0 + q < olim && !ok[q]) set_error(ctr, LV_EINVAL);
+    }
+    int32_t cm[A];
+#pragma unroll
+    for (int q = 0; q < A; ++q) cm[q] = ok[q] ? cmem[mlo + mt[q]] : 0;
+    int64_t pp[A];
+#pragma unroll
+    for (int q = 0; q < A; ++q) pp[q] = ok[q] ? row_start[cm[q]] + (o0 + q - s_moff[mt[q]]) : 0;
+    int32_t js[A], xs[A];
+#pragma unroll
+    for (int q = 0; q < A; ++q) {
+      js[q] = ok[q] ? col[pp[q]] : 0;
+      xs[q] = ok[q] ? wt[pp[q]] : 0;
+    }
+    int32_t ds[A];
+#pragma unroll
+    for (int q = 0; q < A; ++q) ds[q] = ok[q] ? C[js[q]] : c;
+    int64_t self = 0;
+#pragma unroll
+    for (int q = 0; q < A; ++q) {
+      if (!ok[q]) continue;
+      const int32_t d = ds[q], x = xs[q];
+      if (d == c) {
+        self += x;
+        continue;
+      }
+      uint32_t h = mix32(static_cast<uint32_t>(d)) & (kUnitTS - 1);
+      while (true) {  // at most kUnitArcs keys in kUnitTS = 2 kUnitArcs slots: ends
+        const int32_t old = atomicCAS(&tk[h], -1, d);
+        if (old == -1 || old == d) {
+          atomicAdd(&tv[h], x);
+          break;
         }
-        const int64_t p = rs + (a - k_first);
-        const int32_t d = C[col[p]];
-        const int32_t x = wt[p];
-        if (d == c) {
-          self += x;
-          continue;
-        }
-        uint32_t h = hash_slot(static_cast<uint32_t>(d), kUnitTS);
-        bool done = false;
-        for (int q = 0; q < kUnitProbes; ++q) {
-          const int32_t old = atomicCAS(&tk[h], -1, d);
-          if (old == -1 || old == d) {
-            atomicAdd(&tv[h], x);
-            done = true;
-            break;
-          }
-          h = (h + 1) & (kUnitTS - 1);
-        }
-        if (!done) global_table_add(gk, gv, tsz, d, x);
+        h = (h + 1) & (kUnitTS - 1);
       }
     }
     self = wave_sum_i64(self);
     if (lane == 0) r_self[wid] = self;
     __syncthreads();
     if (threadIdx.x == 0) {
-      int64_t s = 0;
-      for (int q = 0; q < kBlock / kWave; ++q) s += r_self[q];
-      if (s) global_table_add(gk, gv, tsz, c, static_cast<int32_t>(s));
+      int64_t sum = 0;
+      for (int q = 0; q < kBlock / kWave; ++q) sum += r_self[q];
+      if (sum) table_add(tab, tsz, c, static_cast<int32_t>(sum));
     }
-    for (int s = threadIdx.x; s < kUnitTS; s += kBlock)
-      if (tk[s] >= 0) global_table_add(gk, gv, tsz, tk[s], tv[s]);
+    // flush: the thread's table slots in rounds of compare-and-swaps
+    constexpr int F = 8;
+    for (int s0 = 0; s0 < kUnitTS; s0 += F * kBlock) {
+      int32_t fk[F], fv[F];
+      uint32_t fp[F];
+      uint32_t pend = 0;
+#pragma unroll
+      for (int q = 0; q < F; ++q) {
+        const int sl = s0 + threadIdx.x + q * kBlock;
+        fk[q] = tk[sl];
+        fv[q] = tv[sl];
+        fp[q] = fk[q] >= 0 ? hash_slot(static_cast<uint32_t>(fk[q]), tsz) : 0;
+        if (fk[q] >= 0) pend |= 1u << q;
+      }
+      while (pend) {
+        unsigned long long old[F];
+#pragma unroll
+        for (int q = 0; q < F; ++q)
+          old[q] = (pend >> q) & 1u ? atomicCAS(&tab[fp[q]], kEmptyPair, pack_pair(fk[q], fv[q])) : kEmptyPair;
+#pragma unroll
+        for (int q = 0; q < F; ++q) {
+          if (!((pend >> q) & 1u)) continue;
+          if (old[q] == kEmptyPair) {
+            pend &= ~(1u << q);
+          } else if (static_cast<int32_t>(old[q] >> 32) == fk[q]) {
+            atomicAdd(&tab[fp[q]], static_cast<unsigned long long>(static_cast<uint32_t>(fv[q])));
+            pend &= ~(1u << q);
+          } else {
+            fp[q] = fp[q] + 1 == tsz ? 0 : fp[q] + 1;
+          }
+        }
+      }
+    }
     __syncthreads();
   }
 }
@@ -263,8 +339,8 @@ __global__ void __launch_bounds__(kBlock) k_big_emit(const int32_t* __restrict__
                                                     const int64_t* __restrict__ emit_s,
                                                     const int32_t* __restrict__ big, const int64_t* __restrict__ big_off,
                                                     const int64_t* __restrict__ out_start, const int64_t* __restrict__ ctr,
-                                                    int32_t nc, const int32_t* __restrict__ keys,
-                                                    const int32_t* __restrict__ vals, int64_t pool_slots,
+                                                    int32_t nc, const unsigned long long* __restrict__ tab,
+                                                    int64_t pool_slots,
                                                     int32_t* __restrict__ out_len, int32_t* __restrict__ out_col,
                                                     int32_t* __restrict__ out_w, int64_t* __restrict__ Kout,
                                                     int64_t* __restrict__ Sout) {
@@ -288,8 +364,9 @@ __global__ void __launch_bounds__(kBlock) k_big_emit(const int32_t* __restrict__
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       const int64_t s = s0 + j;
-      d[j] = s < tsz ? keys[off + s] : -1;
-      x[j] = d[j] >= 0 ? vals[off + s] : 0;
+      const unsigned long long e = s < tsz ? tab[off + s] : kEmptyPair;
+      d[j] = static_cast<int32_t>(e >> 32);
+      x[j] = static_cast<int32_t>(static_cast<uint32_t>(e));
       mine += d[j] >= 0 ? 1 : 0;
     }
     // exclusive scan of `mine` over the workgroup
@@ -567,13 +644,13 @@ void launch_aggregate(const LevelGraph& g, const int32_t* C, int32_t nc, LevelGr
                      ws.u_ins_a, ws.u_emit_b, ws.u_emit_s, ws.ctr);
   const int gb = 4 * tu.blocks_hub;
   hipLaunchKernelGGL(k_big_clear, dim3(gb), dim3(kBlock), 0, st, ws.u_emit_b, ws.u_emit_s, ws.bins[2], ws.hub_off,
-                     out.row_start, ws.ctr, nc, ws.pool_keys, ws.pool_vals, ws.pool_slots);
+                     out.row_start, ws.ctr, nc, reinterpret_cast<unsigned long long*>(ws.pool_pairs), ws.pool_slots);
   hipLaunchKernelGGL(k_big_insert, dim3(gb), dim3(kBlock), 0, st, g.row_start, g.col, g.w, C, ws.coff, ws.cmem,
                      ws.vol, ws.u_ins_b, ws.u_ins_a, ws.bins[2], ws.hub_off, out.row_start, ws.ctr, nc,
-                     ws.pool_keys, ws.pool_vals, ws.pool_slots);
+                     reinterpret_cast<unsigned long long*>(ws.pool_pairs), ws.pool_slots);
   hipLaunchKernelGGL(k_big_emit, dim3(gb), dim3(kBlock), 0, st, ws.u_emit_b, ws.u_emit_s, ws.bins[2], ws.hub_off,
-                     out.row_start, ws.ctr, nc, ws.pool_keys, ws.pool_vals, ws.pool_slots, out.row_len, out.col,
-                     out.w, Kout, Sout);
+                     out.row_start, ws.ctr, nc, reinterpret_cast<const unsigned long long*>(ws.pool_pairs),
+                     ws.pool_slots, out.row_len, out.col, out.w, Kout, Sout);
   // the next level starts from singletons; written only after the merges,
   // which still read the current membership (the same array from pass 1 on)
   launch_iota_i32(Cout, nc, st);

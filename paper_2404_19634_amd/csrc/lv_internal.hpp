@@ -246,6 +246,19 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t key, uint32_t size) {
   return static_cast<uint32_t>((static_cast<uint64_t>(h) * size) >> 32);
 }
 
+// MurmurHash3's 32-bit finalizer: a second hash, independent of hash_slot's
+// ordering, for tables whose keys may arrive sorted by hash_slot (the hub
+// segments chosen by hash_slot, the rows an aggregation emits in
+// hash_slot order).
+__device__ __forceinline__ uint32_t mix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
 // --------------------------------------------------------------------------
 // Launchers (host).  All enqueue on `st`; none synchronises.
 // --------------------------------------------------------------------------

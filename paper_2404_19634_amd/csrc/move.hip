@@ -1006,7 +1006,10 @@ __device__ __forceinline__ void role_hub_insert(const Dev& D, const HubIn& H, in
         kid += x;
         continue;
       }
-      uint32_t p = hash_slot(static_cast<uint32_t>(c), kHubTS);
+      // mix32, not hash_slot: an aggregated row lists its arcs in the order
+      // of its community table's hash_slot, so a unit's keys share their
+      // top hash bits and would pile into a few slots
+      uint32_t p = mix32(static_cast<uint32_t>(c)) & (kHubTS - 1);
       bool done = false;
       // a partitioned row's unit has at most kHubUnitArcs keys, half the
       // table: probing always ends
@@ -1174,17 +1177,6 @@ __global__ void __launch_bounds__(kBlock) k_hub_clear(Dev D, const int32_t* __re
     const int64_t s1 = min(tsz, c_s[u] + kHubClearSlots);
     for (int64_t s = c_s[u] + threadIdx.x; s < s1; s += kBlock) tab[off + s] = kEmptyPair;
   }
-}
-
-// MurmurHash3's 32-bit finalizer: the decide units index their LDS tables
-// with it, independently of the multiplicative hash that chose the segment.
-__device__ __forceinline__ uint32_t mix32(uint32_t h) {
-  h ^= h >> 16;
-  h *= 0x85EBCA6Bu;
-  h ^= h >> 13;
-  h *= 0xC2B2AE35u;
-  h ^= h >> 16;
-  return h;
 }
 
 // Keys one pass of a decide unit holds in its 4096-slot table; the rest of
