@@ -599,6 +599,7 @@ size_t carve_workspace(Workspace& ws, void* base, int32_t n, int64_t cap) {
   ws.dE = take<uint32_t>(cur, total, base, ws.words);
   ws.dC = take<uint32_t>(cur, total, base, ws.words);
   ws.moved = take<uint32_t>(cur, total, base, ws.words);
+  ws.push_flags = take<uint8_t>(cur, total, base, static_cast<size_t>(ws.words) * 32);
   for (int b = 0; b < NBINS; ++b) ws.bins[b] = take<int32_t>(cur, total, base, un);
   ws.hub_off = take<int64_t>(cur, total, base, un);
   ws.hub_kid = take<int64_t>(cur, total, base, un);

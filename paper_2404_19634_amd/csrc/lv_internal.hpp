@@ -107,6 +107,7 @@ struct Workspace {
   uint32_t* dE = nullptr;     // DS: neighbours-affected flags
   uint32_t* dC = nullptr;     // DS: community-affected flags
   uint32_t* moved = nullptr;  // vertices moved in this iteration (pull expansion)
+  uint8_t* push_flags = nullptr;  // one byte per vertex (32 per frontier word) for the push expansion
   int32_t* bins[NBINS] = {};
   int64_t* hub_off = nullptr;  // global-table offset of each hub item
   int64_t* hub_kid = nullptr;  // hub items: weight into the vertex's own community

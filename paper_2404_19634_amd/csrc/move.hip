@@ -1531,15 +1531,17 @@ __global__ void __launch_bounds__(kBlock) k_pull_long(const int64_t* __restrict_
   }
 }
 
-// Push: one wavefront per word of the movers bitmask ORs in the neighbours
+// Push: one wavefront per word of the movers bitmask flags the neighbours
 // of its movers whose rows are short, a lane per arc; longer rows are
-// queued for a workgroup each.
+// queued for a workgroup each.  Flags are byte stores (idempotent, no
+// read-modify-write at the memory side, unlike a bitmask atomicOr per arc);
+// a last kernel packs them into the next frontier's words.
 constexpr int32_t kPushShortMax = 256;
 
 __global__ void __launch_bounds__(kBlock) k_push_words(const int64_t* __restrict__ row_start,
                                                       const int32_t* __restrict__ row_len,
                                                       const int32_t* __restrict__ col, int32_t n,
-                                                      const uint32_t* __restrict__ moved, uint32_t* __restrict__ next,
+                                                      const uint32_t* __restrict__ moved, uint8_t* __restrict__ flags,
                                                       int32_t* __restrict__ longlist, int64_t* __restrict__ ctr,
                                                       const int64_t* __restrict__ sc) {
   if (!expand_by_push(sc)) return;
@@ -1573,7 +1575,7 @@ __global__ void __launch_bounds__(kBlock) k_push_words(const int64_t* __restrict
       const int64_t vs = __shfl(s, b);
       for (int32_t k = lane; k < vl; k += kWave) {
         const int32_t j = col[vs + k];
-        if (j != v) set_bit(next, j);
+        if (j != v) flags[j] = 1;
       }
     }
   }
@@ -1581,7 +1583,7 @@ __global__ void __launch_bounds__(kBlock) k_push_words(const int64_t* __restrict
 
 __global__ void __launch_bounds__(kBlock) k_push_long(const int64_t* __restrict__ row_start,
                                                      const int32_t* __restrict__ row_len,
-                                                     const int32_t* __restrict__ col, uint32_t* __restrict__ next,
+                                                     const int32_t* __restrict__ col, uint8_t* __restrict__ flags,
                                                      const int32_t* __restrict__ longlist,
                                                      const int64_t* __restrict__ ctr, const int64_t* __restrict__ sc) {
   if (!expand_by_push(sc)) return;
@@ -1592,8 +1594,26 @@ __global__ void __launch_bounds__(kBlock) k_push_long(const int64_t* __restrict_
     const int32_t len = row_len[i];
     for (int32_t k = threadIdx.x; k < len; k += kBlock) {
       const int32_t j = col[s + k];
-      if (j != i) set_bit(next, j);
+      if (j != i) flags[j] = 1;
     }
+  }
+}
+
+// The pushed flags of 32 vertices become one word of the next frontier.
+__global__ void __launch_bounds__(kBlock) k_push_pack(const uint8_t* __restrict__ flags, uint32_t* __restrict__ next,
+                                                     int64_t words, const int64_t* __restrict__ sc) {
+  if (!expand_by_push(sc)) return;
+  for (int64_t w = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; w < words;
+       w += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const uint4* f = reinterpret_cast<const uint4*>(flags + w * 32);
+    const uint4 lo = f[0], hi = f[1];
+    const uint32_t part[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    uint32_t bits = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bits |= ((part[q] >> (8 * b)) & 0xFFu ? 1u : 0u) << (4 * q + b);
+    next[w] = bits;
   }
 }
 
@@ -1759,11 +1779,14 @@ void launch_pull_expand(const MoveArgs& a, Workspace& ws, hipStream_t st) {
                      a.g.row_len, a.g.col, a.g.n, a.moved, a.next, ws.bins[NBINS - 1] + 0, ws.ctr, a.sc);
   hipLaunchKernelGGL(k_pull_long, dim3(1024), dim3(kBlock), 0, st, a.g.row_start, a.g.row_len, a.g.col, a.moved,
                      a.next, ws.bins[NBINS - 1] + 0, ws.ctr, a.sc);
-  // (only one of the pair above and the pair below does any work)
+  // (only one of the pair above and the three below does any work)
+  (void)hipMemsetAsync(ws.push_flags, 0, static_cast<size_t>(words) * 32, st);
   hipLaunchKernelGGL(k_push_words, dim3(grid_for(words * kWave, kBlock, 8192)), dim3(kBlock), 0, st, a.g.row_start,
-                     a.g.row_len, a.g.col, a.g.n, a.moved, a.next, ws.bins[NBINS - 1] + 0, ws.ctr, a.sc);
-  hipLaunchKernelGGL(k_push_long, dim3(1024), dim3(kBlock), 0, st, a.g.row_start, a.g.row_len, a.g.col, a.next,
-                     ws.bins[NBINS - 1] + 0, ws.ctr, a.sc);
+                     a.g.row_len, a.g.col, a.g.n, a.moved, ws.push_flags, ws.bins[NBINS - 1] + 0, ws.ctr, a.sc);
+  hipLaunchKernelGGL(k_push_long, dim3(1024), dim3(kBlock), 0, st, a.g.row_start, a.g.row_len, a.g.col,
+                     ws.push_flags, ws.bins[NBINS - 1] + 0, ws.ctr, a.sc);
+  hipLaunchKernelGGL(k_push_pack, dim3(grid_for(words, kBlock, 4096)), dim3(kBlock), 0, st, ws.push_flags, a.next,
+                     words, a.sc);
 }
 
 void launch_apply_moves(const MoveArgs& a, Workspace& ws, bool clear_moved, hipStream_t st) {
