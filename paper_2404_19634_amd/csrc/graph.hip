@@ -138,10 +138,22 @@ __global__ void __launch_bounds__(kBlock) k_rows_group(const int64_t* __restrict
     const int64_t s = row_start[i];
     const int32_t ci = C ? C[i] : 0;
     int64_t acc = 0, in = 0;
-    for (int32_t k = sub; k < len; k += kRowGroup) {
-      const int32_t x = wt[s + k];
-      acc += x;
-      if (C && C[col[s + k]] == ci) in += x;
+    // four arcs per lane per step, loads first, so their latencies overlap
+    for (int32_t k0 = sub; k0 < len; k0 += 4 * kRowGroup) {
+      int32_t x[4], c[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = k0 + q * kRowGroup < len ? wt[s + k0 + q * kRowGroup] : 0;
+      if (C) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[q] = k0 + q * kRowGroup < len ? col[s + k0 + q * kRowGroup] : -1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[q] = c[q] >= 0 ? C[c[q]] : ci - 1;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        acc += x[q];
+        if (C && c[q] == ci) in += x[q];
+      }
     }
 #pragma unroll
     for (int q = 1; q < kRowGroup; q <<= 1) acc += __shfl_xor(acc, q);
