@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as ct
 import os
+from collections.abc import Mapping
 from dataclasses import dataclass
 from typing import Optional
 
@@ -434,7 +435,7 @@ def louvain_static(g: Graph, prm: Params = None, state: State = None, stream=Non
     cg, cs = g.c(), state.c()
     ws, nb = g.ws_args()
     _check(L.louvain_static(ct.byref(cg), ct.byref(prm), ct.byref(cs), ws, nb, ct.byref(st), _stream(stream)))
-    return state, st.as_dict()
+    return state, StatsView(st)
 
 
 def _dynamic(fn, g, b, state, prm, stream, kw):
@@ -445,7 +446,7 @@ def _dynamic(fn, g, b, state, prm, stream, kw):
     ws, nb = g.ws_args()
     _check(getattr(L, fn)(ct.byref(cg), ct.byref(cd), ct.byref(ci), ct.byref(prm), ct.byref(cs), ws, nb,
                           ct.byref(st), _stream(stream)))
-    return state, st.as_dict()
+    return state, StatsView(st)
 
 
 def louvain_nd(g, b, state, prm=None, stream=None, **kw):
@@ -504,6 +505,31 @@ def louvain_df_many(graphs, batches, states, scratches, max_updates, prm=None, w
     return status[:count].tolist(), StatsList(stats, count)
 
 
+class StatsView(Mapping):
+    """One call's lv_stats as a read-only mapping, converted on first read
+    (the conversion is not part of the call)."""
+
+    def __init__(self, st: Stats):
+        self._st, self._d = st, None
+
+    def _dict(self) -> dict:
+        if self._d is None:
+            self._d = self._st.as_dict()
+        return self._d
+
+    def __getitem__(self, k):
+        return self._dict()[k]
+
+    def __iter__(self):
+        return iter(self._dict())
+
+    def __len__(self):
+        return len(self._dict())
+
+    def __repr__(self):
+        return repr(self._dict())
+
+
 class StatsList:
     """Per-item statistics of louvain_df_many, converted to dicts when read."""
 
@@ -521,7 +547,7 @@ class StatsList:
         if not 0 <= k < self._n:
             raise IndexError(k)
         if k not in self._d:
-            self._d[k] = self._a[k].as_dict()
+            self._d[k] = StatsView(self._a[k])
         return self._d[k]
 
     def __iter__(self):
