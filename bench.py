@@ -120,12 +120,22 @@ class KernelMeter:
         return max(range(self.lib.NTIMED), key=lambda k: self.ms[k])
 
 
-def traffic_for(kernel_name):
-    """HBM bytes per launch of `kernel_name` from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there
-    is none or the kernel sources changed since the counters were taken."""
+def move_instance(tuning):
+    """Name of the fused scan instantiation a DF step launches: its
+    wavefront tables hold twice the degree threshold."""
+    return f"k_move_all<{2 * int(tuning['wave_max_degree'])}, 7>"
+
+
+def traffic_for(kernel_name, instance):
+    """HBM bytes per launch of `instance` (a template instantiation of
+    `kernel_name`) from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, copy-calibrated), or None when there is none for that
+    instantiation or the kernel sources changed since the counters were
+    taken."""
     import hashlib
-    path = os.path.join(PROFILES, f"traffic_{kernel_name}_rmat22_df.txt")
+    import re
+    tag = "_".join(re.findall(r"\d+", instance))
+    path = os.path.join(PROFILES, f"traffic_{kernel_name}_{tag}_rmat22_df.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -133,6 +143,8 @@ def traffic_for(kernel_name):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
+    if kv.get("kernel") != instance:
+        return None
     src = os.path.join(ROOT, "paper_2404_19634_amd", "csrc", "move.hip")
     if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv.get("move_hip_sha256_16"):
         return None
@@ -626,10 +638,11 @@ def main():
     if nl and meter.ms[dom] > 0:
         per_launch = meter.bytes[dom] / nl
         achieved = per_launch / (meter.ms[dom] / nl * 1e-3) / 1e9
-        tr = traffic_for(SHORT[dom])
+        inst = move_instance(lib.get_tuning()) if dom == lib.TIME_SCAN else KERNELS[dom]
+        tr = traffic_for(SHORT[dom], inst)
         out["roofline"] = {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": KERNELS[dom],
+            "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": inst,
             "launches": nl, "avg_launch_us": meter.ms[dom] / nl * 1e3, "bytes_per_launch": per_launch,
             "warmup_kernel_ms": {lib.TIMED[k]: round(warm.ms[k], 4) for k in range(lib.NTIMED)},
         }
