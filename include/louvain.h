@@ -301,12 +301,12 @@ lv_status louvain_df_many(const lv_item* items, int32_t count, const lv_params* 
                           void* ws, size_t ws_bytes, int32_t* status, lv_stats* stats, void* stream);
 
 /* Measurement hook.  lv_set_timing(mask) makes every later louvain_* call
- * bracket each launch of the kernels whose bit k is set in `mask` (k =
- * LV_TIME_*) with a pair of HIP events on the call's
- * stream, and report their count and summed time in lv_stats.  Each event
- * adds a little time between launches, so a latency measurement should
- * time one kernel at most.  Up to 4096 launches per call are timed; mask 0
- * turns timing off.  Process-wide setting; LV_EINVAL for unknown bits. */
+ * time each launch of the kernels whose bit k is set in `mask` (k =
+ * LV_TIME_*) with a pair of HIP events that the launch itself stamps with
+ * the kernel's begin and end (hipExtLaunchKernel), and report their count
+ * and summed time in lv_stats.  Up to 4096 launches per call are timed;
+ * mask 0 turns timing off.  Process-wide setting; LV_EINVAL for unknown
+ * bits. */
 lv_status lv_set_timing(uint32_t mask);
 
 void lv_set_tuning(const lv_tuning* t);

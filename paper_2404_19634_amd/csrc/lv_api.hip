@@ -71,8 +71,7 @@ constexpr int kTimerPairs = 4096;
 struct Timer {
   std::vector<hipEvent_t> ev;   // 2 per launch, created on first use
   std::vector<int> kernel;      // kernel of each recorded pair
-  int used = 0;                 // pairs recorded since the last collect
-  int open = -1;                // kernel whose first event is recorded
+  int used = 0;                 // pairs handed out since the last collect
   ~Timer() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
@@ -81,24 +80,21 @@ thread_local Timer g_timer;
 
 }  // namespace
 
-void timer_begin(int kernel, hipStream_t st) {
-  if (!((g_timed_mask.load(std::memory_order_relaxed) >> kernel) & 1u)) return;
+TimerPair timer_pair(int kernel) {
+  TimerPair p;
+  if (!((g_timed_mask.load(std::memory_order_relaxed) >> kernel) & 1u)) return p;
   Timer& t = g_timer;
-  if (t.used >= kTimerPairs) return;
+  if (t.used >= kTimerPairs) return p;
   while (static_cast<int>(t.ev.size()) < 2 * (t.used + 1)) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return;
+    if (hipEventCreate(&e) != hipSuccess) return p;
     t.ev.push_back(e);
   }
   if (static_cast<int>(t.kernel.size()) < t.used + 1) t.kernel.resize(t.used + 1);
-  if (hipEventRecord(t.ev[2 * t.used], st) == hipSuccess) t.open = kernel;
-}
-
-void timer_end(int kernel, hipStream_t st) {
-  Timer& t = g_timer;
-  if (t.open != kernel) return;
-  t.open = -1;
-  if (hipEventRecord(t.ev[2 * t.used + 1], st) == hipSuccess) t.kernel[t.used++] = kernel;
+  p.start = t.ev[2 * t.used];
+  p.stop = t.ev[2 * t.used + 1];
+  t.kernel[t.used++] = kernel;
+  return p;
 }
 
 void timer_collect(int32_t* launches, double* ms) {
@@ -111,7 +107,6 @@ void timer_collect(int32_t* launches, double* ms) {
     }
   }
   t.used = 0;
-  t.open = -1;
 }
 
 namespace {

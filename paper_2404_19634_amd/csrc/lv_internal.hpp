@@ -428,10 +428,15 @@ struct SubRound {
   int32_t deg_lo = 0;
   int32_t deg_hi = 0x7fffffff;
 };
-// Measurement hook (lv_set_timing): HIP events around every launch of the
-// timed kernel on its stream; collected after the stream is synchronised.
-void timer_begin(int kernel, hipStream_t st);
-void timer_end(int kernel, hipStream_t st);
+// Measurement hook (lv_set_timing): the start and stop events of one launch
+// of a timed kernel, for hipExtLaunchKernelGGL, which stamps them with the
+// kernel's own begin and end times from its dispatch (both null when the
+// kernel is not timed); collected after the stream is synchronised.
+struct TimerPair {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+TimerPair timer_pair(int kernel);
 void timer_collect(int32_t* launches, double* ms);  // adds per kernel, resets
 
 // One sub-round: binning, hub table clear, the fused scan over the bins in

@@ -38,6 +38,8 @@
 // (or leave it to the pull kernels when the frontier is large).
 #include <climits>
 
+#include <hip/hip_ext.h>
+
 #include "lv_internal.hpp"
 
 namespace lv {
@@ -1629,21 +1631,23 @@ int grid_by_est(int64_t est, int64_t items_per_block, int max_blocks) {
 }
 
 template <int TS>
-void launch_move_all(const Dev& D, const Bins& b, const Roles& R, const HubIn& H, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL((k_move_all<TS, NBINS>), dim3(static_cast<unsigned>(R.end[NBINS - 1])), dim3(kBlock), lds, st,
-                     D, b, R, H);
+void launch_move_all(const Dev& D, const Bins& b, const Roles& R, const HubIn& H, size_t lds, TimerPair tp,
+                     hipStream_t st) {
+  hipExtLaunchKernelGGL((k_move_all<TS, NBINS>), dim3(static_cast<unsigned>(R.end[NBINS - 1])), dim3(kBlock),
+                        static_cast<uint32_t>(lds), st, tp.start, tp.stop, 0, D, b, R, H);
 }
 
 // One role over its own grid, capped at the workgroups the device holds at
 // once (a grid-stride loop on a larger grid leaves a tail of late
 // workgroups behind the resident ones).
 template <int TS, int ONLY>
-void launch_role(const Dev& D, const Bins& b, const HubIn& H, size_t lds, int64_t grid, hipStream_t st) {
+void launch_role(const Dev& D, const Bins& b, const HubIn& H, size_t lds, int64_t grid, TimerPair tp,
+                 hipStream_t st) {
   const auto fn = k_move_all<TS, ONLY>;
   grid = std::min<int64_t>(grid, resident_blocks(reinterpret_cast<const void*>(fn), kBlock, lds));
   Roles R{};
-  hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(std::max<int64_t>(grid, 1))), dim3(kBlock), lds, st, D, b, R,
-                     H);
+  hipExtLaunchKernelGGL(fn, dim3(static_cast<unsigned>(std::max<int64_t>(grid, 1))), dim3(kBlock),
+                        static_cast<uint32_t>(lds), st, tp.start, tp.stop, 0, D, b, R, H);
 }
 
 // A grid-stride kernel's grid, capped at the workgroups resident at once.
@@ -1654,15 +1658,16 @@ unsigned cap_grid(F fn, int64_t grid) {
 }
 
 template <int TS>
-void launch_one_role(int role, const Dev& D, const Bins& b, const HubIn& H, int64_t grid, hipStream_t st) {
+void launch_one_role(int role, const Dev& D, const Bins& b, const HubIn& H, int64_t grid, TimerPair tp,
+                     hipStream_t st) {
   switch (role) {
-    case BIN_G4: launch_role<128, BIN_G4>(D, b, H, sizeof(MoveAgg), grid, st); break;
-    case BIN_G8: launch_role<128, BIN_G8>(D, b, H, sizeof(MoveAgg), grid, st); break;
-    case BIN_G16: launch_role<128, BIN_G16>(D, b, H, sizeof(MoveAgg), grid, st); break;
-    case BIN_G32: launch_role<128, BIN_G32>(D, b, H, sizeof(MoveAgg), grid, st); break;
-    case BIN_WAVE: launch_role<TS, BIN_WAVE>(D, b, H, lds_wave<TS>(), grid, st); break;
-    case BIN_BLOCK: launch_role<128, BIN_BLOCK>(D, b, H, lds_table(), grid, st); break;
-    default: launch_role<128, BIN_HUB>(D, b, H, lds_table(), grid, st); break;
+    case BIN_G4: launch_role<128, BIN_G4>(D, b, H, sizeof(MoveAgg), grid, tp, st); break;
+    case BIN_G8: launch_role<128, BIN_G8>(D, b, H, sizeof(MoveAgg), grid, tp, st); break;
+    case BIN_G16: launch_role<128, BIN_G16>(D, b, H, sizeof(MoveAgg), grid, tp, st); break;
+    case BIN_G32: launch_role<128, BIN_G32>(D, b, H, sizeof(MoveAgg), grid, tp, st); break;
+    case BIN_WAVE: launch_role<TS, BIN_WAVE>(D, b, H, lds_wave<TS>(), grid, tp, st); break;
+    case BIN_BLOCK: launch_role<128, BIN_BLOCK>(D, b, H, lds_table(), grid, tp, st); break;
+    default: launch_role<128, BIN_HUB>(D, b, H, lds_table(), grid, tp, st); break;
   }
 }
 
@@ -1690,12 +1695,11 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
   Bins b;
   for (int k = 0; k < NBINS; ++k) b.list[k] = ws.bins[k];
   HubOut HO{ws.hub_off, ws.hub_cbase, ws.hub_cnum, ws.u_ins_b, ws.u_ins_a, ws.u_emit_b, ws.u_emit_s};
-  timer_begin(LV_TIME_BINNING, st);
-  hipLaunchKernelGGL(k_bin_frontier, dim3(grid_for(words, kBlock, 4096)), dim3(kBlock), 0, st,
-                     const_cast<uint32_t*>(a.cur), a.range, a.ever, a.g.row_len, a.g.n, a.wave_max, r.hash_round,
-                     r.hash_shift, r.id_lo, r.id_hi, r.deg_lo, r.deg_hi, a.clear_cur, b, HO, a.rc, a.sc, a.rc_next,
-                     a.sc_next);
-  timer_end(LV_TIME_BINNING, st);
+  const TimerPair tb = timer_pair(LV_TIME_BINNING);
+  hipExtLaunchKernelGGL(k_bin_frontier, dim3(grid_for(words, kBlock, 4096)), dim3(kBlock), 0, st, tb.start, tb.stop,
+                        0, const_cast<uint32_t*>(a.cur), a.range, a.ever, a.g.row_len, a.g.n, a.wave_max,
+                        r.hash_round, r.hash_shift, r.id_lo, r.id_hi, r.deg_lo, r.deg_hi, a.clear_cur, b, HO, a.rc,
+                        a.sc, a.rc_next, a.sc_next);
 
   const int64_t est = a.est > 0 ? a.est : 1;
   const int bs = grid_by_est(est, 64, tu.blocks_small);  // 16 rows per wave at G = 4
@@ -1703,11 +1707,10 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
   const int bh = grid_by_est(est, 1, tu.blocks_hub);     // one row / unit per workgroup
   const bool hubs = bin_mask & (1u << BIN_HUB);
   if (hubs) {
-    timer_begin(LV_TIME_HUB_CLEAR, st);
-    hipLaunchKernelGGL(k_hub_clear, dim3(cap_grid(k_hub_clear, bh)), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB],
-                       ws.hub_off, ws.u_emit_b, ws.u_emit_s, reinterpret_cast<unsigned long long*>(ws.pool_pairs),
-                       ws.hub_kid, ws.pool_slots);
-    timer_end(LV_TIME_HUB_CLEAR, st);
+    const TimerPair tc = timer_pair(LV_TIME_HUB_CLEAR);
+    hipExtLaunchKernelGGL(k_hub_clear, dim3(cap_grid(k_hub_clear, bh)), dim3(kBlock), 0, st, tc.start, tc.stop, 0, D,
+                          ws.bins[BIN_HUB], ws.hub_off, ws.u_emit_b, ws.u_emit_s,
+                          reinterpret_cast<unsigned long long*>(ws.pool_pairs), ws.hub_kid, ws.pool_slots);
   }
 
   // The scan: for a small, sparse frontier one launch whose role ranges lie
@@ -1732,38 +1735,35 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
     size_t lds = sizeof(MoveAgg);
     if (bin_mask & (1u << BIN_WAVE)) lds = std::max(lds, lw);
     if (bin_mask & ((1u << BIN_BLOCK) | (1u << BIN_HUB))) lds = std::max(lds, lds_table());
-    timer_begin(LV_TIME_SCAN, st);
+    const TimerPair tp = timer_pair(LV_TIME_SCAN);
     if (ts <= 128)
-      launch_move_all<128>(D, b, R, H, lds, st);
+      launch_move_all<128>(D, b, R, H, lds, tp, st);
     else if (ts <= 256)
-      launch_move_all<256>(D, b, R, H, lds, st);
+      launch_move_all<256>(D, b, R, H, lds, tp, st);
     else if (ts <= 512)
-      launch_move_all<512>(D, b, R, H, lds, st);
+      launch_move_all<512>(D, b, R, H, lds, tp, st);
     else
-      launch_move_all<1024>(D, b, R, H, lds, st);
-    timer_end(LV_TIME_SCAN, st);
+      launch_move_all<1024>(D, b, R, H, lds, tp, st);
   } else {
     for (int k = 0; k < NBINS; ++k) {
       if (!(bin_mask & (1u << k))) continue;
-      timer_begin(LV_TIME_SCAN, st);
+      const TimerPair tp = timer_pair(LV_TIME_SCAN);
       if (ts <= 128)
-        launch_one_role<128>(k, D, b, H, per[k], st);
+        launch_one_role<128>(k, D, b, H, per[k], tp, st);
       else if (ts <= 256)
-        launch_one_role<256>(k, D, b, H, per[k], st);
+        launch_one_role<256>(k, D, b, H, per[k], tp, st);
       else if (ts <= 512)
-        launch_one_role<512>(k, D, b, H, per[k], st);
+        launch_one_role<512>(k, D, b, H, per[k], tp, st);
       else
-        launch_one_role<1024>(k, D, b, H, per[k], st);
-      timer_end(LV_TIME_SCAN, st);
+        launch_one_role<1024>(k, D, b, H, per[k], tp, st);
     }
   }
   if (hubs) {
-    timer_begin(LV_TIME_HUB_DECIDE, st);
-    hipLaunchKernelGGL(k_hub_decide, dim3(cap_grid(k_hub_decide, bh)), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB],
-                       ws.hub_off, ws.u_emit_b, ws.u_emit_s,
-                       reinterpret_cast<const unsigned long long*>(ws.pool_pairs), ws.hub_kid, ws.unit_g, ws.unit_c,
-                       ws.pool_slots);
-    timer_end(LV_TIME_HUB_DECIDE, st);
+    const TimerPair td = timer_pair(LV_TIME_HUB_DECIDE);
+    hipExtLaunchKernelGGL(k_hub_decide, dim3(cap_grid(k_hub_decide, bh)), dim3(kBlock), 0, st, td.start, td.stop, 0,
+                          D, ws.bins[BIN_HUB], ws.hub_off, ws.u_emit_b, ws.u_emit_s,
+                          reinterpret_cast<const unsigned long long*>(ws.pool_pairs), ws.hub_kid, ws.unit_g,
+                          ws.unit_c, ws.pool_slots);
     hipLaunchKernelGGL(k_hub_final, dim3(64), dim3(kBlock), 0, st, D, ws.bins[BIN_HUB], ws.hub_cbase, ws.hub_cnum,
                        ws.unit_g, ws.unit_c, ws.hub_moved);
     if (a.push)

@@ -188,9 +188,9 @@ DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER = 4096
 
 
 def set_timing(kernels=()):
-    """Bracket every launch of the given kernels (indices into TIMED) with
-    HIP events; the louvain_* calls then report timed_launches and timed_ms
-    per kernel.  () turns timing off."""
+    """Time every launch of the given kernels (indices into TIMED) with HIP
+    events stamped by the launch itself; the louvain_* calls then report
+    timed_launches and timed_ms per kernel.  () turns timing off."""
     mask = 0
     for k in kernels:
         mask |= 1 << int(k)
