@@ -163,9 +163,17 @@ def _check(code: int):
         raise LouvainError(code, load().lv_last_error().decode())
 
 
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream(stream=None):
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ct.c_void_p(s.cuda_stream)
+    """The HIP stream handle of `stream`, else of the current stream (read
+    without building a Stream object when torch offers that)."""
+    if stream is not None:
+        return ct.c_void_p(stream.cuda_stream)
+    if _raw_stream is not None:
+        return ct.c_void_p(_raw_stream(torch.cuda.current_device()))
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
 def _ptr(t: torch.Tensor):
