@@ -606,6 +606,66 @@ __device__ __forceinline__ void role_small(const Dev& D, int64_t two_m, const in
   flush_totals(D, gain_acc, moved, marcs);
 }
 
+// Rows of at most 4 arcs: one lane per row, so that a wavefront keeps 64
+// rows' loads in flight; K_{i->c} of the (at most four) neighbour
+// communities is summed in registers, with no exchange between lanes.
+__device__ __forceinline__ void role_lane4(const Dev& D, int64_t two_m, const int32_t* __restrict__ list, int64_t rb,
+                                           int64_t nb, MoveAgg* agg) {
+  const int64_t count = D.rc[rc_bin(BIN_G4)];
+  const int64_t nt = nb * blockDim.x;
+  int64_t gain_acc = 0, moved = 0, marcs = 0;
+  for (int64_t idx = rb * blockDim.x + threadIdx.x; idx < count; idx += nt) {
+    const int32_t i = list[idx];
+    const int64_t start = D.row_start[i];
+    const int32_t deg = D.row_len[i];  // 1..4
+    const int32_t d = D.C[i];
+    const int64_t Ki = D.K[i];
+    int32_t j[4], x[4], c[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      j[q] = q < deg ? D.col[start + q] : -1;
+      x[q] = q < deg ? D.wt[start + q] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (j[q] == i) j[q] = -1;  // self-loop: not a neighbour
+      c[q] = j[q] >= 0 ? D.C[j[q]] : -1;
+    }
+    const int64_t Sd = D.Sigma[d];
+    int64_t sc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sc[q] = (c[q] >= 0 && c[q] != d) ? D.Sigma[c[q]] : 0;
+    int32_t kid = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) kid += (c[q] == d) ? x[q] : 0;
+    int64_t bg = LLONG_MIN;
+    int32_t bc = INT_MAX;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (c[q] < 0 || c[q] == d) continue;
+      int32_t kc = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) kc += (c[r] == c[q]) ? x[r] : 0;
+      const int64_t g = gain_of(two_m, kc, kid, Ki, sc[q], Sd);
+      if (better(g, c[q], bg, bc)) {
+        bg = g;
+        bc = c[q];
+      }
+    }
+    if (decide_move(D, d, bc, bg)) {
+      commit_move(D, agg, i, d, bc, Ki);
+      gain_acc += bg;
+      moved += 1;
+      marcs += deg;
+      if (D.push)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (j[q] >= 0) set_bit(D.next, j[q]);
+    }
+  }
+  flush_totals(D, gain_acc, moved, marcs);
+}
+
 // Table slots (and arcs) a lane holds at once in the gather phases.
 constexpr int kDecideSlots = 4;
 
@@ -1133,7 +1193,7 @@ __global__ void __launch_bounds__(kBlock) k_move_all(Dev D, Bins bins, Roles R, 
     MoveAgg* agg = reinterpret_cast<MoveAgg*>(smem);
     agg_begin(agg);
     switch (role) {
-      case BIN_G4: role_small<4>(D, two_m, bins.list[BIN_G4], BIN_G4, rb, nb, agg); break;
+      case BIN_G4: role_lane4(D, two_m, bins.list[BIN_G4], rb, nb, agg); break;
       case BIN_G8: role_small<8>(D, two_m, bins.list[BIN_G8], BIN_G8, rb, nb, agg); break;
       case BIN_G16: role_small<16>(D, two_m, bins.list[BIN_G16], BIN_G16, rb, nb, agg); break;
       default: role_small<32>(D, two_m, bins.list[BIN_G32], BIN_G32, rb, nb, agg); break;
@@ -1702,7 +1762,8 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
                         a.sc, a.rc_next, a.sc_next);
 
   const int64_t est = a.est > 0 ? a.est : 1;
-  const int bs = grid_by_est(est, 64, tu.blocks_small);  // 16 rows per wave at G = 4
+  const int bs = grid_by_est(est, 64, tu.blocks_small);  // sub-wavefront groups
+  const int b4 = grid_by_est(est, 256, tu.blocks_small);  // one row per lane
   const int bw = grid_by_est(est, 4, tu.blocks_wave);    // one row per wavefront
   const int bh = grid_by_est(est, 1, tu.blocks_hub);     // one row / unit per workgroup
   const bool hubs = bin_mask & (1u << BIN_HUB);
@@ -1717,7 +1778,7 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
   // end to end; otherwise a launch per bin in increasing degree order, so
   // that (in ASYNC mode) each bin sees the moves of the bins before it (on
   // dense frontiers that ordering is worth modularity).
-  const int per[NBINS] = {bs, bs, bs, bs, bw, bh, bh};
+  const int per[NBINS] = {b4, bs, bs, bs, bw, bh, bh};
   const int ts = table_slots_for(a.wave_max);
   const size_t lw = ts <= 128 ? lds_wave<128>() : ts <= 256 ? lds_wave<256>() : ts <= 512 ? lds_wave<512>()
                                                                                         : lds_wave<1024>();
