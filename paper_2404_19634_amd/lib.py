@@ -252,9 +252,14 @@ class Edges:
         return int(self.u.shape[0])
 
     def c(self) -> CEdges:
-        if self.count == 0:
-            return CEdges(None, None, None, 0)
-        return CEdges(self.u.data_ptr(), self.v.data_ptr(), self.w.data_ptr(), self.count)
+        return CEdges(*self.cvals())
+
+    def cvals(self) -> tuple:
+        """The lv_edges fields in order (null pointers as 0)."""
+        n = self.count
+        if n == 0:
+            return 0, 0, 0, 0
+        return self.u.data_ptr(), self.v.data_ptr(), self.w.data_ptr(), n
 
 
 @dataclass
@@ -309,9 +314,12 @@ class _EdgesAt:
         self.buf, self.pu, self.pv, self.pw, self.count = buf, pu, pv, pw, count
 
     def c(self) -> CEdges:
+        return CEdges(*self.cvals())
+
+    def cvals(self) -> tuple:
         if self.count == 0:
-            return CEdges(None, None, None, 0)
-        return CEdges(self.pu, self.pv, self.pw, self.count)
+            return 0, 0, 0, 0
+        return self.pu, self.pv, self.pw, self.count
 
 
 class Graph:
@@ -329,8 +337,12 @@ class Graph:
         self._ws = None
 
     def c(self) -> CGraph:
-        return CGraph(self.n, self.cap, self.row_start.data_ptr(), self.row_len.data_ptr(), self.col.data_ptr(),
-                      self.w.data_ptr(), self.two_m_t.data_ptr())
+        return CGraph(*self.cvals())
+
+    def cvals(self) -> tuple:
+        """The lv_graph fields in order."""
+        return (self.n, self.cap, self.row_start.data_ptr(), self.row_len.data_ptr(), self.col.data_ptr(),
+                self.w.data_ptr(), self.two_m_t.data_ptr())
 
     @property
     def workspace(self) -> torch.Tensor:
@@ -424,8 +436,12 @@ class State:
         return self.C.cpu().numpy(), self.K.cpu().numpy(), self.Sigma.cpu().numpy()
 
     def c(self) -> CState:
-        return CState(self.C.data_ptr(), self.K.data_ptr(), self.Sigma.data_ptr(),
-                      None if self.size is None else self.size.data_ptr())
+        return CState(*self.cvals())
+
+    def cvals(self) -> tuple:
+        """The lv_state fields in order (no member counts: 0)."""
+        return (self.C.data_ptr(), self.K.data_ptr(), self.Sigma.data_ptr(),
+                0 if self.size is None else self.size.data_ptr())
 
 
 def apply_batch(g: Graph, b: Batch, stream=None):
@@ -489,18 +505,9 @@ def louvain_df_many(graphs, batches, states, scratches, max_updates, prm=None, w
     caps = list(max_updates) if hasattr(max_updates, "__len__") else [int(max_updates)] * count
     items = np.zeros(max(count, 1), dtype=_item_dtype())
     if count:
-        cols = [g.c() for g in graphs]
-        for f, _ in CGraph._fields_:
-            items["g." + f][:count] = [getattr(x, f) or 0 for x in cols]
-        cols = [x.c() for x in states]
-        for f, _ in CState._fields_:
-            items["state." + f][:count] = [getattr(x, f) or 0 for x in cols]
-        for side in ("dels", "ins"):
-            cols = [getattr(b, side).c() for b in batches]
-            for f, _ in CEdges._fields_:
-                items[side + "." + f][:count] = [getattr(x, f) or 0 for x in cols]
-        items["scratch"][:count] = [x.data_ptr() for x in scratches]
-        items["max_updates"][:count] = caps
+        # one record per item, fields in lv_item order
+        items[:count] = [g.cvals() + s.cvals() + b.dels.cvals() + b.ins.cvals() + (x.data_ptr(), cap)
+                         for g, s, b, x, cap in zip(graphs, states, batches, scratches, caps)]
     need = int(L.lv_many_desc_bytes(count))
     if desc is None or desc.numel() < need:
         desc = torch.empty(need, dtype=torch.uint8, device=graphs[0].device if count else "cuda")
