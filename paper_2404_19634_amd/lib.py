@@ -287,7 +287,7 @@ class Batch:
         parts = []
         for b in batches:
             parts += [b.del_u, b.del_v, b.del_w, b.ins_u, b.ins_v, b.ins_w]
-        sizes = np.fromiter((len(x) for x in parts), dtype=np.int64, count=len(parts))
+        sizes = np.array([len(x) for x in parts], dtype=np.int64)
         total = int(sizes.sum())
         if staging is None or staging.numel() < total:
             staging = torch.empty(max(total, 1), dtype=torch.int32, pin_memory=True)
@@ -296,13 +296,11 @@ class Batch:
             np.concatenate([np.asarray(x, np.int32) for x in parts], out=host)
         dev = torch.empty(max(total, 1), dtype=torch.int32, device=device)
         dev[:total].copy_(staging[:total], non_blocking=True)
-        addr = dev.data_ptr() + 4 * (np.cumsum(sizes) - sizes)
-        out = []
-        for j in range(len(batches)):
-            a = addr[6 * j:6 * j + 6].tolist()
-            nd, ni = int(sizes[6 * j]), int(sizes[6 * j + 3])
-            out.append(cls(_EdgesAt(dev, a[0], a[1], a[2], nd), _EdgesAt(dev, a[3], a[4], a[5], ni)))
-        return out
+        a = (dev.data_ptr() + 4 * (np.cumsum(sizes) - sizes)).tolist()
+        n = sizes.tolist()
+        E = _EdgesAt
+        return [cls(E(dev, a[k], a[k + 1], a[k + 2], n[k]), E(dev, a[k + 3], a[k + 4], a[k + 5], n[k + 3]))
+                for k in range(0, 6 * len(batches), 6)]
 
 
 class _EdgesAt:
