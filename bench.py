@@ -314,7 +314,10 @@ def approaches(lib, e, sizes, reps=2, seed=777):
     """Update latency of ND, DS and DF Louvain in SYNC and ASYNC mode, and
     static Louvain in both modes, on the same graph: per (approach, mode) a
     fresh copy of the graph, its static state, then `reps` rounds of the
-    batch sizes, each apply_batch followed by the approach (timed)."""
+    batch sizes, each apply_batch followed by the approach (timed).  In
+    ASYNC mode each approach also runs without auxiliary information (K and
+    Sigma recomputed from scratch per batch, "async_no_aux"), and
+    "aux_speedup" is that variant's p50 over the incremental one's."""
     import torch
     dev = torch.device("cuda:0")
     batches = make_batches(e, sizes, reps * len(sizes), seed=seed)
@@ -329,8 +332,12 @@ def approaches(lib, e, sizes, reps=2, seed=777):
         out["static"][mode] = {"latency_ms": (time.perf_counter() - t) * 1e3, "edges_scanned": s0["arcs_scanned"],
                                "modularity": lib.modularity(g, st0.C)}
         del g
-        for name in ("nd", "ds", "df"):
+        runs = [(name, 0) for name in ("nd", "ds", "df")]
+        if mode == "async":
+            runs += [(name, 1) for name in ("nd", "ds", "df")]
+        for name, no_aux in runs:
             fn = getattr(lib, "louvain_" + name)
+            prm_run = lib.params(mode=mode, recompute_weights=no_aux)
             g = lib.Graph.from_edges(e, slack_frac=0.1, slack_min=8)
             st = st0.clone()
             lat, arcs, by = [], [], {}
@@ -345,18 +352,23 @@ def approaches(lib, e, sizes, reps=2, seed=777):
                     lib.apply_batch(g, db)
                 torch.cuda.synchronize()
                 t = time.perf_counter()
-                st, s = fn(g, db, st, prm)
+                st, s = fn(g, db, st, prm_run)
                 torch.cuda.synchronize()
                 ms = (time.perf_counter() - t) * 1e3
                 lat.append(ms)
                 arcs.append(s["arcs_scanned"])
                 by.setdefault(str(b.size), []).append(ms)
-            out.setdefault(name, {})[mode] = {
+            rec = {
                 "latency_ms_p50": pct(lat, 50), "latency_ms_p99": pct(lat, 99),
                 "by_batch_size": {k: float(np.median(v)) for k, v in by.items()},
                 "edges_scanned_per_s": float(np.sum(arcs)) / (np.sum(lat) * 1e-3),
                 "speedup_vs_static": out["static"][mode]["latency_ms"] / pct(lat, 50),
                 "modularity": lib.modularity(g, st.C)}
+            if no_aux:
+                rec["aux_speedup"] = pct(lat, 50) / out[name][mode]["latency_ms_p50"]
+                out[name][mode + "_no_aux"] = rec
+            else:
+                out.setdefault(name, {})[mode] = rec
             del g, st
             torch.cuda.empty_cache()
     return out

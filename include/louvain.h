@@ -109,6 +109,12 @@ typedef struct {
   int32_t max_passes;           /* 1 .. LV_MAX_PASSES */
   int32_t mode;                 /* LV_SYNC or LV_ASYNC */
   int32_t swap_guard;           /* 1: a singleton never joins a singleton of larger id */
+  int32_t recompute_weights;    /* 1: the dynamic calls recompute K^t (row sums of G^t) and Sigma^t
+                                   (from C^{t-1}) instead of updating K^{t-1}, Sigma^{t-1} by the
+                                   batch: the variant without auxiliary information (Section 4.2).
+                                   Same results, more work.  0 (default) for the incremental update;
+                                   louvain_df_many accepts 0 only. */
+  int32_t reserved;             /* must be 0 */
 } lv_params;
 
 /* Degree bins of the local-moving scan: rows of up to 4, 8, 16, 32 arcs

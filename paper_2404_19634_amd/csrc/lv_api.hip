@@ -172,7 +172,8 @@ lv_status read_i64(int64_t* host, const int64_t* dev, hipStream_t st) {
 bool params_ok(const lv_params* p) {
   return p && p->max_iterations >= 1 && p->max_iterations <= LV_MAX_ITERS && p->max_passes >= 1 &&
          p->max_passes <= LV_MAX_PASSES && (p->mode == LV_SYNC || p->mode == LV_ASYNC) &&
-         p->tolerance >= 0.0 && p->tolerance_drop > 0.0 && p->aggregation_tolerance >= 0.0;
+         p->tolerance >= 0.0 && p->tolerance_drop > 0.0 && p->aggregation_tolerance >= 0.0 &&
+         (p->recompute_weights == 0 || p->recompute_weights == 1) && p->reserved == 0;
 }
 
 bool graph_ok(const lv_graph* g) {
@@ -415,6 +416,12 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
         break;
     }
     launch_update_weights(D, I, state->C, state->K, state->Sigma, df_frontier, err, st);
+    if (p->recompute_weights) {
+      // without auxiliary information (Section 4.2): K^t from the rows of
+      // G^t and Sigma^t from C^{t-1}, replacing the incremental values
+      launch_row_sums(L0, nullptr, state->K, nullptr, nullptr, nullptr, ws.bins[5], ws.ctr, st);
+      launch_sigma_from_members(state->C, state->K, N, state->Sigma, st);
+    }
     if (p->swap_guard && !state->size) launch_community_sizes(state->C, N, ws.size, st);
   }
   LV_CHECK_LAUNCH();
@@ -742,6 +749,8 @@ void lv_default_params(lv_params* p) {
   p->max_passes = 10;
   p->mode = LV_ASYNC;
   p->swap_guard = 1;
+  p->recompute_weights = 0;
+  p->reserved = 0;
 }
 
 size_t lv_workspace_bytes(int32_t n, int64_t cap) {
@@ -896,6 +905,7 @@ lv_status louvain_df_many(const lv_item* items, int32_t count, const lv_params* 
                           void* ws, size_t ws_bytes, int32_t* status, lv_stats* stats, void* stream) {
   if (count < 0 || (count > 0 && (!items || !status || !desc))) return fail(LV_EINVAL, "invalid arguments");
   if (!params_ok(p)) return fail(LV_EINVAL, "invalid parameters");
+  if (p->recompute_weights) return fail(LV_EINVAL, "the batched launch updates K and Sigma incrementally only");
   if (desc_bytes < lv_many_desc_bytes(count)) return fail(LV_EWORKSPACE, "descriptor buffer too small");
   if (count == 0) return LV_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);

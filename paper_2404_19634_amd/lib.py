@@ -62,7 +62,8 @@ class CState(ct.Structure):
 class Params(ct.Structure):
     _fields_ = [("tolerance", ct.c_double), ("tolerance_drop", ct.c_double),
                 ("aggregation_tolerance", ct.c_double), ("max_iterations", ct.c_int32),
-                ("max_passes", ct.c_int32), ("mode", ct.c_int32), ("swap_guard", ct.c_int32)]
+                ("max_passes", ct.c_int32), ("mode", ct.c_int32), ("swap_guard", ct.c_int32),
+                ("recompute_weights", ct.c_int32), ("reserved", ct.c_int32)]
 
 
 class Stats(ct.Structure):
@@ -181,11 +182,13 @@ def _ptr(t: torch.Tensor):
 
 
 def params(tolerance=1e-2, tolerance_drop=10.0, aggregation_tolerance=0.8, max_iterations=20, max_passes=10,
-           mode="async", swap_guard=1) -> Params:
-    """Defaults are the paper's (Section 5.1.2)."""
+           mode="async", swap_guard=1, recompute_weights=0) -> Params:
+    """Defaults are the paper's (Section 5.1.2).  recompute_weights=1: the
+    dynamic calls recompute K and Sigma from scratch (Section 4.2's variant
+    without auxiliary information)."""
     m = {"sync": SYNC, "async": ASYNC}[mode] if isinstance(mode, str) else int(mode)
     return Params(float(tolerance), float(tolerance_drop), float(aggregation_tolerance), int(max_iterations),
-                  int(max_passes), m, int(swap_guard))
+                  int(max_passes), m, int(swap_guard), int(recompute_weights), 0)
 
 
 DEFAULT_ASYNC_ROUNDS_LOG2 = 7

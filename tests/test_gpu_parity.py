@@ -166,6 +166,36 @@ def test_dynamic_sync_bit_exact(lib, case, approach, carry_size):
         assert np.array_equal(st.size.cpu().numpy(), _sizes(C, e.n))
 
 
+@pytest.mark.parametrize("approach", ["nd", "ds", "df"])
+def test_without_auxiliary_information_sync_bit_exact(lib, case, approach):
+    """recompute_weights=1 (Section 4.2's variant without auxiliary
+    information): K^t and Sigma^t are recomputed from G^t and C^{t-1}, so
+    every result equals the incremental run's, i.e. the oracle's.  ND and
+    DF never read the carried K and Sigma then, so they get garbage ones
+    (DS scores its marking with them, so it gets the true ones)."""
+    name, e = case
+    b = W.random_batch(e, max(10, e.m // 200), 78)
+    G = _orc(e)
+    state0 = G.louvain("static", mode="async")[:3]
+    assert G.apply_batch(b) == 0
+    Cd, Kd, Sd, os_ = G.louvain(approach, batch=b, state=state0, mode="sync")
+    g = lib.Graph.from_edges(e)
+    bb = lib.Batch.from_host(b)
+    lib.apply_batch(g, bb)
+    C0, K0, S0 = state0
+    if approach != "ds":
+        rng = np.random.default_rng(3)
+        K0 = rng.integers(-1000, 1000, e.n).astype(np.int64)
+        S0 = rng.integers(-1000, 1000, e.n).astype(np.int64)
+    st, gs = getattr(lib, "louvain_" + approach)(g, bb, lib.State.from_host(C0, K0, S0), mode="sync",
+                                                  recompute_weights=1)
+    C, K, S = st.host()
+    assert np.array_equal(K, Kd)
+    assert np.array_equal(C, Cd)
+    assert np.array_equal(S, Sd)
+    _same_stats(gs, os_)
+
+
 @pytest.mark.parametrize("approach", ["static", "nd", "ds", "df"])
 def test_async_consistent_and_close_to_static(lib, approach):
     e = W.config1_sbm()

@@ -34,8 +34,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_header():
     from paper_2404_19634_amd import lib
-    # lv_params: 3 doubles + 4 int32
-    assert ct.sizeof(lib.Params) == 3 * 8 + 4 * 4
+    # lv_params: 3 doubles + 6 int32
+    assert ct.sizeof(lib.Params) == 3 * 8 + 6 * 4
     # lv_stats starts with the oracle's layout
     import oracle
     prefix = ct.sizeof(oracle.Stats)
@@ -59,6 +59,27 @@ def test_default_params_are_the_papers():
     lib.load().lv_default_params(ct.byref(p))
     assert (p.tolerance, p.tolerance_drop, p.aggregation_tolerance) == (1e-2, 10.0, 0.8)
     assert (p.max_iterations, p.max_passes) == (20, 10)
+    assert (p.recompute_weights, p.reserved) == (0, 0)
+
+
+def test_bad_parameters_rejected_before_device_work():
+    # host-side checks only: the graph's pointers are never dereferenced
+    from paper_2404_19634_amd import lib
+    L = lib.load()
+    g = lib.CGraph(10, 40, 8, 8, 8, 8, 8)
+    e = lib.CEdges(None, None, None, 0)
+    s = lib.CState(8, 8, 8, None)
+    st = lib.Stats()
+    for kw in ({"recompute_weights": 2}, {"max_iterations": 0}, {"mode": 7}):
+        p = lib.params(**kw)
+        code = L.louvain_df(ct.byref(g), ct.byref(e), ct.byref(e), ct.byref(p), ct.byref(s), None, 0,
+                            ct.byref(st), None)
+        assert code == lib.LV_EINVAL, kw
+        assert b"parameters" in L.lv_last_error(), kw
+    p = lib.params()
+    p.reserved = 1
+    code = L.louvain_df(ct.byref(g), ct.byref(e), ct.byref(e), ct.byref(p), ct.byref(s), None, 0, ct.byref(st), None)
+    assert code == lib.LV_EINVAL
 
 
 def test_null_arguments_rejected_without_device_work():
