@@ -38,6 +38,7 @@ class Request:
     t_done: float = 0.0
     status: int = 1        # 1 pending, else the library status
     src: tuple = ()        # (per-launch statistics list, index): read on demand
+    refreshed: bool = False  # static Louvain replaced the state after this update
 
     @property
     def stats(self) -> dict:
@@ -51,6 +52,7 @@ class Resident:
         self.graph, self.state, self.scratch = graph, state, scratch
         self.busy = False
         self.last_used = 0.0
+        self.since_refresh = 0  # updates since the state came from static Louvain
 
     @property
     def nbytes(self) -> int:
@@ -68,7 +70,7 @@ class GraphStore:
     admission would exceed the budget."""
 
     def __init__(self, budget_bytes: int, max_updates: int, device="cuda", mode="async", slack_frac=0.5,
-                 slack_min=16, init_mode=None):
+                 slack_min=16, init_mode=None, refresh_every=0):
         self.budget = int(budget_bytes)
         self.max_updates = int(max_updates)
         self.device = torch.device(device)
@@ -76,6 +78,14 @@ class GraphStore:
         # mode of the static Louvain run that gives an admitted graph its
         # first state (SYNC makes it reproducible run to run)
         self.init_mode = init_mode or mode
+        # quality policy (the remedy of the paper's appendix on DF's
+        # correctness: communities that a run of deletions splits, and
+        # outliers the frontier misses, are repaired by running static
+        # Louvain every so many batches): after every `refresh_every`
+        # updates of a graph, static Louvain (in init_mode) replaces its
+        # state; 0 turns this off
+        self.refresh_every = int(refresh_every)
+        self.refreshes = 0
         self.slack = (slack_frac, slack_min)
         self.edges = {}        # gid -> workloads.Edges (never-admitted graphs)
         self.host = {}         # gid -> evicted device arrays, on the host
@@ -96,13 +106,17 @@ class GraphStore:
                 getattr(g, name).copy_(h[name], non_blocking=False)
             st = lib.State(h["C"].to(self.device), h["K"].to(self.device), h["Sigma"].to(self.device),
                            h["size"].to(self.device))
+            since = h["since_refresh"]
         else:
             e = self.edges[gid]
             g = lib.Graph.from_edges(e, slack_frac=self.slack[0], slack_min=self.slack[1], device=self.device)
             st, _ = lib.louvain_static(g, mode=self.init_mode)
             g._ws = None  # the build workspace is not kept; louvain_df_many needs none per graph
+            since = 0
         scratch = lib.many_scratch(g.n, self.max_updates, self.device)
-        return Resident(g, st, scratch)
+        r = Resident(g, st, scratch)
+        r.since_refresh = since
+        return r
 
     def _evict_one(self) -> bool:
         idle = [(r.last_used, gid) for gid, r in self.res.items() if not r.busy]
@@ -113,10 +127,23 @@ class GraphStore:
         g, s = r.graph, r.state
         self.host[gid] = {"n": g.n, "cap": g.cap, "row_start": g.row_start.cpu(), "row_len": g.row_len.cpu(),
                           "col": g.col.cpu(), "w": g.w.cpu(), "two_m_t": g.two_m_t.cpu(), "C": s.C.cpu(),
-                          "K": s.K.cpu(), "Sigma": s.Sigma.cpu(), "size": s.size.cpu()}
+                          "K": s.K.cpu(), "Sigma": s.Sigma.cpu(), "size": s.size.cpu(),
+                          "since_refresh": r.since_refresh}
         self.resident_bytes -= r.nbytes
         self.evictions += 1
         return True
+
+    def refresh(self, r: Resident, ws: torch.Tensor, stream) -> None:
+        """Static Louvain on a resident graph, in place of its state (ws:
+        a workspace of at least lv_workspace_bytes for the graph)."""
+        r.graph._ws = ws
+        try:
+            lib.louvain_static(r.graph, lib.params(mode=self.init_mode), r.state, stream=stream)
+        finally:
+            r.graph._ws = None
+        r.since_refresh = 0
+        with self.lock:
+            self.refreshes += 1
 
     def grow(self, r: Resident, slack_frac: float, slack_min: int) -> None:
         """Lays a resident graph out again with more slack per row."""
@@ -257,11 +284,23 @@ class Server:
                                                     prm=self.params, ws=ws, desc=desc, stream=stream)
                     for q, (j, a) in enumerate(zip(redo, st2)):
                         status[j], src[j] = a, (sts2, q)
+                refreshed = [False] * len(picked)
+                if self.store.refresh_every:
+                    for j, (x, st) in enumerate(zip(residents, status)):
+                        if st != 0:
+                            continue
+                        x.since_refresh += 1
+                        if x.since_refresh >= self.store.refresh_every:
+                            need = int(lib.load().lv_workspace_bytes(x.graph.n, x.graph.cap))
+                            if ws.numel() < need:
+                                ws = torch.empty(need, dtype=torch.uint8, device=self.store.device)
+                            self.store.refresh(x, ws, stream)
+                            refreshed[j] = True
             t1 = time.perf_counter()
             with self.cv:
                 self.launches += 1
-                for r, s, sr in zip(picked, status, src):
-                    r.t_start, r.t_done, r.status, r.src = t0, t1, s, sr
+                for r, s, sr, rf in zip(picked, status, src, refreshed):
+                    r.t_start, r.t_done, r.status, r.src, r.refreshed = t0, t1, s, sr, rf
                     self.done.append(r)
                 self.store.release([r.gid for r in picked])
                 self.cv.notify_all()
@@ -285,5 +324,5 @@ class Server:
         return {"requests": len(self.done), "latency_ms_p50": float(np.percentile(lat, 50)),
                 "latency_ms_p99": float(np.percentile(lat, 99)), "requests_per_s": len(self.done) / (t1 - t0),
                 "launches": self.launches, "admissions": self.store.admissions,
-                "evictions": self.store.evictions,
+                "evictions": self.store.evictions, "refreshes": self.store.refreshes,
                 "failed": sum(1 for r in self.done if r.status != 0)}

@@ -238,3 +238,41 @@ def test_temporal_stream_served(lib, temporal):
         e = _after(e, b)
     r = store.res[0]
     _check_state(lib, r.graph, r.state, _degrees(e), _orc(e))
+
+
+@pytest.mark.timeout(600)
+def test_temporal_stream_served_with_refresh(lib, temporal):
+    """The same stream under the quality policy: static Louvain replaces the
+    state after every 50th batch (the paper's appendix suggests every 1000;
+    the stream has 100), so the final state is a static run's."""
+    from paper_2404_19634_amd import serve
+    e0, batches = temporal
+    store = serve.GraphStore(1 << 40, max_updates=max(b.size for b in batches), mode="async",
+                             refresh_every=50, **{"slack_frac": 0.1, "slack_min": 8})
+    store.add(0, e0)
+    with store.lock:
+        store.acquire([0])
+    store.release([0])
+    srv = serve.Server(store, slots=1, workers=1)
+    srv.start()
+    lat, q = [], []
+    try:
+        for k, b in enumerate(batches):
+            t = time.perf_counter()
+            srv.submit(0, b, t_arrival=t)
+            srv.wait(k + 1)
+            lat.append((srv.done[-1].t_done - t) * 1e3)
+    finally:
+        srv.close()
+    assert all(r.status == 0 for r in srv.done)
+    assert store.refreshes == len(batches) // 50
+    assert [k for k, r in enumerate(srv.done) if r.refreshed] == [49, 99]
+    e = e0
+    for b in batches:
+        e = _after(e, b)
+    r = store.res[0]
+    qf = _check_state(lib, r.graph, r.state, _degrees(e), _orc(e))
+    plain = [x for k, x in enumerate(lat) if not srv.done[k].refreshed]
+    print(f"with refresh: per-batch latency p50 {np.percentile(lat, 50):.3f} ms, refreshing batches "
+          f"{lat[49]:.1f} / {lat[99]:.1f} ms, others p99 {np.percentile(plain, 99):.3f} ms; final Q={qf:.6f}",
+          flush=True)

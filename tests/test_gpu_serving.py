@@ -40,10 +40,10 @@ def _workload(count=24, chain=3, seed=77):
     return graphs, chains
 
 
-def _run(lib, graphs, chains, mode, budget, workers, slots, order):
+def _run(lib, graphs, chains, mode, budget, workers, slots, order, refresh_every=0):
     from paper_2404_19634_amd import serve
     store = serve.GraphStore(budget, max_updates=max(b.size for c in chains for b in c), mode=mode,
-                             init_mode="sync")
+                             init_mode="sync", refresh_every=refresh_every)
     for gid, e in enumerate(graphs):
         store.add(gid, e)
     srv = serve.Server(store, slots=slots, workers=workers)
@@ -98,3 +98,24 @@ def test_results_alone_and_in_the_mix(lib, mode):
                 assert G.apply_batch(b) == 0
                 C, K, S, _ = G.louvain("df", batch=b, state=(C, K, S), mode="sync")
             assert np.array_equal(C, mix[gid][0]) and np.array_equal(S, mix[gid][2])
+
+
+def test_quality_refresh_policy(lib):
+    """refresh_every=2 on chains of four batches: static Louvain replaces
+    each graph's state after its second and fourth update, also across
+    evictions, so the final state is static SYNC Louvain on the final graph:
+    bit for bit the sequential oracle's."""
+    import oracle
+    graphs, chains = _workload(count=12, chain=4, seed=91)
+    order = [(gid, t) for t in range(4) for gid in range(len(graphs))]
+    out, summ = _run(lib, graphs, chains, "async", budget=2 << 20, workers=2, slots=4, order=order,
+                     refresh_every=2)
+    assert summ["refreshes"] == 2 * len(graphs), summ
+    assert summ["evictions"] > 0
+    for gid, e in enumerate(graphs):
+        for b in chains[gid]:
+            e = W.apply_batch_np(e, b)
+        C, K, S, size, csr, q = out[gid]
+        Co, Ko, So, _ = oracle.Graph.from_edges(e).louvain("static", mode="sync")
+        assert np.array_equal(C, Co) and np.array_equal(K, Ko) and np.array_equal(S, So), gid
+        assert np.array_equal(size, np.bincount(C, minlength=e.n)), gid
