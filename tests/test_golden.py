@@ -29,8 +29,8 @@ def test_oracle_reproduces_the_hand_worked_step(orc):
     assert g.two_m == fx["two_m"]
     assert g.degrees().tolist() == fx["K"]
     assert abs(g.modularity(C0) - float(fx["modularity_prev"])) < 1e-15
-    for mode in ("sync", "async"):
-        C, K, S, st = g.louvain("df", batch=b, state=(C0, K0, S0), mode=mode)
+    for approach, mode in (("df", "sync"), ("df", "async"), ("nd", "sync"), ("nd", "async")):
+        C, K, S, st = g.louvain(approach, batch=b, state=(C0, K0, S0), mode=mode)
         assert G.partition(C) == fx["partition"], mode
         assert K.tolist() == fx["K"]
         assert [[int(S[C[grp[0]]])] for grp in G.partition(C)] == fx["community_Sigma"]
