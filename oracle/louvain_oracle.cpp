@@ -539,6 +539,14 @@ void* orc_graph_new(int32_t n, int64_t m, const int32_t* u, const int32_t* v, co
   Graph* g = new Graph();
   g->n = n;
   g->adj.assign(n, {});
+  {  // exact row capacities first (memory only: large inputs would double it)
+    std::vector<int64_t> deg(n, 0);
+    for (int64_t k = 0; k < m; ++k) {
+      if (u[k] >= 0 && u[k] < n) deg[u[k]] += 1;
+      if (v[k] >= 0 && v[k] < n) deg[v[k]] += 1;
+    }
+    for (int32_t i = 0; i < n; ++i) g->adj[i].reserve(deg[i]);
+  }
   for (int64_t k = 0; k < m; ++k) {
     if (u[k] < 0 || v[k] < 0 || u[k] >= n || v[k] >= n || u[k] == v[k] || w[k] <= 0) {
       *status = E_INVAL;
