@@ -46,26 +46,6 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_batches(e, sizes, count, seed):
-    """`count` batches cycling through `sizes` (undirected updates), each 80%
-    insertions of absent uniform pairs and 20% deletions of uniform existing
-    edges.  All batches are drawn at once from disjoint pools, so applying
-    them in sequence is always valid (a deletion's edge still exists, an
-    insertion's pair is still absent)."""
-    from paper_2404_19634_amd import workloads as W
-    plan = [sizes[k % len(sizes)] for k in range(count)]
-    n_ins = [int(round(0.8 * s)) for s in plan]
-    n_del = [s - i for s, i in zip(plan, n_ins)]
-    pool = W.random_batch(e, sum(n_ins) + sum(n_del), seed, ins_frac=sum(n_ins) / max(1, sum(plan)))
-    out, pi, pd = [], 0, 0
-    for a, d in zip(n_ins, n_del):
-        out.append(W.Batch(pool.del_u[pd:pd + d], pool.del_v[pd:pd + d], pool.del_w[pd:pd + d],
-                           pool.ins_u[pi:pi + a], pool.ins_v[pi:pi + a], pool.ins_w[pi:pi + a]))
-        pi += a
-        pd += d
-    return out
-
-
 class ProfilerRegion:
     """Marks the timed region with a ROCTx range named "timed_region" so a
     profile taken with `rocprofv3 --marker-trace --kernel-trace` can be cut
@@ -319,8 +299,9 @@ def approaches(lib, e, sizes, reps=2, seed=777):
     Sigma recomputed from scratch per batch, "async_no_aux"), and
     "aux_speedup" is that variant's p50 over the incremental one's."""
     import torch
+    from paper_2404_19634_amd import workloads as W
     dev = torch.device("cuda:0")
-    batches = make_batches(e, sizes, reps * len(sizes), seed=seed)
+    batches = W.batch_sequence(e, sizes, reps * len(sizes), seed=seed)
     out = {"static": {}}
     for mode in ("sync", "async"):
         prm = lib.params(mode=mode)
@@ -514,7 +495,7 @@ def main():
     fracs = [1e-7, 1e-6, 1e-5, 1e-4, 1e-3]
     sizes = [W.batch_size(f, e.m) for f in fracs]
     total = args.warmup + args.steps
-    batches = make_batches(e, sizes, total, seed=4242)
+    batches = W.batch_sequence(e, sizes, total, seed=4242)
     dbatches = [lib.Batch.from_host(b, dev) for b in batches]
     g = lib.Graph.from_edges(e, slack_frac=0.1, slack_min=8)
     prm = lib.params(mode=args.mode)

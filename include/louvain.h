@@ -175,6 +175,9 @@ typedef struct {
                                 most (else one launch per bin); -1: never */
   int32_t defer_totals;      /* LV_ASYNC: 1 sums a workgroup's Sigma/size changes in LDS and applies
                                 them when it ends; 0 applies each move's changes at once */
+  int32_t revisit_min_degree; /* LV_ASYNC, degree-class order: each iteration visits the degree classes
+                                 whose rows are all longer than this twice in a row (the second visit
+                                 sees the first one's moves); 0: every class once */
 } lv_tuning;
 
 /* The paper's parameter values (Section 5.1.2). */

@@ -21,7 +21,7 @@ namespace lv {
 namespace {
 
 thread_local std::string g_last_error;
-lv_tuning g_tuning = {256, 2048, 2560, 1280, 7, 4096, 2, 1 << 20, 1};
+lv_tuning g_tuning = {256, 2048, 2560, 1280, 7, 4096, 2, 1 << 20, 1, 128};
 
 lv_status fail(lv_status code, const char* msg) {
   g_last_error = msg;
@@ -204,6 +204,7 @@ lv_tuning effective_tuning() {
   if (t.async_rounds_min_frontier < 0) t.async_rounds_min_frontier = 0;
   if (t.fuse_max_frontier < -1) t.fuse_max_frontier = -1;
   t.defer_totals = t.defer_totals ? 1 : 0;
+  if (t.revisit_min_degree < 0) t.revisit_min_degree = 0;
   return t;
 }
 
@@ -264,17 +265,23 @@ std::vector<SubRound> sub_rounds(int32_t mode, int32_t pass, int64_t est_frontie
     static const int32_t cls_lo[4] = {1025, 129, 17, 0};
     static const int32_t cls_hi[4] = {0x7fffffff, 1024, 128, 16};
     const int kh = k - 2;
-    for (int c = 0; c < 4; ++c)
-      for (int r = 0; r < (1 << kh); ++r) {
-        SubRound s = all;
-        s.deg_lo = cls_lo[c];
-        s.deg_hi = cls_hi[c];
-        if (kh > 0) {
-          s.hash_round = static_cast<uint32_t>(r);
-          s.hash_shift = 32u - static_cast<uint32_t>(kh);
+    for (int c = 0; c < 4; ++c) {
+      // classes of long rows are visited twice: hubs that chose on the same
+      // snapshot often picked communities their neighbours were leaving,
+      // and the second visit lets them follow
+      const int visits = (tu.revisit_min_degree > 0 && cls_lo[c] > tu.revisit_min_degree) ? 2 : 1;
+      for (int v = 0; v < visits; ++v)
+        for (int r = 0; r < (1 << kh); ++r) {
+          SubRound s = all;
+          s.deg_lo = cls_lo[c];
+          s.deg_hi = cls_hi[c];
+          if (kh > 0) {
+            s.hash_round = static_cast<uint32_t>(r);
+            s.hash_shift = 32u - static_cast<uint32_t>(kh);
+          }
+          out.push_back(s);
         }
-        out.push_back(s);
-      }
+    }
   }
   return out;
 }

@@ -105,7 +105,8 @@ class Tuning(ct.Structure):
     _fields_ = [("wave_max_degree", ct.c_int32), ("blocks_small", ct.c_int32), ("blocks_wave", ct.c_int32),
                 ("blocks_hub", ct.c_int32), ("async_rounds_log2", ct.c_int32),
                 ("async_rounds_min_frontier", ct.c_int32), ("async_round_order", ct.c_int32),
-                ("fuse_max_frontier", ct.c_int32), ("defer_totals", ct.c_int32)]
+                ("fuse_max_frontier", ct.c_int32), ("defer_totals", ct.c_int32),
+                ("revisit_min_degree", ct.c_int32)]
 
 
 _lib = None
@@ -196,6 +197,7 @@ DEFAULT_ASYNC_ROUNDS_LOG2 = 7
 
 DEFAULT_FUSE_MAX_FRONTIER = 1 << 20
 DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER = 4096
+DEFAULT_REVISIT_MIN_DEGREE = 128
 
 
 def set_timing(kernels=()):
@@ -211,10 +213,11 @@ def set_timing(kernels=()):
 def set_tuning(wave_max_degree=0, blocks_small=0, blocks_wave=0, blocks_hub=0,
                async_rounds_log2=DEFAULT_ASYNC_ROUNDS_LOG2,
                async_rounds_min_frontier=DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER, async_round_order=2,
-               fuse_max_frontier=DEFAULT_FUSE_MAX_FRONTIER, defer_totals=1):
+               fuse_max_frontier=DEFAULT_FUSE_MAX_FRONTIER, defer_totals=1,
+               revisit_min_degree=DEFAULT_REVISIT_MIN_DEGREE):
     load().lv_set_tuning(ct.byref(Tuning(wave_max_degree, blocks_small, blocks_wave, blocks_hub,
                                          async_rounds_log2, async_rounds_min_frontier, async_round_order,
-                                         fuse_max_frontier, defer_totals)))
+                                         fuse_max_frontier, defer_totals, revisit_min_degree)))
 
 
 def autotune(g: "Graph", repeats: int = 2, stream=None) -> dict:

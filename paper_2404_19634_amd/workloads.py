@@ -27,7 +27,7 @@ import numpy as np
 
 __all__ = [
     "Edges", "Batch", "sbm", "config1_sbm", "rmat", "config2_rmat",
-    "random_batch", "batch_size", "two_cliques_bridge", "ring_of_cliques",
+    "random_batch", "batch_size", "batch_sequence", "two_cliques_bridge", "ring_of_cliques",
     "random_small_graph", "apply_batch_np", "chung_lu", "config3_chung_lu", "pa_temporal_stream",
     "temporal_workload", "config4_temporal", "multi_sbm_specs",
 ]
@@ -282,6 +282,25 @@ def random_batch(g: Edges, size: int, seed: int, ins_frac: float = 0.8) -> Batch
                  _i32(iu), _i32(iv), np.ones(ins.shape[0], dtype=np.int32))
 
 
+def batch_sequence(g: Edges, sizes, count: int, seed: int) -> list:
+    """``count`` batches cycling through ``sizes`` (undirected updates), each
+    80% insertions of absent uniform pairs and 20% deletions of uniform
+    existing edges.  All are drawn at once from disjoint pools, so applying
+    them in sequence is always valid (a deletion's edge still exists, an
+    insertion's pair is still absent)."""
+    plan = [sizes[k % len(sizes)] for k in range(count)]
+    n_ins = [int(round(0.8 * s)) for s in plan]
+    n_del = [s - i for s, i in zip(plan, n_ins)]
+    pool = random_batch(g, sum(n_ins) + sum(n_del), seed, ins_frac=sum(n_ins) / max(1, sum(plan)))
+    out, pi, pd = [], 0, 0
+    for a, d in zip(n_ins, n_del):
+        out.append(Batch(pool.del_u[pd:pd + d], pool.del_v[pd:pd + d], pool.del_w[pd:pd + d],
+                         pool.ins_u[pi:pi + a], pool.ins_v[pi:pi + a], pool.ins_w[pi:pi + a]))
+        pi += a
+        pd += d
+    return out
+
+
 def apply_batch_np(g: Edges, b: Batch) -> Edges:
     """Edge list after the batch (deletions subtract, then insertions add);
     used by generators that chain batches, not by either implementation."""
@@ -355,6 +374,32 @@ def random_small_graph(n: int, m: int, seed: int, max_w: int = 1) -> Edges:
 # Larger configurations (power-law, temporal, many graphs)
 # ---------------------------------------------------------------------------
 
+def _splitmix64(x):
+    """SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) of int64 torch
+    counters: one independent 64-bit draw per counter.  Plain integer
+    arithmetic (wrapping products, logical shifts), so CPU and GPU give the
+    same bits."""
+    import torch
+
+    def shr(z, k):  # logical right shift of int64
+        return (z >> k) & ((1 << (64 - k)) - 1)
+
+    def c64(v):  # unsigned 64-bit constant as a wrapped int64
+        return v - (1 << 64) if v >= (1 << 63) else v
+
+    z = x + c64(0x9E3779B97F4A7C15)
+    z = (z ^ shr(z, 30)) * c64(0xBF58476D1CE4E5B9)
+    z = (z ^ shr(z, 27)) * c64(0x94D049BB133111EB)
+    return z ^ shr(z, 31)
+
+
+def _uniform01(counters):
+    """Doubles in [0, 1) from the top 53 bits of SplitMix64 draws."""
+    import torch
+    h = _splitmix64(counters)
+    return ((h >> 11) & ((1 << 53) - 1)).to(torch.float64) * (1.0 / (1 << 53))
+
+
 def chung_lu(n: int, gamma: float, mean_degree: float, seed: int, m_target: int | None = None,
              device: str = "cpu", chunk: int = 1 << 26) -> Edges:
     """Chung-Lu power-law graph: expected weights w_i ~ (i+1)^(-1/(gamma-1)),
@@ -362,9 +407,12 @@ def chung_lu(n: int, gamma: float, mean_degree: float, seed: int, m_target: int 
     endpoints drawn proportional to w, self pairs and repeats dropped until
     ``m_target`` distinct edges (default n*mean_degree/2); unit weights.
 
-    The draws run in torch on ``device`` (seeded generator), so the
-    hundreds of millions of draws of the 20M-vertex configuration take
-    seconds on a GPU; the edge list comes back as numpy arrays."""
+    The draws are counter-based (SplitMix64 of the draw index and the seed)
+    and run in torch on ``device``: the hundreds of millions of draws of
+    the 20M-vertex configuration take seconds on a GPU, and any device
+    yields the same edge list.  When more than ``m_target`` distinct pairs
+    come up, the ones with the smallest SplitMix64 hash of (pair, seed) are
+    kept."""
     import torch
     expo = -1.0 / (gamma - 1.0)
     base = np.power(np.arange(1, n + 1, dtype=np.float64), expo)
@@ -385,9 +433,9 @@ def chung_lu(n: int, gamma: float, mean_degree: float, seed: int, m_target: int 
     cdf /= cdf[-1]
     dev = torch.device(device)
     tcdf = torch.from_numpy(cdf).to(dev)
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(int(seed))
     m_target = int(m_target if m_target is not None else round(n * mean_degree / 2))
+    stream = (int(seed) & 0xFFFFF) << 42   # draw counters of this seed: 2^42 per seed
+    drawn = 0
     keys = torch.zeros(0, dtype=torch.int64, device=dev)
     while keys.numel() < m_target:
         need = m_target - keys.numel()
@@ -395,8 +443,11 @@ def chung_lu(n: int, gamma: float, mean_degree: float, seed: int, m_target: int 
         parts = [keys]
         for off in range(0, cnt, chunk):
             c = min(chunk, cnt - off)
-            a = torch.searchsorted(tcdf, torch.rand(c, generator=gen, device=dev, dtype=torch.float64), right=True)
-            b = torch.searchsorted(tcdf, torch.rand(c, generator=gen, device=dev, dtype=torch.float64), right=True)
+            ctr = torch.arange(drawn, drawn + c, dtype=torch.int64, device=dev) * 2 + stream
+            drawn += c
+            a = torch.searchsorted(tcdf, _uniform01(ctr), right=True)
+            b = torch.searchsorted(tcdf, _uniform01(ctr + 1), right=True)
+            del ctr
             a.clamp_(max=n - 1)
             b.clamp_(max=n - 1)
             ok = a != b
@@ -406,8 +457,10 @@ def chung_lu(n: int, gamma: float, mean_degree: float, seed: int, m_target: int 
         keys = torch.unique(torch.cat(parts))
         del parts
     if keys.numel() > m_target:
-        keep = torch.randperm(keys.numel(), generator=gen, device=dev)[:m_target]
-        keys = torch.sort(keys[keep]).values
+        h = _splitmix64(keys ^ (int(seed) * 0x2545F4914F6CDD1D % (1 << 62)))
+        order = torch.sort(h, stable=True).indices[:m_target]
+        keys = torch.sort(keys[order]).values
+        del h, order
     u = (keys // n).to(torch.int32).cpu().numpy()
     v = (keys % n).to(torch.int32).cpu().numpy()
     return Edges(int(n), u, v, np.ones(u.shape[0], dtype=np.int32))

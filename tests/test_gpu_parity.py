@@ -489,7 +489,7 @@ def test_many_graphs_match_single_graph_results(lib, mode, tol):
         G = _orc(e)
         s0 = G.louvain("static", mode="sync")[:3]
         assert G.apply_batch(b) == 0
-        Co, Ko, So, os_ = G.louvain("df", batch=b, state=s0, mode="sync", tolerance=tol)
+        Co, Ko, So, os_ = G.louvain("df", batch=b, state=s0, mode=mode, tolerance=tol)
         expect.append((G, Co, Ko, So, os_))
         g = lib.Graph.from_edges(e, slack_frac=1.0, slack_min=32)
         st = lib.State.from_host(*s0)
@@ -513,9 +513,9 @@ def test_many_graphs_match_single_graph_results(lib, mode, tol):
         if mode == "sync":
             assert np.array_equal(C, Co) and np.array_equal(S, So)
             _same_stats(s, os_)
-        else:
+        else:  # the oracle's ASYNC DF from the same state: the asynchronous mode's quality bar
             q = lib.modularity(g, st.C)
-            assert q >= G.modularity(Co) - 2e-3
+            assert q >= G.modularity(Co) - 1e-3
     # the call restores what the scratch needs: a second round on the same graphs works too
     b2 = [lib.Batch.from_host(W.random_batch(W.apply_batch_np(e, b), 8, 900 + k))
           for k, (e, b) in enumerate(cases)]
