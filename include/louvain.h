@@ -250,6 +250,24 @@ lv_status louvain_df(const lv_graph* g, const lv_edges* del, const lv_edges* ins
                      lv_state* state, void* ws, size_t ws_bytes, lv_stats* stats, void* stream);
 
 /*
+ * louvain_df_noalloc -- louvain_df for callers that cannot allocate device
+ * or host memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same computation and results, with
+ * no workspace argument.  Its scratch is a device array inside the library
+ * of lv_noalloc_scratch_bytes() bytes (64 MiB), held on each GPU the library
+ * runs on until the process ends; the call allocates nothing (no hipMalloc,
+ * no pinned buffer, no events: the ms_* fields and timed launches of
+ * `stats` stay 0).  Graphs whose lv_workspace_bytes(n, cap) exceeds that size
+ * get LV_EWORKSPACE and are left untouched.  The device is the current one;
+ * `stream` must belong to it.  Every call on a GPU shares that GPU's array,
+ * so calls that overlap on one GPU (other threads or streams) race: the
+ * caller serialises them.  Other arguments and errors as louvain_df.
+ */
+size_t lv_noalloc_scratch_bytes(void);
+lv_status louvain_df_noalloc(const lv_graph* g, const lv_edges* del, const lv_edges* ins, const lv_params* p,
+                             lv_state* state, lv_stats* stats, void* stream);
+
+/*
  * modularity -- Eq. 1: Q = Σ_c [σ_c/2m - (Σ_c/2m)^2] for membership C
  * (device int32[n], ids in [0, n)).  σ_c and Σ_c are exact int64 sums;
  * the host forms the FP64 quotient.  Waits for the stream.

@@ -7,6 +7,7 @@
 // Between passes the communities are renumbered, the dendrogram looked up
 // and the level graph aggregated (Alg. 6); τ drops by the given factor.
 #include <atomic>
+#include <mutex>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -46,6 +47,12 @@ lv_status fail(lv_status code, const char* msg) {
     }                                                                        \
   } while (0)
 
+// Set while a call of louvain_df_noalloc runs on this thread: counters are
+// read back into plain host memory, and no HIP events are created or
+// recorded (no timing), so the call allocates nothing.
+thread_local bool g_no_alloc = false;
+thread_local int64_t g_plain_host[CTR_COUNT + kCtrLine];
+
 // Small pinned buffer for counter readback, one per host thread.
 struct Pinned {
   int64_t* p = nullptr;
@@ -56,6 +63,10 @@ struct Pinned {
 thread_local Pinned g_pinned;
 
 lv_status pinned(int64_t** out) {
+  if (g_no_alloc) {
+    *out = g_plain_host;
+    return LV_OK;
+  }
   if (!g_pinned.p) {
     void* q = nullptr;
     LV_HIP(hipHostMalloc(&q, sizeof(int64_t) * (CTR_COUNT + kCtrLine), hipHostMallocDefault));
@@ -82,7 +93,7 @@ thread_local Timer g_timer;
 
 TimerPair timer_pair(int kernel) {
   TimerPair p;
-  if (!((g_timed_mask.load(std::memory_order_relaxed) >> kernel) & 1u)) return p;
+  if (g_no_alloc || !((g_timed_mask.load(std::memory_order_relaxed) >> kernel) & 1u)) return p;
   Timer& t = g_timer;
   if (t.used >= kTimerPairs) return p;
   while (static_cast<int>(t.ev.size()) < 2 * (t.used + 1)) {
@@ -123,6 +134,10 @@ struct Events {
 thread_local Events g_events;
 
 lv_status events(hipEvent_t** out) {
+  if (g_no_alloc) {
+    *out = nullptr;
+    return LV_OK;
+  }
   if (!g_events.made) {
     for (auto& x : g_events.e) LV_HIP(hipEventCreate(&x));
     g_events.made = true;
@@ -327,10 +342,18 @@ __global__ void k_fill_i64(int64_t* p, int64_t v, int64_t n) {
     p[i] = v;
 }
 
+// Records event k of `ev` (none when ev is null: no timing).
+hipError_t record(hipEvent_t* ev, int k, hipStream_t st) { return ev ? hipEventRecord(ev[k], st) : hipSuccess; }
+
 float ms_between(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
   return ms;
+}
+
+float ms_between(hipEvent_t* ev, int a, int b) {
+  if (!ev) return 0.f;
+  return ms_between(ev[a], ev[b]);
 }
 
 // resume_li > 0: the local-moving iterations of pass 0 already ran (the
@@ -366,7 +389,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
   // The first kernel zeroes counters and frontier bitmasks and checks
   // 0 < 2m < 2^31 on the device; with 2m out of range every later kernel
   // leaves the state alone and the first readback reports the error.
-  LV_HIP(hipEventRecord(ev[0], st));
+  LV_HIP(record(ev, 0, st));
   launch_call_begin(ws, g->two_m, st);
   const int64_t* err = ws.ctr + CTR_ERR;
   LevelGraph L0;
@@ -432,7 +455,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     if (p->swap_guard && !state->size) launch_community_sizes(state->C, N, ws.size, st);
   }
   LV_CHECK_LAUNCH();
-  LV_HIP(hipEventRecord(ev[1], st));
+  LV_HIP(record(ev, 1, st));
 
   // ---- Alg. 4: passes of local-moving and aggregation --------------------
   LevelGraph L = L0;
@@ -450,7 +473,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
   float ms_move = 0.f, ms_agg = 0.f;
   int64_t arcs_agg = 0;
   for (int32_t pass = 0; pass < p->max_passes; ++pass) {
-    LV_HIP(hipEventRecord(ev[2], st));
+    LV_HIP(record(ev, 2, st));
     int32_t li = p->max_iterations;
     MoveArgs a;
     a.g = L;
@@ -470,7 +493,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     if (pass == 0 && ap == A_DF) est_frontier = 2 * (D.count + I.count);
     if (pass == 0 && resume_li > 0) {
       li = resume_li;
-      LV_HIP(hipEventRecord(ev[3], st));
+      LV_HIP(record(ev, 3, st));
     }
     for (int32_t it = 0; it < p->max_iterations && !(pass == 0 && resume_li > 0); ++it, ++iter_seq) {
       a.cur = cur;
@@ -508,7 +531,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
       }
       LV_CHECK_LAUNCH();
       std::swap(cur, next);
-      LV_HIP(hipEventRecord(ev[3], st));
+      LV_HIP(record(ev, 3, st));
       if ((s = read_counters(host, ws, CTR_ROUND0, st))) return s;
       if (host[CTR_ERR]) return device_error(host[CTR_ERR], "local-moving");
       two_m = host[CTR_TWO_M];
@@ -534,7 +557,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
         break;
       }
     }
-    ms_move += ms_between(ev[2], ev[3]);
+    ms_move += ms_between(ev, 2, 3);
     S.passes = pass + 1;
     S.iterations[pass] = li;
     if (li <= 1) break;
@@ -550,7 +573,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     const int32_t nc = nc32;
     S.communities[pass] = nc;
     if (static_cast<double>(nc) / static_cast<double>(L.n) > p->aggregation_tolerance) break;
-    LV_HIP(hipEventRecord(ev[4], st));
+    LV_HIP(record(ev, 4, st));
     launch_relabel(Cl, L.n, ws.newid, st);
     if (pass > 0) launch_lookup(state->C, N, Cl, st);
     LevelGraph out = ws.lg[pass & 1];
@@ -558,11 +581,11 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     LV_CHECK_LAUNCH();
     LV_HIP(hipMemsetAsync(cur, 0, sizeof(uint32_t) * ws.words, st));
     launch_set_all_bits(cur, nc, st);
-    LV_HIP(hipEventRecord(ev[5], st));
+    LV_HIP(record(ev, 5, st));
     LV_HIP(hipMemcpyAsync(&host[CTR_COUNT], out.row_start + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     if ((s = read_counters(host, ws, CTR_STATS0, st))) return s;
     if (host[CTR_ERR]) return device_error(host[CTR_ERR], "aggregation");
-    ms_agg += ms_between(ev[4], ev[5]);
+    ms_agg += ms_between(ev, 4, 5);
     arcs_agg += host[CTR_COUNT];
     L = out;
     Cl = ws.lC;
@@ -573,17 +596,17 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     aggregated = true;
   }
   if (aggregated) {
-    LV_HIP(hipEventRecord(ev[6], st));
+    LV_HIP(record(ev, 6, st));
     launch_lookup(state->C, N, Cl, st);
     launch_sigma_from_members(state->C, state->K, N, state->Sigma, st);
     if (state->size) launch_community_sizes(state->C, N, state->size, st);
     LV_CHECK_LAUNCH();
-    LV_HIP(hipEventRecord(ev[7], st));
+    LV_HIP(record(ev, 7, st));
     LV_HIP(hipStreamSynchronize(st));
-    S.ms_other = ms_between(ev[6], ev[7]);
+    S.ms_other = ms_between(ev, 6, 7);
   }
   timer_collect(S.timed_launches, S.timed_ms);
-  S.ms_mark = ms_between(ev[0], ev[1]);
+  S.ms_mark = ms_between(ev, 0, 1);
   S.ms_move = ms_move;
   S.ms_aggregate = ms_agg;
   S.arcs_aggregated = arcs_agg;
@@ -743,9 +766,71 @@ lv_status many_graph(void* desc, size_t desc_bytes, int32_t count, const lv_para
 
 }  // namespace lv
 
+// ---- scratch of the entry point for callers that cannot allocate ---------
+// A file-scope device array: each GPU the library runs on holds its own copy
+// (64 MiB) from the time the code object is loaded until the process ends.
+// Host code never passes its name to a kernel (the name is a host-side
+// stand-in); it takes the device address once per device with
+// hipGetSymbolAddress and uses that.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace lv {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up on the
+// first call on that device.
+lv_status scratch_address(void** out) {
+  int dev = -1;
+  LV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(LV_EINVAL, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    LV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(LV_EHIP, "hipGetSymbolAddress returned a null address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LV_OK;
+}
+
+struct NoAllocScope {
+  NoAllocScope() { g_no_alloc = true; }
+  ~NoAllocScope() { g_no_alloc = false; }
+};
+
+}  // namespace
+}  // namespace lv
+
 using namespace lv;
 
 extern "C" {
+
+size_t lv_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+lv_status louvain_df_noalloc(const lv_graph* g, const lv_edges* del, const lv_edges* ins, const lv_params* p,
+                             lv_state* state, lv_stats* stats, void* stream) {
+  if (!graph_ok(g)) return fail(LV_EINVAL, "invalid graph");
+  const size_t need = lv_workspace_bytes(g->n, g->cap);
+  if (need > kNoAllocScratchBytes) {
+    static thread_local char msg[160];
+    std::snprintf(msg, sizeof(msg),
+                  "louvain_df_noalloc: the graph needs %zu bytes of scratch, above the %zu bytes it holds "
+                  "(use louvain_df with a workspace)",
+                  need, kNoAllocScratchBytes);
+    return fail(LV_EWORKSPACE, msg);
+  }
+  void* ws = nullptr;
+  lv_status s = scratch_address(&ws);
+  if (s) return s;
+  NoAllocScope scope;
+  return run_louvain(A_DF, g, del, ins, p, state, ws, kNoAllocScratchBytes, stats, stream);
+}
 
 void lv_default_params(lv_params* p) {
   if (!p) return;

@@ -37,7 +37,8 @@ NTIMED = len(TIMED)
 EXPORTS = ["lv_default_params", "lv_workspace_bytes", "lv_graph_capacity_bound", "lv_graph_build",
            "lv_graph_relayout", "apply_batch", "louvain_static", "louvain_nd", "louvain_ds", "louvain_df",
            "modularity", "lv_set_tuning", "lv_get_tuning", "lv_set_timing", "lv_last_error",
-           "lv_many_scratch_bytes", "lv_many_desc_bytes", "louvain_df_many", "lv_autotune"]
+           "lv_many_scratch_bytes", "lv_many_desc_bytes", "louvain_df_many", "lv_autotune",
+           "lv_noalloc_scratch_bytes", "louvain_df_noalloc"]
 
 
 class LouvainError(RuntimeError):
@@ -153,6 +154,10 @@ def load():
     L.louvain_df_many.argtypes = [ct.POINTER(CItem), I32, PP, P, SZ, P, SZ, ct.POINTER(I32), STP, P]
     L.lv_autotune.restype = I32
     L.lv_autotune.argtypes = [GP, SP, P, SZ, I32, ct.POINTER(Tuning), P]
+    L.lv_noalloc_scratch_bytes.restype = SZ
+    L.lv_noalloc_scratch_bytes.argtypes = []
+    L.louvain_df_noalloc.restype = I32
+    L.louvain_df_noalloc.argtypes = [GP, EP, EP, PP, SP, STP, P]
     L.lv_set_timing.restype = I32
     L.lv_set_timing.argtypes = [ct.c_uint32]
     L.lv_last_error.restype = ct.c_char_p
@@ -487,6 +492,19 @@ def louvain_ds(g, b, state, prm=None, stream=None, **kw):
 
 def louvain_df(g, b, state, prm=None, stream=None, **kw):
     return _dynamic("louvain_df", g, b, state, prm, stream, kw)
+
+
+def louvain_df_noalloc(g, b, state, prm=None, stream=None, **kw):
+    """louvain_df through the entry point that allocates nothing: its
+    scratch is the library's own device array (lv_noalloc_scratch_bytes()),
+    so the graph's workspace is neither used nor created."""
+    L = load()
+    prm = prm if prm is not None else params(**kw)
+    st = Stats()
+    cg, cd, ci, cs = g.c(), b.dels.c(), b.ins.c(), state.c()
+    _check(L.louvain_df_noalloc(ct.byref(cg), ct.byref(cd), ct.byref(ci), ct.byref(prm), ct.byref(cs),
+                                ct.byref(st), _stream(stream)))
+    return state, StatsView(st)
 
 
 def many_scratch(n: int, max_updates: int, device="cuda") -> torch.Tensor:
