@@ -1,7 +1,12 @@
 """Benchmark: DF Louvain update latency (p50/p99) and edges scanned per
-second against GPU static Louvain, on R-MAT scale 22 (4,194,304 vertices,
-edge factor 16, a=0.57 b=0.19 c=0.19) with random 80/20 batch updates of
-1e-7|E| .. 1e-3|E| (x10 steps).
+second against GPU static Louvain.
+
+The headline line runs the largest single-GPU workload: a Chung-Lu
+power-law graph of 20,000,000 vertices (degree exponent 2.1, mean degree 50,
+500M undirected edges) with random 80/20 batch updates of 1e-5|E| and
+1e-4|E|.  R-MAT scale 22 (4,194,304 vertices, edge factor 16, batches of
+1e-7..1e-3 |E|) follows as extra keys, with the ND / DS / DF x SYNC /
+ASYNC comparison.
 
 A step is one batch through the whole hot path: apply_batch (in-place CSR
 edit) then louvain_df (marking, weight update, local-moving, aggregation).
@@ -106,16 +111,16 @@ def move_instance(tuning):
     return f"k_move_all<{2 * int(tuning['wave_max_degree'])}, 7>"
 
 
-def traffic_for(kernel_name, instance):
+def traffic_for(kernel_name, instance, workload):
     """HBM bytes per launch of `instance` (a template instantiation of
-    `kernel_name`) from the committed counter summary (FETCH_SIZE +
-    WRITE_SIZE, copy-calibrated), or None when there is none for that
-    instantiation or the kernel sources changed since the counters were
-    taken."""
+    `kernel_name`) in the DF steps of `workload`, from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when there
+    is none for that instantiation or the kernel sources changed since the
+    counters were taken."""
     import hashlib
     import re
     tag = "_".join(re.findall(r"\d+", instance))
-    path = os.path.join(PROFILES, f"traffic_{kernel_name}_{tag}_rmat22_df.txt")
+    path = os.path.join(PROFILES, f"traffic_{kernel_name}_{tag}_{workload}_df.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -211,10 +216,29 @@ def pct(x, q):
     return float(np.percentile(np.asarray(x, dtype=np.float64), q)) if len(x) else None
 
 
-def cpu_baseline(e, batch, budget_s=30.0):
-    """The sequential oracle on a bounded sample of the same workload: one
-    full local-moving sweep of static Louvain (every vertex scanned once),
-    then DF Louvain on one batch starting from that sweep's partition."""
+def host_cpu():
+    """The host's CPU model, the logical CPUs it has and those this process
+    may run on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(e, batch, budget_s=60.0):
+    """The sequential oracle (one thread) on a bounded sample of the same
+    workload: one full local-moving sweep of static Louvain (every vertex
+    scanned once), then DF Louvain on one batch starting from that sweep's
+    partition."""
     import oracle
     t0 = time.perf_counter()
     G = oracle.Graph.from_edges(e)
@@ -224,13 +248,14 @@ def cpu_baseline(e, batch, budget_s=30.0):
     res = {"value": sweep_arcs / sweep_s, "unit": "edges scanned/s", "cores": 1, "kind": "oracle",
            "sample": (f"one static local-moving sweep over all {sweep_arcs} arcs "
                       f"({sweep_s:.2f} s) then DF Louvain on one batch of {batch.size} updates"),
-           "static_sweep_edges_per_s": sweep_arcs / sweep_s, "graph_build_s": build_s}
+           "static_sweep_edges_per_s": sweep_arcs / sweep_s, "graph_build_s": build_s, **host_cpu()}
     if sweep_s < budget_s:
         assert G.apply_batch(batch) == 0
         C2, K2, S2, st2 = G.louvain("df", batch=batch, state=(C, K, S), mode="async")
         res["df_latency_ms"] = st2["seconds"] * 1e3
         res["df_edges_scanned"] = st2["arcs_scanned"]
         res["df_edges_per_s"] = st2["arcs_scanned"] / st2["seconds"] if st2["seconds"] > 0 else None
+    del G
     return res
 
 
@@ -437,74 +462,65 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--scale", type=int, default=22)
-    ap.add_argument("--mode", default="async", choices=["async", "sync"])
-    ap.add_argument("--static-runs", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default tuning instead of lv_autotune's choice for the graph")
-    ap.add_argument("--no-approaches", action="store_true",
-                    help="skip the ND/DS/DF x SYNC/ASYNC comparison and the full-sweep roofline")
-    ap.add_argument("--tuning", default="", help="lv_tuning overrides, e.g. fuse_max_frontier=1024,defer_totals=1")
-    ap.add_argument("--no-final-static", action="store_true",
-                    help="skip the static run on the final graph (counter runs: the timed region's dispatches "
-                         "are then the last ones of each kernel)")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="end with a plain 1 GiB device copy whose counters calibrate FETCH_SIZE / WRITE_SIZE")
-    ap.add_argument("--summarize", metavar="DB", help="print a summary of a rocprofv3 database and exit")
-    ap.add_argument("--kernel", default="k_move_all<512, 7>",
-                    help="kernel of --summarize for counter databases ('all': a table of every kernel)")
-    ap.add_argument("--launches", type=int, default=0, help="last dispatches of --kernel to average")
-    ap.add_argument("--serve", action="store_true", help="many-graph serving benchmark instead of the R-MAT line")
-    ap.add_argument("--serve-graphs", type=int, default=4096)
-    ap.add_argument("--serve-slots", type=int, default=4096)
-    ap.add_argument("--serve-load", type=float, default=0.5, help="Poisson rate as a fraction of the burst rate")
-    ap.add_argument("--sweep", type=int, default=0,
-                    help="profiling mode: run this many single full local-moving sweeps (SYNC, all vertices "
-                         "from singletons) and one 1 GiB device copy for counter calibration, then exit")
-    args = ap.parse_args()
-    if args.summarize:
-        print(summarize(args.summarize, args.kernel, args.launches))
-        return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); the single-GPU line is the result",
-              file=sys.stderr)
-        sys.exit(2)
+# Workloads of the DF line: the batch sizes (fractions of |E|) and the seed
+# of the batch pools.  The sequences match the ones the oracle's ASYNC
+# fixtures were computed on (tests/golden/async_quality_<name>.json) when
+# warmup + steps equals their batch count.
+WORKLOADS = {
+    "chunglu20m": {"desc": "Chung-Lu power-law graph, 20,000,000 vertices, degree exponent 2.1, mean degree 50 "
+                           "(500M undirected edges, unit weights), random 80/20 batches of 1e-5 and 1e-4 |E|",
+                   "fracs": [1e-5, 1e-4], "seed": 4343},
+    "rmat22": {"desc": "R-MAT scale 22 (edge factor 16, a=0.57 b=0.19 c=0.19), random 80/20 batches of "
+                       "1e-7..1e-3 |E|",
+               "fracs": [1e-7, 1e-6, 1e-5, 1e-4, 1e-3], "seed": 4242},
+}
 
-    import torch
-    from paper_2404_19634_amd import lib
+
+def load_workload(name):
     from paper_2404_19634_amd import workloads as W
+    if name == "chunglu20m":
+        return W.config3_chung_lu(device="cuda")
+    if name == "rmat22":
+        return W.config2_rmat()
+    raise SystemExit(f"unknown workload {name}")
 
-    if args.serve:
-        serve_bench(args)
-        return
-    region = ProfilerRegion()
-    tuning = {k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(",") if kv)}
-    lib.set_tuning(**tuning)
-    torch.cuda.set_device(0)
+
+def oracle_fixture(name, batches):
+    """The oracle's ASYNC modularity values for this workload's batch
+    sequence, when the sequence is the one they were computed on."""
+    path = os.path.join(ROOT, "tests", "golden", f"async_quality_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        gold = json.load(f)
+    from tests.golden import make_async_golden as MG
+    if len(batches) != gold["batch_count"] or MG.batches_fingerprint(batches) != gold["batches_sha256_32"]:
+        return None
+    return gold
+
+
+def df_line(args, lib, name, e, region=None):
+    """Static Louvain and the DF steps on workload `name` (graph `e`):
+    returns the line's fields and the GPU graph after the steps."""
+    import torch
+    from paper_2404_19634_amd import workloads as W
     dev = torch.device("cuda:0")
-    t0 = time.perf_counter()
-    e = W.config2_rmat(args.scale)
-    log(f"R-MAT s{args.scale}: n={e.n} undirected edges={e.m} max w={int(e.w.max())} "
-        f"({time.perf_counter() - t0:.1f} s)")
-    fracs = [1e-7, 1e-6, 1e-5, 1e-4, 1e-3]
-    sizes = [W.batch_size(f, e.m) for f in fracs]
+    spec = WORKLOADS[name]
+    sizes = [W.batch_size(f, e.m) for f in spec["fracs"]]
     total = args.warmup + args.steps
-    batches = W.batch_sequence(e, sizes, total, seed=4242)
+    t0 = time.perf_counter()
+    batches = W.batch_sequence(e, sizes, total, seed=spec["seed"])
     dbatches = [lib.Batch.from_host(b, dev) for b in batches]
     g = lib.Graph.from_edges(e, slack_frac=0.1, slack_min=8)
     prm = lib.params(mode=args.mode)
     torch.cuda.synchronize()
+    log(f"{name}: {len(batches)} batches of {sizes}, graph on the device ({time.perf_counter() - t0:.1f} s)")
     if args.sweep:
         sweep(g, e, args.sweep)
-        return
+        return None, g, None
+    lib.set_tuning(**args.tuning_kv)
     autotune_ms = None
-    if not args.no_autotune and "wave_max_degree" not in tuning:
+    if not args.no_autotune and "wave_max_degree" not in args.tuning_kv:
         t = time.perf_counter()
         lib.autotune(g, repeats=2)
         autotune_ms = (time.perf_counter() - t) * 1e3
@@ -538,12 +554,14 @@ def main():
     lib.set_timing(range(lib.NTIMED))
     torch.cuda.synchronize()
     dom = None
+    t_region = time.perf_counter()
     for k in range(total):
         if k == args.warmup:
             dom = warm.dominant() if args.warmup else lib.TIME_BINNING
             lib.set_timing([dom])
             torch.cuda.synchronize()
-            region.resume()
+            if region is not None:
+                region.resume()
             t_region = time.perf_counter()
         b = dbatches[k]
         t = time.perf_counter()
@@ -570,7 +588,8 @@ def main():
             per_size.setdefault(batches[k].size, []).append((t2 - t1) * 1e3)
     torch.cuda.synchronize()
     region_s = time.perf_counter() - t_region
-    region.pause()
+    if region is not None:
+        region.pause()
     for s in stats:
         meter.add(s)
         arcs.append(s["arcs_scanned"])
@@ -587,6 +606,8 @@ def main():
         torch.cuda.synchronize()
         static_final_ms = (time.perf_counter() - t) * 1e3
         q_static_final = lib.modularity(g, st.C)
+        del st
+    del state, state0
     if args.calibrate_copy:
         x = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
         y = torch.empty_like(x)
@@ -596,25 +617,13 @@ def main():
         del x, y
 
     df_arcs = int(np.sum(arcs))
-    value = df_arcs / region_s
     static_eps = float(np.median([a / (m / 1e3) for a, m in zip(static_arcs, static_ms)]))
     out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "edges scanned/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "value": df_arcs / region_s,
         "ms_per_step": region_s * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int64",
-        "data": "synthetic",
-        "config": {"workload": f"R-MAT scale {args.scale} (edge factor 16, a=0.57 b=0.19 c=0.19), "
-                               f"random 80/20 batches of 1e-7..1e-3 |E|",
-                   "vertices": e.n, "undirected_edges": e.m, "batch_sizes": sizes, "mode": args.mode,
-                   "tuning": lib.get_tuning(), "autotuned": autotune_ms is not None, "autotune_ms": autotune_ms},
+        "config": {"workload": spec["desc"], "vertices": e.n, "undirected_edges": e.m, "batch_sizes": sizes,
+                   "mode": args.mode, "tuning": lib.get_tuning(), "autotuned": autotune_ms is not None,
+                   "autotune_ms": autotune_ms},
         "df_latency_ms_p50": pct(lat, 50),
         "df_latency_ms_p99": pct(lat, 99),
         "df_latency_ms_by_batch_size": {str(k): float(np.median(v)) for k, v in sorted(per_size.items())},
@@ -623,16 +632,23 @@ def main():
         "df_edges_scanned_per_s": df_arcs / (np.sum(lat) / 1e3),
         "static_latency_ms": float(np.median(static_ms)),
         "static_edges_scanned_per_s": static_eps,
+        "static_passes": static_stats["passes"], "static_iterations": static_stats["iterations"],
         "df_speedup_vs_static": float(np.median(static_ms)) / pct(lat, 50),
         "modularity": {"static_initial": q_static, "df_final": q_df, "static_final": q_static_final},
         "static_final_ms": static_final_ms,
     }
+    gold = oracle_fixture(name, batches)
+    if gold is not None:
+        out["modularity"]["oracle"] = {"static_initial": gold["static_async"]["modularity"],
+                                       "df_final": gold["df_chain_async"]["modularity"],
+                                       "static_final": gold["static_async_final_graph"]["modularity"],
+                                       "source": f"tests/golden/async_quality_{name}.json"}
     nl = meter.launches[dom]
     if nl and meter.ms[dom] > 0:
         per_launch = meter.bytes[dom] / nl
         achieved = per_launch / (meter.ms[dom] / nl * 1e-3) / 1e9
         inst = move_instance(lib.get_tuning()) if dom == lib.TIME_SCAN else KERNELS[dom]
-        tr = traffic_for(SHORT[dom], inst)
+        tr = traffic_for(SHORT[dom], inst, name)
         out["roofline"] = {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": tr, "kernel": inst,
@@ -642,11 +658,90 @@ def main():
     if not args.no_approaches:
         log("full-sweep roofline ...")
         out["roofline_full_sweep"] = full_sweep_roofline(lib, g)
+    return out, g, batches
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--workload", default="chunglu20m", choices=sorted(WORKLOADS),
+                    help="workload of the headline line (the other one follows as extra keys)")
+    ap.add_argument("--mode", default="async", choices=["async", "sync"])
+    ap.add_argument("--static-runs", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tuning instead of lv_autotune's choice for the graph")
+    ap.add_argument("--no-approaches", action="store_true",
+                    help="skip the ND/DS/DF x SYNC/ASYNC comparison and the full-sweep rooflines")
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only (no R-MAT keys)")
+    ap.add_argument("--tuning", default="", help="lv_tuning overrides, e.g. fuse_max_frontier=1024,defer_totals=1")
+    ap.add_argument("--no-final-static", action="store_true",
+                    help="skip the static run on the final graph (counter runs: the timed region's dispatches "
+                         "are then the last ones of each kernel)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with a plain 1 GiB device copy whose counters calibrate FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--summarize", metavar="DB", help="print a summary of a rocprofv3 database and exit")
+    ap.add_argument("--kernel", default="k_move_all<512, 7>",
+                    help="kernel of --summarize for counter databases ('all': a table of every kernel)")
+    ap.add_argument("--launches", type=int, default=0, help="last dispatches of --kernel to average")
+    ap.add_argument("--serve", action="store_true", help="many-graph serving benchmark instead of the DF line")
+    ap.add_argument("--serve-graphs", type=int, default=4096)
+    ap.add_argument("--serve-slots", type=int, default=4096)
+    ap.add_argument("--serve-load", type=float, default=0.5, help="Poisson rate as a fraction of the burst rate")
+    ap.add_argument("--sweep", type=int, default=0,
+                    help="profiling mode: run this many single full local-moving sweeps (SYNC, all vertices "
+                         "from singletons) of the workload and one 1 GiB device copy for counter "
+                         "calibration, then exit")
+    args = ap.parse_args()
+    if args.summarize:
+        print(summarize(args.summarize, args.kernel, args.launches))
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the single-GPU line is the result",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2404_19634_amd import lib
+
+    if args.serve:
+        serve_bench(args)
+        return
+    args.tuning_kv = {k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(",") if kv)}
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    e = load_workload(args.workload)
+    torch.cuda.synchronize()
+    log(f"{args.workload}: n={e.n} undirected edges={e.m} ({time.perf_counter() - t0:.1f} s)")
+    head, g, batches = df_line(args, lib, args.workload, e, region=ProfilerRegion())
+    if head is None:   # --sweep
+        return
+    out = {"metric": METRIC, "value": head.pop("value"), "unit": "edges scanned/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": head.pop("ms_per_step"),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+           "data": "synthetic", "config": head.pop("config")}
+    out.update(head)
+    if args.workload == "rmat22" and not args.no_approaches:
         log("approaches (ND / DS / DF x SYNC / ASYNC) ...")
-        out["approaches"] = approaches(lib, e, sizes)
+        out["approaches"] = approaches(lib, e, out["config"]["batch_sizes"])
+    del g
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(e, batches[2])
+        out["cpu_baseline"] = cpu_baseline(e, batches[0])
+    del e
+    if not args.no_extras and args.workload != "rmat22":
+        log("rmat22 ...")
+        e2 = load_workload("rmat22")
+        extra, g2, b2 = df_line(args, lib, "rmat22", e2)
+        del g2
+        torch.cuda.empty_cache()
+        if not args.no_approaches:
+            log("approaches (ND / DS / DF x SYNC / ASYNC) ...")
+            extra["approaches"] = approaches(lib, e2, extra["config"]["batch_sizes"])
+        out["rmat22"] = extra
     print(json.dumps(out), flush=True)
 
 
