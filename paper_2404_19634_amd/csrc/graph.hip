@@ -2,6 +2,7 @@
 // the paper's aggregation phase, Alg. 6, reused for in-place batch
 // updates), relayout with more slack, weighted degrees (Section 3), and the
 // per-arc / per-community terms of modularity (Eq. 1).
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -107,106 +108,217 @@ __global__ void k_relayout_copy(const int64_t* __restrict__ s_start, const int32
   }
 }
 
-// Row sums: a group of 16 lanes per row for rows of up to 1024 arcs; longer
-// rows are listed and summed by a whole workgroup each.  With C given, also
-// the total weight of arcs whose endpoints share a community (modularity).
-constexpr int kRowGroup = 16;
-constexpr int kRowGroupMax = 1024;
+// Row sums (K_i, and with C given the weight of arcs inside communities
+// for Eq. 1) in three degree classes, so that no lane idles on a short row
+// and no wavefront walks a long one alone:
+//  - rows of at most kFlatMax arcs: one wavefront per 64 consecutive rows
+//    reads their starts and lengths (coalesced) and walks their arcs as one
+//    flat sequence, 256 consecutive arcs per step (four loads in flight per
+//    lane); an LDS map gives each flat position's row, and LDS atomics add
+//    each arc to its row's sum;
+//  - rows up to kMidMax arcs are listed and summed by one wavefront each;
+//  - longer rows are listed in chunks of kChunk arcs, one wavefront per
+//    chunk, whose partial sums are added atomically (K and Sigma of such a
+//    row are zeroed by the first kernel).
+constexpr int kFlatMax = 64;
+constexpr int kMidMax = 4096;
+constexpr int kChunk = 4096;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kRowUnroll = 4;
 
-__global__ void __launch_bounds__(kBlock) k_rows_group(const int64_t* __restrict__ row_start,
-                                                      const int32_t* __restrict__ row_len,
-                                                      const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
-                                                      int32_t n, const int32_t* __restrict__ C, int64_t* __restrict__ K,
-                                                      int64_t* __restrict__ Sigma, int32_t* __restrict__ Cinit,
-                                                      int32_t* __restrict__ size, int32_t* __restrict__ longlist,
-                                                      int64_t* __restrict__ ctr) {
-  const int lane = lane_id();
-  const int sub = lane % kRowGroup;
-  const int64_t first = (blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x) / kRowGroup;
-  const int64_t ngroups = static_cast<int64_t>(gridDim.x) * blockDim.x / kRowGroup;
-  int64_t intra = 0;
-  for (int64_t i = first; i < n; i += ngroups) {
-    const int32_t len = row_len[i];
-    if (len > kRowGroupMax) {
-      if (sub == 0) {
-        const int64_t pos = static_cast<int64_t>(
-            atomicAdd(reinterpret_cast<unsigned long long*>(&ctr[CTR_AUX1]), 1ull));
-        longlist[pos] = static_cast<int32_t>(i);
-      }
-      continue;
-    }
-    const int64_t s = row_start[i];
-    const int32_t ci = C ? C[i] : 0;
-    int64_t acc = 0, in = 0;
-    // four arcs per lane per step, loads first, so their latencies overlap
-    for (int32_t k0 = sub; k0 < len; k0 += 4 * kRowGroup) {
-      int32_t x[4], c[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) x[q] = k0 + q * kRowGroup < len ? wt[s + k0 + q * kRowGroup] : 0;
-      if (C) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) c[q] = k0 + q * kRowGroup < len ? col[s + k0 + q * kRowGroup] : -1;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) c[q] = c[q] >= 0 ? C[c[q]] : ci - 1;
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        acc += x[q];
-        if (C && c[q] == ci) in += x[q];
-      }
-    }
-#pragma unroll
-    for (int q = 1; q < kRowGroup; q <<= 1) acc += __shfl_xor(acc, q);
-    intra += in;
-    if (sub == 0) {
-      K[i] = acc;
-      if (Sigma) Sigma[i] = acc;
-      if (Cinit) Cinit[i] = static_cast<int32_t>(i);
-      if (size) size[i] = 1;
-    }
-  }
-  intra = wave_sum_i64(intra);
-  if (lane == 0 && C && intra) stat_add(ctr + CTR_STATS0, ST_INTRA, intra);
+struct RowSumOut {
+  int64_t* K;
+  int64_t* Sigma;  // = K (static start), or null
+  int32_t* Cinit;  // identity, or null
+  int32_t* size;   // all ones, or null
+  int32_t* mid;    // rows of the middle class
+  int32_t* lrow;   // chunks of long rows: row, first arc
+  int32_t* loff;
+  int64_t* ctr;    // CTR_AUX0: listed middle rows, CTR_AUX1: listed chunks
+};
+
+__device__ __forceinline__ void wave_barrier_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ void __launch_bounds__(kBlock) k_rows_long(const int64_t* __restrict__ row_start,
+__global__ void __launch_bounds__(kBlock) k_rows_flat(const int64_t* __restrict__ row_start,
                                                      const int32_t* __restrict__ row_len,
                                                      const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
-                                                     const int32_t* __restrict__ C, int64_t* __restrict__ K,
-                                                     int64_t* __restrict__ Sigma, int32_t* __restrict__ Cinit,
-                                                     int32_t* __restrict__ size, const int32_t* __restrict__ longlist,
-                                                     int64_t* __restrict__ ctr) {
-  __shared__ int64_t r[kBlock / kWave];
-  const int64_t count = ctr[CTR_AUX1];
+                                                     int32_t n, const int32_t* __restrict__ C, RowSumOut o) {
+  constexpr int kSpan = kWave * kFlatMax;  // flat positions of a wavefront's short rows, at most
+  __shared__ uint8_t s_own[kWavesPerBlock][kSpan];  // row (lane) of each flat position
+  __shared__ int64_t s_base[kWavesPerBlock][kWave];  // row start minus the row's first flat position
+  __shared__ int32_t s_c[kWavesPerBlock][kWave];
+  __shared__ unsigned long long s_acc[kWavesPerBlock][kWave];
   const int lane = lane_id();
-  const int wid = threadIdx.x / kWave;
+  const int w = threadIdx.x / kWave;
+  uint8_t* own = s_own[w];
+  unsigned long long* acc = s_acc[w];
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
   int64_t intra = 0;
-  for (int64_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
-    const int32_t i = longlist[idx];
-    const int64_t s = row_start[i];
-    const int32_t len = row_len[i];
-    const int32_t ci = C ? C[i] : 0;
-    int64_t acc = 0;
-    for (int32_t k = threadIdx.x; k < len; k += kBlock) {
-      const int32_t x = wt[s + k];
-      acc += x;
-      if (C && C[col[s + k]] == ci) intra += x;
+  for (int64_t r0 = (blockIdx.x * static_cast<int64_t>(kWavesPerBlock) + w) * kWave; r0 < n;
+       r0 += nwaves * kWave) {
+    const int64_t i = r0 + lane;
+    const bool valid = i < n;
+    int32_t len = valid ? row_len[i] : 0;
+    const int64_t st = valid ? row_start[i] : 0;
+    const int32_t ci = (C && valid) ? C[i] : 0;
+    const bool is_mid = len > kFlatMax && len <= kMidMax;
+    const bool is_long = len > kMidMax;
+    const int64_t ms = wave_append(is_mid, &o.ctr[CTR_AUX0]);
+    if (is_mid) o.mid[ms] = static_cast<int32_t>(i);
+    {  // chunks of long rows, reserved together by the wavefront
+      const int32_t nch = is_long ? (len + kChunk - 1) / kChunk : 0;
+      int32_t incl = nch;
+      for (int s = 1; s < kWave; s <<= 1) {
+        const int32_t t = __shfl_up(incl, s);
+        if (lane >= s) incl += t;
+      }
+      const int32_t tot = __shfl(incl, kWave - 1);
+      int64_t base = 0;
+      if (tot > 0) {
+        if (lane == 0)
+          base = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&o.ctr[CTR_AUX1]),
+                                                static_cast<unsigned long long>(tot)));
+        base = __shfl(base, 0);
+      }
+      for (int32_t k = 0; k < nch; ++k) {
+        o.lrow[base + incl - nch + k] = static_cast<int32_t>(i);
+        o.loff[base + incl - nch + k] = k * kChunk;
+      }
     }
-    acc = wave_sum_i64(acc);
-    if (lane == 0) r[wid] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t t = 0;
-      for (int q = 0; q < kBlock / kWave; ++q) t += r[q];
-      K[i] = t;
-      if (Sigma) Sigma[i] = t;
-      if (Cinit) Cinit[i] = i;
-      if (size) size[i] = 1;
+    if (valid) {
+      if (is_long) {
+        o.K[i] = 0;
+        if (o.Sigma) o.Sigma[i] = 0;
+      }
+      if (o.Cinit) o.Cinit[i] = static_cast<int32_t>(i);
+      if (o.size) o.size[i] = 1;
     }
-    __syncthreads();
+    const bool is_short = valid && !is_mid && !is_long;
+    if (!is_short) len = 0;
+    // exclusive prefix of the short rows' lengths over the wavefront; each
+    // lane marks its row's flat positions as its own
+    int32_t incl = len;
+    for (int s = 1; s < kWave; s <<= 1) {
+      const int32_t t = __shfl_up(incl, s);
+      if (lane >= s) incl += t;
+    }
+    const int32_t total = __shfl(incl, kWave - 1);
+    const int32_t first = incl - len;
+    for (int32_t k = 0; k < len; ++k) own[first + k] = static_cast<uint8_t>(lane);
+    s_base[w][lane] = st - first;
+    s_c[w][lane] = ci;
+    acc[lane] = 0;
+    wave_barrier_lds();
+    for (int32_t b = 0; b < total; b += kWave * kRowUnroll) {
+      int32_t r[kRowUnroll];
+      int64_t x[kRowUnroll];
+      int32_t cj[kRowUnroll];
+#pragma unroll
+      for (int q = 0; q < kRowUnroll; ++q) {
+        const int32_t p = b + q * kWave + lane;
+        r[q] = p < total ? own[p] : -1;
+      }
+#pragma unroll
+      for (int q = 0; q < kRowUnroll; ++q) {
+        const int32_t p = b + q * kWave + lane;
+        x[q] = 0;
+        cj[q] = -1;
+        if (r[q] >= 0) {
+          const int64_t a = s_base[w][r[q]] + p;
+          x[q] = wt[a];
+          if (C) cj[q] = col[a];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kRowUnroll; ++q) {
+        if (r[q] < 0) continue;
+        atomicAdd(&acc[r[q]], static_cast<unsigned long long>(x[q]));
+        if (C && C[cj[q]] == s_c[w][r[q]]) intra += x[q];
+      }
+    }
+    wave_barrier_lds();
+    if (is_short) {
+      const int64_t sum = static_cast<int64_t>(acc[lane]);
+      o.K[i] = sum;
+      if (o.Sigma) o.Sigma[i] = sum;
+    }
+    wave_barrier_lds();
   }
   intra = wave_sum_i64(intra);
-  if (lane == 0 && C && intra) stat_add(ctr + CTR_STATS0, ST_INTRA, intra);
+  if (lane == 0 && C && intra) stat_add(o.ctr + CTR_STATS0, ST_INTRA, intra);
+}
+
+// Sum of arcs [a, b) of the row starting at s, over the wavefront, 256 arcs
+// per step; with C, adds the weight of arcs into community ci to *intra.
+__device__ __forceinline__ int64_t wave_row_sum(const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
+                                                const int32_t* __restrict__ C, int64_t s, int32_t a, int32_t b,
+                                                int32_t ci, int64_t* intra) {
+  const int lane = lane_id();
+  int64_t acc = 0;
+  for (int32_t k0 = a + lane; k0 < b; k0 += kWave * kRowUnroll) {
+    int32_t x[kRowUnroll], j[kRowUnroll];
+#pragma unroll
+    for (int q = 0; q < kRowUnroll; ++q) {
+      const int32_t k = k0 + q * kWave;
+      x[q] = k < b ? wt[s + k] : 0;
+      j[q] = (C && k < b) ? col[s + k] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kRowUnroll; ++q) {
+      acc += x[q];
+      if (C && j[q] >= 0 && C[j[q]] == ci) *intra += x[q];
+    }
+  }
+  return wave_sum_i64(acc);
+}
+
+__global__ void __launch_bounds__(kBlock) k_rows_mid(const int64_t* __restrict__ row_start,
+                                                    const int32_t* __restrict__ row_len,
+                                                    const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
+                                                    const int32_t* __restrict__ C, RowSumOut o) {
+  const int64_t count = o.ctr[CTR_AUX0];
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
+  int64_t intra = 0;
+  for (int64_t idx = blockIdx.x * static_cast<int64_t>(kWavesPerBlock) + threadIdx.x / kWave; idx < count;
+       idx += nwaves) {
+    const int32_t i = o.mid[idx];
+    const int32_t ci = C ? C[i] : 0;
+    const int64_t sum = wave_row_sum(col, wt, C, row_start[i], 0, row_len[i], ci, &intra);
+    if (lane_id() == 0) {
+      o.K[i] = sum;
+      if (o.Sigma) o.Sigma[i] = sum;
+    }
+  }
+  intra = wave_sum_i64(intra);
+  if (lane_id() == 0 && C && intra) stat_add(o.ctr + CTR_STATS0, ST_INTRA, intra);
+}
+
+__global__ void __launch_bounds__(kBlock) k_rows_chunks(const int64_t* __restrict__ row_start,
+                                                       const int32_t* __restrict__ row_len,
+                                                       const int32_t* __restrict__ col,
+                                                       const int32_t* __restrict__ wt,
+                                                       const int32_t* __restrict__ C, RowSumOut o) {
+  const int64_t count = o.ctr[CTR_AUX1];
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
+  int64_t intra = 0;
+  for (int64_t idx = blockIdx.x * static_cast<int64_t>(kWavesPerBlock) + threadIdx.x / kWave; idx < count;
+       idx += nwaves) {
+    const int32_t i = o.lrow[idx];
+    const int32_t a = o.loff[idx];
+    const int32_t b = min(row_len[i], a + kChunk);
+    const int32_t ci = C ? C[i] : 0;
+    const int64_t sum = wave_row_sum(col, wt, C, row_start[i], a, b, ci, &intra);
+    if (lane_id() == 0 && sum) {
+      atomic_add_i64(&o.K[i], sum);
+      if (o.Sigma) atomic_add_i64(&o.Sigma[i], sum);
+    }
+  }
+  intra = wave_sum_i64(intra);
+  if (lane_id() == 0 && C && intra) stat_add(o.ctr + CTR_STATS0, ST_INTRA, intra);
 }
 
 __global__ void k_sum_squares(const int64_t* __restrict__ v, int32_t n, int64_t* __restrict__ out) {
@@ -278,17 +390,26 @@ void launch_relayout_copy(const lv_graph& src, const int64_t* dst_start, int32_t
 }
 
 // K[i] = row sum (and Sigma = K, C = identity, size = 1 when given); with
-// C_mod given, ctr[CTR_AUX0] += weight of intra-community arcs.  Uses
-// ctr[CTR_AUX1] and `longlist` (n entries) as scratch.
+// C_mod given, the weight of intra-community arcs is added to statistic
+// ST_INTRA of the first statistics set.  Uses ctr[CTR_AUX0], ctr[CTR_AUX1],
+// one n-entry bin list for the middle rows and the two unit lists (n +
+// cap/2048 + 64 entries each, more than the chunks of cap arcs in rows of
+// over 4096 arcs can take) for the chunks of long rows.
 void launch_row_sums(const LevelGraph& g, const int32_t* C_mod, int64_t* K, int64_t* Sigma, int32_t* Cinit,
-                     int32_t* size, int32_t* longlist, int64_t* ctr, hipStream_t st) {
+                     int32_t* size, Workspace& ws, hipStream_t st) {
   if (g.n == 0) return;
-  (void)hipMemsetAsync(ctr + CTR_AUX1, 0, sizeof(int64_t), st);
-  hipLaunchKernelGGL(k_rows_group, dim3(grid_for(static_cast<int64_t>(g.n) * kRowGroup, kBlock, 8192)),
-                     dim3(kBlock), 0, st, g.row_start, g.row_len, g.col, g.w, g.n, C_mod, K, Sigma, Cinit, size,
-                     longlist, ctr);
-  hipLaunchKernelGGL(k_rows_long, dim3(1024), dim3(kBlock), 0, st, g.row_start, g.row_len, g.col, g.w, C_mod, K,
-                     Sigma, Cinit, size, longlist, ctr);
+  static_assert(CTR_AUX1 == CTR_AUX0 + kCtrLine, "the two list counters are adjacent lines");
+  static_assert(kChunk >= 2048, "the unit lists hold cap / 2048 chunks");
+  (void)hipMemsetAsync(ws.ctr + CTR_AUX0, 0, sizeof(int64_t) * 2 * kCtrLine, st);
+  RowSumOut o{K, Sigma, Cinit, size, ws.bins[BIN_WAVE], ws.u_ins_b, ws.u_emit_b, ws.ctr};
+  const int64_t waves = (static_cast<int64_t>(g.n) + kWave - 1) / kWave;
+  const int64_t blocks = std::min<int64_t>((waves + kWavesPerBlock - 1) / kWavesPerBlock, 65535);
+  hipLaunchKernelGGL(k_rows_flat, dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, st, g.row_start, g.row_len,
+                     g.col, g.w, g.n, C_mod, o);
+  // (grids of many waves, so the memory latencies of the rows overlap; the
+  // waves without a row or chunk return at once)
+  hipLaunchKernelGGL(k_rows_mid, dim3(8192), dim3(kBlock), 0, st, g.row_start, g.row_len, g.col, g.w, C_mod, o);
+  hipLaunchKernelGGL(k_rows_chunks, dim3(8192), dim3(kBlock), 0, st, g.row_start, g.row_len, g.col, g.w, C_mod, o);
 }
 
 void launch_sum_squares(const int64_t* v, int32_t n, int64_t* out, hipStream_t st) {

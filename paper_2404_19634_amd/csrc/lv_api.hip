@@ -173,6 +173,9 @@ int64_t stat(const int64_t* set, int st) {
 lv_status device_error(int64_t code, const char* phase) {
   if (code == LV_EEMPTY) return fail(LV_EEMPTY, "graph has no edges (2m = 0)");
   if (code == LV_EOVERFLOW) return fail(LV_EOVERFLOW, "total arc weight 2m >= 2^31");
+  if (code == LV_EINVAL)
+    return fail(LV_EINVAL, "the batch names a vertex outside [0, n) or a self-loop (not the batch apply_batch "
+                           "took); such updates were skipped and the state is unspecified");
   static thread_local char msg[96];
   std::snprintf(msg, sizeof(msg), "device error in %s", phase);
   return fail(static_cast<lv_status>(code), msg);
@@ -391,7 +394,6 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
   // leaves the state alone and the first readback reports the error.
   LV_HIP(record(ev, 0, st));
   launch_call_begin(ws, g->two_m, st);
-  const int64_t* err = ws.ctr + CTR_ERR;
   LevelGraph L0;
   L0.n = N;
   L0.row_start = g->row_start;
@@ -405,7 +407,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
   if (resume_li > 0) {
     // nothing to mark: pass 0's moves are done
   } else if (ap == A_STATIC) {
-    launch_row_sums(L0, nullptr, state->K, state->Sigma, state->C, size0 ? size0 : ws.size, ws.bins[5], ws.ctr,
+    launch_row_sums(L0, nullptr, state->K, state->Sigma, state->C, size0 ? size0 : ws.size, ws,
                     st);
     launch_set_all_bits(ws.fr_a, N, st);
   } else {
@@ -430,8 +432,8 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
                            static_cast<int64_t>(INT64_MIN), static_cast<int64_t>(t.ssize));
         launch_fill_i32(t.sbestc, 0x7fffffff, t.ssize, st);
         launch_batch_weight_sums(D, I, ws.ctr, st);
-        launch_ds_deletions(D, state->C, ws.range, ws.dE, ws.dC, st);
-        launch_ds_insert_pairs(I, state->C, t.keys, t.vals, t.size, ws.ctr, st);
+        launch_ds_deletions(D, N, state->C, ws.range, ws.dE, ws.dC, ws.ctr, st);
+        launch_ds_insert_pairs(I, N, state->C, t.keys, t.vals, t.size, ws.ctr, st);
         launch_ds_best(t.keys, t.vals, t.size, state->K, state->Sigma, g->two_m, ws.ctr, t.skeys, t.sbest,
                        t.sbestc, t.ssize, 0, st);
         launch_ds_best(t.keys, t.vals, t.size, state->K, state->Sigma, g->two_m, ws.ctr, t.skeys, t.sbest,
@@ -445,11 +447,11 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
       default:
         break;
     }
-    launch_update_weights(D, I, state->C, state->K, state->Sigma, df_frontier, err, st);
+    launch_update_weights(D, I, N, state->C, state->K, state->Sigma, df_frontier, ws.ctr, st);
     if (p->recompute_weights) {
       // without auxiliary information (Section 4.2): K^t from the rows of
       // G^t and Sigma^t from C^{t-1}, replacing the incremental values
-      launch_row_sums(L0, nullptr, state->K, nullptr, nullptr, nullptr, ws.bins[5], ws.ctr, st);
+      launch_row_sums(L0, nullptr, state->K, nullptr, nullptr, nullptr, ws, st);
       launch_sigma_from_members(state->C, state->K, N, state->Sigma, st);
     }
     if (p->swap_guard && !state->size) launch_community_sizes(state->C, N, ws.size, st);
@@ -1106,7 +1108,7 @@ lv_status modularity(const lv_graph* g, const int32_t* C, double* q_host, void* 
   LV_HIP(hipMemsetAsync(ws.ctr, 0, sizeof(int64_t) * CTR_COUNT, st));
   LV_HIP(hipMemsetAsync(ws.i64tmp, 0, sizeof(int64_t) * (static_cast<size_t>(g->n) + 1), st));
   // K_i and the intra-community arc weight (ctr[AUX0]), then Σ_c and Σ_c^2
-  launch_row_sums(L, C, ws.lK, nullptr, nullptr, nullptr, ws.bins[5], ws.ctr, st);
+  launch_row_sums(L, C, ws.lK, nullptr, nullptr, nullptr, ws, st);
   launch_accumulate(C, g->n, nullptr, ws.lK, nullptr, ws.i64tmp, st);
   LV_HIP(hipMemsetAsync(ws.ctr + CTR_AUX1, 0, sizeof(int64_t), st));
   launch_sum_squares(ws.i64tmp, g->n, ws.ctr + CTR_AUX1, st);

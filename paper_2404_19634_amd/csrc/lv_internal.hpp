@@ -287,8 +287,9 @@ void launch_build_scatter(const lv_edges& e, const int64_t* row_start, int32_t* 
                           int32_t* w, int64_t* two_m, hipStream_t st);
 void launch_relayout_copy(const lv_graph& src, const int64_t* dst_start, int32_t* dst_len,
                           int32_t* dst_col, int32_t* dst_w, hipStream_t st);
+struct Workspace;
 void launch_row_sums(const LevelGraph& g, const int32_t* C_mod, int64_t* K, int64_t* Sigma, int32_t* Cinit,
-                     int32_t* size, int32_t* longlist, int64_t* ctr, hipStream_t st);
+                     int32_t* size, Workspace& ws, hipStream_t st);
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 void launch_iota_i32(int32_t* p, int64_t n, hipStream_t st);
 void launch_set_all_bits(uint32_t* bm, int32_t n, hipStream_t st);
@@ -335,14 +336,15 @@ void launch_batch_phase2(const lv_graph& g, const lv_edges& del, const lv_edges&
 
 // mark.hip
 // updateWeights (Alg. 7); with df_frontier given it also marks DF's initial
-// frontier (Alg. 1) in the same pass.  Does nothing if *err is set.
-void launch_update_weights(const lv_edges& del, const lv_edges& ins, const int32_t* C, int64_t* K,
-                           int64_t* Sigma, uint32_t* df_frontier, const int64_t* err, hipStream_t st);
+// frontier (Alg. 1) in the same pass.  Does nothing if ctr[CTR_ERR] is set;
+// flags LV_EINVAL for (and skips) updates outside [0, n) or self-loops.
+void launch_update_weights(const lv_edges& del, const lv_edges& ins, int32_t n, const int32_t* C, int64_t* K,
+                           int64_t* Sigma, uint32_t* df_frontier, int64_t* ctr, hipStream_t st);
 void launch_batch_weight_sums(const lv_edges& del, const lv_edges& ins, int64_t* ctr, hipStream_t st);
 void launch_community_sizes(const int32_t* C, int32_t n, int32_t* size, hipStream_t st);
-void launch_ds_deletions(const lv_edges& del, const int32_t* C, uint32_t* dV, uint32_t* dE,
-                         uint32_t* dC, hipStream_t st);
-void launch_ds_insert_pairs(const lv_edges& ins, const int32_t* C, uint64_t* keys, int64_t* vals,
+void launch_ds_deletions(const lv_edges& del, int32_t n, const int32_t* C, uint32_t* dV, uint32_t* dE,
+                         uint32_t* dC, int64_t* ctr, hipStream_t st);
+void launch_ds_insert_pairs(const lv_edges& ins, int32_t n, const int32_t* C, uint64_t* keys, int64_t* vals,
                             uint32_t size, int64_t* ctr, hipStream_t st);
 void launch_ds_best(const uint64_t* keys, const int64_t* vals, uint32_t size, const int64_t* K,
                     const int64_t* Sigma, const int64_t* two_m_dev, const int64_t* ctr, uint64_t* skeys,

@@ -24,19 +24,27 @@ namespace {
 // batch, and device atomics on one address serialise, so each workgroup
 // first sums its updates' Sigma deltas per community in LDS and then
 // issues one atomic per distinct community.
+// A batch entry names two distinct vertices of the graph.
+__device__ __forceinline__ bool update_ok(int32_t a, int32_t b, int32_t n) {
+  return a >= 0 && b >= 0 && a < n && b < n && a != b;
+}
+
 constexpr int kUwItems = 4;                         // updates per thread
 constexpr int kUwSlots = 2048;                      // LDS table slots
 constexpr int kUwProbes = 16;
 // With `fr` given, the same pass also does DF's initial marking (both read
 // the previous memberships C^{t-1}).  Nothing is done when the call's error
-// slot is already set (2m out of range).
+// slot is already set (2m out of range).  An update naming a vertex outside
+// [0, n) or a self-loop (a batch apply_batch would have refused) is skipped
+// and flags LV_EINVAL, so a mismatched batch is reported, never applied out
+// of bounds.
 __global__ void __launch_bounds__(kBlock) k_update_weights(const int32_t* __restrict__ du, const int32_t* __restrict__ dv,
                                  const int32_t* __restrict__ dw, int64_t nd, const int32_t* __restrict__ iu,
                                  const int32_t* __restrict__ iv, const int32_t* __restrict__ iw, int64_t ni,
-                                 const int32_t* __restrict__ C, int64_t* __restrict__ K,
+                                 int32_t n, const int32_t* __restrict__ C, int64_t* __restrict__ K,
                                  int64_t* __restrict__ Sigma, uint32_t* __restrict__ fr,
-                                 const int64_t* __restrict__ err) {
-  if (*err) return;
+                                 int64_t* __restrict__ ctr) {
+  if (ctr[CTR_ERR]) return;
   __shared__ int32_t tk[kUwSlots];
   __shared__ unsigned long long tv[kUwSlots];
   for (int q = threadIdx.x; q < kUwSlots; q += kBlock) {
@@ -59,6 +67,10 @@ __global__ void __launch_bounds__(kBlock) k_update_weights(const int32_t* __rest
     ea[it] = !ok[it] ? 0 : (del[it] ? du[k] : iu[k - nd]);
     eb[it] = !ok[it] ? 0 : (del[it] ? dv[k] : iv[k - nd]);
     ex[it] = !ok[it] ? 0 : (del[it] ? -static_cast<int64_t>(dw[k]) : static_cast<int64_t>(iw[k - nd]));
+    if (ok[it] && !update_ok(ea[it], eb[it], n)) {
+      set_error(ctr, LV_EINVAL);
+      ok[it] = false;
+    }
   }
 #pragma unroll
   for (int it = 0; it < kUwItems; ++it) {
@@ -116,12 +128,16 @@ __global__ void k_batch_weight_sums(const int32_t* __restrict__ dw, int64_t nd, 
   }
 }
 
-__global__ void k_ds_deletions(const int32_t* __restrict__ du, const int32_t* __restrict__ dv, int64_t nd,
+__global__ void k_ds_deletions(const int32_t* __restrict__ du, const int32_t* __restrict__ dv, int64_t nd, int32_t n,
                                const int32_t* __restrict__ C, uint32_t* __restrict__ dV, uint32_t* __restrict__ dE,
-                               uint32_t* __restrict__ dC) {
+                               uint32_t* __restrict__ dC, int64_t* __restrict__ ctr) {
   for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < nd;
        k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int32_t a = du[k], b = dv[k];
+    if (!update_ok(a, b, n)) {
+      set_error(ctr, LV_EINVAL);
+      continue;
+    }
     if (C[a] != C[b]) continue;
     set_bit(dV, a);
     set_bit(dV, b);
@@ -165,13 +181,18 @@ __device__ __forceinline__ uint32_t table_find(const uint64_t* keys, uint32_t si
 // H[(source, C[target])] += w over cross-community insertion arcs (both
 // directions of every insertion)
 __global__ void k_ds_insert_pairs(const int32_t* __restrict__ iu, const int32_t* __restrict__ iv,
-                                  const int32_t* __restrict__ iw, int64_t ni, const int32_t* __restrict__ C,
-                                  uint64_t* __restrict__ keys, int64_t* __restrict__ vals, uint32_t size) {
+                                  const int32_t* __restrict__ iw, int64_t ni, int32_t n, const int32_t* __restrict__ C,
+                                  uint64_t* __restrict__ keys, int64_t* __restrict__ vals, uint32_t size,
+                                  int64_t* __restrict__ ctr) {
   for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < 2 * ni;
        k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int64_t e = k >> 1;
     const int32_t s = (k & 1) ? iv[e] : iu[e];
     const int32_t t = (k & 1) ? iu[e] : iv[e];
+    if (!update_ok(s, t, n)) {
+      set_error(ctr, LV_EINVAL);
+      continue;
+    }
     const int32_t cs = C[s], ct = C[t];
     if (cs == ct) continue;
     const uint64_t key = (static_cast<uint64_t>(static_cast<uint32_t>(s)) << 32) | static_cast<uint32_t>(ct);
@@ -231,7 +252,7 @@ __global__ void k_ds_community_members(const int32_t* __restrict__ C, int32_t n,
 // neighbours of δE vertices join δV; δE vertices are batch endpoints, so
 // one wavefront per endpoint of every update
 __global__ void k_ds_expand(const int64_t* __restrict__ row_start, const int32_t* __restrict__ row_len,
-                            const int32_t* __restrict__ col, const int32_t* __restrict__ du,
+                            const int32_t* __restrict__ col, int32_t n, const int32_t* __restrict__ du,
                             const int32_t* __restrict__ dv, int64_t nd, const int32_t* __restrict__ iu,
                             const int32_t* __restrict__ iv, int64_t ni, const uint32_t* __restrict__ dE,
                             uint32_t* __restrict__ dV) {
@@ -246,7 +267,7 @@ __global__ void k_ds_expand(const int64_t* __restrict__ row_start, const int32_t
       v = (e & 1) ? dv[k] : du[k];
     else
       v = (e & 1) ? iv[k - nd] : iu[k - nd];
-    if (!test_bit(dE, v)) continue;
+    if (v < 0 || v >= n || !test_bit(dE, v)) continue;  // (ids out of range are flagged by the other kernels)
     const int64_t s = row_start[v];
     const int32_t l = row_len[v];
     for (int32_t t = lane; t < l; t += kWave) set_bit(dV, col[s + t]);
@@ -256,13 +277,13 @@ __global__ void k_ds_expand(const int64_t* __restrict__ row_start, const int32_t
 }  // namespace
 
 
-void launch_update_weights(const lv_edges& del, const lv_edges& ins, const int32_t* C, int64_t* K, int64_t* Sigma,
-                           uint32_t* df_frontier, const int64_t* err, hipStream_t st) {
+void launch_update_weights(const lv_edges& del, const lv_edges& ins, int32_t n, const int32_t* C, int64_t* K,
+                           int64_t* Sigma, uint32_t* df_frontier, int64_t* ctr, hipStream_t st) {
   const int64_t total = del.count + ins.count;
   if (total == 0) return;
   const int blocks = static_cast<int>((total + kBlock * kUwItems - 1) / (kBlock * kUwItems));
   hipLaunchKernelGGL(k_update_weights, dim3(blocks), dim3(kBlock), 0, st, del.u, del.v,
-                     del.w, del.count, ins.u, ins.v, ins.w, ins.count, C, K, Sigma, df_frontier, err);
+                     del.w, del.count, ins.u, ins.v, ins.w, ins.count, n, C, K, Sigma, df_frontier, ctr);
 }
 
 void launch_batch_weight_sums(const lv_edges& del, const lv_edges& ins, int64_t* ctr, hipStream_t st) {
@@ -277,18 +298,18 @@ void launch_community_sizes(const int32_t* C, int32_t n, int32_t* size, hipStrea
   launch_accumulate(C, n, nullptr, nullptr, size, nullptr, st);
 }
 
-void launch_ds_deletions(const lv_edges& del, const int32_t* C, uint32_t* dV, uint32_t* dE, uint32_t* dC,
-                         hipStream_t st) {
+void launch_ds_deletions(const lv_edges& del, int32_t n, const int32_t* C, uint32_t* dV, uint32_t* dE, uint32_t* dC,
+                         int64_t* ctr, hipStream_t st) {
   if (del.count == 0) return;
   hipLaunchKernelGGL(k_ds_deletions, dim3(grid_for(del.count, kBlock, 4096)), dim3(kBlock), 0, st, del.u, del.v,
-                     del.count, C, dV, dE, dC);
+                     del.count, n, C, dV, dE, dC, ctr);
 }
 
-void launch_ds_insert_pairs(const lv_edges& ins, const int32_t* C, uint64_t* keys, int64_t* vals, uint32_t size,
-                            int64_t*, hipStream_t st) {
+void launch_ds_insert_pairs(const lv_edges& ins, int32_t n, const int32_t* C, uint64_t* keys, int64_t* vals,
+                            uint32_t size, int64_t* ctr, hipStream_t st) {
   if (ins.count == 0) return;
   hipLaunchKernelGGL(k_ds_insert_pairs, dim3(grid_for(2 * ins.count, kBlock, 4096)), dim3(kBlock), 0, st, ins.u,
-                     ins.v, ins.w, ins.count, C, keys, vals, size);
+                     ins.v, ins.w, ins.count, n, C, keys, vals, size, ctr);
 }
 
 void launch_ds_best(const uint64_t* keys, const int64_t* vals, uint32_t size, const int64_t* K, const int64_t* Sigma,
@@ -312,7 +333,7 @@ void launch_ds_expand(const LevelGraph& g, const lv_edges& del, const lv_edges& 
   const int64_t total = 2 * (del.count + ins.count);
   if (total == 0) return;
   hipLaunchKernelGGL(k_ds_expand, dim3(grid_for(total * kWave, kBlock, 4096)), dim3(kBlock), 0, st, g.row_start,
-                     g.row_len, g.col, del.u, del.v, del.count, ins.u, ins.v, ins.count, dE, dV);
+                     g.row_len, g.col, g.n, del.u, del.v, del.count, ins.u, ins.v, ins.count, dE, dV);
 }
 
 }  // namespace lv
