@@ -251,6 +251,35 @@ def test_apply_batch_errors_leave_graph_unchanged(lib):
     assert all(np.array_equal(x, y) for x, y in zip(g2.csr_host(), G.csr()))
 
 
+@pytest.mark.parametrize("approach", ["nd", "ds", "df"])
+def test_dynamic_calls_report_batches_outside_the_graph(lib, approach):
+    """A batch that apply_batch would refuse (a vertex id outside [0, n), a
+    self-loop), passed straight to a dynamic call, is reported as
+    LV_EINVAL: the kernels check each update's ids before using them."""
+    e = W.random_small_graph(300, 900, 4)
+    g = lib.Graph.from_edges(e, slack_frac=0.5, slack_min=4)
+    st0, _ = lib.louvain_static(g, mode="sync")
+    z = np.zeros(0, np.int32)
+    one = np.array([1], np.int32)
+    bad = [W.Batch(z, z, z, np.array([5], np.int32), np.array([300], np.int32), one),
+           W.Batch(np.array([-1], np.int32), np.array([7], np.int32), one, z, z, z),
+           W.Batch(z, z, z, np.array([9], np.int32), np.array([9], np.int32), one)]
+    for b in bad:
+        with pytest.raises(lib.LouvainError) as ex:
+            getattr(lib, "louvain_" + approach)(g, lib.Batch.from_host(b), st0.clone(), mode="sync")
+        assert ex.value.code == lib.LV_EINVAL
+    # the graph and a valid call are unaffected
+    b = W.random_batch(e, 20, 5)
+    lib.apply_batch(g, lib.Batch.from_host(b))
+    st, _ = getattr(lib, "louvain_" + approach)(g, lib.Batch.from_host(b), st0.clone(), mode="sync")
+    G = _orc(e)
+    s0 = G.louvain("static", mode="sync")[:3]
+    assert G.apply_batch(b) == 0
+    Co, Ko, So, _ = G.louvain(approach, batch=b, state=s0, mode="sync")
+    C, K, S = st.host()
+    assert np.array_equal(C, Co) and np.array_equal(K, Ko) and np.array_equal(S, So)
+
+
 def test_batch_deleting_and_reinserting_same_pair(lib):
     e = W.random_small_graph(200, 700, 8, max_w=4)
     z = np.zeros(0, np.int32)
