@@ -182,10 +182,11 @@ def summarize(db_path, kernel, launches):
             copies = [v for d, k, c, v in rows if c == cn and "copyBuffer" in k]
             tail = mine[-launches:] if launches else mine
             avg = sum(tail) / len(tail) if tail else float("nan")
-            big = max(copies) if copies else float("nan")
+            # the calibration copy (1 GiB device to device) is the run's last copy
+            big = copies[-1] if copies else float("nan")
             scale = (1 << 20) / big if copies and big > 0 else float("nan")
             out.append(f"{cn}: {kernel} dispatches {len(mine)}, last {len(tail)} average {avg:.1f} KiB")
-            out.append(f"{cn}: largest copy (1 GiB moved) reads {big:.1f} KiB -> scale {scale:.4f}")
+            out.append(f"{cn}: last copy (the 1 GiB calibration copy) reads {big:.1f} KiB -> scale {scale:.4f}")
             out.append(f"{cn}_bytes_per_launch: {avg * scale * 1024:.0f}")
         return "\n".join(out)
     t0 = t1 = None
@@ -415,8 +416,7 @@ def serve_bench(args):
     for gid, (e, _, _) in enumerate(data):
         store.add(gid, e)
     t0 = time.perf_counter()
-    with store.lock:
-        store.acquire(list(range(len(data))))
+    store.acquire(list(range(len(data))))
     store.release(list(range(len(data))))
     torch.cuda.synchronize()
     log(f"resident: {store.resident_bytes / 1e9:.2f} GB after {time.perf_counter() - t0:.1f} s "

@@ -239,8 +239,7 @@ def test_temporal_stream_served(lib, temporal):
     store = serve.GraphStore(1 << 40, max_updates=max(b.size for b in batches), mode="async",
                              **{"slack_frac": 0.1, "slack_min": 8})
     store.add(0, e0)
-    with store.lock:
-        store.acquire([0])
+    store.acquire([0])
     store.release([0])
     srv = serve.Server(store, slots=1, workers=1)
     srv.start()
@@ -272,8 +271,7 @@ def test_temporal_stream_served_with_refresh(lib, temporal):
     store = serve.GraphStore(1 << 40, max_updates=max(b.size for b in batches), mode="async",
                              refresh_every=50, **{"slack_frac": 0.1, "slack_min": 8})
     store.add(0, e0)
-    with store.lock:
-        store.acquire([0])
+    store.acquire([0])
     store.release([0])
     srv = serve.Server(store, slots=1, workers=1)
     srv.start()

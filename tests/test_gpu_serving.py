@@ -130,3 +130,54 @@ def test_quality_refresh_policy(lib):
         Co, Ko, So, _ = oracle.Graph.from_edges(e).louvain("static", mode="sync")
         assert np.array_equal(C, Co) and np.array_equal(K, Ko) and np.array_equal(S, So), gid
         assert np.array_equal(size, np.bincount(C, minlength=e.n)), gid
+
+
+def test_ds_fallback_policy(lib):
+    """ds_drop: after each update a graph's modularity is measured; while it
+    is more than ds_drop below its value after the last static run, the
+    graph's next updates run DS Louvain instead of DF.  In SYNC mode, and
+    across evictions, every request's approach follows that rule applied to
+    the sequential oracle's modularity, every measured Q equals the
+    oracle's, and the final states are bit for bit the oracle's chain of
+    the same approaches."""
+    import oracle
+    from paper_2404_19634_amd import serve
+    graphs, chains = _workload(count=8, chain=4, seed=93)
+    drop = 1e-6
+    store = serve.GraphStore(3 << 20, max_updates=max(b.size for c in chains for b in c), mode="sync",
+                             init_mode="sync", ds_drop=drop)
+    for gid, e in enumerate(graphs):
+        store.add(gid, e)
+    srv = serve.Server(store, slots=2, workers=2)
+    srv.start()
+    try:
+        for t in range(4):
+            for gid in range(len(graphs)):
+                srv.submit(gid, chains[gid][t])
+        srv.wait(4 * len(graphs))
+    finally:
+        srv.close()
+    assert all(r.status == 0 for r in srv.done), [r.status for r in srv.done if r.status]
+    assert store.evictions > 0
+    by_graph = {}
+    for r in sorted(srv.done, key=lambda r: r.rid):
+        by_graph.setdefault(r.gid, []).append(r)
+    used_ds = 0
+    for gid, e in enumerate(graphs):
+        G = oracle.Graph.from_edges(e)
+        C, K, S, _ = G.louvain("static", mode="sync")
+        q_ref = G.modularity(C)
+        q_prev = q_ref
+        for b, r in zip(chains[gid], by_graph[gid]):
+            want = "ds" if q_prev < q_ref - drop else "df"
+            assert r.approach == want, (gid, r.rid, r.approach, q_prev, q_ref)
+            used_ds += r.approach == "ds"
+            assert G.apply_batch(b) == 0
+            C, K, S, _ = G.louvain(r.approach, batch=b, state=(C, K, S), mode="sync")
+            q_prev = G.modularity(C)
+            assert abs(r.modularity - q_prev) <= 1e-12, (gid, r.modularity, q_prev)
+        res = store.acquire([gid])[0]
+        store.release([gid])
+        Cg, Kg, Sg = res.state.host()
+        assert np.array_equal(Cg, C) and np.array_equal(Kg, K) and np.array_equal(Sg, S), gid
+    assert used_ds > 0 and store.ds_updates == used_ds
