@@ -393,7 +393,10 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
   // 0 < 2m < 2^31 on the device; with 2m out of range every later kernel
   // leaves the state alone and the first readback reports the error.
   LV_HIP(record(ev, 0, st));
-  launch_call_begin(ws, g->two_m, st);
+  // fr_a's list is kept for DF's marking (and a resumed pass); the other
+  // approaches fill the bitmask whole
+  const bool dense_start = resume_li == 0 && ap != A_DF;
+  launch_call_begin(ws, g->two_m, dense_start, st);
   LevelGraph L0;
   L0.n = N;
   L0.row_start = g->row_start;
@@ -447,7 +450,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
       default:
         break;
     }
-    launch_update_weights(D, I, N, state->C, state->K, state->Sigma, df_frontier, ws.ctr, st);
+    launch_update_weights(D, I, N, state->C, state->K, state->Sigma, df_frontier, front_list(ws, 0), ws.ctr, st);
     if (p->recompute_weights) {
       // without auxiliary information (Section 4.2): K^t from the rows of
       // G^t and Sigma^t from C^{t-1}, replacing the incremental values
@@ -467,6 +470,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
   int32_t* size = size0;
   uint32_t* cur = ws.fr_a;
   uint32_t* next = ws.fr_b;
+  FrontList cur_fl = front_list(ws, 0), next_fl = front_list(ws, 1);
   double tau = p->tolerance;
   bool aggregated = false;
   bool moved_dirty = false;  // cleared by the first kernel, then by the SYNC apply unless pulled
@@ -500,6 +504,8 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     for (int32_t it = 0; it < p->max_iterations && !(pass == 0 && resume_li > 0); ++it, ++iter_seq) {
       a.cur = cur;
       a.next = next;
+      a.cur_fl = cur_fl;
+      a.next_fl = next_fl;
       // large frontiers pull the next frontier (reads) instead of pushing it
       // (one atomic per arc of every mover)
       const bool pull = est_frontier > L.n / 4;
@@ -533,6 +539,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
       }
       LV_CHECK_LAUNCH();
       std::swap(cur, next);
+      std::swap(cur_fl, next_fl);
       LV_HIP(record(ev, 3, st));
       if ((s = read_counters(host, ws, CTR_ROUND0, st))) return s;
       if (host[CTR_ERR]) return device_error(host[CTR_ERR], "local-moving");
@@ -583,6 +590,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
     LV_CHECK_LAUNCH();
     LV_HIP(hipMemsetAsync(cur, 0, sizeof(uint32_t) * ws.words, st));
     launch_set_all_bits(cur, nc, st);
+    launch_list_invalid(cur_fl, st);
     LV_HIP(record(ev, 5, st));
     LV_HIP(hipMemcpyAsync(&host[CTR_COUNT], out.row_start + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     if ((s = read_counters(host, ws, CTR_STATS0, st))) return s;
@@ -634,6 +642,11 @@ size_t carve_workspace(Workspace& ws, void* base, int32_t n, int64_t cap) {
   ws.dC = take<uint32_t>(cur, total, base, ws.words);
   ws.moved = take<uint32_t>(cur, total, base, ws.words);
   ws.push_flags = take<uint8_t>(cur, total, base, static_cast<size_t>(ws.words) * 32);
+  // frontier lists: regions of n/16 (twice an even share), so a region
+  // overflows only when its writers append far more than their share
+  ws.fl_capr = static_cast<int64_t>(un) / 16 + 64;
+  for (int k = 0; k < 2; ++k)
+    ws.fl[k] = take<int32_t>(cur, total, base, static_cast<size_t>(ws.fl_capr) * kFlRegions);
   for (int b = 0; b < NBINS; ++b) ws.bins[b] = take<int32_t>(cur, total, base, un);
   ws.hub_off = take<int64_t>(cur, total, base, un);
   ws.hub_kid = take<int64_t>(cur, total, base, un);

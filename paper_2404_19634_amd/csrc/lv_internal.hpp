@@ -61,7 +61,25 @@ enum Ctr {
   CTR_B_RESV = 13 * kCtrLine,    // apply_batch: packed (chunks << 32 | partners) reserved
   CTR_STATS0 = 16 * kCtrLine,    // two statistics sets of kStatSet slots
   CTR_ROUND0 = CTR_STATS0 + 2 * kStatSet,  // two sub-round sets of kRoundSet slots
-  CTR_COUNT = CTR_ROUND0 + 2 * kRoundSet
+  CTR_FL0 = CTR_ROUND0 + 2 * kRoundSet,    // two frontier-list count sets of kFlSet slots
+  CTR_COUNT = CTR_FL0 + 2 * (32 * kCtrLine)
+};
+// Frontier lists.  Next to each frontier bitmask the vertices whose bit is
+// set are listed, so that binning reads the frontier rather than every
+// bitmask word.  A list has kFlRegions regions (writers append to the region
+// of their workgroup id modulo kFlRegions, one counter line each, so the
+// appends of many workgroups do not queue on one address).  The list is
+// valid while every region count is at most its capacity; a count above it
+// (an overfull region, or kFlInvalid written by a kernel that sets bits
+// without listing them) makes binning walk the bitmask words instead.
+constexpr int kFlRegions = 32;
+constexpr int kFlSet = kFlRegions * kCtrLine;
+constexpr int64_t kFlInvalid = int64_t(1) << 60;
+static_assert(CTR_COUNT == CTR_FL0 + 2 * kFlSet, "frontier-list counters");
+struct FrontList {
+  int32_t* list;   // kFlRegions regions of capr entries
+  int64_t* cnt;    // region r's count at cnt[r * kCtrLine]
+  int64_t capr;
 };
 // sub-round counters, offsets inside a round set
 enum RoundCtr {
@@ -108,6 +126,8 @@ struct Workspace {
   uint32_t* dC = nullptr;     // DS: community-affected flags
   uint32_t* moved = nullptr;  // vertices moved in this iteration (pull expansion)
   uint8_t* push_flags = nullptr;  // one byte per vertex (32 per frontier word) for the push expansion
+  int32_t* fl[2] = {};        // frontier lists of fr_a and fr_b (kFlRegions regions of fl_capr)
+  int64_t fl_capr = 0;
   int32_t* bins[NBINS] = {};
   int64_t* hub_off = nullptr;  // global-table offset of each hub item
   int64_t* hub_kid = nullptr;  // hub items: weight into the vertex's own community
@@ -241,6 +261,21 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* lds) {
   return t;
 }
 
+// Sets frontier bit i when `pred`; a vertex whose bit was clear is appended
+// to the frontier list (list may be null: bitmask only).  Every active lane
+// of the wavefront calls it together; they share one counter atomic.
+__device__ __forceinline__ void front_mark(uint32_t* bm, const FrontList& F, int32_t i, bool pred) {
+  bool fresh = false;
+  if (pred) {
+    const uint32_t bit = 1u << (i & 31);
+    fresh = !(atomicOr(&bm[i >> 5], bit) & bit);
+  }
+  if (!F.list) return;
+  const int r = static_cast<int>(blockIdx.x % kFlRegions);
+  const int64_t pos = wave_append(fresh, &F.cnt[r * kCtrLine]);
+  if (fresh && pos < F.capr) F.list[r * F.capr + pos] = i;
+}
+
 // Hash of a community id into [0, size) for the open-addressing tables.
 __device__ __forceinline__ uint32_t hash_slot(uint32_t key, uint32_t size) {
   const uint32_t h = key * 0x9E3779B1u;
@@ -339,7 +374,8 @@ void launch_batch_phase2(const lv_graph& g, const lv_edges& del, const lv_edges&
 // frontier (Alg. 1) in the same pass.  Does nothing if ctr[CTR_ERR] is set;
 // flags LV_EINVAL for (and skips) updates outside [0, n) or self-loops.
 void launch_update_weights(const lv_edges& del, const lv_edges& ins, int32_t n, const int32_t* C, int64_t* K,
-                           int64_t* Sigma, uint32_t* df_frontier, int64_t* ctr, hipStream_t st);
+                           int64_t* Sigma, uint32_t* df_frontier, const FrontList& df_list, int64_t* ctr,
+                           hipStream_t st);
 void launch_batch_weight_sums(const lv_edges& del, const lv_edges& ins, int64_t* ctr, hipStream_t st);
 void launch_community_sizes(const int32_t* C, int32_t n, int32_t* size, hipStream_t st);
 void launch_ds_deletions(const lv_edges& del, int32_t n, const int32_t* C, uint32_t* dV, uint32_t* dE,
@@ -403,6 +439,9 @@ struct MoveArgs {
   int32_t* size;
   const uint32_t* cur;
   uint32_t* next;
+  FrontList cur_fl;       // the list of cur (read by binning)
+  FrontList next_fl;      // the list of next (appended to by the pushes; its counts are zeroed by the
+                          // first round's binning)
   const uint32_t* range;  // nullptr: every vertex in range
   uint32_t* ever;         // nullptr: not tracked
   uint32_t* moved;        // movers bitmask (SYNC always; ASYNC when pulling)
@@ -450,7 +489,12 @@ void launch_apply_moves(const MoveArgs& a, Workspace& ws, bool clear_moved, hipS
 void launch_pull_expand(const MoveArgs& a, Workspace& ws, hipStream_t st);
 // First kernel of a louvain call: zeroes the counters and the frontier
 // bitmasks, copies 2m into CTR_TWO_M and flags LV_EEMPTY / LV_EOVERFLOW.
-void launch_call_begin(Workspace& ws, const int64_t* two_m, hipStream_t st);
+// The frontier lists start empty and valid, or with `dense_a` the list of
+// fr_a starts invalid (its bitmask is about to be filled without listing).
+void launch_call_begin(Workspace& ws, const int64_t* two_m, bool dense_a, hipStream_t st);
+FrontList front_list(const Workspace& ws, int k);
+// Marks a frontier list invalid (its bitmask was filled without listing).
+void launch_list_invalid(const FrontList& f, hipStream_t st);
 
 // aggregate.hip
 void launch_mark_exists(const int32_t* C, int32_t n, int32_t* flags, hipStream_t st);

@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(kBlock) k_update_weights(const int32_t* __rest
                                  const int32_t* __restrict__ dw, int64_t nd, const int32_t* __restrict__ iu,
                                  const int32_t* __restrict__ iv, const int32_t* __restrict__ iw, int64_t ni,
                                  int32_t n, const int32_t* __restrict__ C, int64_t* __restrict__ K,
-                                 int64_t* __restrict__ Sigma, uint32_t* __restrict__ fr,
+                                 int64_t* __restrict__ Sigma, uint32_t* __restrict__ fr, FrontList fl,
                                  int64_t* __restrict__ ctr) {
   if (ctr[CTR_ERR]) return;
   __shared__ int32_t tk[kUwSlots];
@@ -77,6 +77,14 @@ __global__ void __launch_bounds__(kBlock) k_update_weights(const int32_t* __rest
     ca[it] = ok[it] ? C[ea[it]] : 0;
     cb[it] = ok[it] ? C[eb[it]] : 0;
   }
+  if (fr) {  // deletion inside a community, or insertion across (every lane takes part in the appends)
+#pragma unroll
+    for (int it = 0; it < kUwItems; ++it) {
+      const bool hit = ok[it] && (ca[it] == cb[it]) == del[it];
+      front_mark(fr, fl, ea[it], hit);
+      front_mark(fr, fl, eb[it], hit);
+    }
+  }
 #pragma unroll
   for (int it = 0; it < kUwItems; ++it) {
     if (!ok[it]) continue;
@@ -84,10 +92,6 @@ __global__ void __launch_bounds__(kBlock) k_update_weights(const int32_t* __rest
     const int64_t x = ex[it];
     atomic_add_i64(&K[a], x);
     atomic_add_i64(&K[b], x);
-    if (fr && (ca[it] == cb[it]) == del[it]) {  // deletion inside a community, or insertion across
-      set_bit(fr, a);
-      set_bit(fr, b);
-    }
     for (int side = 0; side < 2; ++side) {
       const int32_t c = side ? cb[it] : ca[it];
       uint32_t h = hash_slot(static_cast<uint32_t>(c), kUwSlots);
@@ -278,12 +282,13 @@ __global__ void k_ds_expand(const int64_t* __restrict__ row_start, const int32_t
 
 
 void launch_update_weights(const lv_edges& del, const lv_edges& ins, int32_t n, const int32_t* C, int64_t* K,
-                           int64_t* Sigma, uint32_t* df_frontier, int64_t* ctr, hipStream_t st) {
+                           int64_t* Sigma, uint32_t* df_frontier, const FrontList& df_list, int64_t* ctr,
+                           hipStream_t st) {
   const int64_t total = del.count + ins.count;
   if (total == 0) return;
   const int blocks = static_cast<int>((total + kBlock * kUwItems - 1) / (kBlock * kUwItems));
   hipLaunchKernelGGL(k_update_weights, dim3(blocks), dim3(kBlock), 0, st, del.u, del.v,
-                     del.w, del.count, ins.u, ins.v, ins.w, ins.count, n, C, K, Sigma, df_frontier, ctr);
+                     del.w, del.count, ins.u, ins.v, ins.w, ins.count, n, C, K, Sigma, df_frontier, df_list, ctr);
 }
 
 void launch_batch_weight_sums(const lv_edges& del, const lv_edges& ins, int64_t* ctr, hipStream_t st) {

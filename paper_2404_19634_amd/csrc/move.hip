@@ -57,6 +57,7 @@ struct Dev {
   int64_t* Sigma;
   int32_t* size;
   uint32_t* next;
+  FrontList nl;  // the list of next
   uint32_t* moved;
   int32_t* mv_c;
   int32_t push;
@@ -80,6 +81,7 @@ Dev make_dev(const MoveArgs& a, Workspace& ws, const lv_tuning& tu) {
   d.Sigma = a.Sigma;
   d.size = a.size;
   d.next = a.next;
+  d.nl = a.next_fl;
   d.moved = a.moved;
   d.mv_c = ws.mv_c;
   d.push = a.push;
@@ -319,7 +321,7 @@ __device__ __forceinline__ void hub_setup(const HubOut& H, int64_t pos, int32_t 
 // --------------------------------------------------------------------------
 __global__ void k_call_begin(int64_t* __restrict__ ctr, uint32_t* __restrict__ fr_a, uint32_t* __restrict__ fr_b,
                              uint32_t* __restrict__ ever, uint32_t* __restrict__ moved, int64_t words,
-                             const int64_t* __restrict__ two_m) {
+                             const int64_t* __restrict__ two_m, int32_t dense_a) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   const int64_t t0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   for (int64_t k = t0; k < words; k += stride) {
@@ -331,6 +333,7 @@ __global__ void k_call_begin(int64_t* __restrict__ ctr, uint32_t* __restrict__ f
   for (int64_t k = t0; k < CTR_COUNT; k += stride) {
     int64_t v = 0;
     if (k == CTR_TWO_M) v = *two_m;
+    if (k == CTR_FL0 && dense_a) v = kFlInvalid;
     if (k == CTR_ERR) {
       const int64_t t = *two_m;
       v = t <= 0 ? LV_EEMPTY : (t >= kTwoMLimit ? LV_EOVERFLOW : 0);
@@ -350,7 +353,8 @@ constexpr int kBinHubs = 64;              // hubs a workgroup reserves together 
 // set); on the last round of an iteration each word of the frontier is
 // cleared once read.
 // --------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_bin_frontier(uint32_t* __restrict__ cur,
+__global__ void __launch_bounds__(kBlock) k_bin_frontier(uint32_t* __restrict__ cur, FrontList cl,
+                                                        int64_t* __restrict__ next_cnt,
                                                         const uint32_t* __restrict__ range,
                                                         uint32_t* __restrict__ ever,
                                                         const int32_t* __restrict__ row_len, int32_t n,
@@ -367,28 +371,64 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(uint32_t* __restrict__ 
   __shared__ int64_t s_hpos[kBinHubs];
   __shared__ int32_t s_hdeg[kBinHubs];
   __shared__ int64_t s_hbase[3];
+  __shared__ int64_t s_rbase[kFlRegions + 1];  // list mode: first entry of each region
+  __shared__ int32_t s_list;
+  const int64_t words = (static_cast<int64_t>(n) + 31) / 32;
   if (threadIdx.x < kBinStats) s_stat[threadIdx.x] = 0;
-  if (blockIdx.x == 0)
+  if (threadIdx.x < kWave) {  // the frontier list serves when valid and shorter than the bitmask
+    const int lane = threadIdx.x;
+    const int64_t c = (cl.list && lane < kFlRegions) ? cl.cnt[lane * kCtrLine] : 0;
+    const bool ok = cl.list != nullptr && !__any(c > cl.capr);
+    int64_t incl = c;
+    for (int d = 1; d < kFlRegions; d <<= 1) {
+      const int64_t u = __shfl_up(incl, d);
+      if (lane >= d) incl += u;
+    }
+    if (lane < kFlRegions) s_rbase[lane] = ok ? incl - c : 0;
+    if (lane == kFlRegions - 1) {
+      s_rbase[kFlRegions] = ok ? incl : 0;
+      s_list = ok && incl <= words;
+    }
+  }
+  if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < kRoundSet; k += blockDim.x) rc_next[k] = 0;
+    if (next_cnt)  // the next frontier's list starts empty (first round of an iteration)
+      for (int r = threadIdx.x; r < kFlRegions; r += blockDim.x) next_cnt[r * kCtrLine] = 0;
+  }
   if (sc_next)
     for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < kStatSet;
          k += static_cast<int64_t>(gridDim.x) * blockDim.x)
       sc_next[k] = 0;
-  const int64_t words = (static_cast<int64_t>(n) + 31) / 32;
+  __syncthreads();
+  const bool lm = s_list != 0;
+  const int64_t items = lm ? s_rbase[kFlRegions] : words;
   int64_t arcs = 0, processed = 0, affected = 0;
   int64_t bin_verts[NBINS], bin_arcs[NBINS];
 #pragma unroll
   for (int q = 0; q < NBINS; ++q) bin_verts[q] = bin_arcs[q] = 0;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t w0 = blockIdx.x * static_cast<int64_t>(blockDim.x); w0 < words; w0 += stride) {
+  for (int64_t w0 = blockIdx.x * static_cast<int64_t>(blockDim.x); w0 < items; w0 += stride) {
     if (threadIdx.x < NBINS) s_cnt[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_nh = 0;
     __syncthreads();
-    const int64_t k = w0 + threadIdx.x;
+    const int64_t e = w0 + threadIdx.x;
+    int64_t k = 0;   // the word of this thread's vertices
     uint32_t bits = 0;
-    if (k < words) {
-      bits = cur[k];
-      if (clear_cur && bits) cur[k] = 0;
+    if (e < items) {
+      if (lm) {  // one listed vertex
+        int r = 0;
+#pragma unroll
+        for (int h = kFlRegions / 2; h > 0; h >>= 1)
+          if (s_rbase[r + h] <= e) r += h;
+        const int32_t i = cl.list[r * cl.capr + (e - s_rbase[r])];
+        k = i >> 5;
+        bits = 1u << (i & 31);
+        if (clear_cur) cur[k] = 0;  // (every set bit of the word is listed)
+      } else {   // one bitmask word
+        k = e;
+        bits = cur[k];
+        if (clear_cur && bits) cur[k] = 0;
+      }
       if (range) bits &= range[k];
       if (round_shift < 32 && bits) bits &= round_mask(static_cast<uint32_t>(k), round, round_shift);
       if (bits) bits &= range_mask(k, id_lo, id_hi);
@@ -402,9 +442,14 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(uint32_t* __restrict__ 
         bits = keep;
       }
       if (ever && bits) {
-        const uint32_t old = ever[k];
-        affected += __popc(bits & ~old);
-        ever[k] = old | bits;
+        if (lm) {  // other listed vertices may share the word
+          const uint32_t old = atomicOr(&ever[k], bits);
+          affected += __popc(bits & ~old);
+        } else {
+          const uint32_t old = ever[k];
+          affected += __popc(bits & ~old);
+          ever[k] = old | bits;
+        }
       }
     }
     int32_t cnt[NBINS];
@@ -485,6 +530,8 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(uint32_t* __restrict__ 
     __syncthreads();
   }
   // statistics: wavefront sums, then workgroup sums, then one atomic each
+  // (skipped by workgroups that met no vertex)
+  if (__syncthreads_or(processed != 0 || affected != 0) == 0) return;
   {
     int64_t v[kBinStats];
     v[0] = processed;
@@ -601,7 +648,7 @@ __device__ __forceinline__ void role_small(const Dev& D, int64_t two_m, const in
       moved += 1;
       marcs += deg;
     }
-    if (mv && has && D.push) set_bit(D.next, j);
+    front_mark(D.next, D.nl, j, mv && has && D.push);
   }
   flush_totals(D, gain_acc, moved, marcs);
 }
@@ -652,16 +699,15 @@ __device__ __forceinline__ void role_lane4(const Dev& D, int64_t two_m, const in
         bc = c[q];
       }
     }
-    if (decide_move(D, d, bc, bg)) {
+    const bool mv = decide_move(D, d, bc, bg);
+    if (mv) {
       commit_move(D, agg, i, d, bc, Ki);
       gain_acc += bg;
       moved += 1;
       marcs += deg;
-      if (D.push)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (j[q] >= 0) set_bit(D.next, j[q]);
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) front_mark(D.next, D.nl, j[q], mv && D.push && j[q] >= 0);
   }
   flush_totals(D, gain_acc, moved, marcs);
 }
@@ -791,7 +837,7 @@ __device__ __forceinline__ void role_wave(const Dev& D, int64_t two_m, const int
       if (D.push)
         for (int32_t b = lane; b < deg; b += kWave) {
           const int32_t j = D.col[start + b];
-          if (j != i) set_bit(D.next, j);
+          front_mark(D.next, D.nl, j, j != i);
         }
     }
     // the next row's table clear must not overtake this row's reads
@@ -980,7 +1026,7 @@ __device__ __forceinline__ void role_block(const Dev& D, int64_t two_m, const in
       if (D.push)
         for (int32_t k = threadIdx.x; k < deg; k += kBlock) {
           const int32_t j = D.col[start + k];
-          if (j != i) set_bit(D.next, j);
+          front_mark(D.next, D.nl, j, j != i);
         }
     }
     __syncthreads();
@@ -1461,7 +1507,7 @@ __global__ void __launch_bounds__(kBlock) k_hub_expand(Dev D, const int32_t* __r
     const int64_t a1 = min(static_cast<int64_t>(D.row_len[i]), u_a[u] + kHubUnitArcs);
     for (int64_t a = u_a[u] + threadIdx.x; a < a1; a += kBlock) {
       const int32_t j = D.col[start + a];
-      if (j != i) set_bit(D.next, j);
+      front_mark(D.next, D.nl, j, j != i);
     }
   }
 }
@@ -1526,7 +1572,10 @@ __global__ void __launch_bounds__(kBlock) k_pull_words(const int64_t* __restrict
                                                       const int32_t* __restrict__ col, int32_t n,
                                                       const uint32_t* __restrict__ moved, uint32_t* __restrict__ next,
                                                       int32_t* __restrict__ longlist, int64_t* __restrict__ ctr,
-                                                      const int64_t* __restrict__ sc) {
+                                                      const int64_t* __restrict__ sc, int64_t* __restrict__ next_cnt) {
+  // either way (pull here, or the push kernels) the next frontier is built
+  // without its list
+  if (blockIdx.x == 0 && threadIdx.x == 0) *next_cnt = kFlInvalid;
   if (expand_by_push(sc)) return;
   const int lane = lane_id();
   const int grp = lane / kPullGroup;
@@ -1733,9 +1782,20 @@ void launch_one_role(int role, const Dev& D, const Bins& b, const HubIn& H, int6
 
 }  // namespace
 
-void launch_call_begin(Workspace& ws, const int64_t* two_m, hipStream_t st) {
+void launch_call_begin(Workspace& ws, const int64_t* two_m, bool dense_a, hipStream_t st) {
   hipLaunchKernelGGL(k_call_begin, dim3(grid_for(std::max<int64_t>(ws.words, CTR_COUNT), kBlock, 2048)),
-                     dim3(kBlock), 0, st, ws.ctr, ws.fr_a, ws.fr_b, ws.ever, ws.moved, ws.words, two_m);
+                     dim3(kBlock), 0, st, ws.ctr, ws.fr_a, ws.fr_b, ws.ever, ws.moved, ws.words, two_m,
+                     dense_a ? 1 : 0);
+}
+
+FrontList front_list(const Workspace& ws, int k) {
+  return FrontList{ws.fl[k], ws.ctr + CTR_FL0 + k * kFlSet, ws.fl_capr};
+}
+
+__global__ void k_list_invalid(int64_t* cnt) { *cnt = kFlInvalid; }
+
+void launch_list_invalid(const FrontList& f, hipStream_t st) {
+  hipLaunchKernelGGL(k_list_invalid, dim3(1), dim3(1), 0, st, f.cnt);
 }
 
 // Bins whose degree range meets [lo, hi].
@@ -1756,8 +1816,12 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
   for (int k = 0; k < NBINS; ++k) b.list[k] = ws.bins[k];
   HubOut HO{ws.hub_off, ws.hub_cbase, ws.hub_cnum, ws.u_ins_b, ws.u_ins_a, ws.u_emit_b, ws.u_emit_s};
   const TimerPair tb = timer_pair(LV_TIME_BINNING);
-  hipExtLaunchKernelGGL(k_bin_frontier, dim3(grid_for(words, kBlock, 4096)), dim3(kBlock), 0, st, tb.start, tb.stop,
-                        0, const_cast<uint32_t*>(a.cur), a.range, a.ever, a.g.row_len, a.g.n, a.wave_max,
+  // (a listed frontier has at most a.est vertices; a bitmask walk is a
+  // grid-stride loop, so a smaller grid only slows it)
+  const int64_t bin_items = std::max<int64_t>(1, std::min<int64_t>(words, a.est));
+  hipExtLaunchKernelGGL(k_bin_frontier, dim3(grid_for(bin_items, kBlock, 4096)), dim3(kBlock), 0, st, tb.start,
+                        tb.stop, 0, const_cast<uint32_t*>(a.cur), a.cur_fl, a.sc_next ? a.next_fl.cnt : nullptr,
+                        a.range, a.ever, a.g.row_len, a.g.n, a.wave_max,
                         r.hash_round, r.hash_shift, r.id_lo, r.id_hi, r.deg_lo, r.deg_hi, a.clear_cur, b, HO, a.rc,
                         a.sc, a.rc_next, a.sc_next);
 
@@ -1837,7 +1901,8 @@ void launch_pull_expand(const MoveArgs& a, Workspace& ws, hipStream_t st) {
   const int64_t words = (static_cast<int64_t>(a.g.n) + 31) / 32;
   (void)hipMemsetAsync(ws.ctr + CTR_AUX1, 0, sizeof(int64_t), st);
   hipLaunchKernelGGL(k_pull_words, dim3(grid_for(words * kWave, kBlock, 8192)), dim3(kBlock), 0, st, a.g.row_start,
-                     a.g.row_len, a.g.col, a.g.n, a.moved, a.next, ws.bins[NBINS - 1] + 0, ws.ctr, a.sc);
+                     a.g.row_len, a.g.col, a.g.n, a.moved, a.next, ws.bins[NBINS - 1] + 0, ws.ctr, a.sc,
+                     a.next_fl.cnt);
   hipLaunchKernelGGL(k_pull_long, dim3(1024), dim3(kBlock), 0, st, a.g.row_start, a.g.row_len, a.g.col, a.moved,
                      a.next, ws.bins[NBINS - 1] + 0, ws.ctr, a.sc);
   // (only one of the pair above and the three below does any work)
