@@ -260,6 +260,35 @@ def cpu_baseline(e, batch, budget_s=60.0):
     return res
 
 
+def cpu_multicore(e, batches, count=4):
+    """The multi-core CPU implementation (baseline_cpu: the paper's OpenMP
+    design, all host threads) on the same workload: static Louvain in ASYNC
+    mode, then DF Louvain on the first `count` batches of the sequence
+    (apply_batch untimed, as the paper times the algorithm only)."""
+    import baseline_cpu
+    t0 = time.perf_counter()
+    P = baseline_cpu.Graph(e)
+    build_s = time.perf_counter() - t0
+    C, K, S, st = P.louvain("static", mode="async")
+    q = P.modularity(C)
+    lat, arcs = [], []
+    state = (C, K, S)
+    for b in batches[:count]:
+        assert P.apply_batch(b) == 0
+        C, K, S, sd = P.louvain("df", batch=b, state=state, mode="async")
+        state = (C, K, S)
+        lat.append(sd["seconds"] * 1e3)
+        arcs.append(sd["arcs_scanned"])
+    del P
+    return {"kind": "multicore (OpenMP, the paper's parallel design)", "threads": st["threads"],
+            "graph_build_s": build_s, "static_latency_ms": st["seconds"] * 1e3,
+            "static_edges_scanned_per_s": st["arcs_scanned"] / st["seconds"], "static_modularity": q,
+            "static_passes": st["passes"], "static_iterations": st["iterations"],
+            "df_latency_ms": lat, "df_batch_sizes": [b.size for b in batches[:count]],
+            "df_latency_ms_p50": pct(lat, 50), "df_edges_scanned_per_s": float(np.sum(arcs)) / (np.sum(lat) * 1e-3),
+            **host_cpu()}
+
+
 def sweep(g, e, runs):
     """One SYNC local-moving iteration over every vertex from singletons,
     `runs` times (the kernels a full sweep launches, for rocprofv3), then a
@@ -731,6 +760,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(e, batches[0])
+        log("cpu baseline (multi-core) ...")
+        out["cpu_baseline"]["multicore"] = cpu_multicore(e, batches)
     del e
     if not args.no_extras and args.workload != "rmat22":
         log("rmat22 ...")
