@@ -411,13 +411,18 @@ def approaches(lib, e, sizes, reps=2, seed=777):
 
 
 def _gen_graph(spec):
+    """One graph of the many-graph workload and three consecutive 1e-3|E|
+    batches: the tuning pass, the burst and the Poisson phase."""
     from paper_2404_19634_amd import workloads as W
     n, b, seed = spec
     e = W.multi_sbm_graph(int(n), int(b), int(seed))
-    b1 = W.random_batch(e, W.batch_size(1e-3, e.m), int(seed) % (1 << 30))
-    e1 = W.apply_batch_np(e, b1)
-    b2 = W.random_batch(e1, W.batch_size(1e-3, e1.m), (int(seed) + 1) % (1 << 30))
-    return e, b1, b2
+    out = [e]
+    cur = e
+    for k in range(3):
+        bk = W.random_batch(cur, W.batch_size(1e-3, cur.m), (int(seed) + k) % (1 << 30))
+        out.append(bk)
+        cur = W.apply_batch_np(cur, bk)
+    return tuple(out)
 
 
 def serve_bench(args):
@@ -436,25 +441,32 @@ def serve_bench(args):
     t0 = time.perf_counter()
     with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
         data = pool.map(_gen_graph, specs, chunksize=4)
-    sum_n = sum(e.n for e, _, _ in data)
-    sum_m = sum(e.m for e, _, _ in data)
+    sum_n = sum(d[0].n for d in data)
+    sum_m = sum(d[0].m for d in data)
     log(f"{len(data)} graphs, {sum_n} vertices, {sum_m} edges generated in {time.perf_counter() - t0:.1f} s")
-    cap = max(max(b1.size, b2.size) for _, b1, b2 in data)
+    cap = max(max(b.size for b in d[1:]) for d in data)
     free, _ = torch.cuda.mem_get_info()
     store = serve.GraphStore(int(free * 0.8), max_updates=cap, mode=args.mode)
-    for gid, (e, _, _) in enumerate(data):
-        store.add(gid, e)
+    for gid, d in enumerate(data):
+        store.add(gid, d[0])
     t0 = time.perf_counter()
     store.acquire(list(range(len(data))))
     store.release(list(range(len(data))))
     torch.cuda.synchronize()
     log(f"resident: {store.resident_bytes / 1e9:.2f} GB after {time.perf_counter() - t0:.1f} s "
         f"(build + static Louvain per graph)")
+    # tuning pass: every graph's first batch in one lv_autotune_many call,
+    # whose items are dealt to the candidate mappings of the batched launch
+    t0 = time.perf_counter()
+    gids = list(range(len(data)))
+    tuned = store.tune(gids, [d[1] for d in data])
+    tune_s = time.perf_counter() - t0
+    log(f"tuning pass: {len(data)} updates in {tune_s * 1e3:.1f} ms, class {tuned['size_class']}: {tuned['tuning']}")
     srv = serve.Server(store, slots=args.serve_slots, workers=2)
     srv.start()
     t0 = time.perf_counter()
-    for gid, (_, b1, _) in enumerate(data):
-        srv.submit(gid, b1, t_arrival=t0)
+    for gid, d in enumerate(data):
+        srv.submit(gid, d[2], t_arrival=t0)
     srv.wait(len(data))
     burst_s = time.perf_counter() - t0
     burst = srv.summary()
@@ -474,7 +486,7 @@ def serve_bench(args):
     while k < len(order):
         now = time.perf_counter()
         while k < len(order) and due[k] <= now:
-            srv.submit(int(order[k]), data[int(order[k])][2], t_arrival=float(due[k]))
+            srv.submit(int(order[k]), data[int(order[k])][3], t_arrival=float(due[k]))
             k += 1
         time.sleep(2e-4)
     srv.wait(len(data))
@@ -485,6 +497,7 @@ def serve_bench(args):
            "config": {"workload": f"{len(data)} SBM graphs (n log-uniform 1e3..2e5, blocks log-uniform 20..2000, "
                                   f"degree 12/3), 1e-3|E| 80/20 batches", "graphs": len(data),
                       "vertices": sum_n, "undirected_edges": sum_m, "mode": args.mode, "slots": args.serve_slots},
+           "tuning": {"ms": tune_s * 1e3, **tuned},
            "burst": {"graphs_per_s": sat, "ms": burst_s * 1e3, **burst},
            "poisson": {"offered_rate_per_s": rate, "load": args.serve_load, **poisson},
            "resident_gb": store.resident_bytes / 1e9}

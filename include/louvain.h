@@ -327,6 +327,43 @@ size_t lv_many_desc_bytes(int32_t count);
 lv_status louvain_df_many(const lv_item* items, int32_t count, const lv_params* p, void* desc, size_t desc_bytes,
                           void* ws, size_t ws_bytes, int32_t* status, lv_stats* stats, void* stream);
 
+/*
+ * Tuning of the batched launch, one entry per size class of graphs: a call
+ * of louvain_df_many falls in class k when its graphs average at most
+ * 2^(k+9) vertices (k = 0 .. LV_MANY_CLASSES-1; the last class takes all
+ * larger ones).  The entry sets the mapping of the persistent kernel: rows
+ * up to wave_max_degree arcs are scanned by one wavefront each with an LDS
+ * table of twice that many slots, longer rows (up to 2048 arcs) by the
+ * whole workgroup; grid is the number of workgroups the launch holds (one
+ * graph at a time each).  Process-wide; lv_get/lv_set_many_tuning read and
+ * restore the table (so a caller can persist it), lv_many_size_class names
+ * the class of a set of items.
+ */
+#define LV_MANY_CLASSES 12
+typedef struct {
+  int32_t wave_max_degree; /* 1 .. 256 (default 256) */
+  int32_t grid;            /* most workgroups of a launch, 1 .. 65535 (default 65535: one per graph) */
+} lv_many_tuning;
+void lv_get_many_tuning(int32_t size_class, lv_many_tuning* t);
+void lv_set_many_tuning(int32_t size_class, const lv_many_tuning* t);
+int32_t lv_many_size_class(const lv_item* items, int32_t count);
+
+/*
+ * lv_autotune_many -- louvain_df_many on `items` (same arguments, same
+ * results and statistics per item) that also tunes the batched launch for
+ * their size class.  The items, ordered by size, are dealt round-robin to
+ * the candidate mappings (wave_max_degree 32, 64, 128, 256; the class's
+ * grid), so each candidate gets a like mix of small and large graphs; each
+ * runs its share in one launch timed with HIP events, and the one with the
+ * least time per item becomes the class's entry (and *best when non-null).
+ * Needs at least one item per candidate to time them all (fewer items: the
+ * untimed candidates are skipped).  SYNC results do not depend on the
+ * tuning.  Not to be called while other batched calls run.
+ */
+lv_status lv_autotune_many(const lv_item* items, int32_t count, const lv_params* p, void* desc, size_t desc_bytes,
+                           void* ws, size_t ws_bytes, int32_t* status, lv_stats* stats, lv_many_tuning* best,
+                           void* stream);
+
 /* Measurement hook.  lv_set_timing(mask) makes every later louvain_* call
  * time each launch of the kernels whose bit k is set in `mask` (k =
  * LV_TIME_*) with a pair of HIP events that the launch itself stamps with

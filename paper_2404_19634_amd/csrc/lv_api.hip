@@ -704,6 +704,7 @@ struct ManyGraph {
   void* desc = nullptr;
   int32_t bucket = 0;
   lv_params p{};
+  lv_many_tuning t{};
   char* host = nullptr;  // the thread's pinned staging buffer
   hipGraphExec_t exec = nullptr;
 };
@@ -731,7 +732,19 @@ bool same_params(const lv_params& a, const lv_params& b) {
          a.swap_guard == b.swap_guard;
 }
 
-lv_status many_graph(void* desc, size_t desc_bytes, int32_t count, const lv_params& p, ManyGraph** out) {
+// Batched-launch tuning per size class (lv_many_tuning).
+lv_many_tuning g_many_tuning[LV_MANY_CLASSES] = {
+    {256, 65535}, {256, 65535}, {256, 65535}, {256, 65535}, {256, 65535}, {256, 65535},
+    {256, 65535}, {256, 65535}, {256, 65535}, {256, 65535}, {256, 65535}, {256, 65535}};
+
+lv_many_tuning clamp_many(lv_many_tuning t) {
+  t.wave_max_degree = std::max(1, std::min(t.wave_max_degree, kManyWaveDeg));
+  t.grid = std::max(1, std::min(t.grid, 65535));
+  return t;
+}
+
+lv_status many_graph(void* desc, size_t desc_bytes, int32_t count, const lv_params& p, const lv_many_tuning& tu,
+                     ManyGraph** out) {
   // the next power of two, within the descriptor buffer (>= count: checked by the caller)
   const int64_t fit = static_cast<int64_t>((desc_bytes - kManyHeader) / sizeof(ManyItem));
   int64_t b = 1;
@@ -750,7 +763,8 @@ lv_status many_graph(void* desc, size_t desc_bytes, int32_t count, const lv_para
     G.host_bytes = bytes;
   }
   for (auto& x : G.g)
-    if (x.desc == desc && x.bucket == bucket && same_params(x.p, p)) {
+    if (x.desc == desc && x.bucket == bucket && same_params(x.p, p) && x.t.wave_max_degree == tu.wave_max_degree &&
+        x.t.grid == tu.grid) {
       *out = &x;
       return LV_OK;
     }
@@ -761,7 +775,7 @@ lv_status many_graph(void* desc, size_t desc_bytes, int32_t count, const lv_para
   LV_HIP(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
   (void)hipMemcpyAsync(d, G.host, bytes, hipMemcpyHostToDevice, G.cap);
   launch_many_df(reinterpret_cast<const int32_t*>(d), reinterpret_cast<ManyItem*>(d + kManyHeader),
-                 bucket < 4096 ? bucket : 4096, p, G.cap);
+                 std::min(bucket, tu.grid), p, tu.wave_max_degree, G.cap);
   (void)hipMemcpyAsync(G.host, d, bytes, hipMemcpyDeviceToHost, G.cap);
   LV_HIP(hipStreamEndCapture(G.cap, &graph));
   hipGraphExec_t exec = nullptr;
@@ -772,6 +786,7 @@ lv_status many_graph(void* desc, size_t desc_bytes, int32_t count, const lv_para
   x.desc = desc;
   x.bucket = bucket;
   x.p = p;
+  x.t = tu;
   x.host = G.host;
   x.exec = exec;
   G.g.push_back(x);
@@ -1008,16 +1023,15 @@ size_t lv_many_desc_bytes(int32_t count) {
   return kManyHeader + sizeof(ManyItem) * static_cast<size_t>(count > 0 ? count : 1);
 }
 
-lv_status louvain_df_many(const lv_item* items, int32_t count, const lv_params* p, void* desc, size_t desc_bytes,
-                          void* ws, size_t ws_bytes, int32_t* status, lv_stats* stats, void* stream) {
-  if (count < 0 || (count > 0 && (!items || !status || !desc))) return fail(LV_EINVAL, "invalid arguments");
-  if (!params_ok(p)) return fail(LV_EINVAL, "invalid parameters");
-  if (p->recompute_weights) return fail(LV_EINVAL, "the batched launch updates K and Sigma incrementally only");
-  if (desc_bytes < lv_many_desc_bytes(count)) return fail(LV_EWORKSPACE, "descriptor buffer too small");
-  if (count == 0) return LV_OK;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const auto t_start = std::chrono::steady_clock::now();
-  std::vector<ManyItem> h(static_cast<size_t>(count));
+}  // extern "C"
+
+namespace lv {
+namespace {
+
+// Host side of a batched call: item descriptors (LV_ETOOLARGE marks items
+// the kernel must leave to the single-graph path).
+lv_status many_prepare(const lv_item* items, int32_t count, std::vector<ManyItem>& h) {
+  h.assign(static_cast<size_t>(count), ManyItem{});
   for (int32_t k = 0; k < count; ++k) {
     const lv_item& x = items[k];
     ManyItem& m = h[k];
@@ -1050,15 +1064,14 @@ lv_status louvain_df_many(const lv_item* items, int32_t count, const lv_params* 
         x.max_updates <= 0 || x.g.n <= 0)
       m.status = LV_ETOOLARGE;
   }
-  ManyGraph* mg = nullptr;
-  lv_status gs = many_graph(desc, desc_bytes, count, *p, &mg);
-  if (gs) return gs;
-  *reinterpret_cast<int32_t*>(mg->host) = count;
-  std::memcpy(mg->host + kManyHeader, h.data(), sizeof(ManyItem) * h.size());
-  LV_HIP(hipGraphLaunch(mg->exec, st));
-  LV_HIP(hipStreamSynchronize(st));
-  std::memcpy(h.data(), mg->host + kManyHeader, sizeof(ManyItem) * h.size());
-  const double batched_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  return LV_OK;
+}
+
+// After the batched kernel: statuses and statistics, the single-graph path
+// for items outside the kernel's limits, and aggregation with later passes
+// for graphs whose pass 0 iterated more than once (Alg. 4).
+void many_finish(const lv_item* items, int32_t count, const std::vector<ManyItem>& h, const lv_params* p, void* ws,
+                 size_t ws_bytes, int32_t* status, lv_stats* stats, void* stream, double batched_s) {
   for (int32_t k = 0; k < count; ++k) {
     const ManyItem& m = h[k];
     const lv_item& x = items[k];
@@ -1101,6 +1114,145 @@ lv_status louvain_df_many(const lv_item* items, int32_t count, const lv_params* 
     }
     S.seconds += batched_s;
   }
+}
+
+int32_t many_size_class(const std::vector<ManyItem>& h) {
+  if (h.empty()) return 0;
+  double sum = 0.0;
+  for (const ManyItem& m : h) sum += static_cast<double>(m.n);
+  const double mean = sum / static_cast<double>(h.size());
+  int32_t k = 0;
+  while (k + 1 < LV_MANY_CLASSES && mean > static_cast<double>(int64_t(1) << (k + 9))) ++k;
+  return k;
+}
+
+lv_status many_check(int32_t count, const lv_item* items, const int32_t* status, const void* desc, const lv_params* p,
+                     size_t desc_bytes) {
+  if (count < 0 || (count > 0 && (!items || !status || !desc))) return fail(LV_EINVAL, "invalid arguments");
+  if (!params_ok(p)) return fail(LV_EINVAL, "invalid parameters");
+  if (p->recompute_weights) return fail(LV_EINVAL, "the batched launch updates K and Sigma incrementally only");
+  if (desc_bytes < lv_many_desc_bytes(count)) return fail(LV_EWORKSPACE, "descriptor buffer too small");
+  return LV_OK;
+}
+
+}  // namespace
+}  // namespace lv
+
+extern "C" {
+
+void lv_get_many_tuning(int32_t size_class, lv_many_tuning* t) {
+  if (t && size_class >= 0 && size_class < LV_MANY_CLASSES) *t = g_many_tuning[size_class];
+}
+
+void lv_set_many_tuning(int32_t size_class, const lv_many_tuning* t) {
+  if (t && size_class >= 0 && size_class < LV_MANY_CLASSES) g_many_tuning[size_class] = clamp_many(*t);
+}
+
+int32_t lv_many_size_class(const lv_item* items, int32_t count) {
+  if (!items || count <= 0) return 0;
+  std::vector<ManyItem> h(static_cast<size_t>(count));
+  for (int32_t k = 0; k < count; ++k) h[k].n = items[k].g.n;
+  return many_size_class(h);
+}
+
+lv_status louvain_df_many(const lv_item* items, int32_t count, const lv_params* p, void* desc, size_t desc_bytes,
+                          void* ws, size_t ws_bytes, int32_t* status, lv_stats* stats, void* stream) {
+  lv_status s = many_check(count, items, status, desc, p, desc_bytes);
+  if (s) return s;
+  if (count == 0) return LV_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const auto t_start = std::chrono::steady_clock::now();
+  std::vector<ManyItem> h;
+  if ((s = many_prepare(items, count, h))) return s;
+  const lv_many_tuning tu = clamp_many(g_many_tuning[many_size_class(h)]);
+  ManyGraph* mg = nullptr;
+  if ((s = many_graph(desc, desc_bytes, count, *p, tu, &mg))) return s;
+  *reinterpret_cast<int32_t*>(mg->host) = count;
+  std::memcpy(mg->host + kManyHeader, h.data(), sizeof(ManyItem) * h.size());
+  LV_HIP(hipGraphLaunch(mg->exec, st));
+  LV_HIP(hipStreamSynchronize(st));
+  std::memcpy(h.data(), mg->host + kManyHeader, sizeof(ManyItem) * h.size());
+  const double batched_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  many_finish(items, count, h, p, ws, ws_bytes, status, stats, stream, batched_s);
+  return LV_OK;
+}
+
+lv_status lv_autotune_many(const lv_item* items, int32_t count, const lv_params* p, void* desc, size_t desc_bytes,
+                           void* ws, size_t ws_bytes, int32_t* status, lv_stats* stats, lv_many_tuning* best,
+                           void* stream) {
+  lv_status s = many_check(count, items, status, desc, p, desc_bytes);
+  if (s) return s;
+  if (count == 0) return LV_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const auto t_start = std::chrono::steady_clock::now();
+  std::vector<ManyItem> h;
+  if ((s = many_prepare(items, count, h))) return s;
+  const int32_t cls = many_size_class(h);
+  // one graph per workgroup (the hardware hands workgroups to free compute
+  // units, which balances graphs of uneven size); the candidates differ in
+  // the wavefront / workgroup split and the LDS table size it implies
+  static const int32_t waves[] = {32, 64, 128, 256};
+  const int32_t grid_cap = g_many_tuning[cls].grid;
+  std::vector<lv_many_tuning> cand;
+  for (int32_t w : waves) cand.push_back(lv_many_tuning{w, grid_cap});
+  const int32_t nc = static_cast<int32_t>(cand.size());
+  // items by size, dealt round-robin: every candidate gets a like share of
+  // small and large graphs (a launch lasts as long as its largest graph)
+  std::vector<int32_t> order(static_cast<size_t>(count));
+  for (int32_t k = 0; k < count; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return static_cast<int64_t>(h[a].n) + h[a].nd + h[a].ni > static_cast<int64_t>(h[b].n) + h[b].nd + h[b].ni;
+  });
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  LV_HIP(hipEventCreate(&e0));
+  LV_HIP(hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } guard{e0, e1};
+  char* d = static_cast<char*>(desc);
+  // the kernel's code is loaded by a first launch with no items
+  int32_t zero = 0;
+  LV_HIP(hipMemcpyAsync(d, &zero, sizeof(int32_t), hipMemcpyHostToDevice, st));
+  launch_many_df(reinterpret_cast<const int32_t*>(d), reinterpret_cast<ManyItem*>(d + kManyHeader), 1, *p,
+                 cand[0].wave_max_degree, st);
+  LV_CHECK_LAUNCH();
+  LV_HIP(hipStreamSynchronize(st));
+  double best_t = 0.0;
+  int32_t best_k = -1;
+  std::vector<ManyItem> grp;
+  for (int32_t c = 0; c < nc; ++c) {
+    grp.clear();
+    for (int32_t k = c; k < count; k += nc) grp.push_back(h[order[k]]);
+    if (grp.empty()) continue;
+    const int32_t gn = static_cast<int32_t>(grp.size());
+    LV_HIP(hipMemcpyAsync(d, &gn, sizeof(int32_t), hipMemcpyHostToDevice, st));
+    LV_HIP(hipMemcpyAsync(d + kManyHeader, grp.data(), sizeof(ManyItem) * grp.size(), hipMemcpyHostToDevice, st));
+    LV_HIP(hipEventRecord(e0, st));
+    launch_many_df(reinterpret_cast<const int32_t*>(d), reinterpret_cast<ManyItem*>(d + kManyHeader),
+                   std::min(gn, cand[c].grid), *p, cand[c].wave_max_degree, st);
+    LV_CHECK_LAUNCH();
+    LV_HIP(hipEventRecord(e1, st));
+    LV_HIP(hipMemcpyAsync(grp.data(), d + kManyHeader, sizeof(ManyItem) * grp.size(), hipMemcpyDeviceToHost, st));
+    LV_HIP(hipStreamSynchronize(st));
+    float ms = 0.f;
+    LV_HIP(hipEventElapsedTime(&ms, e0, e1));
+    for (int32_t k = c, q = 0; k < count; k += nc, ++q) h[order[k]] = grp[q];
+    const double per_item = static_cast<double>(ms) / gn;
+    if (best_k < 0 || per_item < best_t) {
+      best_t = per_item;
+      best_k = c;
+    }
+  }
+  if (best_k >= 0) {
+    g_many_tuning[cls] = clamp_many(cand[best_k]);
+    if (best) *best = g_many_tuning[cls];
+  }
+  const double batched_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  many_finish(items, count, h, p, ws, ws_bytes, status, stats, stream, batched_s);
   return LV_OK;
 }
 

@@ -428,7 +428,10 @@ size_t many_scratch_bytes(int32_t n, int32_t max_updates);
 // The descriptor buffer: an int32 item count in a header of kManyHeader
 // bytes, then the items.  The kernel reads the count there.
 constexpr size_t kManyHeader = 256;
-void launch_many_df(const int32_t* count, ManyItem* items, int32_t grid, const lv_params& p, hipStream_t st);
+// wave_deg: rows up to this many arcs take one wavefront (at most
+// kManyWaveDeg), longer ones the whole workgroup.
+void launch_many_df(const int32_t* count, ManyItem* items, int32_t grid, const lv_params& p, int32_t wave_deg,
+                    hipStream_t st);
 
 // move.hip
 struct MoveArgs {

@@ -22,6 +22,7 @@
 // shared data is read with agent-scope atomic loads after other lanes of
 // the workgroup wrote it with device atomics, and phases are separated by
 // workgroup barriers.
+#include <algorithm>
 #include <climits>
 
 #include "lv_internal.hpp"
@@ -523,9 +524,10 @@ __device__ int64_t scan_block(const ManyItem& it, const ItemScratch& s, const Mo
 }
 
 // Frontier bitmask -> list (clearing the words), with the degree split:
-// rows up to kManyWaveDeg from the front of the list, longer ones from the
-// back.  Counts first-time vertices and scanned arcs.
-__device__ void build_list(const ManyItem& it, const ItemScratch& s, Shared& sh, int64_t& affected, int64_t& arcs) {
+// rows up to wave_deg (at most kManyWaveDeg: the LDS tables hold twice
+// that) from the front of the list, longer ones from the back.  Counts first-time vertices and scanned arcs.
+__device__ void build_list(const ManyItem& it, const ItemScratch& s, Shared& sh, int32_t wave_deg, int64_t& affected,
+                           int64_t& arcs) {
   const int64_t words = (static_cast<int64_t>(it.n) + 31) / 32;
   if (threadIdx.x == 0) {
     sh.nlist = 0;
@@ -543,7 +545,7 @@ __device__ void build_list(const ManyItem& it, const ItemScratch& s, Shared& sh,
       const int32_t v = static_cast<int32_t>(k * 32 + (__ffs(r) - 1));
       const int32_t deg = ld(&it.row_len[v]);
       arcs += deg;
-      if (deg <= kManyWaveDeg)
+      if (deg <= wave_deg)
         s.list[atomicAdd(&sh.nlist, 1)] = v;
       else
         s.list[it.n - 1 - atomicAdd(&sh.nbig, 1)] = v;
@@ -554,7 +556,7 @@ __device__ void build_list(const ManyItem& it, const ItemScratch& s, Shared& sh,
 
 __global__ void __launch_bounds__(kBlock) k_many_df(const int32_t* __restrict__ count_ptr,
                                                    ManyItem* __restrict__ items, double tol, int32_t max_iterations,
-                                                   int32_t mode, int32_t guard) {
+                                                   int32_t mode, int32_t guard, int32_t wave_deg) {
   __shared__ Shared sh;
   const int32_t count = *count_ptr;  // the descriptor header: a captured launch serves any count
   for (int32_t idx = blockIdx.x; idx < count; idx += gridDim.x) {
@@ -583,7 +585,7 @@ __global__ void __launch_bounds__(kBlock) k_many_df(const int32_t* __restrict__ 
       si.cur = cur;
       si.next = next;
       int64_t affected = 0, arcs = 0;
-      build_list(it, si, sh, affected, arcs);
+      build_list(it, si, sh, wave_deg, affected, arcs);
       const int32_t nsmall = sh.nlist, nbig = sh.nbig;
       int64_t gain = 0, movers = 0;
       // wavefront rows
@@ -668,9 +670,11 @@ size_t many_scratch_bytes(int32_t n, int32_t max_updates) {
   return 3 * a(4 * words) + 2 * a(4 * un + 4) + a(8 * ps) + 2 * a(4 * ps) + 3 * a(4 * rs) + 2 * a(8 * cap + 4);
 }
 
-void launch_many_df(const int32_t* count, ManyItem* items, int32_t grid, const lv_params& p, hipStream_t st) {
+void launch_many_df(const int32_t* count, ManyItem* items, int32_t grid, const lv_params& p, int32_t wave_deg,
+                    hipStream_t st) {
+  wave_deg = std::max(1, std::min(wave_deg, kManyWaveDeg));
   hipLaunchKernelGGL(k_many_df, dim3(grid), dim3(kBlock), 0, st, count, items, p.tolerance, p.max_iterations,
-                     p.mode, p.swap_guard);
+                     p.mode, p.swap_guard, wave_deg);
 }
 
 }  // namespace lv

@@ -38,7 +38,8 @@ EXPORTS = ["lv_default_params", "lv_workspace_bytes", "lv_graph_capacity_bound",
            "lv_graph_relayout", "apply_batch", "louvain_static", "louvain_nd", "louvain_ds", "louvain_df",
            "modularity", "lv_set_tuning", "lv_get_tuning", "lv_set_timing", "lv_last_error",
            "lv_many_scratch_bytes", "lv_many_desc_bytes", "louvain_df_many", "lv_autotune",
-           "lv_noalloc_scratch_bytes", "louvain_df_noalloc"]
+           "lv_noalloc_scratch_bytes", "louvain_df_noalloc", "lv_get_many_tuning", "lv_set_many_tuning",
+           "lv_many_size_class", "lv_autotune_many"]
 
 
 class LouvainError(RuntimeError):
@@ -152,6 +153,12 @@ def load():
     L.lv_many_desc_bytes.argtypes = [I32]
     L.louvain_df_many.restype = I32
     L.louvain_df_many.argtypes = [ct.POINTER(CItem), I32, PP, P, SZ, P, SZ, ct.POINTER(I32), STP, P]
+    L.lv_get_many_tuning.argtypes = [I32, P]
+    L.lv_set_many_tuning.argtypes = [I32, P]
+    L.lv_many_size_class.restype = I32
+    L.lv_many_size_class.argtypes = [P, I32]
+    L.lv_autotune_many.restype = I32
+    L.lv_autotune_many.argtypes = [ct.POINTER(CItem), I32, PP, P, SZ, P, SZ, ct.POINTER(I32), STP, P, P]
     L.lv_autotune.restype = I32
     L.lv_autotune.argtypes = [GP, SP, P, SZ, I32, ct.POINTER(Tuning), P]
     L.lv_noalloc_scratch_bytes.restype = SZ
@@ -521,6 +528,54 @@ def louvain_df_many(graphs, batches, states, scratches, max_updates, prm=None, w
     for (an int, or one per graph); `ws` is a workspace tensor for graphs
     that continue on the single-graph path (None: they report
     LV_EWORKSPACE).  Returns (status list, stats list)."""
+    return _many("louvain_df_many", graphs, batches, states, scratches, max_updates, prm, ws, desc, stream, kw)
+
+
+def autotune_many(graphs, batches, states, scratches, max_updates, prm=None, ws=None, desc=None, stream=None,
+                  **kw):
+    """louvain_df_many that also tunes the batched launch for the items'
+    size class (lv_autotune_many).  Returns (status list, stats list,
+    the chosen tuning as a dict)."""
+    best = ManyTuning()
+    status, stats = _many("lv_autotune_many", graphs, batches, states, scratches, max_updates, prm, ws, desc,
+                          stream, kw, best)
+    return status, stats, {f: getattr(best, f) for f, _ in ManyTuning._fields_}
+
+
+class ManyTuning(ct.Structure):
+    _fields_ = [("wave_max_degree", ct.c_int32), ("grid", ct.c_int32)]
+
+
+MANY_CLASSES = 12
+
+
+def get_many_tuning() -> list:
+    """The batched launch's tuning table, one dict per size class."""
+    L = load()
+    out = []
+    for k in range(MANY_CLASSES):
+        t = ManyTuning()
+        L.lv_get_many_tuning(k, ct.byref(t))
+        out.append({f: getattr(t, f) for f, _ in ManyTuning._fields_})
+    return out
+
+
+def set_many_tuning(table) -> None:
+    """Restores a table from get_many_tuning (e.g. one saved to a file)."""
+    L = load()
+    for k, row in enumerate(table[:MANY_CLASSES]):
+        L.lv_set_many_tuning(k, ct.byref(ManyTuning(int(row["wave_max_degree"]), int(row["grid"]))))
+
+
+def many_size_class(graphs) -> int:
+    """The size class of a batched call on these graphs."""
+    items = (CItem * max(len(graphs), 1))()
+    for k, g in enumerate(graphs):
+        items[k].g.n = g.n
+    return int(load().lv_many_size_class(items, len(graphs)))
+
+
+def _many(fn, graphs, batches, states, scratches, max_updates, prm, ws, desc, stream, kw, best=None):
     L = load()
     count = len(graphs)
     prm = prm if prm is not None else params(**kw)
@@ -536,9 +591,11 @@ def louvain_df_many(graphs, batches, states, scratches, max_updates, prm=None, w
     status = np.zeros(max(count, 1), dtype=np.int32)
     stats = (Stats * max(count, 1))()
     wp, wb = (ct.c_void_p(ws.data_ptr()), ws.numel()) if ws is not None else (None, 0)
-    _check(L.louvain_df_many(items.ctypes.data_as(ct.POINTER(CItem)), count, ct.byref(prm),
-                             ct.c_void_p(desc.data_ptr()), desc.numel(), wp, wb,
-                             status.ctypes.data_as(ct.POINTER(ct.c_int32)), stats, _stream(stream)))
+    args = [items.ctypes.data_as(ct.POINTER(CItem)), count, ct.byref(prm), ct.c_void_p(desc.data_ptr()),
+            desc.numel(), wp, wb, status.ctypes.data_as(ct.POINTER(ct.c_int32)), stats]
+    if best is not None:
+        args.append(ct.byref(best))
+    _check(getattr(L, fn)(*args, _stream(stream)))
     return status[:count].tolist(), StatsList(stats, count)
 
 

@@ -233,6 +233,41 @@ class GraphStore:
         with self.lock:
             self.refreshes += 1
 
+    def tune(self, gids, batches) -> dict:
+        """One update per listed graph through lv_autotune_many: the updates
+        are applied (results as louvain_df_many's) while the batched launch
+        is tuned for their size class.  Call with no worker running.
+        Returns the class and the tuning chosen."""
+        residents = self.acquire(gids)
+        try:
+            big = max(residents, key=lambda x: x.graph.n * 4 + x.graph.cap)
+            ws = torch.empty(int(lib.load().lv_workspace_bytes(big.graph.n, big.graph.cap)), dtype=torch.uint8,
+                             device=self.device)
+            dev = [lib.Batch.from_host(b, self.device) for b in batches]
+            status, _, best = lib.autotune_many([r.graph for r in residents], dev, [r.state for r in residents],
+                                                [r.scratch for r in residents], self.max_updates,
+                                                prm=lib.params(mode=self.mode), ws=ws)
+            if any(s != 0 for s in status):
+                raise RuntimeError(f"tuning pass: statuses {sorted(set(status))}")
+        finally:
+            self.release(gids)
+        return {"size_class": lib.many_size_class([r.graph for r in residents]), "tuning": best}
+
+    @staticmethod
+    def save_tuning(path: str) -> None:
+        """Writes the batched launch's tuning table (one entry per size
+        class) to a JSON file."""
+        import json
+        with open(path, "w") as f:
+            json.dump(lib.get_many_tuning(), f)
+
+    @staticmethod
+    def load_tuning(path: str) -> None:
+        """Restores a tuning table written by save_tuning."""
+        import json
+        with open(path) as f:
+            lib.set_many_tuning(json.load(f))
+
     def measure(self, r: Resident, ws: torch.Tensor, stream) -> float:
         """Q of a resident graph's state (Eq. 1); sets or clears its DS
         fallback against the reference of its last static run."""

@@ -609,3 +609,56 @@ def test_many_graphs_isolate_bad_batches(lib):
     assert status == [0, lib.LV_ENOEDGE, 0]
     assert all(np.array_equal(x, y) for x, y in zip(before, graphs[1].csr_host()))
     assert torch.equal(C1, states[1].C)
+
+
+def test_autotune_many_keeps_results_and_sets_the_class_entry(lib):
+    """lv_autotune_many deals its items to the candidate mappings of the
+    batched launch (one timed launch each): every item's SYNC result is
+    still the sequential oracle's, the chosen candidate becomes the entry
+    of the items' size class, and a following louvain_df_many call (which
+    uses that entry) stays bit-exact."""
+    specs = W.multi_sbm_specs(24, 61, n_lo=400, n_hi=3000, b_lo=10, b_hi=300)
+    graphs, states, scratches, orcs, first = [], [], [], [], []
+    cap = 0
+    cases = []
+    for k, (n, b, sd) in enumerate(specs):
+        e = W.multi_sbm_graph(int(n), int(b), int(sd))
+        b1 = W.random_batch(e, max(4, e.m // 100), 700 + k)
+        b2 = W.random_batch(W.apply_batch_np(e, b1), max(4, e.m // 100), 800 + k)
+        cases.append((e, b1, b2))
+        cap = max(cap, b1.size, b2.size)
+    saved = lib.get_many_tuning()
+    try:
+        for e, b1, _ in cases:
+            G = _orc(e)
+            s0 = G.louvain("static", mode="sync")[:3]
+            g = lib.Graph.from_edges(e, slack_frac=1.0, slack_min=32)
+            st = lib.State.from_host(*s0)
+            st.size = torch.from_numpy(_sizes(s0[0], e.n)).cuda()
+            graphs.append(g)
+            states.append(st)
+            scratches.append(lib.many_scratch(e.n, cap))
+            orcs.append((G, s0))
+        ws = max(graphs, key=lambda g: g.n * 4 + g.cap).workspace
+        cls = lib.many_size_class(graphs)
+        status, stats, best = lib.autotune_many(graphs, [lib.Batch.from_host(c[1]) for c in cases], states,
+                                                scratches, cap, ws=ws, mode="sync")
+        assert status == [0] * len(cases), status
+        assert best["wave_max_degree"] in (32, 64, 128, 256) and best["grid"] == saved[cls]["grid"]
+        assert lib.get_many_tuning()[cls] == best
+        for (G, s0), (e, b1, _), st in zip(orcs, cases, states):
+            assert G.apply_batch(b1) == 0
+            Co, Ko, So, _ = G.louvain("df", batch=b1, state=s0, mode="sync")
+            C, K, S = st.host()
+            assert np.array_equal(C, Co) and np.array_equal(K, Ko) and np.array_equal(S, So)
+            first.append((Co, Ko, So))
+        status, _ = lib.louvain_df_many(graphs, [lib.Batch.from_host(c[2]) for c in cases], states, scratches, cap,
+                                        ws=ws, mode="sync")
+        assert status == [0] * len(cases), status
+        for (G, _), (e, _, b2), st, s1 in zip(orcs, cases, states, first):
+            assert G.apply_batch(b2) == 0
+            Co, Ko, So, _ = G.louvain("df", batch=b2, state=s1, mode="sync")
+            C, K, S = st.host()
+            assert np.array_equal(C, Co) and np.array_equal(K, Ko) and np.array_equal(S, So)
+    finally:
+        lib.set_many_tuning(saved)
