@@ -19,6 +19,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "louvain_oracle.cpp")
+SRC_FP = os.path.join(HERE, "louvain_oracle_fp.cpp")  # the paper's precision: float32 weights, FP64 sums
 LIB = os.path.join(HERE, "liboracle.so")
 
 STATIC, ND, DS, DF = 0, 1, 2, 3
@@ -34,9 +35,10 @@ MAX_ITERS = 32
 
 def build(force: bool = True) -> str:
     """Compile the oracle into ``liboracle.so`` with the host compiler."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(SRC),
+                                                                         os.path.getmtime(SRC_FP)):
         tmp = LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", tmp, SRC])
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", tmp, SRC, SRC_FP])
         os.replace(tmp, LIB)
     return LIB
 
@@ -82,6 +84,29 @@ class Stats(ct.Structure):
         }
 
 
+class StatsF(ct.Structure):
+    """Statistics of the paper-precision oracle (ΔQ sums in FP64)."""
+    _fields_ = [
+        ("passes", ct.c_int32),
+        ("iterations", ct.c_int32 * MAX_PASSES),
+        ("communities", ct.c_int64 * MAX_PASSES),
+        ("moves", ct.c_int64),
+        ("arcs_scanned", ct.c_int64),
+        ("iter_moves", (ct.c_int64 * MAX_ITERS) * MAX_PASSES),
+        ("iter_dq", (ct.c_double * MAX_ITERS) * MAX_PASSES),
+        ("seconds", ct.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        p = self.passes
+        its = [self.iterations[k] for k in range(p)]
+        return {"passes": p, "iterations": its, "communities": [int(self.communities[k]) for k in range(p)],
+                "moves": int(self.moves), "arcs_scanned": int(self.arcs_scanned),
+                "iter_moves": [[int(self.iter_moves[k][t]) for t in range(its[k])] for k in range(p)],
+                "iter_dq": [[float(self.iter_dq[k][t]) for t in range(its[k])] for k in range(p)],
+                "seconds": float(self.seconds)}
+
+
 def params(tolerance=1e-2, tolerance_drop=10.0, aggregation_tolerance=0.8,
            max_iterations=20, max_passes=10, mode="sync", swap_guard=1) -> Params:
     """Defaults are the paper's (Section 5.1.2)."""
@@ -96,7 +121,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(SRC), os.path.getmtime(SRC_FP)):
             build(force=True)
         L = ct.CDLL(LIB)
         P = ct.c_void_p
@@ -132,6 +157,24 @@ def lib():
         L.orc_aggregate.argtypes = [P, i32p, ct.c_int32]
         L.orc_graph_from_arcs.restype = P
         L.orc_graph_from_arcs.argtypes = [ct.c_int32, ct.c_int64, i32p, i32p, i64p]
+        f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        L.orcf_graph_new.restype = P
+        L.orcf_graph_new.argtypes = [ct.c_int32, ct.c_int64, i32p, i32p, f32p, ct.POINTER(ct.c_int32)]
+        L.orcf_graph_free.argtypes = [P]
+        L.orcf_two_m.restype = ct.c_double
+        L.orcf_two_m.argtypes = [P]
+        L.orcf_apply_batch.restype = ct.c_int32
+        L.orcf_apply_batch.argtypes = [P, ct.c_int64, i32p, i32p, f32p, ct.c_int64, i32p, i32p, f32p]
+        L.orcf_degrees.argtypes = [P, f64p]
+        L.orcf_modularity.restype = ct.c_double
+        L.orcf_modularity.argtypes = [P, i32p]
+        L.orcf_decide.argtypes = [P, i32p, f64p, f64p, i32p, ct.c_int32, ct.c_int64, i32p, i32p, f64p, u8p]
+        L.orcf_louvain.restype = ct.c_int32
+        L.orcf_louvain.argtypes = [P, ct.c_int32, ct.POINTER(Params), ct.c_int64, i32p, i32p, f32p, ct.c_int64,
+                                   i32p, i32p, f32p, i32p, f64p, f64p, ct.POINTER(StatsF)]
+        L.orcf_stats_size.restype = ct.c_int32
+        assert L.orcf_stats_size() == ct.sizeof(StatsF)
         L.orc_stats_size.restype = ct.c_int32
         L.orc_params_size.restype = ct.c_int32
         assert L.orc_stats_size() == ct.sizeof(Stats)
@@ -272,3 +315,86 @@ def update_weights(n, batch, C, K, Sig):
     S = np.array(Sig, dtype=np.int64)
     lib().orc_update_weights(int(n), *_batch_args(batch), _a32(C), K, S)
     return K, S
+
+
+def _f32(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+
+
+_EMPTYF = np.zeros(0, dtype=np.float32)
+
+
+def _batch_args_f(batch):
+    if batch is None:
+        return (0, _EMPTY32, _EMPTY32, _EMPTYF, 0, _EMPTY32, _EMPTY32, _EMPTYF)
+    du, dv, dw = _a32(batch.del_u), _a32(batch.del_v), _f32(batch.del_w)
+    iu, iv, iw = _a32(batch.ins_u), _a32(batch.ins_v), _f32(batch.ins_w)
+    return (du.shape[0], du, dv, dw, iu.shape[0], iu, iv, iw)
+
+
+class GraphF:
+    """The paper-precision oracle's graph: float32 weights, FP64 sums
+    (louvain_oracle_fp.cpp)."""
+
+    def __init__(self, n, u, v, w):
+        st = ct.c_int32(0)
+        u, v, w = _a32(u), _a32(v), _f32(w)
+        h = lib().orcf_graph_new(int(n), int(u.shape[0]), u, v, w, ct.byref(st))
+        if not h:
+            raise OracleError(st.value, "graph build")
+        self._h = h
+        self.n = int(n)
+
+    @classmethod
+    def from_edges(cls, e):
+        return cls(e.n, e.u, e.v, e.w)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.orcf_graph_free(h)
+            self._h = None
+
+    @property
+    def two_m(self) -> float:
+        return float(lib().orcf_two_m(self._h))
+
+    def apply_batch(self, batch) -> int:
+        return lib().orcf_apply_batch(self._h, *_batch_args_f(batch))
+
+    def degrees(self) -> np.ndarray:
+        K = np.zeros(self.n, dtype=np.float64)
+        lib().orcf_degrees(self._h, K)
+        return K
+
+    def modularity(self, C) -> float:
+        return float(lib().orcf_modularity(self._h, _a32(C)))
+
+    def decide(self, C, K, Sig, size, verts, guard=1):
+        verts = _a32(verts)
+        oc = np.zeros(verts.shape[0], dtype=np.int32)
+        odq = np.zeros(verts.shape[0], dtype=np.float64)
+        om = np.zeros(verts.shape[0], dtype=np.uint8)
+        lib().orcf_decide(self._h, _a32(C), np.ascontiguousarray(K, dtype=np.float64),
+                          np.ascontiguousarray(Sig, dtype=np.float64), _a32(size), int(guard), verts.shape[0],
+                          verts, oc, odq, om)
+        return oc, odq, om.astype(bool)
+
+    def louvain(self, approach="static", batch=None, state=None, prm=None, **kw):
+        """Static or DF Louvain in the paper's precision.  ``state`` =
+        (C, K, Sigma) before the batch (FP64 K and Sigma).  Returns (C, K,
+        Sigma, stats dict)."""
+        n = self.n
+        if prm is None:
+            prm = params(**kw)
+        if state is None:
+            C, K, S = np.zeros(n, np.int32), np.zeros(n, np.float64), np.zeros(n, np.float64)
+        else:
+            C, K, S = (np.array(state[0], dtype=np.int32), np.array(state[1], dtype=np.float64),
+                       np.array(state[2], dtype=np.float64))
+        st = StatsF()
+        code = lib().orcf_louvain(self._h, APPROACH[approach], ct.byref(prm), *_batch_args_f(batch), C, K, S,
+                                  ct.byref(st))
+        if code != OK:
+            raise OracleError(code, "louvain (paper precision)")
+        return C, K, S, st.as_dict()

@@ -27,7 +27,7 @@ import numpy as np
 
 __all__ = [
     "Edges", "Batch", "sbm", "config1_sbm", "rmat", "config2_rmat",
-    "random_batch", "batch_size", "batch_sequence", "two_cliques_bridge", "ring_of_cliques",
+    "random_batch", "batch_size", "batch_sequence", "real_weights", "real_batch", "two_cliques_bridge", "ring_of_cliques",
     "random_small_graph", "apply_batch_np", "chung_lu", "config3_chung_lu", "pa_temporal_stream",
     "temporal_workload", "config4_temporal", "multi_sbm_specs",
 ]
@@ -282,6 +282,27 @@ def random_batch(g: Edges, size: int, seed: int, ins_frac: float = 0.8) -> Batch
                  _i32(iu), _i32(iv), np.ones(ins.shape[0], dtype=np.int32))
 
 
+def real_weights(e: Edges, seed: int, lo: float = 0.25, hi: float = 4.0) -> Edges:
+    """The same edges with float32 weights drawn uniformly from [lo, hi)
+    (seeded): the weighted graphs of the paper's precision (Section 5.1.2
+    keeps edge weights in 32-bit floats)."""
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(lo, hi, e.m).astype(np.float32)
+    return Edges(e.n, e.u, e.v, w)
+
+
+def real_batch(b: Batch, g: Edges, seed: int, lo: float = 0.25, hi: float = 4.0) -> Batch:
+    """A batch for a real-weighted graph `g`: deletions remove the whole
+    current weight of their edge (looked up in g), insertions get float32
+    weights drawn uniformly from [lo, hi) (seeded)."""
+    keys = _canon(g.u, g.v, g.n)
+    order = np.argsort(keys)
+    pos = order[np.searchsorted(keys[order], _canon(b.del_u, b.del_v, g.n))]
+    rng = np.random.default_rng(seed)
+    return Batch(b.del_u, b.del_v, np.asarray(g.w, dtype=np.float32)[pos], b.ins_u, b.ins_v,
+                 rng.uniform(lo, hi, b.ins_u.shape[0]).astype(np.float32))
+
+
 def batch_sequence(g: Edges, sizes, count: int, seed: int) -> list:
     """``count`` batches cycling through ``sizes`` (undirected updates), each
     80% insertions of absent uniform pairs and 20% deletions of uniform
@@ -305,20 +326,24 @@ def apply_batch_np(g: Edges, b: Batch) -> Edges:
     """Edge list after the batch (deletions subtract, then insertions add);
     used by generators that chain batches, not by either implementation."""
     n = g.n
+    real = np.issubdtype(np.asarray(g.w).dtype, np.floating)
+    acc = np.float32 if real else np.int64   # float32 weights stay float32, as the implementations keep them
     keys = _canon(g.u, g.v, n)
-    w = g.w.astype(np.int64).copy()
+    w = g.w.astype(acc).copy()
     order = np.argsort(keys)
     keys, w = keys[order], w[order]
     dk = _canon(b.del_u, b.del_v, n)
     pos = np.searchsorted(keys, dk)
-    w[pos] -= b.del_w
+    w[pos] -= np.asarray(b.del_w).astype(acc)
     ik = _canon(b.ins_u, b.ins_v, n)
     allk = np.concatenate([keys, ik])
-    allw = np.concatenate([w, b.ins_w.astype(np.int64)])
+    allw = np.concatenate([w, np.asarray(b.ins_w).astype(acc)])
     uk, inv = np.unique(allk, return_inverse=True)
-    ww = np.zeros(uk.shape[0], dtype=np.int64)
+    ww = np.zeros(uk.shape[0], dtype=acc)
     np.add.at(ww, inv, allw)
     keep = ww > 0
+    if real:
+        return Edges(int(n), _i32(uk[keep] // n), _i32(uk[keep] % n), ww[keep].astype(np.float32))
     return _from_keys(uk[keep], n, ww[keep])
 
 
