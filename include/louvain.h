@@ -364,6 +364,65 @@ lv_status lv_autotune_many(const lv_item* items, int32_t count, const lv_params*
                            void* ws, size_t ws_bytes, int32_t* status, lv_stats* stats, lv_many_tuning* best,
                            void* stream);
 
+/*
+ * Paper precision (Section 5.1.2: float32 edge weights, FP64 hashtable
+ * values, sums and modularity).  The same slack CSR with float32 weights,
+ * FP64 K, Sigma and 2m, and Eq. 2 evaluated as printed in FP64:
+ *     ΔQ(i: d -> c) = (K_{i->c} - K_{i->d}) / m - K_i (K_i + Σ_c - Σ_d) / (2 m^2)
+ * The best community has the largest ΔQ (lowest id on ties) and a vertex
+ * moves only for ΔQ > 0; iterations stop when the movers' ΔQ sum to at most
+ * the tolerance.  LV_ASYNC mode only (the results depend on the order of
+ * floating-point sums, so there is no bit-exact SYNC contract); the
+ * parameters, the swap guard, the sub-round schedule and the pass control
+ * are the integer path's.  Aggregated arc weights are summed in FP64 and
+ * stored as float32.  lv_stats reports passes, iterations, moves and arcs;
+ * iter_gain stays 0 (the ΔQ sums are FP64).  Weights must be finite and
+ * positive (LV_EINVAL).  No 2^31 bound applies.
+ */
+typedef struct {
+  int32_t n;
+  int64_t cap;
+  int64_t* row_start; /* device int64[n + 1] */
+  int32_t* row_len;   /* device int32[n] */
+  int32_t* col;       /* device int32[cap] */
+  float* w;           /* device float32[cap] */
+  double* two_m;      /* device double[1]: total arc weight */
+} lv_graph_f;
+
+typedef struct {
+  const int32_t* u;
+  const int32_t* v;
+  const float* w;
+  int64_t count;
+} lv_edges_f;
+
+typedef struct {
+  int32_t* C;
+  double* K;
+  double* Sigma;
+  int32_t* size; /* optional, as in lv_state */
+} lv_state_f;
+
+size_t lv_workspace_bytes_f(int32_t n, int64_t cap);
+/* As lv_graph_build (capacity bound: lv_graph_capacity_bound). */
+lv_status lv_graph_build_f(lv_graph_f* g, const lv_edges_f* edges, float slack_frac, int32_t slack_min, void* ws,
+                           size_t ws_bytes, void* stream);
+/* As apply_batch (Section 3.4): deletions subtract (an arc whose weight
+ * reaches 0 is removed; LV_ENOEDGE for a missing pair or more weight than
+ * present), insertions add or append; all-or-nothing; *two_m moves by
+ * 2(Σw_ins - Σw_del) in FP64. */
+lv_status apply_batch_f(lv_graph_f* g, const lv_edges_f* del, const lv_edges_f* ins, void* ws, size_t ws_bytes,
+                        void* stream);
+/* Static Louvain (Alg. 4 from singletons) in the paper's precision. */
+lv_status louvain_static_f(const lv_graph_f* g, const lv_params* p, lv_state_f* out, void* ws, size_t ws_bytes,
+                           lv_stats* stats, void* stream);
+/* DF Louvain (Alg. 1, updateWeights Alg. 7 in FP64) after apply_batch_f. */
+lv_status louvain_df_f(const lv_graph_f* g, const lv_edges_f* del, const lv_edges_f* ins, const lv_params* p,
+                       lv_state_f* state, void* ws, size_t ws_bytes, lv_stats* stats, void* stream);
+/* Eq. 1 in FP64.  Waits for the stream. */
+lv_status modularity_f(const lv_graph_f* g, const int32_t* C, double* q_host, void* ws, size_t ws_bytes,
+                       void* stream);
+
 /* Measurement hook.  lv_set_timing(mask) makes every later louvain_* call
  * time each launch of the kernels whose bit k is set in `mask` (k =
  * LV_TIME_*) with a pair of HIP events that the launch itself stamps with

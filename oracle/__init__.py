@@ -173,6 +173,9 @@ def lib():
         L.orcf_louvain.restype = ct.c_int32
         L.orcf_louvain.argtypes = [P, ct.c_int32, ct.POINTER(Params), ct.c_int64, i32p, i32p, f32p, ct.c_int64,
                                    i32p, i32p, f32p, i32p, f64p, f64p, ct.POINTER(StatsF)]
+        L.orcf_arc_count.restype = ct.c_int64
+        L.orcf_arc_count.argtypes = [P]
+        L.orcf_export.argtypes = [P, i64p, i32p, f32p]
         L.orcf_stats_size.restype = ct.c_int32
         assert L.orcf_stats_size() == ct.sizeof(StatsF)
         L.orc_stats_size.restype = ct.c_int32
@@ -361,6 +364,15 @@ class GraphF:
 
     def apply_batch(self, batch) -> int:
         return lib().orcf_apply_batch(self._h, *_batch_args_f(batch))
+
+    def csr(self):
+        """(offsets int64[n+1], col int32[arcs], w float32[arcs]), rows sorted."""
+        a = int(lib().orcf_arc_count(self._h))
+        off = np.zeros(self.n + 1, dtype=np.int64)
+        col = np.zeros(a, dtype=np.int32)
+        w = np.zeros(a, dtype=np.float32)
+        lib().orcf_export(self._h, off, col, w)
+        return off, col, w
 
     def degrees(self) -> np.ndarray:
         K = np.zeros(self.n, dtype=np.float64)

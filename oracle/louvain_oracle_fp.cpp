@@ -427,4 +427,27 @@ int32_t orcf_louvain(void* h, int32_t approach, const ParamsF* P, int64_t nd, co
 
 int32_t orcf_stats_size(void) { return static_cast<int32_t>(sizeof(StatsF)); }
 
+int64_t orcf_arc_count(void* h) {
+  int64_t a = 0;
+  for (const auto& row : static_cast<GraphF*>(h)->adj) a += static_cast<int64_t>(row.size());
+  return a;
+}
+
+// The adjacency as CSR, every row sorted by neighbour.
+void orcf_export(void* h, int64_t* off, int32_t* col, float* w) {
+  const GraphF& g = *static_cast<GraphF*>(h);
+  off[0] = 0;
+  for (int32_t i = 0; i < g.n; ++i) {
+    std::vector<ArcF> row = g.adj[i];
+    std::sort(row.begin(), row.end(), [](const ArcF& a, const ArcF& b) { return a.j < b.j; });
+    int64_t o = off[i];
+    for (const ArcF& a : row) {
+      col[o] = a.j;
+      w[o] = a.w;
+      ++o;
+    }
+    off[i + 1] = o;
+  }
+}
+
 }  // extern "C"

@@ -22,7 +22,7 @@ namespace lv {
 namespace {
 
 thread_local std::string g_last_error;
-lv_tuning g_tuning = {256, 2048, 2560, 1280, 7, 4096, 2, 1 << 20, 1, 128};
+lv_tuning g_tuning = {256, 2048, 2560, 1280, 7, 256, 2, 1 << 20, 1, 128};
 
 lv_status fail(lv_status code, const char* msg) {
   g_last_error = msg;
@@ -208,6 +208,12 @@ lv_status setup_ws(Workspace& ws, const lv_graph* g, void* base, size_t bytes) {
   return LV_OK;
 }
 
+}  // namespace
+
+lv_status lv_fail(lv_status code, const char* msg) { return fail(code, msg); }
+
+namespace {
+
 lv_tuning effective_tuning() {
   lv_tuning t = g_tuning;
   if (t.wave_max_degree <= 0) t.wave_max_degree = 256;
@@ -225,6 +231,12 @@ lv_tuning effective_tuning() {
   if (t.revisit_min_degree < 0) t.revisit_min_degree = 0;
   return t;
 }
+
+}  // namespace
+
+lv_tuning lv_effective_tuning() { return effective_tuning(); }
+
+namespace {
 
 enum Approach { A_STATIC, A_ND, A_DS, A_DF };
 
@@ -303,6 +315,15 @@ std::vector<SubRound> sub_rounds(int32_t mode, int32_t pass, int64_t est_frontie
   }
   return out;
 }
+
+}  // namespace
+
+std::vector<SubRound> lv_sub_rounds(int32_t mode, int32_t pass, int64_t est_frontier, int32_t n,
+                                    const lv_tuning& tu) {
+  return sub_rounds(mode, pass, est_frontier, n, tu);
+}
+
+namespace {
 
 struct DsTables {
   uint64_t* keys;

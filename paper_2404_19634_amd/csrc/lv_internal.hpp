@@ -7,6 +7,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "louvain.h"
 
@@ -490,6 +491,14 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
                   hipStream_t st);
 void launch_apply_moves(const MoveArgs& a, Workspace& ws, bool clear_moved, hipStream_t st);
 void launch_pull_expand(const MoveArgs& a, Workspace& ws, hipStream_t st);
+// Host helpers shared with the paper-precision path (fp.hip): the error
+// message of lv_last_error, the tuning in force, and the sub-rounds of an
+// ASYNC iteration.
+lv_status lv_fail(lv_status code, const char* msg);
+lv_tuning lv_effective_tuning();
+std::vector<SubRound> lv_sub_rounds(int32_t mode, int32_t pass, int64_t est_frontier, int32_t n,
+                                    const lv_tuning& tu);
+
 // First kernel of a louvain call: zeroes the counters and the frontier
 // bitmasks, copies 2m into CTR_TWO_M and flags LV_EEMPTY / LV_EOVERFLOW.
 // The frontier lists start empty and valid, or with `dense_a` the list of

@@ -39,7 +39,8 @@ EXPORTS = ["lv_default_params", "lv_workspace_bytes", "lv_graph_capacity_bound",
            "modularity", "lv_set_tuning", "lv_get_tuning", "lv_set_timing", "lv_last_error",
            "lv_many_scratch_bytes", "lv_many_desc_bytes", "louvain_df_many", "lv_autotune",
            "lv_noalloc_scratch_bytes", "louvain_df_noalloc", "lv_get_many_tuning", "lv_set_many_tuning",
-           "lv_many_size_class", "lv_autotune_many"]
+           "lv_many_size_class", "lv_autotune_many", "lv_workspace_bytes_f", "lv_graph_build_f", "apply_batch_f",
+           "louvain_static_f", "louvain_df_f", "modularity_f"]
 
 
 class LouvainError(RuntimeError):
@@ -167,6 +168,18 @@ def load():
     L.louvain_df_noalloc.argtypes = [GP, EP, EP, PP, SP, STP, P]
     L.lv_set_timing.restype = I32
     L.lv_set_timing.argtypes = [ct.c_uint32]
+    L.lv_workspace_bytes_f.restype = SZ
+    L.lv_workspace_bytes_f.argtypes = [I32, I64]
+    L.lv_graph_build_f.restype = I32
+    L.lv_graph_build_f.argtypes = [GP, EP, ct.c_float, I32, P, SZ, P]
+    L.apply_batch_f.restype = I32
+    L.apply_batch_f.argtypes = [GP, EP, EP, P, SZ, P]
+    L.louvain_static_f.restype = I32
+    L.louvain_static_f.argtypes = [GP, PP, SP, P, SZ, STP, P]
+    L.louvain_df_f.restype = I32
+    L.louvain_df_f.argtypes = [GP, EP, EP, PP, SP, P, SZ, STP, P]
+    L.modularity_f.restype = I32
+    L.modularity_f.argtypes = [GP, P, ct.POINTER(ct.c_double), P, SZ, P]
     L.lv_last_error.restype = ct.c_char_p
     _lib = L
     return L
@@ -208,7 +221,7 @@ DEFAULT_ASYNC_ROUNDS_LOG2 = 7
 
 
 DEFAULT_FUSE_MAX_FRONTIER = 1 << 20
-DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER = 4096
+DEFAULT_ASYNC_ROUNDS_MIN_FRONTIER = 256
 DEFAULT_REVISIT_MIN_DEGREE = 128
 
 
@@ -684,3 +697,138 @@ def modularity(g: Graph, C: torch.Tensor, stream=None) -> float:
 
 
 RUN = {"static": None, "nd": louvain_nd, "ds": louvain_ds, "df": louvain_df}
+
+
+# ---------------------------------------------------------------------------
+# Paper precision (float32 edge weights, FP64 sums; Section 5.1.2).  The C
+# structs have the integer ones' layout, so CGraph / CEdges / CState carry
+# the pointers; only the element types differ.
+# ---------------------------------------------------------------------------
+class EdgesF(Edges):
+    """Undirected edge or update list with float32 weights on the device."""
+
+    def __init__(self, u, v, w, device="cuda"):
+        self.u = _dev_i32(u, device)
+        self.v = _dev_i32(v, device)
+        if isinstance(w, torch.Tensor):
+            self.w = w.to(device=device, dtype=torch.float32).contiguous()
+        else:
+            self.w = torch.from_numpy(np.ascontiguousarray(np.asarray(w, dtype=np.float32))).to(device)
+
+
+@dataclass
+class BatchF:
+    dels: EdgesF
+    ins: EdgesF
+
+    @classmethod
+    def from_host(cls, b, device="cuda"):
+        return cls(EdgesF(b.del_u, b.del_v, b.del_w, device), EdgesF(b.ins_u, b.ins_v, b.ins_w, device))
+
+
+class GraphF(Graph):
+    """Slack-padded CSR with float32 weights and an FP64 total."""
+
+    def __init__(self, n: int, cap: int, device="cuda"):
+        self.device = torch.device(device)
+        self.n = int(n)
+        self.cap = int(cap)
+        self.row_start = torch.zeros(self.n + 1, dtype=torch.int64, device=self.device)
+        self.row_len = torch.zeros(self.n, dtype=torch.int32, device=self.device)
+        self.col = torch.zeros(max(self.cap, 1), dtype=torch.int32, device=self.device)
+        self.w = torch.zeros(max(self.cap, 1), dtype=torch.float32, device=self.device)
+        self.two_m_t = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self._ws = None
+
+    @property
+    def workspace(self) -> torch.Tensor:
+        if self._ws is None:
+            nbytes = int(load().lv_workspace_bytes_f(self.n, self.cap))
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    @property
+    def two_m(self) -> float:
+        return float(self.two_m_t.item())
+
+    @classmethod
+    def build(cls, n, u, v, w, slack_frac=0.1, slack_min=4, device="cuda", stream=None) -> "GraphF":
+        L = load()
+        e = EdgesF(u, v, w, device)
+        cap = int(L.lv_graph_capacity_bound(int(n), e.count, float(slack_frac), int(slack_min)))
+        g = cls(n, cap, device)
+        ce, cg = e.c(), g.c()
+        ws, nb = g.ws_args()
+        _check(L.lv_graph_build_f(ct.byref(cg), ct.byref(ce), float(slack_frac), int(slack_min), ws, nb,
+                                  _stream(stream)))
+        return g
+
+    def relayout(self, *a, **kw):
+        raise NotImplementedError("relayout is offered for the integer graph only")
+
+    def csr_host(self):
+        """(offsets, col, w) on the host with every row sorted by neighbour."""
+        rs = self.row_start.cpu().numpy()
+        rl = self.row_len.cpu().numpy().astype(np.int64)
+        col, w = self.col.cpu().numpy(), self.w.cpu().numpy()
+        off = np.zeros(self.n + 1, dtype=np.int64)
+        off[1:] = np.cumsum(rl)
+        idx = (np.concatenate([np.arange(rs[i], rs[i] + rl[i]) for i in range(self.n)]) if self.n
+               else np.zeros(0, np.int64)).astype(np.int64)
+        rows = np.repeat(np.arange(self.n), rl)
+        c2, w2 = col[idx], w[idx]
+        order = np.lexsort((c2, rows))
+        return off, c2[order], w2[order]
+
+
+@dataclass
+class StateF(State):
+    """C (int32), K and Sigma (FP64), optional member counts."""
+
+    @classmethod
+    def empty(cls, n, device="cuda", with_size=True):
+        return cls(torch.zeros(n, dtype=torch.int32, device=device),
+                   torch.zeros(n, dtype=torch.float64, device=device),
+                   torch.zeros(n, dtype=torch.float64, device=device),
+                   torch.zeros(n, dtype=torch.int32, device=device) if with_size else None)
+
+    @classmethod
+    def from_host(cls, C, K, S, device="cuda"):
+        return cls(torch.from_numpy(np.asarray(C, np.int32).copy()).to(device),
+                   torch.from_numpy(np.asarray(K, np.float64).copy()).to(device),
+                   torch.from_numpy(np.asarray(S, np.float64).copy()).to(device))
+
+    def clone(self) -> "StateF":
+        return StateF(self.C.clone(), self.K.clone(), self.Sigma.clone(),
+                      None if self.size is None else self.size.clone())
+
+
+def apply_batch_f(g: GraphF, b: BatchF, stream=None):
+    L = load()
+    cg, cd, ci = g.c(), b.dels.c(), b.ins.c()
+    ws, nb = g.ws_args()
+    _check(L.apply_batch_f(ct.byref(cg), ct.byref(cd), ct.byref(ci), ws, nb, _stream(stream)))
+
+
+def louvain_static_f(g: GraphF, prm: Params = None, state: StateF = None, stream=None, **kw):
+    L = load()
+    prm = prm if prm is not None else params(**kw)
+    state = state if state is not None else StateF.empty(g.n, g.device)
+    st = Stats()
+    cg, cs = g.c(), state.c()
+    ws, nb = g.ws_args()
+    _check(L.louvain_static_f(ct.byref(cg), ct.byref(prm), ct.byref(cs), ws, nb, ct.byref(st), _stream(stream)))
+    return state, StatsView(st)
+
+
+def louvain_df_f(g: GraphF, b: BatchF, state: StateF, prm: Params = None, stream=None, **kw):
+    return _dynamic("louvain_df_f", g, b, state, prm, stream, kw)
+
+
+def modularity_f(g: GraphF, C: torch.Tensor, stream=None) -> float:
+    L = load()
+    q = ct.c_double(0.0)
+    cg = g.c()
+    ws, nb = g.ws_args()
+    _check(L.modularity_f(ct.byref(cg), _ptr(C), ct.byref(q), ws, nb, _stream(stream)))
+    return float(q.value)
