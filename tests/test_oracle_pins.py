@@ -455,3 +455,48 @@ def test_aggregation_preserves_modularity_and_weight(orc, seed):
         self_w = w[row][col[row] == c]
         sig_in = int(e.w[(C[e.u] == c) & (C[e.v] == c)].sum()) * 2
         assert (self_w.sum() if self_w.size else 0) == sig_in
+
+
+# --------------------------------------------------------------------------
+# Alg. 4: the aggregation stop and the renumbering of communities
+# --------------------------------------------------------------------------
+
+
+def test_aggregation_tolerance_boundary(orc):
+    """Alg. 4 stops when the pass leaves more than τ_agg of the vertices as
+    communities (|communities| / |vertices| > τ_agg); at equality it
+    aggregates.  A ring of 4 cliques of 5 ends pass 0 as its 4 cliques:
+    the ratio is 4/20 = 0.2 exactly."""
+    e = W.ring_of_cliques(4, 5)
+    G = _graph(orc, e)
+    _, _, _, st = G.louvain("static", mode="async", aggregation_tolerance=0.2)
+    assert st["communities"][0] == 4
+    assert st["passes"] == 2  # equal ratio: aggregated, then level 1 runs
+    _, _, _, st = G.louvain("static", mode="async", aggregation_tolerance=float(np.nextafter(0.2, 0.0)))
+    assert st["communities"][0] == 4
+    assert st["passes"] == 1  # ratio above: stopped before aggregating
+
+
+def test_renumbering_is_ascending_old_id(orc):
+    """Communities are renumbered in ascending order of their old ids (the
+    reading the implementations share), worked by hand on 10 vertices:
+    a 5-clique {1..5} (weights 1), an edge 6-7 (weight 1), and a triangle
+    0-8 (1), 0-9 (1), 8-9 (3); 2m = 32.  ASYNC visits ascending ids; the
+    integer gain is 2m (K_i->c - K_i->d) - K_i (Σ_c - Σ_d + K_i).
+
+    Iteration 1: vertex 0 prefers 8 (gain 24, tied with 9, lower id) but
+    the swap guard keeps a singleton from joining a larger singleton; 1
+    likewise stays, 2..5 join 1; 6 stays, 7 joins 6; 8 prefers 9 (gain 80)
+    and is blocked; 9 joins 8 (gain 80).  Iteration 2 (neighbours of
+    movers): 0 joins community 8, now of size 2 (gain 64 - 16 = 48).  So
+    the old labels are 1 for {1..5}, 6 for {6, 7} and 8 for {0, 8, 9}, and
+    ascending old id gives 0, 1 and 2.  Level 1 has three isolated
+    super-vertices: no moves, so the labels are final.  Numbering by first
+    member would instead give {0, 8, 9} the label 0."""
+    pairs = [(a, b, 1) for a in range(1, 6) for b in range(a + 1, 6)] + [(6, 7, 1), (0, 8, 1), (0, 9, 1),
+                                                                        (8, 9, 3)]
+    u, v, w = (np.array(x, dtype=np.int32) for x in zip(*pairs))
+    G = _graph(orc, W.Edges(10, u, v, w))
+    C, _, _, st = G.louvain("static", mode="async")
+    assert C.tolist() == [2, 0, 0, 0, 0, 0, 1, 1, 2, 2]
+    assert st["passes"] == 2 and st["communities"][0] == 3
