@@ -250,6 +250,20 @@ lv_status louvain_df(const lv_graph* g, const lv_edges* del, const lv_edges* ins
                      lv_state* state, void* ws, size_t ws_bytes, lv_stats* stats, void* stream);
 
 /*
+ * One dynamic update (Section 3.4, then Alg. 1): apply_batch(g, del, ins)
+ * followed by louvain_df on the edited graph, enqueued together so that the
+ * host waits once, at the end of the first local-moving iteration, instead
+ * of also after the edit.  Same arguments, results and statistics as the two
+ * calls in sequence.  Errors of the edit (LV_EINVAL, LV_ENOEDGE, LV_ENOSLACK,
+ * LV_EOVERFLOW) are returned by this call with graph and state untouched;
+ * the other errors are louvain_df's.  With p->recompute_weights = 1 the two
+ * calls are made one after the other (K and Sigma are then read from the
+ * edited rows).
+ */
+lv_status louvain_df_apply(lv_graph* g, const lv_edges* del, const lv_edges* ins, const lv_params* p,
+                           lv_state* state, void* ws, size_t ws_bytes, lv_stats* stats, void* stream);
+
+/*
  * louvain_df_noalloc -- louvain_df for callers that cannot allocate device
  * or host memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc): the same computation and results, with

@@ -155,9 +155,9 @@ __global__ void __launch_bounds__(kBlock) k_validate(Upd U, int32_t n, BatchScra
   }
   si = block_sum(si, lds);
   sd = block_sum(sd, lds);
-  if (threadIdx.x == 0) {
-    if (si) atomic_add_i64(&ctr[CTR_AUX2], si);
-    if (sd) atomic_add_i64(&ctr[CTR_AUX3], sd);
+  if (threadIdx.x == 0) {  // (replicated counters: one address per workgroup would serialise)
+    if (si) stat_add(ctr + CTR_STATS0, ST_W_INS, si);
+    if (sd) stat_add(ctr + CTR_STATS0, ST_W_DEL, sd);
   }
 }
 
@@ -177,39 +177,60 @@ __global__ void k_rank(Upd U, BatchScratch b) {
 }
 
 // per touched row: its length, its range in the partner list, its chunks
-// (one packed reservation, chunks << 32 | partners, per workgroup).
+// (one packed reservation, chunks << 32 | partners, per workgroup and pass
+// of kRowsPer rows per thread: the reservations all hit one counter).
+constexpr int kRowsPer = 4;
 __global__ void __launch_bounds__(kBlock) k_rows(const int64_t* __restrict__ row_start,
                                                  const int32_t* __restrict__ row_len, BatchScratch b,
                                                  int64_t* __restrict__ ctr) {
   __shared__ int64_t lds[kBlock / kWave + 1];
-  for (int64_t r0 = blockIdx.x * static_cast<int64_t>(kBlock); r0 < b.dirs;
-       r0 += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const int64_t r = r0 + threadIdx.x;
-    const int32_t a = r < b.dirs ? b.row_of[r] : -1;
-    int32_t len = 0, cnt = 0;
-    if (a >= 0) {
-      len = row_len[a];
-      cnt = b.r_cnt[r];
-      b.r_len[r] = len;
+  const int64_t per_pass = static_cast<int64_t>(kBlock) * kRowsPer;
+  for (int64_t r0 = blockIdx.x * per_pass; r0 < b.dirs; r0 += static_cast<int64_t>(gridDim.x) * per_pass) {
+    int32_t a[kRowsPer], len[kRowsPer], cnt[kRowsPer];
+    int64_t rs[kRowsPer];
+    int64_t packed = 0;
+#pragma unroll
+    for (int j = 0; j < kRowsPer; ++j) {
+      const int64_t r = r0 + static_cast<int64_t>(j) * kBlock + threadIdx.x;
+      a[j] = r < b.dirs ? b.row_of[r] : -1;
     }
-    const int64_t nch = (len + kChunk - 1) / kChunk;
-    const int64_t at = block_reserve(a >= 0 ? ((nch << 32) | cnt) : 0, &ctr[CTR_B_RESV], lds);
-    if (a >= 0) {
+#pragma unroll
+    for (int j = 0; j < kRowsPer; ++j) {  // (all loads issued together)
+      const int64_t r = r0 + static_cast<int64_t>(j) * kBlock + threadIdx.x;
+      const bool on = a[j] >= 0;
+      len[j] = on ? row_len[a[j]] : 0;
+      cnt[j] = on ? b.r_cnt[r] : 0;
+      rs[j] = on ? row_start[a[j]] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kRowsPer; ++j) {
+      if (a[j] < 0) continue;
+      const int64_t r = r0 + static_cast<int64_t>(j) * kBlock + threadIdx.x;
+      b.r_len[r] = len[j];
+      packed += ((static_cast<int64_t>(len[j]) + kChunk - 1) / kChunk << 32) | cnt[j];
+    }
+    int64_t at = block_reserve(packed, &ctr[CTR_B_RESV], lds);
+#pragma unroll
+    for (int j = 0; j < kRowsPer; ++j) {
+      if (a[j] < 0) continue;
+      const int64_t r = r0 + static_cast<int64_t>(j) * kBlock + threadIdx.x;
+      const int64_t nch = (static_cast<int64_t>(len[j]) + kChunk - 1) / kChunk;
       const int32_t pbase = static_cast<int32_t>(at & 0xffffffffll);
       const int64_t cbase = at >> 32;
-      const int64_t s = row_start[a];
+      const int64_t s = rs[j];
       b.r_pbase[r] = pbase;
-      for (int64_t j = 0; j < nch; ++j) {
+      for (int64_t q = 0; q < nch; ++q) {
         BatchScratch::Chunk c;
         c.s = s;
-        c.a = a;
-        c.off = static_cast<int32_t>(j * kChunk);
-        c.end = static_cast<int32_t>(min(static_cast<int64_t>(len), (j + 1) * kChunk));
-        c.cnt = cnt;
+        c.a = a[j];
+        c.off = static_cast<int32_t>(q * kChunk);
+        c.end = static_cast<int32_t>(min(static_cast<int64_t>(len[j]), (q + 1) * kChunk));
+        c.cnt = cnt[j];
         c.pbase = pbase;
         c.pad = 0;
-        b.chunk[cbase + j] = c;
+        b.chunk[cbase + q] = c;
       }
+      at += (nch << 32) | cnt[j];
     }
   }
 }
@@ -307,7 +328,7 @@ __global__ void k_check(Upd U, const int32_t* __restrict__ wt, BatchScratch b, i
 __global__ void k_capacity(const int64_t* __restrict__ row_start, const int64_t* __restrict__ two_m, BatchScratch b,
                            int64_t* __restrict__ ctr) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const int64_t nm = *two_m + 2 * ctr[CTR_AUX2] - 2 * ctr[CTR_AUX3];
+    const int64_t nm = *two_m + 2 * stat_total(ctr + CTR_STATS0, ST_W_INS) - 2 * stat_total(ctr + CTR_STATS0, ST_W_DEL);
     if (nm >= (int64_t(1) << 31)) set_error(ctr, LV_EOVERFLOW);
   }
   for (int64_t r = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; r < b.dirs;
@@ -324,7 +345,8 @@ __global__ void k_capacity(const int64_t* __restrict__ row_start, const int64_t*
 __global__ void k_apply(Upd U, int32_t* __restrict__ wt, int64_t* __restrict__ two_m, BatchScratch b,
                         const int64_t* __restrict__ ctr) {
   if (failed(ctr)) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *two_m += 2 * ctr[CTR_AUX2] - 2 * ctr[CTR_AUX3];
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    *two_m += 2 * stat_total(ctr + CTR_STATS0, ST_W_INS) - 2 * stat_total(ctr + CTR_STATS0, ST_W_DEL);
   const int64_t dirs = 2 * (U.nd + U.ni);
   for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < dirs;
        e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -438,7 +460,8 @@ void launch_batch_phase1(const lv_graph& g, const lv_edges& del, const lv_edges&
                      dim3(kBlock), 0, st, b, words, ctr);
   hipLaunchKernelGGL(k_validate, dim3(grid_for(total, kBlock, 256)), dim3(kBlock), 0, st, U, g.n, b, ctr);
   hipLaunchKernelGGL(k_rank, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, U, b);
-  hipLaunchKernelGGL(k_rows, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, g.row_start, g.row_len, b, ctr);
+  hipLaunchKernelGGL(k_rows, dim3(grid_for(dirs, kBlock * kRowsPer, 4096)), dim3(kBlock), 0, st, g.row_start,
+                     g.row_len, b, ctr);
   hipLaunchKernelGGL(k_place, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, U, b);
   // chunks: one per touched row plus one per kChunk arcs of long rows; the
   // grid covers a few per touched row and strides over the rest

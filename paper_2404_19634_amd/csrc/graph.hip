@@ -116,7 +116,9 @@ __global__ void k_relayout_copy(const int64_t* __restrict__ s_start, const int32
 //    flat sequence, 256 consecutive arcs per step (four loads in flight per
 //    lane); an LDS map gives each flat position's row, and LDS atomics add
 //    each arc to its row's sum;
-//  - rows up to kMidMax arcs are listed and summed by one wavefront each;
+//  - rows up to kMidMax arcs are summed by the same wavefront right after,
+//    one at a time, 256 arcs per step (a list of them would take one device
+//    atomic per wavefront on a single counter, and those serialise);
 //  - longer rows are listed in chunks of kChunk arcs, one wavefront per
 //    chunk, whose partial sums are added atomically (K and Sigma of such a
 //    row are zeroed by the first kernel).
@@ -131,16 +133,39 @@ struct RowSumOut {
   int64_t* Sigma;  // = K (static start), or null
   int32_t* Cinit;  // identity, or null
   int32_t* size;   // all ones, or null
-  int32_t* mid;    // rows of the middle class
   int32_t* lrow;   // chunks of long rows: row, first arc
   int32_t* loff;
-  int64_t* ctr;    // CTR_AUX0: listed middle rows, CTR_AUX1: listed chunks
+  int64_t* ctr;    // CTR_AUX1: listed chunks
 };
 
 __device__ __forceinline__ void wave_barrier_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum of arcs [a, b) of the row starting at s, over the wavefront, 256 arcs
+// per step; with C, adds the weight of arcs into community ci to *intra.
+__device__ __forceinline__ int64_t wave_row_sum(const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
+                                                const int32_t* __restrict__ C, int64_t s, int32_t a, int32_t b,
+                                                int32_t ci, int64_t* intra) {
+  const int lane = lane_id();
+  int64_t acc = 0;
+  for (int32_t k0 = a + lane; k0 < b; k0 += kWave * kRowUnroll) {
+    int32_t x[kRowUnroll], j[kRowUnroll];
+#pragma unroll
+    for (int q = 0; q < kRowUnroll; ++q) {
+      const int32_t k = k0 + q * kWave;
+      x[q] = k < b ? wt[s + k] : 0;
+      j[q] = (C && k < b) ? col[s + k] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kRowUnroll; ++q) {
+      acc += x[q];
+      if (C && j[q] >= 0 && C[j[q]] == ci) *intra += x[q];
+    }
+  }
+  return wave_sum_i64(acc);
 }
 
 __global__ void __launch_bounds__(kBlock) k_rows_flat(const int64_t* __restrict__ row_start,
@@ -162,13 +187,12 @@ __global__ void __launch_bounds__(kBlock) k_rows_flat(const int64_t* __restrict_
        r0 += nwaves * kWave) {
     const int64_t i = r0 + lane;
     const bool valid = i < n;
-    int32_t len = valid ? row_len[i] : 0;
+    const int32_t row_len_l = valid ? row_len[i] : 0;
+    int32_t len = row_len_l;
     const int64_t st = valid ? row_start[i] : 0;
     const int32_t ci = (C && valid) ? C[i] : 0;
     const bool is_mid = len > kFlatMax && len <= kMidMax;
     const bool is_long = len > kMidMax;
-    const int64_t ms = wave_append(is_mid, &o.ctr[CTR_AUX0]);
-    if (is_mid) o.mid[ms] = static_cast<int32_t>(i);
     {  // chunks of long rows, reserved together by the wavefront
       const int32_t nch = is_long ? (len + kChunk - 1) / kChunk : 0;
       int32_t incl = nch;
@@ -247,54 +271,21 @@ __global__ void __launch_bounds__(kBlock) k_rows_flat(const int64_t* __restrict_
       if (o.Sigma) o.Sigma[i] = sum;
     }
     wave_barrier_lds();
+    // the middle rows of the 64, one after the other over the wavefront
+    for (uint64_t mm = __ballot(is_mid); mm; mm &= mm - 1) {
+      const int l = __ffsll(static_cast<unsigned long long>(mm)) - 1;
+      const int64_t rs = __shfl(st, l);
+      const int32_t rl = __shfl(row_len_l, l);
+      const int32_t rc = __shfl(ci, l);
+      const int64_t sum = wave_row_sum(col, wt, C, rs, 0, rl, rc, &intra);
+      if (lane == l) {
+        o.K[i] = sum;
+        if (o.Sigma) o.Sigma[i] = sum;
+      }
+    }
   }
   intra = wave_sum_i64(intra);
   if (lane == 0 && C && intra) stat_add(o.ctr + CTR_STATS0, ST_INTRA, intra);
-}
-
-// Sum of arcs [a, b) of the row starting at s, over the wavefront, 256 arcs
-// per step; with C, adds the weight of arcs into community ci to *intra.
-__device__ __forceinline__ int64_t wave_row_sum(const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
-                                                const int32_t* __restrict__ C, int64_t s, int32_t a, int32_t b,
-                                                int32_t ci, int64_t* intra) {
-  const int lane = lane_id();
-  int64_t acc = 0;
-  for (int32_t k0 = a + lane; k0 < b; k0 += kWave * kRowUnroll) {
-    int32_t x[kRowUnroll], j[kRowUnroll];
-#pragma unroll
-    for (int q = 0; q < kRowUnroll; ++q) {
-      const int32_t k = k0 + q * kWave;
-      x[q] = k < b ? wt[s + k] : 0;
-      j[q] = (C && k < b) ? col[s + k] : -1;
-    }
-#pragma unroll
-    for (int q = 0; q < kRowUnroll; ++q) {
-      acc += x[q];
-      if (C && j[q] >= 0 && C[j[q]] == ci) *intra += x[q];
-    }
-  }
-  return wave_sum_i64(acc);
-}
-
-__global__ void __launch_bounds__(kBlock) k_rows_mid(const int64_t* __restrict__ row_start,
-                                                    const int32_t* __restrict__ row_len,
-                                                    const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
-                                                    const int32_t* __restrict__ C, RowSumOut o) {
-  const int64_t count = o.ctr[CTR_AUX0];
-  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
-  int64_t intra = 0;
-  for (int64_t idx = blockIdx.x * static_cast<int64_t>(kWavesPerBlock) + threadIdx.x / kWave; idx < count;
-       idx += nwaves) {
-    const int32_t i = o.mid[idx];
-    const int32_t ci = C ? C[i] : 0;
-    const int64_t sum = wave_row_sum(col, wt, C, row_start[i], 0, row_len[i], ci, &intra);
-    if (lane_id() == 0) {
-      o.K[i] = sum;
-      if (o.Sigma) o.Sigma[i] = sum;
-    }
-  }
-  intra = wave_sum_i64(intra);
-  if (lane_id() == 0 && C && intra) stat_add(o.ctr + CTR_STATS0, ST_INTRA, intra);
 }
 
 __global__ void __launch_bounds__(kBlock) k_rows_chunks(const int64_t* __restrict__ row_start,
@@ -391,24 +382,22 @@ void launch_relayout_copy(const lv_graph& src, const int64_t* dst_start, int32_t
 
 // K[i] = row sum (and Sigma = K, C = identity, size = 1 when given); with
 // C_mod given, the weight of intra-community arcs is added to statistic
-// ST_INTRA of the first statistics set.  Uses ctr[CTR_AUX0], ctr[CTR_AUX1],
-// one n-entry bin list for the middle rows and the two unit lists (n +
-// cap/2048 + 64 entries each, more than the chunks of cap arcs in rows of
-// over 4096 arcs can take) for the chunks of long rows.
+// ST_INTRA of the first statistics set.  Uses ctr[CTR_AUX1] and the two
+// unit lists (n + cap/2048 + 64 entries each, more than the chunks of cap
+// arcs in rows of over 4096 arcs can take) for the chunks of long rows.
 void launch_row_sums(const LevelGraph& g, const int32_t* C_mod, int64_t* K, int64_t* Sigma, int32_t* Cinit,
                      int32_t* size, Workspace& ws, hipStream_t st) {
   if (g.n == 0) return;
-  static_assert(CTR_AUX1 == CTR_AUX0 + kCtrLine, "the two list counters are adjacent lines");
   static_assert(kChunk >= 2048, "the unit lists hold cap / 2048 chunks");
-  (void)hipMemsetAsync(ws.ctr + CTR_AUX0, 0, sizeof(int64_t) * 2 * kCtrLine, st);
-  RowSumOut o{K, Sigma, Cinit, size, ws.bins[BIN_WAVE], ws.u_ins_b, ws.u_emit_b, ws.ctr};
+  (void)hipMemsetAsync(ws.ctr + CTR_AUX1, 0, sizeof(int64_t) * kCtrLine, st);
+  RowSumOut o{K, Sigma, Cinit, size, ws.u_ins_b, ws.u_emit_b, ws.ctr};
   const int64_t waves = (static_cast<int64_t>(g.n) + kWave - 1) / kWave;
-  const int64_t blocks = std::min<int64_t>((waves + kWavesPerBlock - 1) / kWavesPerBlock, 65535);
+  // (a grid-stride loop: each wavefront ends with one statistics atomic)
+  const int64_t blocks = std::min<int64_t>((waves + kWavesPerBlock - 1) / kWavesPerBlock, 8192);
   hipLaunchKernelGGL(k_rows_flat, dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, st, g.row_start, g.row_len,
                      g.col, g.w, g.n, C_mod, o);
-  // (grids of many waves, so the memory latencies of the rows overlap; the
-  // waves without a row or chunk return at once)
-  hipLaunchKernelGGL(k_rows_mid, dim3(8192), dim3(kBlock), 0, st, g.row_start, g.row_len, g.col, g.w, C_mod, o);
+  // (many waves, so the memory latencies of the chunks overlap; the waves
+  // without a chunk return at once)
   hipLaunchKernelGGL(k_rows_chunks, dim3(8192), dim3(kBlock), 0, st, g.row_start, g.row_len, g.col, g.w, C_mod, o);
 }
 

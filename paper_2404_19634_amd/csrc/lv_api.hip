@@ -181,6 +181,18 @@ lv_status device_error(int64_t code, const char* phase) {
   return fail(static_cast<lv_status>(code), msg);
 }
 
+// Errors of a batch edit (Section 3.4's update refused as a whole), or of
+// the first kernel of the call that follows it.
+lv_status batch_error(int64_t code) {
+  switch (code) {
+    case LV_ENOEDGE: return fail(LV_ENOEDGE, "a deletion names a missing edge or too much weight");
+    case LV_ENOSLACK: return fail(LV_ENOSLACK, "a row lacks free capacity (relayout with more slack)");
+    case LV_EOVERFLOW: return fail(LV_EOVERFLOW, "total arc weight would reach 2^31");
+    case LV_EINVAL: return fail(LV_EINVAL, "bad id, self-loop, non-positive weight or repeated pair");
+    default: return device_error(code, "batch edit");
+  }
+}
+
 lv_status read_i64(int64_t* host, const int64_t* dev, hipStream_t st) {
   LV_HIP(hipMemcpyAsync(host, dev, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   LV_HIP(hipStreamSynchronize(st));
@@ -383,9 +395,11 @@ float ms_between(hipEvent_t* ev, int a, int b) {
 // resume_li > 0: the local-moving iterations of pass 0 already ran (the
 // batched kernel did them, with that l_i); the call goes on from the end of
 // pass 0 with the state as it is (Alg. 4: renumber, aggregate, passes >= 1).
+// after_batch: a batch edit of the same batch was enqueued just before on
+// the stream, unread; its error (if any) is reported by this call.
 lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const lv_edges* ins,
                       const lv_params* p, lv_state* state, void* wsp, size_t ws_bytes, lv_stats* stats,
-                      void* stream, int32_t resume_li = 0) {
+                      void* stream, int32_t resume_li = 0, bool after_batch = false) {
   const auto t_start = std::chrono::steady_clock::now();
   if (!graph_ok(g)) return fail(LV_EINVAL, "invalid graph");
   if (!params_ok(p)) return fail(LV_EINVAL, "invalid parameters");
@@ -417,7 +431,7 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
   // fr_a's list is kept for DF's marking (and a resumed pass); the other
   // approaches fill the bitmask whole
   const bool dense_start = resume_li == 0 && ap != A_DF;
-  launch_call_begin(ws, g->two_m, dense_start, st);
+  launch_call_begin(ws, g->two_m, dense_start, after_batch, st);
   LevelGraph L0;
   L0.n = N;
   L0.row_start = g->row_start;
@@ -563,7 +577,8 @@ lv_status run_louvain(Approach ap, const lv_graph* g, const lv_edges* del, const
       std::swap(cur_fl, next_fl);
       LV_HIP(record(ev, 3, st));
       if ((s = read_counters(host, ws, CTR_ROUND0, st))) return s;
-      if (host[CTR_ERR]) return device_error(host[CTR_ERR], "local-moving");
+      if (host[CTR_ERR])
+        return after_batch ? batch_error(host[CTR_ERR]) : device_error(host[CTR_ERR], "local-moving");
       two_m = host[CTR_TWO_M];
       const int64_t* hs = host + CTR_STATS0 + (iter_seq & 1) * kStatSet;
       const int64_t movers = stat(hs, ST_MOVERS), gain = stat(hs, ST_GAIN);
@@ -957,15 +972,11 @@ lv_status lv_graph_relayout(const lv_graph* src, lv_graph* dst, float slack_frac
   return LV_OK;
 }
 
-lv_status apply_batch(lv_graph* g, const lv_edges* del, const lv_edges* ins, void* wsp, size_t ws_bytes,
-                      void* stream) {
-  if (!graph_ok(g) || !edges_ok(del) || !edges_ok(ins)) return fail(LV_EINVAL, "invalid graph or batch");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  Workspace ws;
-  lv_status s = setup_ws(ws, g, wsp, ws_bytes);
-  if (s) return s;
-  int64_t* host = nullptr;
-  if ((s = pinned(&host))) return s;
+namespace {
+
+// Enqueues the whole batch edit (both phases; phase 2 is gated on the
+// device by the error slot) without waiting.  Host-side failures only.
+lv_status enqueue_batch(lv_graph* g, const lv_edges* del, const lv_edges* ins, Workspace& ws, hipStream_t st) {
   if (del->count + ins->count == 0) return LV_OK;
   const int64_t U = del->count + ins->count, E = 2 * U;
   BatchScratch b;
@@ -1006,15 +1017,24 @@ lv_status apply_batch(lv_graph* g, const lv_edges* del, const lv_edges* ins, voi
   launch_batch_phase1(*g, *del, *ins, b, ws.words, ws.ctr, st);
   launch_batch_phase2(*g, *del, *ins, b, ws.ctr, st);
   LV_CHECK_LAUNCH();
+  return LV_OK;
+}
+
+}  // namespace
+
+lv_status apply_batch(lv_graph* g, const lv_edges* del, const lv_edges* ins, void* wsp, size_t ws_bytes,
+                      void* stream) {
+  if (!graph_ok(g) || !edges_ok(del) || !edges_ok(ins)) return fail(LV_EINVAL, "invalid graph or batch");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Workspace ws;
+  lv_status s = setup_ws(ws, g, wsp, ws_bytes);
+  if (s) return s;
+  int64_t* host = nullptr;
+  if ((s = pinned(&host))) return s;
+  if (del->count + ins->count == 0) return LV_OK;
+  if ((s = enqueue_batch(g, del, ins, ws, st))) return s;
   if ((s = read_counters(host, ws, CTR_COUNT, st))) return s;
-  if (host[CTR_ERR]) {
-    const lv_status code = static_cast<lv_status>(host[CTR_ERR]);
-    const char* msg = code == LV_ENOEDGE    ? "a deletion names a missing edge or too much weight"
-                      : code == LV_ENOSLACK ? "a row lacks free capacity (relayout with more slack)"
-                      : code == LV_EOVERFLOW ? "total arc weight would reach 2^31"
-                                             : "bad id, self-loop, non-positive weight or repeated pair";
-    return fail(code, msg);
-  }
+  if (host[CTR_ERR]) return batch_error(host[CTR_ERR]);
   return LV_OK;
 }
 
@@ -1036,6 +1056,22 @@ lv_status louvain_ds(const lv_graph* g, const lv_edges* del, const lv_edges* ins
 lv_status louvain_df(const lv_graph* g, const lv_edges* del, const lv_edges* ins, const lv_params* p,
                      lv_state* state, void* ws, size_t ws_bytes, lv_stats* stats, void* stream) {
   return run_louvain(A_DF, g, del, ins, p, state, ws, ws_bytes, stats, stream);
+}
+
+lv_status louvain_df_apply(lv_graph* g, const lv_edges* del, const lv_edges* ins, const lv_params* p,
+                           lv_state* state, void* wsp, size_t ws_bytes, lv_stats* stats, void* stream) {
+  if (!graph_ok(g) || !edges_ok(del) || !edges_ok(ins)) return fail(LV_EINVAL, "invalid graph or batch");
+  if (!params_ok(p)) return fail(LV_EINVAL, "invalid parameters");
+  if (!state || !state->C || !state->K || !state->Sigma) return fail(LV_EINVAL, "invalid state");
+  if (p->recompute_weights) {  // K and Sigma come from the edited rows: the edit must be complete
+    const lv_status s = apply_batch(g, del, ins, wsp, ws_bytes, stream);
+    return s ? s : run_louvain(A_DF, g, del, ins, p, state, wsp, ws_bytes, stats, stream);
+  }
+  Workspace ws;
+  lv_status s = setup_ws(ws, g, wsp, ws_bytes);
+  if (s) return s;
+  if ((s = enqueue_batch(g, del, ins, ws, static_cast<hipStream_t>(stream)))) return s;
+  return run_louvain(A_DF, g, del, ins, p, state, wsp, ws_bytes, stats, stream, 0, true);
 }
 
 size_t lv_many_scratch_bytes(int32_t n, int32_t max_updates) { return many_scratch_bytes(n, max_updates); }

@@ -100,7 +100,9 @@ enum Stat {
   ST_INTRA,       // modularity: weight of arcs inside communities
   ST_BIN_V0,      // .. + NBINS - 1: vertices processed per bin
   ST_BIN_A0 = ST_BIN_V0 + 7,  // .. + NBINS - 1: arcs scanned per bin
-  NSTATS = ST_BIN_A0 + 7
+  ST_W_INS = ST_BIN_A0 + 7,   // batch edit (first set): total weight of the insertions
+  ST_W_DEL,                   // ... and of the deletions
+  NSTATS
 };
 static_assert(NSTATS <= kStatStride, "statistics exceed a replica");
 constexpr int rc_bin(int b) { return RC_BIN0 + b * kCtrLine; }
@@ -196,6 +198,13 @@ __device__ __forceinline__ void stat_add(int64_t* sc, int st, int64_t v) {
             static_cast<unsigned long long>(v));
 }
 
+// A statistic of one set summed over its replicas (on the device).
+__device__ __forceinline__ int64_t stat_total(const int64_t* sc, int st) {
+  int64_t v = 0;
+  for (int r = 0; r < kStatReplicas; ++r) v += sc[r * kStatStride + st];
+  return v;
+}
+
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
   for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s);
   return v;
@@ -275,6 +284,43 @@ __device__ __forceinline__ void front_mark(uint32_t* bm, const FrontList& F, int
   const int r = static_cast<int>(blockIdx.x % kFlRegions);
   const int64_t pos = wave_append(fresh, &F.cnt[r * kCtrLine]);
   if (fresh && pos < F.capr) F.list[r * F.capr + pos] = i;
+}
+
+// front_mark of N vertices per lane: the N bitmask atomics are issued
+// together (one memory round trip, not N), and one counter atomic per
+// wavefront reserves the list slots of all fresh vertices.
+template <int N>
+__device__ __forceinline__ void front_mark_n(uint32_t* bm, const FrontList& F, const int32_t (&v)[N],
+                                             const bool (&pred)[N]) {
+  uint32_t old[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) old[q] = pred[q] ? atomicOr(&bm[v[q] >> 5], 1u << (v[q] & 31)) : ~0u;
+  if (!F.list) return;
+  uint64_t mask[N];
+  int64_t total = 0;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    const bool fresh = pred[q] && !((old[q] >> (v[q] & 31)) & 1u);
+    mask[q] = __ballot(fresh);
+    total += __popcll(mask[q]);
+  }
+  if (total == 0) return;
+  const int lane = lane_id();
+  const int r = static_cast<int>(blockIdx.x % kFlRegions);
+  int64_t base = 0;
+  if (lane == 0)
+    base = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&F.cnt[r * kCtrLine]),
+                                          static_cast<unsigned long long>(total)));
+  base = __shfl(base, 0);
+  const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    if ((mask[q] >> lane) & 1ull) {
+      const int64_t pos = base + __popcll(mask[q] & below);
+      if (pos < F.capr) F.list[r * F.capr + pos] = v[q];
+    }
+    base += __popcll(mask[q]);
+  }
 }
 
 // Hash of a community id into [0, size) for the open-addressing tables.
@@ -503,7 +549,7 @@ std::vector<SubRound> lv_sub_rounds(int32_t mode, int32_t pass, int64_t est_fron
 // bitmasks, copies 2m into CTR_TWO_M and flags LV_EEMPTY / LV_EOVERFLOW.
 // The frontier lists start empty and valid, or with `dense_a` the list of
 // fr_a starts invalid (its bitmask is about to be filled without listing).
-void launch_call_begin(Workspace& ws, const int64_t* two_m, bool dense_a, hipStream_t st);
+void launch_call_begin(Workspace& ws, const int64_t* two_m, bool dense_a, bool keep_err, hipStream_t st);
 FrontList front_list(const Workspace& ws, int k);
 // Marks a frontier list invalid (its bitmask was filled without listing).
 void launch_list_invalid(const FrontList& f, hipStream_t st);

@@ -78,12 +78,16 @@ __global__ void __launch_bounds__(kBlock) k_update_weights(const int32_t* __rest
     cb[it] = ok[it] ? C[eb[it]] : 0;
   }
   if (fr) {  // deletion inside a community, or insertion across (every lane takes part in the appends)
+    int32_t vs[2 * kUwItems];
+    bool hits[2 * kUwItems];
 #pragma unroll
     for (int it = 0; it < kUwItems; ++it) {
       const bool hit = ok[it] && (ca[it] == cb[it]) == del[it];
-      front_mark(fr, fl, ea[it], hit);
-      front_mark(fr, fl, eb[it], hit);
+      vs[2 * it] = ea[it];
+      vs[2 * it + 1] = eb[it];
+      hits[2 * it] = hits[2 * it + 1] = hit;
     }
+    front_mark_n(fr, fl, vs, hits);
   }
 #pragma unroll
   for (int it = 0; it < kUwItems; ++it) {

@@ -287,21 +287,32 @@ __device__ __forceinline__ int64_t hub_slots(int32_t deg) {
   return hub_part(deg) ? base + (hub_units(deg) * (hub_cunits(deg) + 1) + 1) / 2 : base;
 }
 
-// Writes a hub row's table offset and unit descriptors at the given bases.
-__device__ __forceinline__ void hub_write(const HubOut& H, int64_t pos, int32_t deg, int64_t off, int64_t bu,
-                                         int64_t bc) {
-  const int64_t nu = hub_units(deg), nc = hub_cunits(deg);
+// A hub row's table offset and first clear / decide unit.
+__device__ __forceinline__ void hub_head(const HubOut& H, int64_t pos, int32_t deg, int64_t off, int64_t bc) {
   H.off[pos] = off;
   H.cbase[pos] = bc;
-  H.cnum[pos] = static_cast<int32_t>(nc);
-  for (int64_t u = 0; u < nu; ++u) {
+  H.cnum[pos] = static_cast<int32_t>(hub_cunits(deg));
+}
+
+// Its unit descriptors at the given bases, entries t, t + stride, ... (a
+// mega-hub has thousands: the workgroup writes them together).
+__device__ __forceinline__ void hub_units_write(const HubOut& H, int64_t pos, int32_t deg, int64_t bu, int64_t bc,
+                                               int t, int stride) {
+  const int64_t nu = hub_units(deg), nc = hub_cunits(deg);
+  for (int64_t u = t; u < nu; u += stride) {
     H.u_b[bu + u] = static_cast<int32_t>(pos);
     H.u_a[bu + u] = u * kHubUnitArcs;
   }
-  for (int64_t u = 0; u < nc; ++u) {
+  for (int64_t u = t; u < nc; u += stride) {
     H.c_b[bc + u] = static_cast<int32_t>(pos);
     H.c_s[bc + u] = u * kHubClearSlots;
   }
+}
+
+__device__ __forceinline__ void hub_write(const HubOut& H, int64_t pos, int32_t deg, int64_t off, int64_t bu,
+                                         int64_t bc) {
+  hub_head(H, pos, deg, off, bc);
+  hub_units_write(H, pos, deg, bu, bc, 0, 1);
 }
 
 // Reserves the hub row's global table (2*deg slots) and its units alone
@@ -319,9 +330,12 @@ __device__ __forceinline__ void hub_setup(const HubOut& H, int64_t pos, int32_t 
 // --------------------------------------------------------------------------
 // First kernel of a call: counters, frontier bitmasks, 2m.
 // --------------------------------------------------------------------------
+// keep_err: the call follows a batch edit enqueued on the same stream; its
+// error (the edit was refused) stays in the error slot, so every later
+// kernel leaves the state alone.
 __global__ void k_call_begin(int64_t* __restrict__ ctr, uint32_t* __restrict__ fr_a, uint32_t* __restrict__ fr_b,
                              uint32_t* __restrict__ ever, uint32_t* __restrict__ moved, int64_t words,
-                             const int64_t* __restrict__ two_m, int32_t dense_a) {
+                             const int64_t* __restrict__ two_m, int32_t dense_a, int32_t keep_err) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   const int64_t t0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   for (int64_t k = t0; k < words; k += stride) {
@@ -336,19 +350,22 @@ __global__ void k_call_begin(int64_t* __restrict__ ctr, uint32_t* __restrict__ f
     if (k == CTR_FL0 && dense_a) v = kFlInvalid;
     if (k == CTR_ERR) {
       const int64_t t = *two_m;
-      v = t <= 0 ? LV_EEMPTY : (t >= kTwoMLimit ? LV_EOVERFLOW : 0);
+      const int64_t prev = keep_err ? ctr[k] : 0;
+      v = prev ? prev : (t <= 0 ? LV_EEMPTY : (t >= kTwoMLimit ? LV_EOVERFLOW : 0));
     }
     ctr[k] = v;
   }
 }
 
 constexpr int kBinStats = 3 + 2 * NBINS;  // processed, arcs, affected, per-bin vertices and arcs
-constexpr int kBinHubs = 64;              // hubs a workgroup reserves together per pass
+constexpr int kBinPer = 4;                // items (words or listed vertices) per thread per pass
+constexpr int kBinHubs = 2 * kBlock;      // hubs a workgroup reserves together per pass
 
 // --------------------------------------------------------------------------
-// Frontier -> degree bins.  One thread per 32-vertex bitmask word.  Each
-// workgroup counts its vertices per bin in LDS, reserves one range per bin
-// with a single global atomic, then places them.  Block 0 zeroes the other
+// Frontier -> degree bins.  Each thread takes kBinPer 32-vertex bitmask
+// words (or kBinPer listed vertices) per pass.  Each workgroup counts its
+// vertices per bin in LDS, reserves one range per bin with a single global
+// atomic, then places them.  Block 0 zeroes the other
 // round set (and, on the first round of an iteration, the other statistics
 // set); on the last round of an iteration each word of the frontier is
 // cleared once read.
@@ -370,6 +387,9 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(uint32_t* __restrict__ 
   __shared__ int32_t s_nh;                          // hubs placed in this pass of the block
   __shared__ int64_t s_hpos[kBinHubs];
   __shared__ int32_t s_hdeg[kBinHubs];
+  __shared__ int64_t s_hoff[kBinHubs];  // inclusive sums of the queued hubs' table slots,
+  __shared__ int32_t s_pu[kBinHubs];    // insert units
+  __shared__ int32_t s_pc[kBinHubs];    // and clear / decide units
   __shared__ int64_t s_hbase[3];
   __shared__ int64_t s_rbase[kFlRegions + 1];  // list mode: first entry of each region
   __shared__ int32_t s_list;
@@ -406,67 +426,114 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(uint32_t* __restrict__ 
   int64_t bin_verts[NBINS], bin_arcs[NBINS];
 #pragma unroll
   for (int q = 0; q < NBINS; ++q) bin_verts[q] = bin_arcs[q] = 0;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t w0 = blockIdx.x * static_cast<int64_t>(blockDim.x); w0 < items; w0 += stride) {
+  // each thread takes kBinPer items (words or listed vertices) per pass and
+  // issues their loads together: a pass costs a few memory round trips,
+  // not a few per item.  A listed vertex's degree is read once.
+  const int64_t per_pass = static_cast<int64_t>(kBlock) * kBinPer;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * per_pass;
+  const bool filter_deg = deg_lo > 0 || deg_hi < INT_MAX;
+  for (int64_t w0 = blockIdx.x * per_pass; w0 < items; w0 += stride) {
     if (threadIdx.x < NBINS) s_cnt[threadIdx.x] = 0;
     if (threadIdx.x == 0) s_nh = 0;
     __syncthreads();
-    const int64_t e = w0 + threadIdx.x;
-    int64_t k = 0;   // the word of this thread's vertices
-    uint32_t bits = 0;
-    if (e < items) {
-      if (lm) {  // one listed vertex
-        int r = 0;
+    int64_t kv[kBinPer];   // the word of each item's vertices
+    uint32_t bv[kBinPer];  // its vertices in this round
+    int32_t dv[kBinPer];   // list mode: the degree of the item's vertex
+    if (lm) {
+      int32_t iv[kBinPer];
 #pragma unroll
-        for (int h = kFlRegions / 2; h > 0; h >>= 1)
-          if (s_rbase[r + h] <= e) r += h;
-        const int32_t i = cl.list[r * cl.capr + (e - s_rbase[r])];
-        k = i >> 5;
-        bits = 1u << (i & 31);
-        if (clear_cur) cur[k] = 0;  // (every set bit of the word is listed)
-      } else {   // one bitmask word
-        k = e;
-        bits = cur[k];
-        if (clear_cur && bits) cur[k] = 0;
-      }
-      if (range) bits &= range[k];
-      if (round_shift < 32 && bits) bits &= round_mask(static_cast<uint32_t>(k), round, round_shift);
-      if (bits) bits &= range_mask(k, id_lo, id_hi);
-      if (bits && (deg_lo > 0 || deg_hi < INT_MAX)) {  // this round's degree class only
-        uint32_t keep = 0;
-        for (uint32_t r = bits; r; r &= r - 1) {
-          const int b = __ffs(r) - 1;
-          const int32_t deg = row_len[k * 32 + b];
-          if (deg >= deg_lo && deg <= deg_hi) keep |= 1u << b;
+      for (int j = 0; j < kBinPer; ++j) {
+        const int64_t e = w0 + static_cast<int64_t>(j) * kBlock + threadIdx.x;
+        iv[j] = -1;
+        if (e < items) {
+          int r = 0;
+#pragma unroll
+          for (int h = kFlRegions / 2; h > 0; h >>= 1)
+            if (s_rbase[r + h] <= e) r += h;
+          iv[j] = cl.list[r * cl.capr + (e - s_rbase[r])];
         }
-        bits = keep;
       }
-      if (ever && bits) {
-        if (lm) {  // other listed vertices may share the word
-          const uint32_t old = atomicOr(&ever[k], bits);
-          affected += __popc(bits & ~old);
-        } else {
+#pragma unroll
+      for (int j = 0; j < kBinPer; ++j) dv[j] = iv[j] >= 0 ? row_len[iv[j]] : 0;
+#pragma unroll
+      for (int j = 0; j < kBinPer; ++j) {
+        const int32_t i = iv[j];
+        const int64_t k = i >= 0 ? (i >> 5) : 0;
+        uint32_t bits = i >= 0 ? 1u << (i & 31) : 0u;
+        if (i >= 0 && clear_cur) cur[k] = 0;  // (every set bit of the word is listed)
+        if (bits && range) bits &= range[k];
+        if (bits && round_shift < 32) bits &= round_mask(static_cast<uint32_t>(k), round, round_shift);
+        if (bits) bits &= range_mask(k, id_lo, id_hi);
+        if (bits && filter_deg && (dv[j] < deg_lo || dv[j] > deg_hi)) bits = 0;
+        kv[j] = k;
+        bv[j] = bits;
+      }
+      if (ever) {  // (other listed vertices may share a word)
+        uint32_t old[kBinPer];
+#pragma unroll
+        for (int j = 0; j < kBinPer; ++j) old[j] = bv[j] ? atomicOr(&ever[kv[j]], bv[j]) : ~0u;
+#pragma unroll
+        for (int j = 0; j < kBinPer; ++j) affected += __popc(bv[j] & ~old[j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kBinPer; ++j) {
+        const int64_t e = w0 + static_cast<int64_t>(j) * kBlock + threadIdx.x;
+        kv[j] = e;
+        bv[j] = e < items ? cur[e] : 0u;
+        dv[j] = 0;
+      }
+#pragma unroll
+      for (int j = 0; j < kBinPer; ++j) {
+        const int64_t k = kv[j];
+        uint32_t bits = bv[j];
+        if (clear_cur && bits) cur[k] = 0;
+        if (bits && range) bits &= range[k];
+        if (bits && round_shift < 32) bits &= round_mask(static_cast<uint32_t>(k), round, round_shift);
+        if (bits) bits &= range_mask(k, id_lo, id_hi);
+        if (bits && filter_deg) {  // this round's degree class only
+          uint32_t keep = 0;
+          for (uint32_t r = bits; r; r &= r - 1) {
+            const int b = __ffs(r) - 1;
+            const int32_t deg = row_len[k * 32 + b];
+            if (deg >= deg_lo && deg <= deg_hi) keep |= 1u << b;
+          }
+          bits = keep;
+        }
+        if (ever && bits) {
           const uint32_t old = ever[k];
           affected += __popc(bits & ~old);
           ever[k] = old | bits;
         }
+        bv[j] = bits;
       }
     }
+    // the vertices of item j with their degrees
+    auto for_each_vertex = [&](int j, auto&& f) {
+      if (lm) {
+        if (bv[j]) f(static_cast<int32_t>(kv[j] * 32 + (__ffs(bv[j]) - 1)), dv[j]);
+      } else {
+        for (uint32_t r = bv[j]; r; r &= r - 1) {
+          const int32_t i = static_cast<int32_t>(kv[j] * 32 + (__ffs(r) - 1));
+          f(i, row_len[i]);
+        }
+      }
+    };
     int32_t cnt[NBINS];
 #pragma unroll
     for (int q = 0; q < NBINS; ++q) cnt[q] = 0;
-    for (uint32_t r = bits; r; r &= r - 1) {
-      const int32_t i = static_cast<int32_t>(k * 32 + (__ffs(r) - 1));
-      const int32_t deg = row_len[i];
-      processed += 1;
-      arcs += deg;
-      const int bin = bin_of(deg, wave_max);
 #pragma unroll
-      for (int q = 0; q < NBINS; ++q) {
-        cnt[q] += (bin == q) ? 1 : 0;
-        bin_arcs[q] += (bin == q) ? deg : 0;
-      }
-    }
+    for (int j = 0; j < kBinPer; ++j)
+      for_each_vertex(j, [&](int32_t, int32_t deg) {
+        processed += 1;
+        arcs += deg;
+        const int bin = bin_of(deg, wave_max);
+#pragma unroll
+        for (int q = 0; q < NBINS; ++q) {
+          cnt[q] += (bin == q) ? 1 : 0;
+          bin_arcs[q] += (bin == q) ? deg : 0;
+        }
+      });
 #pragma unroll
     for (int q = 0; q < NBINS; ++q) bin_verts[q] += cnt[q];
 #pragma unroll
@@ -482,49 +549,92 @@ __global__ void __launch_bounds__(kBlock) k_bin_frontier(uint32_t* __restrict__ 
       s_cnt[threadIdx.x] = 0;
     }
     __syncthreads();
-    for (uint32_t r = bits; r; r &= r - 1) {
-      const int32_t i = static_cast<int32_t>(k * 32 + (__ffs(r) - 1));
-      const int32_t deg = row_len[i];
-      const int bin = bin_of(deg, wave_max);
-      if (bin < 0) continue;
-      const int64_t pos = s_base[bin] + atomicAdd(&s_cnt[bin], 1);
-      bins.list[bin][pos] = i;
-      if (bin == BIN_HUB) {  // queued for one reservation per workgroup
-        const int q = atomicAdd(&s_nh, 1);
-        if (q < kBinHubs) {
-          s_hpos[q] = pos;
-          s_hdeg[q] = deg;
-        } else {
-          hub_setup(H, pos, deg, rc);
+#pragma unroll
+    for (int j = 0; j < kBinPer; ++j)
+      for_each_vertex(j, [&](int32_t i, int32_t deg) {
+        const int bin = bin_of(deg, wave_max);
+        if (bin < 0) return;
+        const int64_t pos = s_base[bin] + atomicAdd(&s_cnt[bin], 1);
+        bins.list[bin][pos] = i;
+        if (bin == BIN_HUB) {  // queued for one reservation per workgroup
+          const int q = atomicAdd(&s_nh, 1);
+          if (q < kBinHubs) {
+            s_hpos[q] = pos;
+            s_hdeg[q] = deg;
+          } else {
+            hub_setup(H, pos, deg, rc);
+          }
         }
-      }
-    }
+      });
     __syncthreads();
     const int nh = min(s_nh, kBinHubs);
     if (nh > 0) {
-      if (threadIdx.x == 0) {
-        int64_t slots = 0, nu = 0, nc = 0;
-        for (int q = 0; q < nh; ++q) {
-          slots += hub_slots(s_hdeg[q]);
-          nu += hub_units(s_hdeg[q]);
-          nc += hub_cunits(s_hdeg[q]);
-        }
-        s_hbase[0] = static_cast<int64_t>(
-            atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_POOL]), static_cast<unsigned long long>(slots)));
-        s_hbase[1] = static_cast<int64_t>(
-            atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_HUB_UNITS]), static_cast<unsigned long long>(nu)));
-        s_hbase[2] = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_HUB_CUNITS]),
-                                                    static_cast<unsigned long long>(nc)));
+      // inclusive prefix sums of the queued hubs' table slots, insert units
+      // and clear units (Hillis-Steele over at most kBinHubs entries)
+      for (int q = threadIdx.x; q < nh; q += kBlock) {
+        s_hoff[q] = hub_slots(s_hdeg[q]);
+        s_pu[q] = static_cast<int32_t>(hub_units(s_hdeg[q]));
+        s_pc[q] = static_cast<int32_t>(hub_cunits(s_hdeg[q]));
       }
       __syncthreads();
-      if (threadIdx.x < nh) {
-        int64_t off = s_hbase[0], bu = s_hbase[1], bc = s_hbase[2];
-        for (int q = 0; q < static_cast<int>(threadIdx.x); ++q) {
-          off += hub_slots(s_hdeg[q]);
-          bu += hub_units(s_hdeg[q]);
-          bc += hub_cunits(s_hdeg[q]);
+      for (int d = 1; d < nh; d <<= 1) {
+        int64_t a0[kBinHubs / kBlock];
+        int32_t a1[kBinHubs / kBlock], a2[kBinHubs / kBlock];
+#pragma unroll
+        for (int t = 0; t < kBinHubs / kBlock; ++t) {
+          const int q = threadIdx.x + t * kBlock;
+          const bool on = q < nh && q >= d;
+          a0[t] = on ? s_hoff[q - d] : 0;
+          a1[t] = on ? s_pu[q - d] : 0;
+          a2[t] = on ? s_pc[q - d] : 0;
         }
-        hub_write(H, s_hpos[threadIdx.x], s_hdeg[threadIdx.x], off, bu, bc);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < kBinHubs / kBlock; ++t) {
+          const int q = threadIdx.x + t * kBlock;
+          if (q < nh) {
+            s_hoff[q] += a0[t];
+            s_pu[q] += a1[t];
+            s_pc[q] += a2[t];
+          }
+        }
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) {
+        s_hbase[0] = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_POOL]),
+                                                    static_cast<unsigned long long>(s_hoff[nh - 1])));
+        s_hbase[1] = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_HUB_UNITS]),
+                                                    static_cast<unsigned long long>(s_pu[nh - 1])));
+        s_hbase[2] = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&rc[RC_HUB_CUNITS]),
+                                                    static_cast<unsigned long long>(s_pc[nh - 1])));
+      }
+      __syncthreads();
+      for (int q = threadIdx.x; q < nh; q += kBlock) {
+        const int32_t deg = s_hdeg[q];
+        hub_head(H, s_hpos[q], deg, s_hbase[0] + s_hoff[q] - hub_slots(deg),
+                 s_hbase[2] + s_pc[q] - hub_cunits(deg));
+      }
+      // the unit descriptors, all queued hubs' at once: entry x of the
+      // block's range belongs to the first hub whose inclusive sum exceeds x
+      auto owner = [&](const int32_t* incl, int32_t x) {
+        int lo = 0, hi = nh - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (incl[mid] > x) hi = mid; else lo = mid + 1;
+        }
+        return lo;
+      };
+      for (int32_t x = threadIdx.x; x < s_pu[nh - 1]; x += kBlock) {
+        const int q = owner(s_pu, x);
+        const int64_t u = x - (s_pu[q] - hub_units(s_hdeg[q]));
+        H.u_b[s_hbase[1] + x] = static_cast<int32_t>(s_hpos[q]);
+        H.u_a[s_hbase[1] + x] = u * kHubUnitArcs;
+      }
+      for (int32_t x = threadIdx.x; x < s_pc[nh - 1]; x += kBlock) {
+        const int q = owner(s_pc, x);
+        const int64_t u = x - (s_pc[q] - hub_cunits(s_hdeg[q]));
+        H.c_b[s_hbase[2] + x] = static_cast<int32_t>(s_hpos[q]);
+        H.c_s[s_hbase[2] + x] = u * kHubClearSlots;
       }
     }
     __syncthreads();
@@ -1782,10 +1892,10 @@ void launch_one_role(int role, const Dev& D, const Bins& b, const HubIn& H, int6
 
 }  // namespace
 
-void launch_call_begin(Workspace& ws, const int64_t* two_m, bool dense_a, hipStream_t st) {
+void launch_call_begin(Workspace& ws, const int64_t* two_m, bool dense_a, bool keep_err, hipStream_t st) {
   hipLaunchKernelGGL(k_call_begin, dim3(grid_for(std::max<int64_t>(ws.words, CTR_COUNT), kBlock, 2048)),
                      dim3(kBlock), 0, st, ws.ctr, ws.fr_a, ws.fr_b, ws.ever, ws.moved, ws.words, two_m,
-                     dense_a ? 1 : 0);
+                     dense_a ? 1 : 0, keep_err ? 1 : 0);
 }
 
 FrontList front_list(const Workspace& ws, int k) {
@@ -1819,7 +1929,7 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
   // (a listed frontier has at most a.est vertices; a bitmask walk is a
   // grid-stride loop, so a smaller grid only slows it)
   const int64_t bin_items = std::max<int64_t>(1, std::min<int64_t>(words, a.est));
-  hipExtLaunchKernelGGL(k_bin_frontier, dim3(grid_for(bin_items, kBlock, 4096)), dim3(kBlock), 0, st, tb.start,
+  hipExtLaunchKernelGGL(k_bin_frontier, dim3(grid_for(bin_items, kBlock * kBinPer, 4096)), dim3(kBlock), 0, st, tb.start,
                         tb.stop, 0, const_cast<uint32_t*>(a.cur), a.cur_fl, a.sc_next ? a.next_fl.cnt : nullptr,
                         a.range, a.ever, a.g.row_len, a.g.n, a.wave_max,
                         r.hash_round, r.hash_shift, r.id_lo, r.id_hi, r.deg_lo, r.deg_hi, a.clear_cur, b, HO, a.rc,

@@ -36,7 +36,7 @@ NTIMED = len(TIMED)
 
 EXPORTS = ["lv_default_params", "lv_workspace_bytes", "lv_graph_capacity_bound", "lv_graph_build",
            "lv_graph_relayout", "apply_batch", "louvain_static", "louvain_nd", "louvain_ds", "louvain_df",
-           "modularity", "lv_set_tuning", "lv_get_tuning", "lv_set_timing", "lv_last_error",
+           "modularity", "louvain_df_apply", "lv_set_tuning", "lv_get_tuning", "lv_set_timing", "lv_last_error",
            "lv_many_scratch_bytes", "lv_many_desc_bytes", "louvain_df_many", "lv_autotune",
            "lv_noalloc_scratch_bytes", "louvain_df_noalloc", "lv_get_many_tuning", "lv_set_many_tuning",
            "lv_many_size_class", "lv_autotune_many", "lv_workspace_bytes_f", "lv_graph_build_f", "apply_batch_f",
@@ -140,7 +140,7 @@ def load():
     L.apply_batch.argtypes = [GP, EP, EP, P, SZ, P]
     L.louvain_static.restype = I32
     L.louvain_static.argtypes = [GP, PP, SP, P, SZ, STP, P]
-    for name in ("louvain_nd", "louvain_ds", "louvain_df"):
+    for name in ("louvain_nd", "louvain_ds", "louvain_df", "louvain_df_apply"):
         f = getattr(L, name)
         f.restype = I32
         f.argtypes = [GP, EP, EP, PP, SP, P, SZ, STP, P]
@@ -512,6 +512,13 @@ def louvain_ds(g, b, state, prm=None, stream=None, **kw):
 
 def louvain_df(g, b, state, prm=None, stream=None, **kw):
     return _dynamic("louvain_df", g, b, state, prm, stream, kw)
+
+
+def louvain_df_apply(g, b, state, prm=None, stream=None, **kw):
+    """apply_batch(g, b) and louvain_df(g, b, state) in one call (one host
+    wait).  On LV_EINVAL / LV_ENOEDGE / LV_ENOSLACK / LV_EOVERFLOW the
+    batch was refused and graph and state are unchanged."""
+    return _dynamic("louvain_df_apply", g, b, state, prm, stream, kw)
 
 
 def louvain_df_noalloc(g, b, state, prm=None, stream=None, **kw):

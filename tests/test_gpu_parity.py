@@ -166,6 +166,66 @@ def test_dynamic_sync_bit_exact(lib, case, approach, carry_size):
         assert np.array_equal(st.size.cpu().numpy(), _sizes(C, e.n))
 
 
+@pytest.mark.parametrize("recompute", [0, 1])
+def test_df_apply_one_call_sync_bit_exact(lib, case, recompute):
+    """louvain_df_apply (the batch edit and DF in one call) gives the
+    oracle's graph, state and statistics, as the two calls do."""
+    name, e = case
+    b = W.random_batch(e, max(10, e.m // 200), 79)
+    G = _orc(e)
+    state0 = G.louvain("static", mode="async")[:3]
+    assert G.apply_batch(b) == 0
+    Cd, Kd, Sd, os_ = G.louvain("df", batch=b, state=state0, mode="sync")
+    g = lib.Graph.from_edges(e)
+    st = lib.State.from_host(*state0)
+    st.size = torch.from_numpy(_sizes(state0[0], e.n)).cuda()
+    st, gs = lib.louvain_df_apply(g, lib.Batch.from_host(b), st, mode="sync", recompute_weights=recompute)
+    assert all(np.array_equal(x, y) for x, y in zip(g.csr_host(), G.csr()))
+    assert g.two_m == G.two_m
+    C, K, S = st.host()
+    assert np.array_equal(K, Kd) and np.array_equal(C, Cd) and np.array_equal(S, Sd)
+    assert np.array_equal(st.size.cpu().numpy(), _sizes(C, e.n))
+    _same_stats(gs, os_)
+
+
+def test_df_apply_refused_batch_changes_nothing(lib):
+    """An edit the batch cannot make (no slack, a missing edge, a repeated
+    pair) is refused by louvain_df_apply with graph and state untouched;
+    after a relayout the same call succeeds and matches the oracle."""
+    e = W.random_small_graph(400, 1500, 12)
+    G = _orc(e)
+    state0 = G.louvain("static", mode="async")[:3]
+    g = lib.Graph.from_edges(e, slack_frac=0.0, slack_min=0)
+    present = set(zip(e.u.tolist(), e.v.tolist()))
+    absent = [(a, c) for a in range(400) for c in range(a + 1, 400) if (a, c) not in present][:3]
+    z = np.zeros(0, np.int32)
+    iu, iv = (np.array(x, np.int32) for x in zip(*absent))
+    cases = [
+        (lib.LV_ENOSLACK, W.Batch(z, z, z, iu, iv, np.ones(3, np.int32))),
+        (lib.LV_ENOEDGE, W.Batch(iu[:1], iv[:1], np.ones(1, np.int32), z, z, z)),
+        (lib.LV_EINVAL, W.Batch(z, z, z, np.array([iu[0], iv[0]], np.int32), np.array([iv[0], iu[0]], np.int32),
+                                np.ones(2, np.int32))),
+    ]
+    before = g.csr_host()
+    st = lib.State.from_host(*state0)
+    for code, b in cases:
+        with pytest.raises(lib.LouvainError) as ex:
+            lib.louvain_df_apply(g, lib.Batch.from_host(b), st, mode="sync")
+        assert ex.value.code == code
+        assert all(np.array_equal(x, y) for x, y in zip(before, g.csr_host()))
+        assert g.two_m == 2 * int(e.w.sum())
+        for x, y in zip(st.host(), state0):
+            assert np.array_equal(x, y)
+    b = cases[0][1]
+    g = g.relayout(slack_frac=0.5, slack_min=8)
+    st, gs = lib.louvain_df_apply(g, lib.Batch.from_host(b), st, mode="sync")
+    assert G.apply_batch(b) == 0
+    Cd, Kd, Sd, os_ = G.louvain("df", batch=b, state=state0, mode="sync")
+    C, K, S = st.host()
+    assert np.array_equal(C, Cd) and np.array_equal(K, Kd) and np.array_equal(S, Sd)
+    _same_stats(gs, os_)
+
+
 @pytest.mark.parametrize("approach", ["nd", "ds", "df"])
 def test_without_auxiliary_information_sync_bit_exact(lib, case, approach):
     """recompute_weights=1 (Section 4.2's variant without auxiliary
