@@ -109,21 +109,24 @@ __global__ void k_relayout_copy(const int64_t* __restrict__ s_start, const int32
 }
 
 // Row sums (K_i, and with C given the weight of arcs inside communities
-// for Eq. 1) in three degree classes, so that no lane idles on a short row
-// and no wavefront walks a long one alone:
-//  - rows of at most kFlatMax arcs: one wavefront per 64 consecutive rows
-//    reads their starts and lengths (coalesced) and walks their arcs as one
-//    flat sequence, 256 consecutive arcs per step (four loads in flight per
-//    lane); an LDS map gives each flat position's row, and LDS atomics add
-//    each arc to its row's sum;
-//  - rows up to kMidMax arcs are summed by the same wavefront right after,
-//    one at a time, 256 arcs per step (a list of them would take one device
-//    atomic per wavefront on a single counter, and those serialise);
+// for Eq. 1) by row length, so that every lane has loads in flight and no
+// wavefront walks a long row alone:
+//  - rows of at most kLaneMax arcs: each lane sums its own row, all of its
+//    loads issued at once (one memory round trip);
+//  - rows up to kGroupMax arcs: listed, then 16 lanes per row (four rows per
+//    wavefront at a time);
+//  - rows up to kMidMax arcs: listed, then one wavefront per row, the next
+//    row's metadata loaded before this row's arcs are summed;
 //  - longer rows are listed in chunks of kChunk arcs, one wavefront per
 //    chunk, whose partial sums are added atomically (K and Sigma of such a
 //    row are zeroed by the first kernel).
-constexpr int kFlatMax = 64;
+// The lists are kept per region (row task mod kRegions), each region with
+// its own counters, so a workgroup reserves its entries with one atomic per
+// class on a counter shared with few others.
+constexpr int kLaneMax = 16;
+constexpr int kGroupMax = 64;
 constexpr int kMidMax = 4096;
+constexpr int kRegions = 32;
 constexpr int kChunk = 4096;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kRowUnroll = 4;
@@ -136,13 +139,12 @@ struct RowSumOut {
   int32_t* lrow;   // chunks of long rows: row, first arc
   int32_t* loff;
   int64_t* ctr;    // CTR_AUX1: listed chunks
+  int32_t* grp;    // group rows, region r at grp[r * cap ...]
+  int32_t* mid;    // wavefront rows, likewise
+  int64_t cap;     // list entries per region
+  int64_t* cnt;    // region r's counts: cnt[(2r) * kCtrLine] (group), cnt[(2r + 1) * kCtrLine] (wavefront)
 };
 
-__device__ __forceinline__ void wave_barrier_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Sum of arcs [a, b) of the row starting at s, over the wavefront, 256 arcs
 // per step; with C, adds the weight of arcs into community ci to *intra.
@@ -172,33 +174,29 @@ __global__ void __launch_bounds__(kBlock) k_rows_flat(const int64_t* __restrict_
                                                      const int32_t* __restrict__ row_len,
                                                      const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
                                                      int32_t n, const int32_t* __restrict__ C, RowSumOut o) {
-  constexpr int kSpan = kWave * kFlatMax;  // flat positions of a wavefront's short rows, at most
-  __shared__ uint8_t s_own[kWavesPerBlock][kSpan];  // row (lane) of each flat position
-  __shared__ int64_t s_base[kWavesPerBlock][kWave];  // row start minus the row's first flat position
-  __shared__ int32_t s_c[kWavesPerBlock][kWave];
-  __shared__ unsigned long long s_acc[kWavesPerBlock][kWave];
+  __shared__ int32_t s_n[2];
+  __shared__ int64_t s_b[2];
   const int lane = lane_id();
-  const int w = threadIdx.x / kWave;
-  uint8_t* own = s_own[w];
-  unsigned long long* acc = s_acc[w];
-  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
   int64_t intra = 0;
-  for (int64_t r0 = (blockIdx.x * static_cast<int64_t>(kWavesPerBlock) + w) * kWave; r0 < n;
-       r0 += nwaves * kWave) {
-    const int64_t i = r0 + lane;
+  const int64_t tasks = (static_cast<int64_t>(n) + kBlock - 1) / kBlock;
+  for (int64_t t = blockIdx.x; t < tasks; t += gridDim.x) {
+    const int region = static_cast<int>(t % kRegions);
+    if (threadIdx.x < 2) s_n[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t i = t * kBlock + threadIdx.x;
     const bool valid = i < n;
-    const int32_t row_len_l = valid ? row_len[i] : 0;
-    int32_t len = row_len_l;
+    const int32_t len = valid ? row_len[i] : 0;
     const int64_t st = valid ? row_start[i] : 0;
     const int32_t ci = (C && valid) ? C[i] : 0;
-    const bool is_mid = len > kFlatMax && len <= kMidMax;
     const bool is_long = len > kMidMax;
+    const bool is_mid = len > kGroupMax && !is_long;
+    const bool is_grp = len > kLaneMax && len <= kGroupMax;
     {  // chunks of long rows, reserved together by the wavefront
       const int32_t nch = is_long ? (len + kChunk - 1) / kChunk : 0;
       int32_t incl = nch;
       for (int s = 1; s < kWave; s <<= 1) {
-        const int32_t t = __shfl_up(incl, s);
-        if (lane >= s) incl += t;
+        const int32_t u = __shfl_up(incl, s);
+        if (lane >= s) incl += u;
       }
       const int32_t tot = __shfl(incl, kWave - 1);
       int64_t base = 0;
@@ -213,79 +211,148 @@ __global__ void __launch_bounds__(kBlock) k_rows_flat(const int64_t* __restrict_
         o.loff[base + incl - nch + k] = k * kChunk;
       }
     }
+    // the group and wavefront rows: LDS counts, one reservation per class
+    int32_t pg = -1, pm = -1;
+    if (is_grp) pg = atomicAdd(&s_n[0], 1);
+    if (is_mid) pm = atomicAdd(&s_n[1], 1);
+    __syncthreads();
+    if (threadIdx.x < 2) {
+      const int32_t c = s_n[threadIdx.x];
+      s_b[threadIdx.x] = c ? static_cast<int64_t>(atomicAdd(
+                                 reinterpret_cast<unsigned long long*>(&o.cnt[(region * 2 + threadIdx.x) * kCtrLine]),
+                                 static_cast<unsigned long long>(c)))
+                           : 0;
+    }
+    __syncthreads();
+    if (pg >= 0) o.grp[region * o.cap + s_b[0] + pg] = static_cast<int32_t>(i);
+    if (pm >= 0) o.mid[region * o.cap + s_b[1] + pm] = static_cast<int32_t>(i);
     if (valid) {
-      if (is_long) {
-        o.K[i] = 0;
-        if (o.Sigma) o.Sigma[i] = 0;
+      int64_t sum = 0;
+      if (len <= kLaneMax) {  // this lane's own row: all of its loads at once
+        int32_t x[kLaneMax], j[kLaneMax];
+#pragma unroll
+        for (int k = 0; k < kLaneMax; ++k) {
+          x[k] = k < len ? wt[st + k] : 0;
+          j[k] = (C && k < len) ? col[st + k] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < kLaneMax; ++k) {
+          sum += x[k];
+          if (C && j[k] >= 0 && C[j[k]] == ci) intra += x[k];
+        }
+      }
+      if (len <= kLaneMax || is_long) {
+        o.K[i] = sum;  // (long rows: zero, their chunks add)
+        if (o.Sigma) o.Sigma[i] = sum;
       }
       if (o.Cinit) o.Cinit[i] = static_cast<int32_t>(i);
       if (o.size) o.size[i] = 1;
     }
-    const bool is_short = valid && !is_mid && !is_long;
-    if (!is_short) len = 0;
-    // exclusive prefix of the short rows' lengths over the wavefront; each
-    // lane marks its row's flat positions as its own
-    int32_t incl = len;
-    for (int s = 1; s < kWave; s <<= 1) {
-      const int32_t t = __shfl_up(incl, s);
-      if (lane >= s) incl += t;
-    }
-    const int32_t total = __shfl(incl, kWave - 1);
-    const int32_t first = incl - len;
-    for (int32_t k = 0; k < len; ++k) own[first + k] = static_cast<uint8_t>(lane);
-    s_base[w][lane] = st - first;
-    s_c[w][lane] = ci;
-    acc[lane] = 0;
-    wave_barrier_lds();
-    for (int32_t b = 0; b < total; b += kWave * kRowUnroll) {
-      int32_t r[kRowUnroll];
-      int64_t x[kRowUnroll];
-      int32_t cj[kRowUnroll];
-#pragma unroll
-      for (int q = 0; q < kRowUnroll; ++q) {
-        const int32_t p = b + q * kWave + lane;
-        r[q] = p < total ? own[p] : -1;
-      }
-#pragma unroll
-      for (int q = 0; q < kRowUnroll; ++q) {
-        const int32_t p = b + q * kWave + lane;
-        x[q] = 0;
-        cj[q] = -1;
-        if (r[q] >= 0) {
-          const int64_t a = s_base[w][r[q]] + p;
-          x[q] = wt[a];
-          if (C) cj[q] = col[a];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kRowUnroll; ++q) {
-        if (r[q] < 0) continue;
-        atomicAdd(&acc[r[q]], static_cast<unsigned long long>(x[q]));
-        if (C && C[cj[q]] == s_c[w][r[q]]) intra += x[q];
-      }
-    }
-    wave_barrier_lds();
-    if (is_short) {
-      const int64_t sum = static_cast<int64_t>(acc[lane]);
-      o.K[i] = sum;
-      if (o.Sigma) o.Sigma[i] = sum;
-    }
-    wave_barrier_lds();
-    // the middle rows of the 64, one after the other over the wavefront
-    for (uint64_t mm = __ballot(is_mid); mm; mm &= mm - 1) {
-      const int l = __ffsll(static_cast<unsigned long long>(mm)) - 1;
-      const int64_t rs = __shfl(st, l);
-      const int32_t rl = __shfl(row_len_l, l);
-      const int32_t rc = __shfl(ci, l);
-      const int64_t sum = wave_row_sum(col, wt, C, rs, 0, rl, rc, &intra);
-      if (lane == l) {
-        o.K[i] = sum;
-        if (o.Sigma) o.Sigma[i] = sum;
-      }
-    }
+    __syncthreads();
   }
   intra = wave_sum_i64(intra);
   if (lane == 0 && C && intra) stat_add(o.ctr + CTR_STATS0, ST_INTRA, intra);
+}
+
+// First entry of each region in the concatenation of a class's lists
+// (cls 0: group rows, 1: wavefront rows); rb has kRegions + 1 entries.
+__device__ __forceinline__ void region_bases(const int64_t* cnt, int cls, int64_t* rb) {
+  if (threadIdx.x < kWave) {
+    const int64_t c = threadIdx.x < kRegions ? cnt[(threadIdx.x * 2 + cls) * kCtrLine] : 0;
+    int64_t incl = c;
+    for (int s = 1; s < kWave; s <<= 1) {
+      const int64_t u = __shfl_up(incl, s);
+      if (static_cast<int>(threadIdx.x) >= s) incl += u;
+    }
+    if (threadIdx.x < kRegions) rb[threadIdx.x] = incl - c;
+    if (threadIdx.x == kRegions - 1) rb[kRegions] = incl;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int32_t listed(const int64_t* rb, const int32_t* list, int64_t cap, int64_t idx) {
+  int r = 0;
+#pragma unroll
+  for (int h = kRegions / 2; h > 0; h >>= 1)
+    if (rb[r + h] <= idx) r += h;
+  return list[r * cap + (idx - rb[r])];
+}
+
+// group rows: 16 lanes per row, four rows per wavefront at a time
+__global__ void __launch_bounds__(kBlock) k_rows_grp(const int64_t* __restrict__ row_start,
+                                                    const int32_t* __restrict__ row_len,
+                                                    const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
+                                                    const int32_t* __restrict__ C, RowSumOut o) {
+  __shared__ int64_t s_rb[kRegions + 1];
+  region_bases(o.cnt, 0, s_rb);
+  const int64_t count = s_rb[kRegions];
+  const int sub = threadIdx.x & 15;
+  const int64_t ngroups = static_cast<int64_t>(gridDim.x) * (kBlock / 16);
+  int64_t intra = 0;
+  for (int64_t idx = blockIdx.x * static_cast<int64_t>(kBlock / 16) + threadIdx.x / 16; idx < count;
+       idx += ngroups) {
+    const int32_t i = listed(s_rb, o.grp, o.cap, idx);
+    const int64_t s = row_start[i];
+    const int32_t len = row_len[i];
+    const int32_t ci = C ? C[i] : 0;
+    int32_t x[kGroupMax / 16], j[kGroupMax / 16];
+#pragma unroll
+    for (int q = 0; q < kGroupMax / 16; ++q) {
+      const int32_t k = sub + q * 16;
+      x[q] = k < len ? wt[s + k] : 0;
+      j[q] = (C && k < len) ? col[s + k] : -1;
+    }
+    int64_t acc = 0;
+#pragma unroll
+    for (int q = 0; q < kGroupMax / 16; ++q) {
+      acc += x[q];
+      if (C && j[q] >= 0 && C[j[q]] == ci) intra += x[q];
+    }
+    for (int m = 8; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 16);
+    if (sub == 0) {
+      o.K[i] = acc;
+      if (o.Sigma) o.Sigma[i] = acc;
+    }
+  }
+  intra = wave_sum_i64(intra);
+  if (lane_id() == 0 && C && intra) stat_add(o.ctr + CTR_STATS0, ST_INTRA, intra);
+}
+
+// wavefront rows, the next row's list entry and metadata loaded before this
+// row's arcs are summed
+__global__ void __launch_bounds__(kBlock) k_rows_mid(const int64_t* __restrict__ row_start,
+                                                    const int32_t* __restrict__ row_len,
+                                                    const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
+                                                    const int32_t* __restrict__ C, RowSumOut o) {
+  __shared__ int64_t s_rb[kRegions + 1];
+  region_bases(o.cnt, 1, s_rb);
+  const int64_t count = s_rb[kRegions];
+  const int64_t nwaves = static_cast<int64_t>(gridDim.x) * kWavesPerBlock;
+  int64_t intra = 0;
+  int64_t idx = blockIdx.x * static_cast<int64_t>(kWavesPerBlock) + threadIdx.x / kWave;
+  int32_t i = idx < count ? listed(s_rb, o.mid, o.cap, idx) : -1;
+  int64_t s = i >= 0 ? row_start[i] : 0;
+  int32_t len = i >= 0 ? row_len[i] : 0;
+  int32_t ci = (C && i >= 0) ? C[i] : 0;
+  while (idx < count) {
+    const int64_t nidx = idx + nwaves;
+    const int32_t ni = nidx < count ? listed(s_rb, o.mid, o.cap, nidx) : -1;
+    const int64_t ns = ni >= 0 ? row_start[ni] : 0;
+    const int32_t nlen = ni >= 0 ? row_len[ni] : 0;
+    const int32_t nci = (C && ni >= 0) ? C[ni] : 0;
+    const int64_t sum = wave_row_sum(col, wt, C, s, 0, len, ci, &intra);
+    if (lane_id() == 0) {
+      o.K[i] = sum;
+      if (o.Sigma) o.Sigma[i] = sum;
+    }
+    idx = nidx;
+    i = ni;
+    s = ns;
+    len = nlen;
+    ci = nci;
+  }
+  intra = wave_sum_i64(intra);
+  if (lane_id() == 0 && C && intra) stat_add(o.ctr + CTR_STATS0, ST_INTRA, intra);
 }
 
 __global__ void __launch_bounds__(kBlock) k_rows_chunks(const int64_t* __restrict__ row_start,
@@ -382,22 +449,31 @@ void launch_relayout_copy(const lv_graph& src, const int64_t* dst_start, int32_t
 
 // K[i] = row sum (and Sigma = K, C = identity, size = 1 when given); with
 // C_mod given, the weight of intra-community arcs is added to statistic
-// ST_INTRA of the first statistics set.  Uses ctr[CTR_AUX1] and the two
-// unit lists (n + cap/2048 + 64 entries each, more than the chunks of cap
-// arcs in rows of over 4096 arcs can take) for the chunks of long rows.
+// ST_INTRA of the first statistics set.  Uses ctr[CTR_AUX1], the second
+// statistics set (list counters), the first two bin lists (the group and
+// wavefront row lists, n + kRowListPad entries each) and the two unit lists
+// (n + cap/2048 + 64 entries each, more than the chunks of cap arcs in rows
+// of over 4096 arcs can take) for the chunks of long rows.
 void launch_row_sums(const LevelGraph& g, const int32_t* C_mod, int64_t* K, int64_t* Sigma, int32_t* Cinit,
                      int32_t* size, Workspace& ws, hipStream_t st) {
   if (g.n == 0) return;
   static_assert(kChunk >= 2048, "the unit lists hold cap / 2048 chunks");
+  static_assert(2 * kRegions * kCtrLine <= kStatSet, "the list counters fit a statistics set");
+  static_assert(kRegions * kBlock <= kRowListPad, "region lists of whole row tasks fit the padded bin lists");
+  int64_t* cnt = ws.ctr + CTR_STATS0 + kStatSet;
   (void)hipMemsetAsync(ws.ctr + CTR_AUX1, 0, sizeof(int64_t) * kCtrLine, st);
-  RowSumOut o{K, Sigma, Cinit, size, ws.u_ins_b, ws.u_emit_b, ws.ctr};
-  const int64_t waves = (static_cast<int64_t>(g.n) + kWave - 1) / kWave;
-  // (a grid-stride loop: each wavefront ends with one statistics atomic)
-  const int64_t blocks = std::min<int64_t>((waves + kWavesPerBlock - 1) / kWavesPerBlock, 8192);
-  hipLaunchKernelGGL(k_rows_flat, dim3(static_cast<uint32_t>(blocks)), dim3(kBlock), 0, st, g.row_start, g.row_len,
-                     g.col, g.w, g.n, C_mod, o);
-  // (many waves, so the memory latencies of the chunks overlap; the waves
-  // without a chunk return at once)
+  (void)hipMemsetAsync(cnt, 0, sizeof(int64_t) * 2 * kRegions * kCtrLine, st);
+  // region r takes the row tasks t = r mod kRegions: ceil(tasks / kRegions)
+  // tasks of kBlock rows
+  const int64_t tasks = (static_cast<int64_t>(g.n) + kBlock - 1) / kBlock;
+  const int64_t cap = (tasks + kRegions - 1) / kRegions * kBlock;
+  RowSumOut o{K, Sigma, Cinit, size, ws.u_ins_b, ws.u_emit_b, ws.ctr, ws.bins[0], ws.bins[1], cap, cnt};
+  hipLaunchKernelGGL(k_rows_flat, dim3(static_cast<uint32_t>(std::min<int64_t>(tasks, 8192))), dim3(kBlock), 0, st,
+                     g.row_start, g.row_len, g.col, g.w, g.n, C_mod, o);
+  // (grids of many waves, so the memory latencies of the rows overlap; the
+  // waves without a row or chunk return at once)
+  hipLaunchKernelGGL(k_rows_grp, dim3(8192), dim3(kBlock), 0, st, g.row_start, g.row_len, g.col, g.w, C_mod, o);
+  hipLaunchKernelGGL(k_rows_mid, dim3(8192), dim3(kBlock), 0, st, g.row_start, g.row_len, g.col, g.w, C_mod, o);
   hipLaunchKernelGGL(k_rows_chunks, dim3(8192), dim3(kBlock), 0, st, g.row_start, g.row_len, g.col, g.w, C_mod, o);
 }
 

@@ -683,7 +683,7 @@ size_t carve_workspace(Workspace& ws, void* base, int32_t n, int64_t cap) {
   ws.fl_capr = static_cast<int64_t>(un) / 16 + 64;
   for (int k = 0; k < 2; ++k)
     ws.fl[k] = take<int32_t>(cur, total, base, static_cast<size_t>(ws.fl_capr) * kFlRegions);
-  for (int b = 0; b < NBINS; ++b) ws.bins[b] = take<int32_t>(cur, total, base, un);
+  for (int b = 0; b < NBINS; ++b) ws.bins[b] = take<int32_t>(cur, total, base, un + kRowListPad);
   ws.hub_off = take<int64_t>(cur, total, base, un);
   ws.hub_kid = take<int64_t>(cur, total, base, un);
   ws.hub_moved = take<int32_t>(cur, total, base, un);

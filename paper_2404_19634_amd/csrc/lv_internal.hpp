@@ -41,6 +41,7 @@ constexpr int kHubClearSlots = 4096;      // table slots per clear unit of a hub
 // first kernel of an iteration zeroes the statistics set of the iteration
 // after it (the host read it at the end of the previous iteration).
 constexpr int kCtrLine = 16;        // int64 slots per 128-byte line
+constexpr int64_t kRowListPad = 8192;  // bin lists hold n + this many entries (row-sum region lists)
 constexpr int kStatReplicas = 32;
 constexpr int kStatStride = 2 * kCtrLine;  // slots per replica (two lines)
 constexpr int kStatSet = kStatReplicas * kStatStride;
