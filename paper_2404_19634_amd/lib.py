@@ -369,9 +369,15 @@ class Graph:
         return CGraph(*self.cvals())
 
     def cvals(self) -> tuple:
-        """The lv_graph fields in order."""
-        return (self.n, self.cap, self.row_start.data_ptr(), self.row_len.data_ptr(), self.col.data_ptr(),
-                self.w.data_ptr(), self.two_m_t.data_ptr())
+        """The lv_graph fields in order (kept while the arrays are the same
+        objects: a batched call marshals thousands of graphs)."""
+        key = (self.n, self.cap, id(self.row_start), id(self.row_len), id(self.col), id(self.w), id(self.two_m_t))
+        c = self.__dict__.get("_cv")
+        if c is None or c[0] != key:
+            c = (key, (self.n, self.cap, self.row_start.data_ptr(), self.row_len.data_ptr(), self.col.data_ptr(),
+                       self.w.data_ptr(), self.two_m_t.data_ptr()))
+            self.__dict__["_cv"] = c
+        return c[1]
 
     @property
     def workspace(self) -> torch.Tensor:
@@ -468,9 +474,15 @@ class State:
         return CState(*self.cvals())
 
     def cvals(self) -> tuple:
-        """The lv_state fields in order (no member counts: 0)."""
-        return (self.C.data_ptr(), self.K.data_ptr(), self.Sigma.data_ptr(),
-                0 if self.size is None else self.size.data_ptr())
+        """The lv_state fields in order (no member counts: 0); kept while
+        the arrays are the same objects."""
+        key = (id(self.C), id(self.K), id(self.Sigma), id(self.size))
+        c = self.__dict__.get("_cv")
+        if c is None or c[0] != key:
+            c = (key, (self.C.data_ptr(), self.K.data_ptr(), self.Sigma.data_ptr(),
+                       0 if self.size is None else self.size.data_ptr()))
+            self.__dict__["_cv"] = c
+        return c[1]
 
 
 def apply_batch(g: Graph, b: Batch, stream=None):
@@ -609,10 +621,13 @@ def _many(fn, graphs, batches, states, scratches, max_updates, prm, ws, desc, st
     if desc is None or desc.numel() < need:
         desc = torch.empty(need, dtype=torch.uint8, device=graphs[0].device if count else "cuda")
     status = np.zeros(max(count, 1), dtype=np.int32)
-    stats = (Stats * max(count, 1))()
+    # uninitialised records (the call writes every one it returns): a
+    # zero-filled ctypes array of 8.6 KB per item costs more than the launch
+    stats = np.empty(max(count, 1) * ct.sizeof(Stats), dtype=np.uint8)
     wp, wb = (ct.c_void_p(ws.data_ptr()), ws.numel()) if ws is not None else (None, 0)
     args = [items.ctypes.data_as(ct.POINTER(CItem)), count, ct.byref(prm), ct.c_void_p(desc.data_ptr()),
-            desc.numel(), wp, wb, status.ctypes.data_as(ct.POINTER(ct.c_int32)), stats]
+            desc.numel(), wp, wb, status.ctypes.data_as(ct.POINTER(ct.c_int32)),
+            stats.ctypes.data_as(ct.POINTER(Stats))]
     if best is not None:
         args.append(ct.byref(best))
     _check(getattr(L, fn)(*args, _stream(stream)))
@@ -645,7 +660,8 @@ class StatsView(Mapping):
 
 
 class StatsList:
-    """Per-item statistics of louvain_df_many, converted to dicts when read."""
+    """Per-item statistics of louvain_df_many (records in a byte array),
+    converted to dicts when read."""
 
     def __init__(self, arr, count):
         self._a, self._n, self._d = arr, count, {}
@@ -661,7 +677,7 @@ class StatsList:
         if not 0 <= k < self._n:
             raise IndexError(k)
         if k not in self._d:
-            self._d[k] = StatsView(self._a[k])
+            self._d[k] = StatsView(Stats.from_buffer(self._a, k * ct.sizeof(Stats)))
         return self._d[k]
 
     def __iter__(self):
