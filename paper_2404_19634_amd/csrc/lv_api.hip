@@ -723,6 +723,7 @@ size_t carve_workspace(Workspace& ws, void* base, int32_t n, int64_t cap) {
   ws.pool_pairs = take<uint64_t>(cur, total, base, static_cast<size_t>(ws.pool_slots));
   ws.pool_keys = reinterpret_cast<int32_t*>(ws.pool_pairs);
   ws.pool_vals = base ? ws.pool_keys + ws.pool_slots : nullptr;
+  ws.hot = take<HotRec>(cur, total, base, static_cast<size_t>(kHotRegions * kHotCap));
   ws.scan_part_len = scan_parts_needed(static_cast<int64_t>(un) + 2) + 8;
   ws.scan_part = take<int64_t>(cur, total, base, static_cast<size_t>(ws.scan_part_len));
   ws.ctr = take<int64_t>(cur, total, base, CTR_COUNT);

@@ -45,7 +45,8 @@ constexpr int64_t kRowListPad = 8192;  // bin lists hold n + this many entries (
 constexpr int kStatReplicas = 32;
 constexpr int kStatStride = 2 * kCtrLine;  // slots per replica (two lines)
 constexpr int kStatSet = kStatReplicas * kStatStride;
-constexpr int kRoundSet = 10 * kCtrLine;
+constexpr int kHotRegions = 16;     // reservation counters of the deferred-total records
+constexpr int kRoundSet = (10 + kHotRegions) * kCtrLine;
 enum Ctr {
   CTR_ERR = 0 * kCtrLine,        // error code (first nonzero wins)
   CTR_TOTAL = 1 * kCtrLine,      // generic total (scans, counts)
@@ -88,7 +89,8 @@ enum RoundCtr {
   RC_BIN0 = 0,                   // lines 0 .. NBINS-1: items per bin (rc_bin)
   RC_POOL = 7 * kCtrLine,        // hub table slots handed out
   RC_HUB_UNITS = 8 * kCtrLine,   // hub insert units
-  RC_HUB_CUNITS = 9 * kCtrLine   // hub table-slot (clear / decide) units
+  RC_HUB_CUNITS = 9 * kCtrLine,  // hub table-slot (clear / decide) units
+  RC_HOT = 10 * kCtrLine         // lines 10 .. 10+kHotRegions-1: deferred-total records per region
 };
 // per-iteration statistics, slots of every replica
 enum Stat {
@@ -118,6 +120,16 @@ struct LevelGraph {
 };
 
 // Carving of the caller's workspace.  Every region is 256-byte aligned.
+// A move role's change to a large community's total and size, applied after
+// the scan launch (k_hot_apply) instead of by device atomics at the end of
+// every workgroup.
+struct HotRec {
+  int32_t c;
+  int32_t ds;
+  int64_t dk;
+};
+constexpr int64_t kHotCap = 8192;  // records per region
+
 struct Workspace {
   int32_t n = 0;
   int64_t cap = 0;
@@ -162,6 +174,7 @@ struct Workspace {
   int32_t* pool_vals = nullptr;  // (as pool_pairs) packed key:value slots
   uint64_t* pool_pairs = nullptr;
   int64_t pool_slots = 0;
+  HotRec* hot = nullptr;         // deferred totals of large communities (kHotRegions x kHotCap)
   int64_t* scan_part = nullptr;  // per-block partial sums of the scans
   int64_t scan_part_len = 0;
   int64_t* ctr = nullptr;        // CTR_COUNT counters
@@ -275,11 +288,16 @@ __device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* lds) {
 // Sets frontier bit i when `pred`; a vertex whose bit was clear is appended
 // to the frontier list (list may be null: bitmask only).  Every active lane
 // of the wavefront calls it together; they share one counter atomic.
+// The word is read first and the atomic issued only while the bit is clear:
+// the neighbours of movers in a skewed graph are mostly the same few hubs,
+// and device atomics on one line serialise, while reads of it do not.  (A
+// stale read of a clear bit only costs the atomic; bits are not cleared
+// while a kernel marks.)
 __device__ __forceinline__ void front_mark(uint32_t* bm, const FrontList& F, int32_t i, bool pred) {
   bool fresh = false;
   if (pred) {
     const uint32_t bit = 1u << (i & 31);
-    fresh = !(atomicOr(&bm[i >> 5], bit) & bit);
+    if (!(bm[i >> 5] & bit)) fresh = !(atomicOr(&bm[i >> 5], bit) & bit);
   }
   if (!F.list) return;
   const int r = static_cast<int>(blockIdx.x % kFlRegions);
@@ -295,7 +313,10 @@ __device__ __forceinline__ void front_mark_n(uint32_t* bm, const FrontList& F, c
                                              const bool (&pred)[N]) {
   uint32_t old[N];
 #pragma unroll
-  for (int q = 0; q < N; ++q) old[q] = pred[q] ? atomicOr(&bm[v[q] >> 5], 1u << (v[q] & 31)) : ~0u;
+  for (int q = 0; q < N; ++q) old[q] = pred[q] ? bm[v[q] >> 5] : ~0u;  // read first, as in front_mark
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    if (!((old[q] >> (v[q] & 31)) & 1u)) old[q] = atomicOr(&bm[v[q] >> 5], 1u << (v[q] & 31));
   if (!F.list) return;
   uint64_t mask[N];
   int64_t total = 0;

@@ -431,11 +431,14 @@ __device__ int64_t scan_wave(const ManyItem& it, const ItemScratch& s, const Mov
   kid = wave_sum_i32(kid);
   const int64_t Kv = ld(&it.K[v]);
   const int64_t Sd = ld(&it.Sigma[d]);
+  // candidates whose gain bound K_{v->c} (2m - K_v) - tb is not positive
+  // (Σ_c >= K_{v->c}) cannot be chosen; their Σ_c is not read
+  const int64_t tb = m.two_m * kid - Kv * (Sd - Kv), dm = m.two_m - Kv;
   int64_t bg = LLONG_MIN;
   int32_t bc = INT_MAX;
   for (uint32_t t = lane; t < ts; t += kWave) {
     const int32_t c = keys[t];
-    if (c < 0) continue;
+    if (c < 0 || static_cast<int64_t>(vals[t]) * dm <= tb) continue;
     const int64_t g = m.two_m * (static_cast<int64_t>(vals[t]) - kid) - Kv * (ld(&it.Sigma[c]) - Sd + Kv);
     if (better(g, c, bg, bc)) {
       bg = g;
@@ -500,11 +503,12 @@ __device__ int64_t scan_block(const ManyItem& it, const ItemScratch& s, const Mo
   kid = block_sum(kid, sh.red);
   const int64_t Kv = ld(&it.K[v]);
   const int64_t Sd = ld(&it.Sigma[d]);
+  const int64_t tb = m.two_m * kid - Kv * (Sd - Kv), dm = m.two_m - Kv;  // as in scan_wave
   int64_t bg = LLONG_MIN;
   int32_t bc = INT_MAX;
   for (uint32_t t = threadIdx.x; t < ts; t += kBlock) {
     const int32_t c = keys[t];
-    if (c < 0) continue;
+    if (c < 0 || static_cast<int64_t>(vals[t]) * dm <= tb) continue;
     const int64_t g = m.two_m * (static_cast<int64_t>(vals[t]) - kid) - Kv * (ld(&it.Sigma[c]) - Sd + Kv);
     if (better(g, c, bg, bc)) {
       bg = g;

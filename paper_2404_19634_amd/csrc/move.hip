@@ -68,6 +68,7 @@ struct Dev {
   int32_t mode;
   int32_t guard;
   int32_t defer;  // ASYNC: Sigma / size changes through the workgroup aggregate
+  HotRec* hot;    // ASYNC with defer: record buffer of large communities' changes (else null)
 };
 
 Dev make_dev(const MoveArgs& a, Workspace& ws, const lv_tuning& tu) {
@@ -92,6 +93,7 @@ Dev make_dev(const MoveArgs& a, Workspace& ws, const lv_tuning& tu) {
   d.mode = a.mode;
   d.guard = a.guard;
   d.defer = tu.defer_totals;
+  d.hot = (a.mode == LV_ASYNC && tu.defer_totals) ? ws.hot : nullptr;
   return d;
 }
 
@@ -109,6 +111,23 @@ __device__ __forceinline__ bool better(int64_t g1, int32_t c1, int64_t g0, int32
 __device__ __forceinline__ int64_t gain_of(int64_t two_m, int64_t kic, int64_t kid, int64_t Ki, int64_t Sc,
                                            int64_t Sd) {
   return two_m * (kic - kid) - Ki * (Sc - Sd + Ki);
+}
+
+// Exact pruning of candidates before their total is read.  The gain of a
+// move to c != d is 2m K_{i->c} - K_i Σ_c - t with
+// t = 2m K_{i->d} - K_i (Σ_d - K_i).  Every member j of c counts the arc
+// j -> i in K_j, so Σ_c >= K_{i->c}, and the gain is at most
+// K_{i->c} (2m - K_i) - t.  A community that fails open() cannot gain, so
+// it is never the target of a move and its Σ_c (a random 8-byte gather)
+// is skipped; the move decided is the same.  (Under ASYNC a total that
+// lags its membership can undercut K_{i->c}; such a candidate's gain is
+// then inflated by the lag, and the bound leaves it out.)
+struct GainBar {
+  int64_t t, dm;
+  __device__ __forceinline__ bool open(int64_t kic) const { return kic * dm > t; }
+};
+__device__ __forceinline__ GainBar gain_bar(int64_t two_m, int64_t kid, int64_t Ki, int64_t Sd) {
+  return GainBar{two_m * kid - Ki * (Sd - Ki), two_m - Ki};
 }
 
 // Final decision with the optional swap guard (singleton into a singleton
@@ -196,6 +215,118 @@ __device__ __forceinline__ void commit_move(const Dev& D, Agg* A, int32_t i, int
       atomicSub(&D.size[d], 1);
       atomicAdd(&D.size[c], 1);
     }
+  }
+}
+
+// End of a move role's workgroup: its aggregate is flushed.  The
+// communities whose total is at least 2m / 1024 (at most 1024 of them) are
+// the ones that most workgroups of a launch move vertices into or out of:
+// device atomics on their lines queue at the memory side, one at a time,
+// and reads of the same lines wait behind them.  Their changes are written
+// as records instead (one counter atomic per workgroup) and k_hot_apply adds
+// them after the launch, one atomic per community; every other community is
+// updated here.  Within the launch this only delays what other workgroups
+// see of the changes, which they did not see before their own end either.
+template <class A>
+__device__ __forceinline__ void agg_end_moves(A* a, const Dev& D, int64_t two_m) {
+  if (!D.hot) {
+    agg_end(a, D.Sigma, D.size);
+    return;
+  }
+  constexpr int kPer = (A::kSlots + kBlock - 1) / kBlock;
+  __shared__ int32_t s_n;
+  __shared__ int64_t s_base;
+  __syncthreads();  // every agg_add of the workgroup is done
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  const int64_t hmin = two_m >> 10;
+  int32_t pos[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    pos[q] = -1;
+    const int sl = threadIdx.x + q * kBlock;
+    if (sl >= A::kSlots) continue;
+    const int32_t c = a->key[sl];
+    if (c < 0) continue;
+    const int64_t dk = static_cast<int64_t>(a->dsig[sl]);
+    const int32_t ds = a->dsize[sl];
+    if (!dk && !ds) continue;
+    if (D.Sigma[c] >= hmin) {
+      pos[q] = atomicAdd(&s_n, 1);
+      continue;
+    }
+    if (dk) atomic_add_i64(&D.Sigma[c], dk);
+    if (D.size && ds) atomicAdd(&D.size[c], ds);
+  }
+  __syncthreads();
+  const int region = static_cast<int>(blockIdx.x % kHotRegions);
+  if (threadIdx.x == 0 && s_n)
+    s_base = static_cast<int64_t>(atomicAdd(reinterpret_cast<unsigned long long*>(&D.rc[RC_HOT + region * kCtrLine]),
+                                            static_cast<unsigned long long>(s_n)));
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    if (pos[q] < 0) continue;
+    const int sl = threadIdx.x + q * kBlock;
+    const int32_t c = a->key[sl];
+    const int64_t dk = static_cast<int64_t>(a->dsig[sl]);
+    const int32_t ds = a->dsize[sl];
+    const int64_t at = s_base + pos[q];
+    if (at < kHotCap) {
+      D.hot[region * kHotCap + at] = HotRec{c, ds, dk};
+    } else {  // the region is full: added here after all
+      if (dk) atomic_add_i64(&D.Sigma[c], dk);
+      if (D.size && ds) atomicAdd(&D.size[c], ds);
+    }
+  }
+}
+
+// The records of one scan launch: workgroup p owns the communities c with
+// c mod gridDim == p, sums their records in LDS and adds each total with
+// one atomic.
+constexpr int kHotApplyBlocks = 64;
+constexpr int64_t kHotMinFrontier = 1 << 16;  // frontier estimate of a launch that defers
+constexpr int kHotSlots = 2048;
+__global__ void __launch_bounds__(kBlock) k_hot_apply(const int64_t* __restrict__ rc, const HotRec* __restrict__ hot,
+                                                     int64_t* __restrict__ Sigma, int32_t* __restrict__ size) {
+  __shared__ int32_t key[kHotSlots];
+  __shared__ unsigned long long dk[kHotSlots];
+  __shared__ int32_t ds[kHotSlots];
+  for (int t = threadIdx.x; t < kHotSlots; t += kBlock) {
+    key[t] = -1;
+    dk[t] = 0;
+    ds[t] = 0;
+  }
+  __syncthreads();
+  for (int r = 0; r < kHotRegions; ++r) {
+    const int64_t cnt = min(rc[RC_HOT + r * kCtrLine], kHotCap);
+    for (int64_t k = threadIdx.x; k < cnt; k += kBlock) {
+      const HotRec h = hot[r * kHotCap + k];
+      if (static_cast<uint32_t>(h.c) % gridDim.x != blockIdx.x) continue;
+      uint32_t t = hash_slot(static_cast<uint32_t>(h.c), kHotSlots);
+      bool done = false;
+      for (int p = 0; p < kHotSlots; ++p) {
+        const int32_t old = atomicCAS(&key[t], -1, h.c);
+        if (old == -1 || old == h.c) {
+          atomicAdd(&dk[t], static_cast<unsigned long long>(h.dk));
+          atomicAdd(&ds[t], h.ds);
+          done = true;
+          break;
+        }
+        t = (t + 1) & (kHotSlots - 1);
+      }
+      if (!done) {  // (more owned communities than slots)
+        atomic_add_i64(&Sigma[h.c], h.dk);
+        if (size) atomicAdd(&size[h.c], h.ds);
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kHotSlots; t += kBlock) {
+    const int32_t c = key[t];
+    if (c < 0) continue;
+    if (dk[t]) atomic_add_i64(&Sigma[c], static_cast<int64_t>(dk[t]));
+    if (size && ds[t]) atomicAdd(&size[c], ds[t]);
   }
 }
 
@@ -733,7 +864,7 @@ __device__ __forceinline__ void role_small(const Dev& D, int64_t two_m, const in
     int32_t kid = (has && c == d) ? kc : 0;
 #pragma unroll
     for (int s = 1; s < G; s <<= 1) kid = max(kid, __shfl_xor(kid, s));
-    const bool cand = has && c != d;
+    const bool cand = has && c != d && gain_bar(two_m, kid, Ki, Sd).open(kc);
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
     if (cand) {
@@ -789,21 +920,28 @@ __device__ __forceinline__ void role_lane4(const Dev& D, int64_t two_m, const in
       c[q] = j[q] >= 0 ? D.C[j[q]] : -1;
     }
     const int64_t Sd = D.Sigma[d];
-    int64_t sc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) sc[q] = (c[q] >= 0 && c[q] != d) ? D.Sigma[c[q]] : 0;
     int32_t kid = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) kid += (c[q] == d) ? x[q] : 0;
+    const GainBar bar = gain_bar(two_m, kid, Ki, Sd);
+    int32_t kc[4];
+    bool op[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      kc[q] = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) kc[q] += (c[r] == c[q]) ? x[r] : 0;
+      op[q] = c[q] >= 0 && c[q] != d && bar.open(kc[q]);
+    }
+    int64_t sc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sc[q] = op[q] ? D.Sigma[c[q]] : 0;
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (c[q] < 0 || c[q] == d) continue;
-      int32_t kc = 0;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) kc += (c[r] == c[q]) ? x[r] : 0;
-      const int64_t g = gain_of(two_m, kc, kid, Ki, sc[q], Sd);
+      if (!op[q]) continue;
+      const int64_t g = gain_of(two_m, kc[q], kid, Ki, sc[q], Sd);
       if (better(g, c[q], bg, bc)) {
         bg = g;
         bc = c[q];
@@ -904,6 +1042,7 @@ __device__ __forceinline__ void role_wave(const Dev& D, int64_t two_m, const int
       n_d = D.C[n_i];
     }
     kid = wave_sum_i32(kid);
+    const GainBar bar = gain_bar(two_m, kid, Ki, Sd);
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
     // the table in chunks of kDecideSlots slots per lane (the gathers of a
@@ -918,10 +1057,10 @@ __device__ __forceinline__ void role_wave(const Dev& D, int64_t two_m, const int
         vv[q] = t < ts ? vals[t] : 0;
       }
 #pragma unroll
-      for (int q = 0; q < kDecideSlots; ++q) sg[q] = cc[q] >= 0 ? D.Sigma[cc[q]] : 0;
+      for (int q = 0; q < kDecideSlots; ++q) sg[q] = cc[q] >= 0 && bar.open(vv[q]) ? D.Sigma[cc[q]] : 0;
 #pragma unroll
       for (int q = 0; q < kDecideSlots; ++q)
-        if (cc[q] >= 0) {
+        if (cc[q] >= 0 && bar.open(vv[q])) {
           const int64_t g = gain_of(two_m, vv[q], kid, Ki, sg[q], Sd);
           if (better(g, cc[q], bg, bc)) {
             bg = g;
@@ -1102,6 +1241,7 @@ __device__ __forceinline__ void role_block(const Dev& D, int64_t two_m, const in
       n_d = D.C[n_i];
     }
     kid = block_total(kid, red->s);
+    const GainBar bar = gain_bar(two_m, kid, Ki, Sd);
     int64_t bg = LLONG_MIN;
     int32_t bc = INT_MAX;
     for (uint32_t t0 = 0; t0 < ts; t0 += kDecideSlots * kBlock) {
@@ -1114,10 +1254,10 @@ __device__ __forceinline__ void role_block(const Dev& D, int64_t two_m, const in
         vv[q] = t < ts ? vals[t] : 0;
       }
 #pragma unroll
-      for (int q = 0; q < kDecideSlots; ++q) sg[q] = cc[q] >= 0 ? D.Sigma[cc[q]] : 0;
+      for (int q = 0; q < kDecideSlots; ++q) sg[q] = cc[q] >= 0 && bar.open(vv[q]) ? D.Sigma[cc[q]] : 0;
 #pragma unroll
       for (int q = 0; q < kDecideSlots; ++q)
-        if (cc[q] >= 0) {
+        if (cc[q] >= 0 && bar.open(vv[q])) {
           const int64_t g = gain_of(two_m, vv[q], kid, Ki, sg[q], Sd);
           if (better(g, cc[q], bg, bc)) {
             bg = g;
@@ -1354,20 +1494,20 @@ __global__ void __launch_bounds__(kBlock) k_move_all(Dev D, Bins bins, Roles R, 
       case BIN_G16: role_small<16>(D, two_m, bins.list[BIN_G16], BIN_G16, rb, nb, agg); break;
       default: role_small<32>(D, two_m, bins.list[BIN_G32], BIN_G32, rb, nb, agg); break;
     }
-    agg_end(agg, D.Sigma, D.size);
+    agg_end_moves(agg, D, two_m);
   } else if ((kAny || ONLY == BIN_WAVE) && role == BIN_WAVE) {
     MoveAgg* agg = reinterpret_cast<MoveAgg*>(smem);
     int32_t* keys = reinterpret_cast<int32_t*>(smem + sizeof(MoveAgg));
     int32_t* vals = keys + (kBlock / kWave) * TS;
     agg_begin(agg);
     role_wave<TS>(D, two_m, bins.list[BIN_WAVE], rb, nb, keys, vals, agg);
-    agg_end(agg, D.Sigma, D.size);
+    agg_end_moves(agg, D, two_m);
   } else if ((kAny || ONLY == BIN_BLOCK) && role == BIN_BLOCK) {
     Red* red = reinterpret_cast<Red*>(smem);
     int32_t* keys = reinterpret_cast<int32_t*>(smem + sizeof(Red));
     agg_begin(&red->agg);
     role_block(D, two_m, bins.list[BIN_BLOCK], rb, nb, keys, keys + kBlockTS, red);
-    agg_end(&red->agg, D.Sigma, D.size);
+    agg_end_moves(&red->agg, D, two_m);
   } else if (kAny || ONLY == BIN_HUB) {
     Red* red = reinterpret_cast<Red*>(smem);
     int32_t* tk = reinterpret_cast<int32_t*>(smem + sizeof(Red));
@@ -1404,12 +1544,13 @@ constexpr int kDecideMaxKeys = kHubTS - 2 * kBlock;
 // Best (gain, community) over table entries held by this thread.
 __device__ __forceinline__ void best_of(const Dev& D, int64_t two_m, int64_t kid, int64_t Ki, int64_t Sd,
                                         const int32_t* cc, const int32_t* vv, int64_t& bg, int32_t& bc) {
+  const GainBar bar = gain_bar(two_m, kid, Ki, Sd);
   int64_t sg[kDecideSlots];
 #pragma unroll
-  for (int q = 0; q < kDecideSlots; ++q) sg[q] = cc[q] >= 0 ? D.Sigma[cc[q]] : 0;
+  for (int q = 0; q < kDecideSlots; ++q) sg[q] = cc[q] >= 0 && bar.open(vv[q]) ? D.Sigma[cc[q]] : 0;
 #pragma unroll
   for (int q = 0; q < kDecideSlots; ++q)
-    if (cc[q] >= 0) {
+    if (cc[q] >= 0 && bar.open(vv[q])) {
       const int64_t g = gain_of(two_m, vv[q], kid, Ki, sg[q], Sd);
       if (better(g, cc[q], bg, bc)) {
         bg = g;
@@ -1920,8 +2061,14 @@ uint32_t bins_for_degrees(int32_t lo, int32_t hi, int32_t wave_max) {
 
 void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const SubRound& r, uint32_t bin_mask,
                   hipStream_t st) {
-  const Dev D = make_dev(a, ws, tu);
+  Dev D = make_dev(a, ws, tu);
   const int64_t words = (static_cast<int64_t>(a.g.n) + 31) / 32;
+  // Large communities' changes are deferred only in a fused launch over a
+  // frontier large enough for their atomics to queue (a smaller one does not
+  // repay the extra launch); the launches per bin of a dense frontier run in
+  // degree order so that each sees every change of the bins before it.
+  const bool fuse = a.sparse && a.est <= tu.fuse_max_frontier;
+  if (!fuse || a.est < kHotMinFrontier) D.hot = nullptr;
   Bins b;
   for (int k = 0; k < NBINS; ++k) b.list[k] = ws.bins[k];
   HubOut HO{ws.hub_off, ws.hub_cbase, ws.hub_cnum, ws.u_ins_b, ws.u_ins_a, ws.u_emit_b, ws.u_emit_s};
@@ -1958,7 +2105,6 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
                                                                                         : lds_wave<1024>();
   const HubIn H{ws.bins[BIN_HUB], ws.hub_off, ws.u_ins_b, ws.u_ins_a,
                 reinterpret_cast<unsigned long long*>(ws.pool_pairs), ws.hub_kid, ws.pool_slots};
-  const bool fuse = a.sparse && a.est <= tu.fuse_max_frontier;
   if (fuse) {
     Roles R;
     int64_t end = 0;
@@ -1993,6 +2139,8 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
         launch_one_role<1024>(k, D, b, H, per[k], tp, st);
     }
   }
+  if (D.hot)
+    hipLaunchKernelGGL(k_hot_apply, dim3(kHotApplyBlocks), dim3(kBlock), 0, st, a.rc, D.hot, a.Sigma, a.size);
   if (hubs) {
     const TimerPair td = timer_pair(LV_TIME_HUB_DECIDE);
     hipExtLaunchKernelGGL(k_hub_decide, dim3(cap_grid(k_hub_decide, bh)), dim3(kBlock), 0, st, td.start, td.stop, 0,
