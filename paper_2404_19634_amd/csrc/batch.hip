@@ -113,7 +113,9 @@ __global__ void k_init(BatchScratch b, int64_t words, int64_t* __restrict__ ctr)
 // Validation, the pair table, and the touched rows.  A row is listed
 // under the first direction that reaches it: row_slot[vertex] = that
 // direction's index e, row_of[e] = vertex (-1 for every other direction).
-__global__ void __launch_bounds__(kBlock) k_validate(Upd U, int32_t n, BatchScratch b, int64_t* __restrict__ ctr) {
+constexpr uint64_t kTagMul = 2654435761ull;  // a prime above any tag bit count
+__global__ void __launch_bounds__(kBlock) k_validate(Upd U, int32_t n, BatchScratch b, int64_t* __restrict__ ctr,
+                                                    uint64_t tag_bits) {
   __shared__ int64_t lds[kBlock / kWave];
   int64_t si = 0, sd = 0;
   const int64_t total = U.nd + U.ni;
@@ -144,8 +146,14 @@ __global__ void __launch_bounds__(kBlock) k_validate(Upd U, int32_t n, BatchScra
       const int64_t e = 2 * k + side;
       int32_t head = -1;
       if (ok) {
-        const uint32_t bit = 1u << (r & 31);
-        if ((atomicOr(&b.tag[r >> 5], bit) & bit) == 0) {
+        // Row r's tag is bit (r * kTagMul) mod tag_bits: a bijection (the
+        // prime kTagMul exceeds tag_bits), which scatters the rows of
+        // neighbouring ids -- in a skewed graph often all hubs, touched by
+        // many updates -- over many lines instead of one, whose atomics
+        // would queue.
+        const int64_t t = static_cast<int64_t>((static_cast<uint64_t>(r) * kTagMul) % tag_bits);
+        const uint32_t bit = 1u << (t & 31);
+        if ((atomicOr(&b.tag[t >> 5], bit) & bit) == 0) {
           b.row_slot[r] = static_cast<int32_t>(e);
           head = r;
         }
@@ -285,12 +293,23 @@ __global__ void __launch_bounds__(kBlock) k_scan(const int64_t* __restrict__ row
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int32_t k = off + lane; k < end; k += kWave) {
-      const int32_t c = col[s + k];
-      const uint32_t h = hash_slot(static_cast<uint32_t>(c), kFilterBits);
-      if (!((F[h >> 5] >> (h & 31)) & 1u)) continue;
-      const int32_t p = pair_find(b.keys, b.size, canon(a, c));
-      if (p >= 0) b.pos[2 * static_cast<int64_t>(p) + (a > c ? 1 : 0)] = s + k;
+    // four arcs per lane in flight per step (the loads are independent)
+    for (int32_t k0 = off + lane; k0 < end; k0 += 4 * kWave) {
+      int32_t cc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int32_t k = k0 + q * kWave;
+        cc[q] = k < end ? col[s + k] : -1;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int32_t c = cc[q];
+        if (c < 0) continue;
+        const uint32_t h = hash_slot(static_cast<uint32_t>(c), kFilterBits);
+        if (!((F[h >> 5] >> (h & 31)) & 1u)) continue;
+        const int32_t p = pair_find(b.keys, b.size, canon(a, c));
+        if (p >= 0) b.pos[2 * static_cast<int64_t>(p) + (a > c ? 1 : 0)] = s + k0 + q * kWave;
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -458,7 +477,8 @@ void launch_batch_phase1(const lv_graph& g, const lv_edges& del, const lv_edges&
   const int64_t total = del.count + ins.count, dirs = 2 * total;
   hipLaunchKernelGGL(k_init, dim3(grid_for(std::max<int64_t>(std::max<int64_t>(b.size, dirs), words), kBlock, 2048)),
                      dim3(kBlock), 0, st, b, words, ctr);
-  hipLaunchKernelGGL(k_validate, dim3(grid_for(total, kBlock, 256)), dim3(kBlock), 0, st, U, g.n, b, ctr);
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(total, kBlock, 256)), dim3(kBlock), 0, st, U, g.n, b, ctr,
+                     static_cast<uint64_t>(words) * 32);
   hipLaunchKernelGGL(k_rank, dim3(grid_for(dirs, kBlock, 4096)), dim3(kBlock), 0, st, U, b);
   hipLaunchKernelGGL(k_rows, dim3(grid_for(dirs, kBlock * kRowsPer, 4096)), dim3(kBlock), 0, st, g.row_start,
                      g.row_len, b, ctr);

@@ -281,10 +281,9 @@ __device__ __forceinline__ void agg_end_moves(A* a, const Dev& D, int64_t two_m)
   }
 }
 
-// The records of one scan launch: workgroup p owns the communities c with
-// c mod gridDim == p, sums their records in LDS and adds each total with
-// one atomic.
-constexpr int kHotApplyBlocks = 64;
+// The records of one scan launch: workgroup r sums region r's records per
+// community in LDS (four records per thread in flight) and adds each sum
+// with one atomic, so a community gets at most kHotRegions atomics.
 constexpr int64_t kHotMinFrontier = 1 << 16;  // frontier estimate of a launch that defers
 constexpr int kHotSlots = 2048;
 __global__ void __launch_bounds__(kBlock) k_hot_apply(const int64_t* __restrict__ rc, const HotRec* __restrict__ hot,
@@ -298,26 +297,34 @@ __global__ void __launch_bounds__(kBlock) k_hot_apply(const int64_t* __restrict_
     ds[t] = 0;
   }
   __syncthreads();
-  for (int r = 0; r < kHotRegions; ++r) {
-    const int64_t cnt = min(rc[RC_HOT + r * kCtrLine], kHotCap);
-    for (int64_t k = threadIdx.x; k < cnt; k += kBlock) {
-      const HotRec h = hot[r * kHotCap + k];
-      if (static_cast<uint32_t>(h.c) % gridDim.x != blockIdx.x) continue;
-      uint32_t t = hash_slot(static_cast<uint32_t>(h.c), kHotSlots);
+  const int64_t cnt = min(rc[RC_HOT + blockIdx.x * kCtrLine], kHotCap);
+  const HotRec* src = hot + blockIdx.x * kHotCap;
+  constexpr int U = 4;
+  for (int64_t k0 = 0; k0 < cnt; k0 += U * kBlock) {
+    HotRec h[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int64_t k = k0 + q * kBlock + threadIdx.x;
+      h[q] = k < cnt ? src[k] : HotRec{-1, 0, 0};
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      if (h[q].c < 0) continue;
+      uint32_t t = hash_slot(static_cast<uint32_t>(h[q].c), kHotSlots);
       bool done = false;
       for (int p = 0; p < kHotSlots; ++p) {
-        const int32_t old = atomicCAS(&key[t], -1, h.c);
-        if (old == -1 || old == h.c) {
-          atomicAdd(&dk[t], static_cast<unsigned long long>(h.dk));
-          atomicAdd(&ds[t], h.ds);
+        const int32_t old = atomicCAS(&key[t], -1, h[q].c);
+        if (old == -1 || old == h[q].c) {
+          atomicAdd(&dk[t], static_cast<unsigned long long>(h[q].dk));
+          atomicAdd(&ds[t], h[q].ds);
           done = true;
           break;
         }
         t = (t + 1) & (kHotSlots - 1);
       }
-      if (!done) {  // (more owned communities than slots)
-        atomic_add_i64(&Sigma[h.c], h.dk);
-        if (size) atomicAdd(&size[h.c], h.ds);
+      if (!done) {  // (more communities in the region than slots)
+        atomic_add_i64(&Sigma[h[q].c], h[q].dk);
+        if (size) atomicAdd(&size[h[q].c], h[q].ds);
       }
     }
   }
@@ -2140,7 +2147,7 @@ void launch_round(const MoveArgs& a, Workspace& ws, const lv_tuning& tu, const S
     }
   }
   if (D.hot)
-    hipLaunchKernelGGL(k_hot_apply, dim3(kHotApplyBlocks), dim3(kBlock), 0, st, a.rc, D.hot, a.Sigma, a.size);
+    hipLaunchKernelGGL(k_hot_apply, dim3(kHotRegions), dim3(kBlock), 0, st, a.rc, D.hot, a.Sigma, a.size);
   if (hubs) {
     const TimerPair td = timer_pair(LV_TIME_HUB_DECIDE);
     hipExtLaunchKernelGGL(k_hub_decide, dim3(cap_grid(k_hub_decide, bh)), dim3(kBlock), 0, st, td.start, td.stop, 0,
