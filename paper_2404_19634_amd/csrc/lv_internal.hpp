@@ -311,12 +311,9 @@ __device__ __forceinline__ void front_mark(uint32_t* bm, const FrontList& F, int
 template <int N>
 __device__ __forceinline__ void front_mark_n(uint32_t* bm, const FrontList& F, const int32_t (&v)[N],
                                              const bool (&pred)[N]) {
-  uint32_t old[N];
+  uint32_t old[N];  // (no read first: a batch's endpoints are mostly fresh)
 #pragma unroll
-  for (int q = 0; q < N; ++q) old[q] = pred[q] ? bm[v[q] >> 5] : ~0u;  // read first, as in front_mark
-#pragma unroll
-  for (int q = 0; q < N; ++q)
-    if (!((old[q] >> (v[q] & 31)) & 1u)) old[q] = atomicOr(&bm[v[q] >> 5], 1u << (v[q] & 31));
+  for (int q = 0; q < N; ++q) old[q] = pred[q] ? atomicOr(&bm[v[q] >> 5], 1u << (v[q] & 31)) : ~0u;
   if (!F.list) return;
   uint64_t mask[N];
   int64_t total = 0;
