@@ -722,3 +722,37 @@ def test_autotune_many_keeps_results_and_sets_the_class_entry(lib):
             assert np.array_equal(C, Co) and np.array_equal(K, Ko) and np.array_equal(S, So)
     finally:
         lib.set_many_tuning(saved)
+
+
+@pytest.mark.gpu
+def test_df_large_frontier_keeps_totals_and_sizes_exact(lib):
+    """A DF update whose scan runs as one launch over a frontier bound of at
+    least 65,536 (2 x 12,000 updates on 2M vertices: sparse, one sub-round):
+    there the changes of communities with a total of at least 2m/1024 are
+    deferred past the launch and summed per community afterwards.  Totals,
+    sizes and degrees must still be exact, over several updates in a row."""
+    e = W.chung_lu(2_000_000, 2.1, 8.0, 77, device="cuda")
+    g = lib.Graph.from_edges(e, slack_frac=0.2, slack_min=8)
+    lib.set_tuning(wave_max_degree=256)
+    try:
+        st, _ = lib.louvain_static(g, mode="async")
+        batches = W.batch_sequence(e, [12000], 3, seed=91)
+        for b in batches:
+            st, s = lib.louvain_df_apply(g, lib.Batch.from_host(b), st, lib.params(mode="async"))
+            assert s["passes"] >= 1
+            C, K, S = st.host()
+            size = st.size.cpu().numpy()
+            deg = np.zeros(e.n, dtype=np.int64)
+            rs = g.row_start.cpu().numpy()
+            rl = g.row_len.cpu().numpy().astype(np.int64)
+            w = g.w.cpu().numpy()
+            idx = np.repeat(np.arange(e.n), rl)
+            pos = (np.repeat(rs[:-1], rl) + (np.arange(rl.sum()) - np.repeat(np.cumsum(rl) - rl, rl))).astype(np.int64)
+            np.add.at(deg, idx, w[pos].astype(np.int64))
+            assert np.array_equal(K, deg)
+            assert np.array_equal(S, np.bincount(C, weights=K, minlength=e.n).astype(np.int64))
+            assert np.array_equal(size, np.bincount(C, minlength=e.n).astype(size.dtype))
+            big = S >= int(g.two_m_t.item()) // 1024
+            assert big.sum() >= 1  # the deferred path had large communities to defer
+    finally:
+        lib.set_tuning()
