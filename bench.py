@@ -470,6 +470,18 @@ def serve_bench(args):
     srv.wait(len(data))
     burst_s = time.perf_counter() - t0
     burst = srv.summary()
+    # the burst's scan work, from the per-graph statistics of its launches
+    # (the k_many_df roofline divides its algorithmic bytes by the launch's
+    # duration in a kernel trace)
+    arcs = verts = 0
+    for r in srv.done:
+        if r.src:
+            sts, q = r.src
+            arcs += int(sts[q]["arcs_scanned"])
+            verts += int(sts[q]["vertices_affected"])
+    burst["arcs_scanned"] = arcs
+    burst["vertices_affected"] = verts
+    burst["scan_algorithmic_bytes"] = SCAN_BYTES_PER_ARC * arcs + SCAN_BYTES_PER_VERTEX * verts
     sat = len(data) / burst_s
     log(f"burst: {len(data)} updates in {burst_s * 1e3:.1f} ms ({sat:.0f} graphs/s), {burst}")
     srv.done.clear()
